@@ -1,0 +1,90 @@
+"""Shapes and invariants of the synthetic workloads (harness, no decoding)."""
+import numpy as np
+import scipy.sparse as sp
+
+from workloads import codes, sample
+
+
+def _rank(h):
+    return codes.gf2_rank(h)
+
+
+def test_rotated_surface_invariants():
+    for d in (3, 5, 7, 11):
+        hx, hz = codes.rotated_surface(d)
+        assert hx.shape == hz.shape == ((d * d - 1) // 2, d * d)
+        assert not ((hx @ hz.T).toarray() % 2).any()
+        assert d * d - _rank(hx) - _rank(hz) == 1            # one logical qubit
+        assert hx.nnz == hz.nnz == 2 * d * (d - 1)
+        assert set(np.diff(hz.indptr)) == {2, 4}
+
+
+def test_bb_codes():
+    hx, hz = codes.bb144()
+    assert hx.shape == (72, 144)
+    assert not ((hx @ hz.T).toarray() % 2).any()
+    assert _rank(hx) == 66 and _rank(hz) == 66               # k = 144 - 132 = 12
+    assert set(np.diff(hx.indptr)) == {6}
+    assert set(np.asarray(hx.sum(0)).ravel()) == {3}
+    gx, gz = codes.bb288()
+    assert gx.shape == (144, 288)
+    assert not ((gx @ gz.T).toarray() % 2).any()
+    assert 288 - _rank(gx) - _rank(gz) == 12
+
+
+def test_spacetime_shapes_match_configs():
+    expect = {"surface11_phen": (660, 1991, 3680), "bb144_phen": (864, 2592, 6840),
+              "surface5_phen": (60, 185, 308), "surface9_phen": (360, 1089, 1976),
+              "surface13_phen": (1092, 3289, 6156)}
+    for name, (m, n, e) in expect.items():
+        h, _, r = codes.workload_matrices(name)
+        assert h.shape == (m, n) and h.nnz == e, name
+    h, _, _ = codes.workload_matrices("bb144_phen")
+    assert set(np.diff(h.indptr)) == {7, 8}
+    assert _rank(h) == 864                                      # D invertible: full row rank
+
+
+def test_eq1_block_structure():
+    h1 = sp.csr_matrix(np.array([[1, 1, 0], [0, 1, 1]], dtype=np.uint8))
+    st = codes.spacetime(h1, 3).toarray()
+    # round 0 sees its data block and its own measurement; later rounds the previous one too
+    assert st.shape == (6, 9 + 6)
+    assert (st[0:2, 0:3] == h1.toarray()).all() and (st[2:4, 3:6] == h1.toarray()).all()
+    meas = st[:, 9:]
+    assert (meas[0:2, 0:2] == np.eye(2)).all() and not meas[0:2, 2:].any()
+    assert (meas[2:4, 0:2] == np.eye(2)).all() and (meas[2:4, 2:4] == np.eye(2)).all()
+
+
+def test_worked_example_matrix():
+    h = codes.worked_example_h()
+    assert (h != codes.unrotated_surface_x(3)).nnz == 0
+    e = np.zeros((1, 13), np.uint8)
+    e[0, [2, 8, 9]] = 1                                          # Fig. 4: errors {q2, q8, q9}
+    s = sample.syndromes(h, sp.csr_matrix(e))[0]
+    assert list(np.nonzero(s)[0]) == [0, 1, 2, 5]                # triggers {X0, X1, X2, X5}
+
+
+def test_table2_column_counts():
+    # Table II: H_st columns of the d-round unrotated code
+    for d, cols in ((3, 57), (9, 1953)):
+        h = codes.unrotated_surface_x(d)
+        st = codes.spacetime(h, d)
+        assert st.shape[1] == cols
+    # Table II's nonzero counts equal r*nnz(H) + 2*r*m (a weight-2 measurement
+    # column per round), while Eq. 1 with a bidiagonal D gives (2r-1)*m.
+    h = codes.unrotated_surface_x(9)
+    assert 9 * h.nnz + 2 * 9 * h.shape[0] == 3744
+    assert codes.spacetime(h, 9).nnz == 9 * h.nnz + 17 * h.shape[0]
+
+
+def test_pack_roundtrip_and_chunk_independence():
+    rng = np.random.default_rng(0)
+    bits = (rng.random((7, 77)) < 0.3).astype(np.uint8)
+    packed = sample.pack_bits(bits)
+    assert packed.shape == (7, 3) and packed.dtype == np.uint32
+    assert (sample.unpack_bits(packed, 77) == bits).all()
+    assert packed[0, 0] == int("".join(str(b) for b in bits[0, :32][::-1]), 2)
+    h, _, _ = codes.workload_matrices("surface5_cc")
+    e_all = sample.sample_errors(25, 0.1, 70000, seed=5)
+    e_part = sample.sample_errors(25, 0.1, 1000, seed=5, first_shot=65000)
+    assert (e_all[65000:66000] != e_part).nnz == 0
