@@ -1,0 +1,147 @@
+/*
+ * lbp.h -- C ABI of the MI355X Lottery BP (+OSD) decoder.
+ *
+ * The library decodes batches of syndromes of a sparse GF(2) parity-check
+ * matrix H (m checks x n columns) with normalized min-sum belief propagation
+ * (Algorithm 1 of "Lottery BP: Unlocking Quantum Error Decoding at Scale"),
+ * the lottery sign-flip policy of Algorithm 3, and ordered-statistics
+ * decoding (OSD-0 of Algorithm 2, or the OSD-CS combination sweep) for the
+ * shots whose BP run does not converge.
+ *
+ * Conventions
+ *  - Bit vectors (syndromes, corrections) are packed LSB-first into uint32
+ *    words, ceil(bits/32) words per shot, shots stored back to back:
+ *    bit b of shot k is word (k*W + b/32), bit (b % 32).
+ *  - Functions return an lbp_status; on failure lbp_last_error() returns a
+ *    thread-local message.  No C++ exception crosses the boundary.
+ *  - Handles are not thread-safe: one thread at a time per handle.
+ *  - Every result of shot k depends only on (code, params, seed,
+ *    first_shot_id + k, syndrome k): never on batch size or composition.
+ */
+#ifndef LBP_H
+#define LBP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LBP_OK = 0,
+    LBP_EINVAL = -1,        /* malformed argument (bad CSR, prior outside (0,1), size, NULL) */
+    LBP_ENOMEM = -2,        /* device or host allocation failed */
+    LBP_EDEVICE = -3,       /* HIP runtime error (message says which call) */
+    LBP_EBUSY = -4,         /* admission refused (reserved for serving) */
+    LBP_ENOTREADY = -5,     /* result not available yet (reserved for serving) */
+    LBP_EUNSUPPORTED = -6   /* valid input outside what the kernels handle (see lbp_code_create) */
+} lbp_status;
+
+typedef struct lbp_code_s *lbp_code;       /* immutable Tanner graph + priors (device copy) */
+typedef struct lbp_decoder_s *lbp_decoder; /* parameters + device workspace for up to max_batch shots */
+
+/* Message storage format.  INT8 is the paper's Int3.4 fixed point (Sec. VII-A):
+ * signed 8-bit, LSB = 1/16, saturated symmetrically to +-127; column LLRs are
+ * accumulated exactly in 32-bit integers.  FP16 / FP32 store V2C and C2V
+ * messages (and the prior) rounded to nearest even, saturating at the largest
+ * finite value, and accumulate in fp32. */
+typedef enum { LBP_MSG_FP32 = 0, LBP_MSG_FP16 = 1, LBP_MSG_INT8 = 2 } lbp_msg;
+
+/* Check-node scale (Algorithm 1, CN update).  PAPER: sigma_i = 1 - 2^-(i+1),
+ * evaluated in fp32 (exactly 1.0 from i = 24); Int3.4 applies it as
+ * mag - (mag >> (i+1)).  CONST: a fixed factor (Int3.4 requires k/8, applied as
+ * (k*mag) >> 3). */
+typedef enum { LBP_SCALE_PAPER = 0, LBP_SCALE_CONST = 1 } lbp_scale;
+
+/* What the lottery flips (Algorithm 3, last step).  MSG: the messages v* sends
+ * into the next check-node update are negated for that one update (the
+ * hardware's sign-flip stage in front of the CNU, Sec. IV-B).  LLR: lambda_v*
+ * itself is negated before the next VN update (the literal Algorithm 3). */
+typedef enum { LBP_FLIP_MSG = 0, LBP_FLIP_LLR = 1 } lbp_flip;
+
+/* Fallback for shots whose BP run ends without matching the syndrome. */
+typedef enum { LBP_OSD_NONE = 0, LBP_OSD_0 = 1, LBP_OSD_CS = 2 } lbp_osd;
+
+typedef struct {
+    int32_t max_iter;     /* I >= 1 (Algorithm 1 input) */
+    int32_t scale_mode;   /* lbp_scale */
+    float scale;          /* constant scale for LBP_SCALE_CONST */
+    int32_t msg;          /* lbp_msg */
+    int32_t lottery;      /* 0 = plain NMS BP, 1 = Lottery BP */
+    int32_t lottery_skip; /* K: the lottery runs after iterations K..I-2 (0-based); paper uses 6 */
+    int32_t flip;         /* lbp_flip */
+    int32_t osd;          /* lbp_osd */
+    int32_t osd_order;    /* OSD-CS: weight-2 patterns among the first osd_order non-basis columns */
+    int32_t reserved;     /* must be 0 */
+    uint64_t seed;        /* lottery key: Philox4x64-10, key (seed, 0), counter (shot_id, i, 0, 0) */
+} lbp_params;
+
+/* flags[k] bits */
+enum {
+    LBP_FLAG_CONVERGED = 1,        /* BP matched the syndrome */
+    LBP_FLAG_OSD = 2,              /* BP did not converge; OSD was run */
+    LBP_FLAG_OSD_INCONSISTENT = 4  /* s is not in the column space of H; correction = BP hard decision */
+};
+
+/* Fill *p with the defaults: I = 100, PAPER scale, INT8, lottery on, K = 6,
+ * MSG flip, OSD-0, order 10, seed 0. */
+void lbp_params_default(lbp_params *p);
+
+/* Load a parity-check matrix and per-column priors (Algorithm 1 inputs H and p).
+ * row_ptr[m+1], col_idx[row_ptr[m]] (host pointers): CSR with strictly
+ * increasing column indices per row; p[n] (host): error probability of each
+ * column, 0 < p < 1.  The library copies everything; the caller may free its
+ * arrays on return.  The prior LLR mu_v = ln((1-p_v)/p_v) is evaluated in
+ * fp64 on the host (Algorithm 1, line 1).
+ * Limits (LBP_EUNSUPPORTED otherwise): 1 <= row weight <= 8, column weight
+ * <= 4, m <= 8191, n <= 65535.  Empty rows and malformed CSR: LBP_EINVAL.
+ * The code lives on the device that is current when it is created. */
+lbp_status lbp_code_create(int32_t m, int32_t n, const int32_t *row_ptr, const int32_t *col_idx,
+                           const double *p, lbp_code *out);
+void lbp_code_destroy(lbp_code code);
+/* Shape queries (never fail on a valid handle). */
+int32_t lbp_code_rows(lbp_code code);
+int32_t lbp_code_cols(lbp_code code);
+
+/* Create a decoder for `code` with parameters *prm, able to decode up to
+ * max_batch shots per call.  Allocates the device workspace (on the code's
+ * device).  OSD-CS requires a uniform prior (LBP_EUNSUPPORTED otherwise): its
+ * candidate cost is the Hamming weight.  The code must outlive the decoder. */
+lbp_status lbp_decoder_create(lbp_code code, const lbp_params *prm, int64_t max_batch, lbp_decoder *out);
+void lbp_decoder_destroy(lbp_decoder dec);
+
+/* Decode n_shots syndromes, asynchronously on `stream` (a hipStream_t; NULL =
+ * the default stream).  All array arguments are DEVICE pointers owned by the
+ * caller, which must keep them alive until the stream has passed this call:
+ *   syndromes   [n_shots][ceil(m/32)]  in
+ *   corrections [n_shots][ceil(n/32)]  out: e_hat (BP hard decision, or OSD result)
+ *   flags       [n_shots]              out: LBP_FLAG_*
+ *   iters       [n_shots]              out, may be NULL: BP iterations executed
+ *   llr_out     [n_shots][n]           out, may be NULL: lambda of the last BP
+ *               iteration executed (Int3.4: integer units of 1/16)
+ * Shot k uses lottery counter shot_id = first_shot_id + k.  0 <= n_shots <=
+ * max_batch.  The call may synchronize `stream` when more shots fail BP than
+ * the decoder's OSD staging capacity (lbp_decoder_osd_capacity). */
+lbp_status lbp_decode(lbp_decoder dec, int64_t n_shots, uint64_t first_shot_id, const uint32_t *syndromes,
+                      uint32_t *corrections, uint8_t *flags, int32_t *iters, float *llr_out, void *stream);
+
+/* Same contract with HOST pointers; synchronous.  Allocates and frees device
+ * staging buffers internally. */
+lbp_status lbp_decode_host(lbp_decoder dec, int64_t n_shots, uint64_t first_shot_id, const uint32_t *syndromes,
+                           uint32_t *corrections, uint8_t *flags, int32_t *iters, float *llr_out);
+
+/* Number of failed shots whose lambda one OSD pass can stage; failures beyond
+ * it are re-decoded (BP is deterministic) and handled in further passes. */
+int64_t lbp_decoder_osd_capacity(lbp_decoder dec);
+/* Testing aid: lower the staging capacity (>= 1) to exercise the overflow path. */
+lbp_status lbp_decoder_set_osd_capacity(lbp_decoder dec, int64_t cap);
+
+/* Thread-local description of the last error (empty string if none). */
+const char *lbp_last_error(void);
+/* Library version as major*10000 + minor*100 + patch. */
+int32_t lbp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBP_H */

@@ -1,0 +1,611 @@
+// Batched Lottery BP on gfx950: one wavefront decodes one shot at a time.
+//
+// Normalized min-sum BP (Algorithm 1) with the lottery policy (Algorithm 3)
+// and the delayed-syndrome trick of Sec. IV-B: the unsatisfied set of
+// iteration i is taken from the syndrome estimate of iteration i-1, so the
+// lottery can be decided between the check-node and variable-node halves of
+// iteration i without waiting for iteration i's syndrome.
+//
+// Work distribution: the grid is persistent; each wave pulls the next shot from
+// a global counter, runs it to convergence (or I iterations) and writes its
+// outputs.  A wave never waits for another wave, so early-terminating shots do
+// not idle the SIMD behind a slow one.
+//
+// Per-wave LDS (the shot's whole state):
+//   E  [m][DEG] messages, in place: alpha (V2C) before the check-node half,
+//               beta (C2V) after it; padding slots hold a sentinel that never
+//               wins a minimum and is never read by a column.
+//   S  [mw]     measured syndrome
+//   SH [2][mw]  syndrome estimate of the current / previous iteration
+//   EH [2*ceil(n/64)] hard decision of the current iteration (ballot words)
+//
+// Check-node half: lane L owns checks L, L+64, ...; it reads its padded row
+// with one vector LDS load, runs min1/min2/argmin/sign-parity sequentially over
+// the row in registers and writes the row back.  A sequential pass costs ~3
+// VALU ops per edge against ~9 for a cross-lane segmented butterfly, which is
+// why rows are not spread across lanes.
+// Variable-node half: lane L owns columns L, L+64, ...; it gathers its <= CDEG
+// C2V messages through the column table, forms lambda (fixed ascending-check
+// order, so float results are deterministic), the hard decision, the syndrome
+// estimate (LDS atomic XOR, order-independent) and the next V2C messages.
+#include "lbp_internal.h"
+
+#include <hip/hip_fp16.h>
+
+namespace lbp {
+namespace {
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ int wave_sum(int x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    return x;
+}
+
+__device__ __forceinline__ int wave_incl_scan(int x, int lane) {
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        int y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    return x;
+}
+
+__device__ __forceinline__ uint64_t wave_min_u64(uint64_t x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        uint64_t y = __shfl_xor(x, o, 64);
+        x = y < x ? y : x;
+    }
+    return x;
+}
+
+// Philox4x64-10 (Salmon et al., SC'11): word 0 of the block for counter
+// (ctr0, ctr1, 0, 0) under key (k0, 0).
+__device__ uint64_t philox_word0(uint64_t k0, uint64_t ctr0, uint64_t ctr1) {
+    uint64_t x0 = ctr0, x1 = ctr1, x2 = 0, x3 = 0, ka = k0, kb = 0;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        uint64_t p0hi = __umul64hi(0xD2E7470EE14C6C93ULL, x0), p0lo = 0xD2E7470EE14C6C93ULL * x0;
+        uint64_t p1hi = __umul64hi(0xCA5A826395121157ULL, x2), p1lo = 0xCA5A826395121157ULL * x2;
+        uint64_t n0 = p1hi ^ x1 ^ ka, n2 = p0hi ^ x3 ^ kb;
+        x0 = n0; x1 = p1lo; x2 = n2; x3 = p0lo;
+        ka += 0x9E3779B97F4A7C15ULL;
+        kb += 0xBB67AE8584CAA73BULL;
+    }
+    return x0;
+}
+
+// ---------------------------------------------------------------- formats
+
+template <int MSG> struct Fmt;
+
+template <> struct Fmt<MSG_INT8> {
+    using T = int8_t;
+    using A = int32_t;
+    static __device__ __forceinline__ A load(T x) { return (A)x; }
+    static __device__ __forceinline__ T sat(A x) { return (T)(x > 127 ? 127 : (x < -127 ? -127 : x)); }
+    static __device__ __forceinline__ T pad() { return (T)127; }
+    static __device__ __forceinline__ A mu(const DevCode &C, int v) { return C.mu_q[v]; }
+    static __device__ __forceinline__ bool hard(A l) { return l <= 0; }
+};
+
+template <> struct Fmt<MSG_FP16> {
+    using T = __half;
+    using A = float;
+    static __device__ __forceinline__ A load(T x) { return __half2float(x); }
+    static __device__ __forceinline__ T sat(A x) {
+        __half h = __float2half_rn(x);
+        if (__hisinf(h)) h = __float2half_rn(x > 0.f ? 65504.f : -65504.f);
+        return h;
+    }
+    static __device__ __forceinline__ T pad() { return __ushort_as_half((unsigned short)0x7C00u); }
+    static __device__ __forceinline__ A mu(const DevCode &C, int v) { return C.mu_f16[v]; }
+    static __device__ __forceinline__ bool hard(A l) { return l <= TAU_FLOAT; }
+};
+
+template <> struct Fmt<MSG_FP32> {
+    using T = float;
+    using A = float;
+    static __device__ __forceinline__ A load(T x) { return x; }
+    static __device__ __forceinline__ T sat(A x) {
+        if (__builtin_isinf(x)) return x > 0.f ? 3.402823466e38f : -3.402823466e38f;
+        return x;
+    }
+    static __device__ __forceinline__ T pad() { return __builtin_inff(); }
+    static __device__ __forceinline__ A mu(const DevCode &C, int v) { return C.mu_f32[v]; }
+    static __device__ __forceinline__ bool hard(A l) { return l <= TAU_FLOAT; }
+};
+
+// Check-node scale applied to a magnitude.
+__device__ __forceinline__ int scale_int8(const BpParams &P, int i, int mag) {
+    if (P.scale_mode == 1) return (P.scale_k * mag) >> 3;
+    int sh = i + 1 > 30 ? 30 : i + 1;
+    return mag - (mag >> sh);
+}
+
+__device__ __forceinline__ float scale_float(const BpParams &P, int i, float mag) {
+    if (P.scale_mode == 1) return P.scale_f * mag;
+    // sigma_i = fl32(1 - 2^-(i+1)) is exact for i <= 23 and 1.0 beyond; the fma
+    // rounds mag * sigma_i once.
+    if (i >= 24) return mag;
+    return __builtin_fmaf(-mag, __builtin_ldexpf(1.0f, -(i + 1)), mag);
+}
+
+// Error-free sum of two floats: s + e == a + b exactly (Knuth's TwoSum).
+__device__ __forceinline__ void two_sum(float a, float b, float &s, float &e) {
+    s = a + b;
+    float bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+}
+
+// A column sum carried as an unevaluated pair hi + lo.  Int3.4 and FP16 sums
+// are exact in their accumulator (lo = 0); FP32 sums use TwoSum so that the
+// pair equals the exact sum, hi is that sum rounded once to fp32, and every
+// decision taken on lambda sees the exact value.
+template <typename A> struct Lam {
+    A hi;
+    float lo;
+};
+
+// mu plus the C2V messages b[j] selected by `mask`, in ascending check order.
+template <int MSG>
+__device__ __forceinline__ Lam<typename Fmt<MSG>::A> sum_terms(typename Fmt<MSG>::A mu,
+                                                               const typename Fmt<MSG>::A b[CDEG], uint32_t mask) {
+    using A = typename Fmt<MSG>::A;
+    if constexpr (MSG == MSG_FP32) {
+        float hi = mu, lo = 0.f;
+#pragma unroll
+        for (int j = 0; j < CDEG; ++j)
+            if ((mask >> j) & 1u) {
+                float s, e;
+                two_sum(hi, b[j], s, e);
+                hi = s;
+                lo += e;
+            }
+        if (__builtin_isinf(hi)) return {hi, 0.f};
+        float s, e;
+        two_sum(hi, lo, s, e);
+        return {s, e};
+    } else {
+        A acc = mu;
+#pragma unroll
+        for (int j = 0; j < CDEG; ++j)
+            if ((mask >> j) & 1u) acc += b[j];
+        return {acc, 0.f};
+    }
+}
+
+// Loads the column's C2V messages; returns the slot mask and lambda = mu + sum.
+template <int MSG>
+__device__ __forceinline__ Lam<typename Fmt<MSG>::A> column_lambda(const DevCode &C, int v, uint64_t tab,
+                                                                   const typename Fmt<MSG>::T *E,
+                                                                   typename Fmt<MSG>::A b[CDEG], uint32_t &mask) {
+    using F = Fmt<MSG>;
+    mask = 0;
+#pragma unroll
+    for (int j = 0; j < CDEG; ++j) {
+        uint32_t p = (uint32_t)(tab >> (16 * j)) & 0xFFFFu;
+        b[j] = p != NOPOS ? F::load(E[p]) : (typename F::A)0;
+        if (p != NOPOS) mask |= 1u << j;
+    }
+    return sum_terms<MSG>(F::mu(C, v), b, mask);
+}
+
+// Hard decision e = [lambda <= threshold] on the exact value hi + lo.
+template <int MSG>
+__device__ __forceinline__ bool hard_decision(const Lam<typename Fmt<MSG>::A> &l) {
+    if constexpr (MSG == MSG_INT8) return l.hi <= 0;
+    else return l.hi < TAU_FLOAT || (l.hi == TAU_FLOAT && l.lo <= 0.f);
+}
+
+// Q(|lambda|): |lambda| for Int3.4, floor(|lambda| * 2^12) for float (exact,
+// saturating at 2^62).
+template <int MSG>
+__device__ __forceinline__ uint64_t quantized_abs(const Lam<typename Fmt<MSG>::A> &l) {
+    if constexpr (MSG == MSG_INT8) {
+        return (uint64_t)(l.hi < 0 ? -l.hi : l.hi);
+    } else {
+        float hi = l.hi, lo = l.lo;
+        if (hi < 0.f || (hi == 0.f && lo < 0.f)) { hi = -hi; lo = -lo; }
+        float H = hi * 4096.0f, L = lo * 4096.0f;  // exact scalings
+        if (!(H < 4.6116860e18f)) return (uint64_t)1 << 62;
+        float fh = __builtin_floorf(H);
+        if (fh == H) {
+            // H integral: floor(H + L) = H + floor(L)
+            float fl = __builtin_floorf(L);
+            return (uint64_t)((int64_t)H + (int64_t)fl);
+        }
+        return (uint64_t)fh;  // H not integral: H + L cannot cross an integer
+    }
+}
+
+// ------------------------------------------------------------ check-node half
+
+template <int MSG>
+__device__ void cn_half(const DevCode &C, const BpParams &P, int i, typename Fmt<MSG>::T *E,
+                        const uint32_t *S, int lane) {
+    using F = Fmt<MSG>;
+    using T = typename F::T;
+    for (int c = lane; c < C.m; c += 64) {
+        T a[DEG];
+        T *row = E + c * DEG;
+#pragma unroll
+        for (int k = 0; k < DEG; ++k) a[k] = row[k];
+        const int deg = C.cn_deg[c];
+        int par = (S[c >> 5] >> (c & 31)) & 1;  // (-1)^{s_c}
+        T out[DEG];
+        if constexpr (MSG == MSG_INT8) {
+            int m1 = 1 << 20, m2 = 1 << 20, arg = 0;
+#pragma unroll
+            for (int k = 0; k < DEG; ++k) {
+                int x = a[k];
+                int mag = x < 0 ? -x : x;
+                if (mag < m1) { m2 = m1; m1 = mag; arg = k; }
+                else if (mag < m2) m2 = mag;
+                par ^= (x < 0);
+            }
+            const int s1 = scale_int8(P, i, m1), s2 = scale_int8(P, i, m2);
+#pragma unroll
+            for (int k = 0; k < DEG; ++k) {
+                int mag = k == arg ? s2 : s1;
+                int neg = par ^ ((int)a[k] < 0);
+                out[k] = k < deg ? (T)(neg ? -mag : mag) : F::pad();
+            }
+        } else {
+            float m1 = __builtin_inff(), m2 = __builtin_inff();
+            int arg = 0;
+            float x[DEG];
+#pragma unroll
+            for (int k = 0; k < DEG; ++k) {
+                x[k] = F::load(a[k]);
+                float mag = __builtin_fabsf(x[k]);
+                if (mag < m1) { m2 = m1; m1 = mag; arg = k; }
+                else if (mag < m2) m2 = mag;
+                par ^= (x[k] < 0.f);
+            }
+            if (deg == 1) m2 = CAP_FLOAT;
+            const float s1 = scale_float(P, i, m1), s2 = scale_float(P, i, m2);
+#pragma unroll
+            for (int k = 0; k < DEG; ++k) {
+                float mag = k == arg ? s2 : s1;
+                int neg = par ^ (x[k] < 0.f);
+                out[k] = k < deg ? F::sat(neg ? -mag : mag) : F::pad();
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < DEG; ++k) row[k] = out[k];
+    }
+}
+
+// ------------------------------------------------------------ lottery selection
+
+// Algorithm 3 with U taken from the previous iteration's syndrome estimate
+// SHp; lambda^(i) of the candidates is rebuilt from the C2V messages of
+// iteration i still held in E, with the same arithmetic as the VN half.
+template <int MSG>
+__device__ int lottery_select(const DevCode &C, const BpParams &P, uint64_t shot_id, int i,
+                              const typename Fmt<MSG>::T *E, const uint32_t *S, const uint32_t *SHp, int lane) {
+    using F = Fmt<MSG>;
+    int N = 0;
+    for (int w0 = 0; w0 < C.mw; w0 += 64) {
+        int w = w0 + lane;
+        uint32_t u = w < C.mw ? (SHp[w] ^ S[w]) : 0u;
+        N += wave_sum(__popc(u));
+    }
+    if (N == 0) return -1;
+    const uint64_t x = philox_word0(P.seed, shot_id, (uint64_t)i);
+    uint32_t k = (uint32_t)(((x >> 32) * (uint64_t)N) >> 32);  // floor(r * N)
+    int cstar = -1;
+    for (int w0 = 0; w0 < C.mw; w0 += 64) {
+        int w = w0 + lane;
+        uint32_t u = w < C.mw ? (SHp[w] ^ S[w]) : 0u;
+        int cnt = __popc(u);
+        int incl = wave_incl_scan(cnt, lane);
+        int tot = __shfl(incl, 63, 64);
+        if ((int)k < tot) {
+            int excl = incl - cnt;
+            bool here = (int)k >= excl && (int)k < incl;
+            int pos = 0;
+            if (here) {
+                uint32_t t = u;
+                for (int q = (int)k - excl; q > 0; --q) t &= t - 1;
+                pos = w * 32 + __ffs(t) - 1;
+            }
+            uint64_t b = __ballot(here);
+            cstar = __shfl(pos, __ffsll((unsigned long long)b) - 1, 64);
+            break;
+        }
+        k -= (uint32_t)tot;
+    }
+    // candidates v in V(c*): (most unsatisfied checks, smallest Q(|lambda|), smallest v)
+    int cnt = -1, v = 0x7FFFFFFF;
+    uint64_t q = 0;
+    if (lane < DEG) {
+        uint32_t vv = C.cn_cols[cstar * DEG + lane];
+        if (vv != NOPOS) {
+            v = (int)vv;
+            uint64_t tab = C.vn_tab[v];
+            typename F::A b[CDEG];
+            uint32_t mask;
+            Lam<typename F::A> lam = column_lambda<MSG>(C, v, tab, E, b, mask);
+            cnt = 0;
+#pragma unroll
+            for (int j = 0; j < CDEG; ++j) {
+                uint32_t p = (uint32_t)(tab >> (16 * j)) & 0xFFFFu;
+                if (p != NOPOS) {
+                    uint32_t c = p / DEG;
+                    cnt += ((SHp[c >> 5] ^ S[c >> 5]) >> (c & 31)) & 1u;
+                }
+            }
+            q = quantized_abs<MSG>(lam);
+        }
+    }
+    int bc = -1, bv = -1;
+    uint64_t bq = 0;
+#pragma unroll
+    for (int k = 0; k < DEG; ++k) {
+        int ck = __shfl(cnt, k, 64), vk = __shfl(v, k, 64);
+        uint64_t qk = __shfl(q, k, 64);
+        if (ck < 0) continue;
+        if (bv < 0 || ck > bc || (ck == bc && (qk < bq || (qk == bq && vk < bv)))) {
+            bc = ck;
+            bq = qk;
+            bv = vk;
+        }
+    }
+    return bv;
+}
+
+// ------------------------------------------------------------ variable-node half
+
+template <int MSG>
+__device__ void vn_half(const DevCode &C, const BpParams &P, int fv, bool last, typename Fmt<MSG>::T *E,
+                        uint32_t *SH, uint32_t *EH, int lane, float *llr_row, float *stage) {
+    using F = Fmt<MSG>;
+    using A = typename F::A;
+    const int nvs = (C.n + 63) >> 6;
+    for (int vs = 0; vs < nvs; ++vs) {
+        const int v = vs * 64 + lane;
+        const bool valid = v < C.n;
+        const uint64_t tab = valid ? C.vn_tab[v] : ~0ull;
+        A b[CDEG];
+        uint32_t mask = 0;
+        Lam<A> lam{(A)1, 0.f};
+        if (valid) lam = column_lambda<MSG>(C, v, tab, E, b, mask);
+        const bool e = valid && hard_decision<MSG>(lam);
+        const uint64_t bal = __ballot(e);
+        if (lane == 0) {
+            EH[2 * vs] = (uint32_t)bal;
+            EH[2 * vs + 1] = (uint32_t)(bal >> 32);
+        }
+        if (e) {
+#pragma unroll
+            for (int j = 0; j < CDEG; ++j) {
+                uint32_t p = (uint32_t)(tab >> (16 * j)) & 0xFFFFu;
+                if (p != NOPOS) {
+                    uint32_t c = p / DEG;
+                    atomicXor(&SH[c >> 5], 1u << (c & 31));
+                }
+            }
+        }
+        if (!valid) continue;
+        if (llr_row) llr_row[v] = (float)lam.hi;
+        if (last) {
+            stage[v] = (float)lam.hi;
+            stage[C.n + v] = lam.lo;
+            continue;
+        }
+        const bool flipv = v == fv;
+        if constexpr (MSG == MSG_INT8) {
+            const int l2 = (P.flip == FLIP_LLR && flipv) ? -lam.hi : lam.hi;
+#pragma unroll
+            for (int j = 0; j < CDEG; ++j) {
+                uint32_t p = (uint32_t)(tab >> (16 * j)) & 0xFFFFu;
+                if (p != NOPOS) {
+                    int a = l2 - b[j];  // == mu + sum of the other C2V messages
+                    a = a > 127 ? 127 : (a < -127 ? -127 : a);
+                    if (P.flip == FLIP_MSG && flipv) a = -a;
+                    E[p] = (int8_t)a;
+                }
+            }
+        } else if (P.flip == FLIP_MSG) {
+            const A mu = F::mu(C, v);
+#pragma unroll
+            for (int j = 0; j < CDEG; ++j) {
+                uint32_t p = (uint32_t)(tab >> (16 * j)) & 0xFFFFu;
+                if (p != NOPOS) {
+                    // extrinsic sum in ascending check order, rounded once to the format
+                    A a = sum_terms<MSG>(mu, b, mask & ~(1u << j)).hi;
+                    E[p] = F::sat(flipv ? -a : a);
+                }
+            }
+        } else {
+            const float sg = flipv ? -1.f : 1.f;
+#pragma unroll
+            for (int j = 0; j < CDEG; ++j) {
+                uint32_t p = (uint32_t)(tab >> (16 * j)) & 0xFFFFu;
+                if (p != NOPOS) {
+                    // (+-lambda) - beta_j from the exact pair, rounded once
+                    float s1, e1, s2, e2;
+                    two_sum(sg * (float)lam.hi, -(float)b[j], s1, e1);
+                    two_sum(s1, e1 + sg * lam.lo, s2, e2);
+                    E[p] = F::sat(__builtin_isinf(s1) ? s1 : s2);
+                }
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ kernel
+
+template <int MSG>
+__global__ __launch_bounds__(1024) void bp_kernel(BpArgs a) {
+    using F = Fmt<MSG>;
+    using T = typename F::T;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const DevCode &C = a.code;
+    const BpParams &P = a.prm;
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    unsigned char *base = smem + (size_t)wv * a.wave_bytes;
+    T *E = (T *)base;
+    size_t off = ((size_t)C.m * DEG * sizeof(T) + 15) & ~(size_t)15;
+    uint32_t *S = (uint32_t *)(base + off);
+    uint32_t *SH0 = S + C.mw;
+    uint32_t *SH1 = SH0 + C.mw;
+    uint32_t *EH = SH1 + C.mw;
+    const int gwave = blockIdx.x * (blockDim.x >> 6) + wv;
+    float *stage = a.stage + (size_t)gwave * 2 * C.n;
+
+    for (;;) {
+        uint32_t item = 0;
+        if (lane == 0) item = atomicAdd(&a.counters[0], 1u);
+        item = __shfl(item, 0, 64);
+        if ((int64_t)item >= a.n_work) break;
+        const int64_t shot = a.work_list ? (int64_t)a.work_list[item] : (int64_t)item;
+        const uint64_t shot_id = a.first_shot_id + (uint64_t)shot;
+        float *llr_row = a.llr_out ? a.llr_out + shot * C.n : nullptr;
+
+        // padding bits of the last word are ignored (they could otherwise name checks >= m)
+        const uint32_t last_mask = (C.m & 31) ? ((1u << (C.m & 31)) - 1u) : ~0u;
+        for (int w = lane; w < C.mw; w += 64) {
+            uint32_t x = a.synd[shot * C.mw + w];
+            S[w] = w == C.mw - 1 ? (x & last_mask) : x;
+        }
+        // Algorithm 1, line 4: alpha^(0) = mu; padding slots get the sentinel.
+        for (int c = lane; c < C.m; c += 64) {
+            const int deg = C.cn_deg[c];
+#pragma unroll
+            for (int k = 0; k < DEG; ++k)
+                if (k >= deg) E[c * DEG + k] = F::pad();
+        }
+        for (int v = lane; v < C.n; v += 64) {
+            const uint64_t tab = C.vn_tab[v];
+            const T mu = F::sat(F::mu(C, v));
+#pragma unroll
+            for (int j = 0; j < CDEG; ++j) {
+                uint32_t p = (uint32_t)(tab >> (16 * j)) & 0xFFFFu;
+                if (p != NOPOS) E[p] = mu;
+            }
+        }
+        wave_sync();
+
+        int it = 0;
+        bool converged = false;
+        for (int i = 0; i < P.max_iter; ++i) {
+            uint32_t *SHc = (i & 1) ? SH1 : SH0;
+            uint32_t *SHp = (i & 1) ? SH0 : SH1;
+            cn_half<MSG>(C, P, i, E, S, lane);
+            wave_sync();
+            int fv = -1;
+            if (P.lottery && i >= P.skip && i <= P.max_iter - 2) fv = lottery_select<MSG>(C, P, shot_id, i, E, S, SHp, lane);
+            for (int w = lane; w < C.mw; w += 64) SHc[w] = 0u;
+            wave_sync();
+            const bool last = i == P.max_iter - 1;
+            vn_half<MSG>(C, P, fv, last, E, SHc, EH, lane, llr_row, stage);
+            wave_sync();
+            bool mism = false;
+            for (int w = lane; w < C.mw; w += 64) mism |= SHc[w] != S[w];
+            it = i + 1;
+            if (__ballot(mism) == 0ull) {
+                converged = true;
+                break;
+            }
+        }
+
+        for (int w = lane; w < C.nw; w += 64) a.corr[shot * C.nw + w] = EH[w];
+        const uint8_t fl = converged ? (uint8_t)FLAG_CONVERGED : (uint8_t)(P.osd != OSD_NONE ? FLAG_OSD : 0);
+        if (lane == 0) {
+            a.flags[shot] = fl;
+            if (a.iters) a.iters[shot] = it;
+        }
+        if (!converged && P.osd != OSD_NONE) {
+            uint32_t q = 0;
+            if (lane == 0) q = atomicAdd(&a.counters[1], 1u);
+            q = __shfl(q, 0, 64);
+            if (lane == 0) a.fail_list[q] = (int32_t)shot;
+            if ((int64_t)q < a.fail_cap) {
+                float *dst = a.fail_llr + (size_t)q * 2 * C.n;
+                for (int v = lane; v < 2 * C.n; v += 64) dst[v] = stage[v];
+            }
+        }
+        wave_sync();
+    }
+}
+
+__global__ void reset_kernel(uint32_t *c, int count) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) c[i] = 0u;
+}
+
+__global__ void gather_list_kernel(const uint32_t *counters, const int32_t *fail_list, int64_t from, int32_t *out,
+                                   int64_t count) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) out[i] = fail_list[from + i];
+    (void)counters;
+}
+
+}  // namespace
+
+int bp_wave_bytes(int msg, int m, int n) {
+    size_t esz = msg == MSG_INT8 ? 1 : (msg == MSG_FP16 ? 2 : 4);
+    size_t off = ((size_t)m * DEG * esz + 15) & ~(size_t)15;
+    size_t mw = (size_t)(m + 31) / 32;
+    size_t eh = 2 * (size_t)((n + 63) / 64);
+    size_t tot = off + 4 * (3 * mw + eh);
+    return (int)((tot + 15) & ~(size_t)15);
+}
+
+hipError_t launch_reset(uint32_t *counters, int count, hipStream_t s) {
+    hipLaunchKernelGGL(reset_kernel, dim3((count + 255) / 256), dim3(256), 0, s, counters, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_list(const uint32_t *counters, const int32_t *fail_list, int64_t from, int32_t *out,
+                              int64_t count, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(gather_list_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, counters,
+                       fail_list, from, out, count);
+    return hipGetLastError();
+}
+
+template <int MSG>
+static hipError_t launch_t(const BpArgs &a, int blocks, int wpb, hipStream_t s) {
+    size_t lds = (size_t)a.wave_bytes * wpb;
+    hipError_t e = hipFuncSetAttribute((const void *)bp_kernel<MSG>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(bp_kernel<MSG>, dim3(blocks), dim3(64 * wpb), lds, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_bp(int msg, const BpArgs &a, int blocks, int wpb, hipStream_t s) {
+    switch (msg) {
+    case MSG_INT8: return launch_t<MSG_INT8>(a, blocks, wpb, s);
+    case MSG_FP16: return launch_t<MSG_FP16>(a, blocks, wpb, s);
+    default: return launch_t<MSG_FP32>(a, blocks, wpb, s);
+    }
+}
+
+template <int MSG>
+static hipError_t occ_t(int wpb, int lds, int *out) {
+    hipError_t e = hipFuncSetAttribute((const void *)bp_kernel<MSG>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e != hipSuccess) return e;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(out, bp_kernel<MSG>, 64 * wpb, (size_t)lds);
+}
+
+hipError_t bp_max_blocks_per_cu(int msg, int wpb, int lds, int *out) {
+    switch (msg) {
+    case MSG_INT8: return occ_t<MSG_INT8>(wpb, lds, out);
+    case MSG_FP16: return occ_t<MSG_FP16>(wpb, lds, out);
+    default: return occ_t<MSG_FP32>(wpb, lds, out);
+    }
+}
+
+}  // namespace lbp

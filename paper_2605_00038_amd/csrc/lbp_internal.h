@@ -1,0 +1,92 @@
+// Internal interface between the host runtime and the HIP kernels of the
+// Lottery BP (+OSD) decoder.  gfx950 (CDNA4), wave64.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbp {
+
+// Padded row width of the per-shot edge array: check c owns slots c*DEG .. c*DEG+DEG-1.
+constexpr int DEG = 8;
+// Column table: up to CDEG edge slots per column packed as u16 into one u64.
+constexpr int CDEG = 4;
+constexpr uint32_t NOPOS = 0xFFFFu;
+// Magnitude sent by a degree-1 check (empty minimum) in float modes.
+constexpr float CAP_FLOAT = 1024.0f;
+// Hard-decision threshold in float modes: e = [lambda <= TAU].
+constexpr float TAU_FLOAT = 1.0f / 4096.0f;
+
+enum { MSG_FP32 = 0, MSG_FP16 = 1, MSG_INT8 = 2 };
+enum { FLIP_MSG = 0, FLIP_LLR = 1 };
+enum { OSD_NONE = 0, OSD_0 = 1, OSD_CS = 2 };
+enum { FLAG_CONVERGED = 1, FLAG_OSD = 2, FLAG_OSD_INCONSISTENT = 4 };
+
+struct DevCode {
+    int32_t m, n, mw, nw;     // mw = ceil(m/32), nw = ceil(n/32)
+    const uint16_t *cn_cols;  // [m*DEG]   column of each slot, NOPOS for padding
+    const uint8_t *cn_deg;    // [m]       row weight
+    const uint64_t *vn_tab;   // [n]       CDEG x u16 slot positions, ascending check, NOPOS-filled
+    const float *mu_f32;      // [n]       prior LLR rounded to fp32
+    const float *mu_f16;      // [n]       prior LLR rounded to fp16 (held as float)
+    const int32_t *mu_q;      // [n]       Int3.4 prior
+};
+
+struct BpParams {
+    int32_t max_iter;
+    int32_t scale_mode;  // 0 paper schedule, 1 constant
+    float scale_f;       // constant (float modes)
+    int32_t scale_k;     // constant k of k/8 (Int3.4)
+    int32_t lottery, skip, flip, osd;
+    uint64_t seed;
+};
+
+struct BpArgs {
+    DevCode code;
+    BpParams prm;
+    int64_t n_work;             // work items in this launch
+    uint64_t first_shot_id;
+    const int32_t *work_list;   // nullable: work item -> shot index
+    const uint32_t *synd;       // [shots][mw]
+    uint32_t *corr;             // [shots][nw]
+    uint8_t *flags;             // [shots]
+    int32_t *iters;             // [shots] or null
+    float *llr_out;             // [shots][n] or null
+    uint32_t *counters;         // [0] next work item, [1] failed shots
+    int32_t *fail_list;         // [n_work]
+    float *fail_llr;            // [fail_cap][2n]: lambda as hi[n], lo[n] (value = hi + lo)
+    int64_t fail_cap;
+    float *stage;               // [grid waves][2n]
+    int32_t wave_bytes;         // LDS bytes per wave
+};
+
+struct OsdArgs {
+    int32_t m, n, mw, nw, mws;  // mws: G row stride in words (odd)
+    const uint64_t *vn_tab;
+    int32_t mode, order;
+    const uint32_t *synd;
+    uint32_t *corr;
+    uint8_t *flags;
+    const uint32_t *counters;   // [1] failed shots
+    const int32_t *fail_list;
+    const float *fail_llr;      // [fail_cap][2n]
+    int64_t fail_cap;
+    uint32_t *gscratch;         // per-block G when it does not fit in LDS (else null)
+    int32_t sort_p;             // power of two >= n
+    int32_t g_in_lds;
+    int32_t has_lo;             // lambda carries a non-zero low part (fp32 messages)
+};
+
+// LDS bytes the BP kernel needs per wave for a code.
+int bp_wave_bytes(int msg, int m, int n);
+// LDS bytes per block of the OSD kernel (and whether G fits in LDS).
+int osd_block_bytes(int m, int n, int lds_limit, int *g_in_lds, int *mws, int *sort_p);
+
+hipError_t launch_reset(uint32_t *counters, int count, hipStream_t s);
+hipError_t launch_bp(int msg, const BpArgs &a, int blocks, int waves_per_block, hipStream_t s);
+hipError_t bp_max_blocks_per_cu(int msg, int waves_per_block, int lds_bytes, int *out);
+hipError_t launch_osd(const OsdArgs &a, int blocks, int lds_bytes, hipStream_t s);
+hipError_t launch_gather_list(const uint32_t *counters, const int32_t *fail_list, int64_t from, int32_t *out,
+                              int64_t count, hipStream_t s);
+
+}  // namespace lbp

@@ -1,0 +1,373 @@
+// OSD-0 (Algorithm 2) and OSD-CS for the shots whose BP run did not converge.
+//
+// One 1024-thread workgroup per failed shot (persistent over the failure list).
+//  1. LLR sorting: bitonic sort of (orderable(lambda) << 32 | column) keys in
+//     LDS, i.e. ascending lambda with ties broken by column (stable order).
+//  2. Basis selection + LU/forward substitution as one Gauss-Jordan sweep in
+//     sorted column order.  The permuted matrix is never materialised: the
+//     workgroup keeps only G, the accumulated row operations (m x m bits,
+//     identity at the start) and s' = G s.  The reduced form of any column j
+//     of H is G h_j, and h_j has at most CDEG non-zeros, so testing column j
+//     costs <= CDEG bit reads per row.  A column whose reduced form has a 1 in
+//     a row that is not yet a pivot becomes a basis column: the lowest such row
+//     is its pivot and the pivot row of G is XORed into every other row with a
+//     1 there (packed 32-bit words).  The first rank(H) independent columns in
+//     sorted order form the basis S (unique), so the result is independent of
+//     the pivot-row choice.
+//  3. Backward substitution is implicit (Gauss-Jordan): e_S[pivot row r] = s'_r.
+//     A row never chosen as pivot must have s'_r = 0, else s is not in the
+//     column space of H (flag, keep the BP hard decision).
+//  4. OSD-CS: candidate t (no column, one non-basis column, or two of the
+//     first `order` non-basis columns in sorted order) costs
+//     |s' + G H_T t| + |t|; the first candidate of minimum cost wins.
+//  5. Error vector construction / inverse mapping: bits are scattered to the
+//     original column indices.
+// G lives in LDS (row-major, odd word stride: conflict-free column access)
+// when it fits, otherwise in a per-workgroup global buffer (word-major, so
+// that a column word of all rows is one coalesced access).
+#include "lbp_internal.h"
+
+namespace lbp {
+namespace {
+
+constexpr int OSD_THREADS = 1024;
+constexpr int OSD_WAVES = OSD_THREADS / 64;
+constexpr int MAX_ROWS_PER_THREAD = 8;  // m <= 8191
+
+__device__ __forceinline__ uint32_t orderable(float f) {
+    uint32_t u = __float_as_uint(f);
+    if (u == 0x80000000u) u = 0u;  // -0 sorts with +0
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        uint32_t y = __shfl_xor(x, o, 64);
+        x = y < x ? y : x;
+    }
+    return x;
+}
+
+__device__ __forceinline__ uint64_t wave_min_u64(uint64_t x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        uint64_t y = __shfl_xor(x, o, 64);
+        x = y < x ? y : x;
+    }
+    return x;
+}
+
+__device__ __forceinline__ int wave_incl_scan(int x, int lane) {
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        int y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    return x;
+}
+
+__device__ __forceinline__ int wave_sum(int x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    return x;
+}
+
+struct GView {
+    uint32_t *g;
+    int m, mws, in_lds;
+    __device__ __forceinline__ uint32_t &at(int r, int w) const {
+        return in_lds ? g[(size_t)r * mws + w] : g[(size_t)w * m + r];
+    }
+};
+
+// Bit of row r of the reduced column with check rows rows[0..nr).
+__device__ __forceinline__ uint32_t xbit(const GView &G, int r, const int *rows, int nr) {
+    uint32_t x = 0;
+    for (int k = 0; k < nr; ++k) x ^= (G.at(r, rows[k] >> 5) >> (rows[k] & 31)) & 1u;
+    return x;
+}
+
+__device__ __forceinline__ int col_rows(const uint64_t *vn_tab, int col, int *rows) {
+    uint64_t tab = vn_tab[col];
+    int nr = 0;
+#pragma unroll
+    for (int j = 0; j < CDEG; ++j) {
+        uint32_t p = (uint32_t)(tab >> (16 * j)) & 0xFFFFu;
+        if (p != NOPOS) rows[nr++] = (int)(p / DEG);
+    }
+    return nr;
+}
+
+// Exclusive block scan of one int per thread; *total receives the sum.
+__device__ int block_excl_scan(int x, int *scr, int *total) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    int incl = wave_incl_scan(x, lane);
+    if (lane == 63) scr[wid] = incl;
+    __syncthreads();
+    if (wid == 0) {
+        int v = lane < OSD_WAVES ? scr[lane] : 0;
+        int vi = wave_incl_scan(v, lane);
+        if (lane < OSD_WAVES) scr[lane] = vi - v;
+        if (lane == OSD_WAVES - 1) scr[OSD_WAVES] = vi;
+    }
+    __syncthreads();
+    int r = scr[wid] + incl - x;
+    *total = scr[OSD_WAVES];
+    __syncthreads();
+    return r;
+}
+
+__global__ __launch_bounds__(OSD_THREADS) void osd_kernel(OsdArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int m = a.m, n = a.n, tid = threadIdx.x, lane = tid & 63;
+    const int P = a.sort_p;
+    size_t gbytes = a.g_in_lds ? (size_t)m * a.mws * 4 : 0;
+    size_t rbytes = gbytes > (size_t)P * 8 ? gbytes : (size_t)P * 8;
+    rbytes = (rbytes + 15) & ~(size_t)15;
+    unsigned char *q0 = smem + rbytes;
+    float *lo_s = (float *)q0;                       q0 += ((size_t)n * 4 + 15) & ~(size_t)15;
+    uint16_t *perm = (uint16_t *)q0;                 q0 += ((size_t)n * 2 + 15) & ~(size_t)15;
+    uint16_t *tl = (uint16_t *)q0;                   q0 += ((size_t)n * 2 + 15) & ~(size_t)15;
+    uint8_t *isb = q0;                               q0 += ((size_t)n + 15) & ~(size_t)15;
+    uint16_t *pcol = (uint16_t *)q0;                 q0 += ((size_t)m * 2 + 15) & ~(size_t)15;
+    uint8_t *piv = q0;                               q0 += ((size_t)m + 15) & ~(size_t)15;
+    uint8_t *sp = q0;                                q0 += ((size_t)m + 15) & ~(size_t)15;
+    uint32_t *cw = (uint32_t *)q0;                   q0 += ((size_t)a.nw * 4 + 15) & ~(size_t)15;
+    uint32_t *red = (uint32_t *)q0;                  q0 += 16 * 4;
+    int *scr = (int *)q0;                            q0 += 32 * 4;
+    unsigned long long *best64 = (unsigned long long *)q0;
+
+    GView G;
+    G.g = a.g_in_lds ? (uint32_t *)smem : a.gscratch + (size_t)blockIdx.x * m * a.mws;
+    G.m = m;
+    G.mws = a.mws;
+    G.in_lds = a.g_in_lds;
+
+    uint32_t nfail = a.counters[1];
+    if ((int64_t)nfail > a.fail_cap) nfail = (uint32_t)a.fail_cap;
+
+    for (uint32_t q = blockIdx.x; q < nfail; q += gridDim.x) {
+        const int64_t shot = a.fail_list[q];
+        const float *lam = a.fail_llr + (size_t)q * 2 * n;  // hi[n] then lo[n]: lambda = hi + lo
+
+        // ---- 1. sort (lambda, column) ascending: bitonic on (hi, column), then
+        // runs of equal hi are ordered by lo (stable, so ties stay by column)
+        unsigned long long *keys = (unsigned long long *)smem;
+        for (int j = tid; j < P; j += OSD_THREADS)
+            keys[j] = j < n ? (((unsigned long long)orderable(lam[j]) << 32) | (unsigned)j) : ~0ull;
+        if (a.has_lo)
+            for (int j = tid; j < n; j += OSD_THREADS) lo_s[j] = lam[n + j];
+        __syncthreads();
+        for (int k = 2; k <= P; k <<= 1) {
+            for (int jj = k >> 1; jj > 0; jj >>= 1) {
+                for (int t = tid; t < (P >> 1); t += OSD_THREADS) {
+                    int i = ((t & ~(jj - 1)) << 1) | (t & (jj - 1));
+                    int l = i + jj;
+                    bool asc = (i & k) == 0;
+                    unsigned long long x = keys[i], y = keys[l];
+                    if ((x > y) == asc) { keys[i] = y; keys[l] = x; }
+                }
+                __syncthreads();
+            }
+        }
+        if (a.has_lo) {
+            for (int j = tid; j < n; j += OSD_THREADS) {
+                const uint32_t h = (uint32_t)(keys[j] >> 32);
+                if (j > 0 && (uint32_t)(keys[j - 1] >> 32) == h) continue;  // not the start of a run
+                int e = j + 1;
+                while (e < n && (uint32_t)(keys[e] >> 32) == h) ++e;
+                for (int x = j + 1; x < e; ++x) {  // insertion sort by lo (stable)
+                    unsigned long long kx = keys[x];
+                    uint32_t ox = orderable(lo_s[kx & 0xFFFFu]);
+                    int y = x - 1;
+                    while (y >= j && orderable(lo_s[keys[y] & 0xFFFFu]) > ox) {
+                        keys[y + 1] = keys[y];
+                        --y;
+                    }
+                    keys[y + 1] = kx;
+                }
+            }
+            __syncthreads();
+        }
+        for (int j = tid; j < n; j += OSD_THREADS) perm[j] = (uint16_t)(keys[j] & 0xFFFFu);
+        __syncthreads();
+
+        // ---- 2. G = I, s' = s
+        const int mw = a.mw;
+        for (size_t idx = tid; idx < (size_t)m * mw; idx += OSD_THREADS) {
+            int r = (int)(idx / mw), w = (int)(idx % mw);
+            G.at(r, w) = (w == (r >> 5)) ? (1u << (r & 31)) : 0u;
+        }
+        const uint32_t *sw = a.synd + shot * a.mw;
+        for (int r = tid; r < m; r += OSD_THREADS) {
+            sp[r] = (uint8_t)((sw[r >> 5] >> (r & 31)) & 1u);
+            piv[r] = 0;
+        }
+        for (int j = tid; j < n; j += OSD_THREADS) isb[j] = 0;
+        if (tid < 3) red[tid] = 0xFFFFFFFFu;
+        __syncthreads();
+
+        // ---- 3. Gauss-Jordan in sorted column order
+        int rank = 0, step = 0;
+        for (int j = 0; j < n && rank < m; ++j) {
+            const int col = perm[j];
+            int rows[CDEG];
+            const int nr = col_rows(a.vn_tab, col, rows);
+            const int slot = step % 3;
+            if (tid == 0) red[(step + 1) % 3] = 0xFFFFFFFFu;
+            uint32_t xm = 0, cand = 0xFFFFFFFFu;
+            int k = 0;
+            for (int r = tid; r < m; r += OSD_THREADS, ++k) {
+                uint32_t x = xbit(G, r, rows, nr);
+                xm |= x << k;
+                if (x && !piv[r] && (uint32_t)r < cand) cand = (uint32_t)r;
+            }
+            cand = wave_min_u32(cand);
+            if (lane == 0 && cand != 0xFFFFFFFFu) atomicMin(&red[slot], cand);
+            __syncthreads();
+            const uint32_t pv = red[slot];
+            ++step;
+            if (pv == 0xFFFFFFFFu) continue;
+            k = 0;
+            const uint8_t spv = sp[pv];
+            for (int r = tid; r < m; r += OSD_THREADS, ++k) {
+                if ((uint32_t)r == pv) {
+                    piv[r] = 1;
+                    pcol[r] = (uint16_t)col;
+                } else if ((xm >> k) & 1u) {
+                    for (int w = 0; w < mw; ++w) G.at(r, w) ^= G.at((int)pv, w);
+                    sp[r] ^= spv;
+                }
+            }
+            if (tid == 0) isb[j] = 1;
+            ++rank;
+            __syncthreads();
+        }
+
+        // ---- consistency: a row with no pivot reduced to 0 = s'_r
+        int bad = 0;
+        for (int r = tid; r < m; r += OSD_THREADS) bad |= (!piv[r] && sp[r]);
+        bad = __syncthreads_or(bad);
+        if (bad) {
+            if (tid == 0) a.flags[shot] = (uint8_t)(FLAG_OSD | FLAG_OSD_INCONSISTENT);
+            __syncthreads();
+            continue;
+        }
+
+        // ---- 4. OSD-CS candidate sweep
+        int t0 = -1, t1 = -1;
+        if (a.mode == OSD_CS) {
+            const int chunk = (n + OSD_THREADS - 1) / OSD_THREADS;
+            const int lo = tid * chunk, hi = lo + chunk < n ? lo + chunk : n;
+            int cnt = 0;
+            for (int j = lo; j < hi; ++j) cnt += !isb[j];
+            int nt;
+            int off = block_excl_scan(cnt, scr, &nt);
+            for (int j = lo; j < hi; ++j)
+                if (!isb[j]) tl[off++] = perm[j];
+            int w0 = 0;
+            for (int r = tid; r < m; r += OSD_THREADS) w0 += sp[r];
+            w0 = wave_sum(w0);
+            if (tid == 0) {
+                *best64 = ~0ull;
+                scr[21] = 0;
+            }
+            __syncthreads();
+            if (lane == 0) atomicAdd(&scr[21], w0);
+            __syncthreads();
+            // OSD-0 candidate: cost |s'|, enumeration index 0
+            unsigned long long best = (unsigned long long)scr[21] << 32;
+            for (int ai = tid; ai < nt; ai += OSD_THREADS) {
+                int rows[CDEG];
+                int nr = col_rows(a.vn_tab, tl[ai], rows);
+                unsigned long long cost = 1;
+                for (int r = 0; r < m; ++r) cost += sp[r] ^ xbit(G, r, rows, nr);
+                unsigned long long key = (cost << 32) | (unsigned long long)(1 + ai);
+                best = key < best ? key : best;
+            }
+            const int w = a.order < nt ? a.order : nt;
+            const int npairs = w * (w - 1) / 2;
+            for (int pi = tid; pi < npairs; pi += OSD_THREADS) {
+                int aa = 0, rem = pi;
+                while (rem >= w - 1 - aa) { rem -= w - 1 - aa; ++aa; }
+                int bb = aa + 1 + rem;
+                int ra[CDEG], rb[CDEG];
+                int na = col_rows(a.vn_tab, tl[aa], ra), nb = col_rows(a.vn_tab, tl[bb], rb);
+                unsigned long long cost = 2;
+                for (int r = 0; r < m; ++r) cost += sp[r] ^ xbit(G, r, ra, na) ^ xbit(G, r, rb, nb);
+                unsigned long long key = (cost << 32) | (unsigned long long)(1 + nt + pi);
+                best = key < best ? key : best;
+            }
+            best = wave_min_u64(best);
+            if (lane == 0) atomicMin(best64, best);
+            __syncthreads();
+            const unsigned idx = (unsigned)(*best64 & 0xFFFFFFFFull);
+            if (idx >= 1 && idx <= (unsigned)nt) {
+                t0 = tl[idx - 1];
+            } else if (idx > (unsigned)nt) {
+                int pi = (int)idx - 1 - nt, aa = 0, rem = pi;
+                while (rem >= w - 1 - aa) { rem -= w - 1 - aa; ++aa; }
+                t0 = tl[aa];
+                t1 = tl[aa + 1 + rem];
+            }
+        }
+
+        // ---- 5. e_S = s' + G H_T t on the basis, t on the rest; scatter to columns
+        for (int ww = tid; ww < a.nw; ww += OSD_THREADS) cw[ww] = 0u;
+        __syncthreads();
+        int r0[CDEG], r1[CDEG], n0 = 0, n1 = 0;
+        if (t0 >= 0) n0 = col_rows(a.vn_tab, t0, r0);
+        if (t1 >= 0) n1 = col_rows(a.vn_tab, t1, r1);
+        for (int r = tid; r < m; r += OSD_THREADS) {
+            if (!piv[r]) continue;
+            uint32_t e = sp[r];
+            if (t0 >= 0) e ^= xbit(G, r, r0, n0);
+            if (t1 >= 0) e ^= xbit(G, r, r1, n1);
+            if (e) {
+                int c = pcol[r];
+                atomicOr(&cw[c >> 5], 1u << (c & 31));
+            }
+        }
+        if (tid == 0) {
+            if (t0 >= 0) atomicOr(&cw[t0 >> 5], 1u << (t0 & 31));
+            if (t1 >= 0) atomicOr(&cw[t1 >> 5], 1u << (t1 & 31));
+        }
+        __syncthreads();
+        for (int ww = tid; ww < a.nw; ww += OSD_THREADS) a.corr[shot * a.nw + ww] = cw[ww];
+        __syncthreads();
+    }
+}
+
+}  // namespace
+
+int osd_block_bytes(int m, int n, int lds_limit, int *g_in_lds, int *mws, int *sort_p) {
+    int P = 1;
+    while (P < n) P <<= 1;
+    int mw = (m + 31) / 32;
+    int s = mw | 1;
+    auto al = [](size_t x) { return (x + 15) & ~(size_t)15; };
+    size_t rest = al((size_t)n * 4) + al((size_t)n * 2) * 2 + al((size_t)n) + al((size_t)m * 2) + al((size_t)m) * 2 +
+                  al((size_t)((n + 31) / 32) * 4) + 16 * 4 + 32 * 4 + 16;
+    size_t gb = (size_t)m * s * 4;
+    size_t with_g = al(gb > (size_t)P * 8 ? gb : (size_t)P * 8) + rest;
+    size_t without = al((size_t)P * 8) + rest;
+    *sort_p = P;
+    if ((int64_t)with_g <= lds_limit) {
+        *g_in_lds = 1;
+        *mws = s;
+        return (int)with_g;
+    }
+    *g_in_lds = 0;
+    *mws = mw;
+    return (int)without;
+}
+
+hipError_t launch_osd(const OsdArgs &a, int blocks, int lds, hipStream_t s) {
+    hipError_t e = hipFuncSetAttribute((const void *)osd_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(osd_kernel, dim3(blocks), dim3(OSD_THREADS), (size_t)lds, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace lbp

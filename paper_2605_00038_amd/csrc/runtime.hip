@@ -1,0 +1,441 @@
+// Host runtime of the C ABI in include/lbp.h: validation, device tables,
+// workspace sizing, launch configuration and the OSD overflow loop.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/lbp.h"
+#include "lbp_internal.h"
+
+using namespace lbp;
+
+namespace {
+
+thread_local std::string g_err;
+
+lbp_status fail(lbp_status s, const std::string &msg) {
+    g_err = msg;
+    return s;
+}
+
+#define HIPCHK(call)                                                                          \
+    do {                                                                                      \
+        hipError_t e_ = (call);                                                               \
+        if (e_ != hipSuccess) {                                                               \
+            lbp_status st_ = e_ == hipErrorOutOfMemory ? LBP_ENOMEM : LBP_EDEVICE;            \
+            return fail(st_, std::string(#call) + ": " + hipGetErrorString(e_));              \
+        }                                                                                     \
+    } while (0)
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) == hipSuccess && prev != dev) hipSetDevice(dev);
+        else prev = -1;
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) hipSetDevice(prev);
+    }
+};
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Round a double to the nearest binary16 value (ties to even), saturating at 65504.
+float to_fp16_value(double x) {
+    _Float16 h = (_Float16)x;
+    float f = (float)h;
+    if (std::isinf(f)) f = x > 0 ? 65504.0f : -65504.0f;
+    return f;
+}
+
+}  // namespace
+
+struct lbp_code_s {
+    int m = 0, n = 0, nnz = 0, device = 0;
+    bool uniform = true;
+    void *dmem = nullptr;
+    DevCode dc{};
+};
+
+struct lbp_decoder_s {
+    lbp_code code = nullptr;
+    lbp_params prm{};
+    int64_t max_batch = 0;
+    BpParams bp{};
+    int wpb = 1, bp_blocks = 1, wave_bytes = 0;
+    int osd_blocks = 0, osd_lds = 0, g_in_lds = 1, mws = 1, sort_p = 1;
+    int64_t fail_cap = 0;
+    uint32_t *d_counters = nullptr;
+    int32_t *d_fail_list = nullptr;
+    int32_t *d_list2 = nullptr;
+    float *d_fail_llr = nullptr;
+    float *d_stage = nullptr;
+    uint32_t *d_gscratch = nullptr;
+    uint32_t *h_count = nullptr;  // pinned
+};
+
+extern "C" {
+
+const char *lbp_last_error(void) { return g_err.c_str(); }
+
+int32_t lbp_version(void) { return 100; }
+
+void lbp_params_default(lbp_params *p) {
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->max_iter = 100;
+    p->scale_mode = LBP_SCALE_PAPER;
+    p->scale = 0.625f;
+    p->msg = LBP_MSG_INT8;
+    p->lottery = 1;
+    p->lottery_skip = 6;
+    p->flip = LBP_FLIP_MSG;
+    p->osd = LBP_OSD_0;
+    p->osd_order = 10;
+    p->seed = 0;
+}
+
+lbp_status lbp_code_create(int32_t m, int32_t n, const int32_t *row_ptr, const int32_t *col_idx, const double *p,
+                           lbp_code *out) {
+    g_err.clear();
+    if (!out || !row_ptr || !col_idx || !p) return fail(LBP_EINVAL, "lbp_code_create: NULL argument");
+    *out = nullptr;
+    if (m < 1 || n < 1) return fail(LBP_EINVAL, "lbp_code_create: m and n must be >= 1");
+    if (m > 8191 || n > 65535) return fail(LBP_EUNSUPPORTED, "lbp_code_create: m <= 8191 and n <= 65535 supported");
+    if (row_ptr[0] != 0) return fail(LBP_EINVAL, "lbp_code_create: row_ptr[0] must be 0");
+    for (int c = 0; c < m; ++c) {
+        int w = row_ptr[c + 1] - row_ptr[c];
+        if (w < 1) return fail(LBP_EINVAL, "lbp_code_create: row " + std::to_string(c) + " is empty or row_ptr decreases");
+        if (w > DEG) return fail(LBP_EUNSUPPORTED, "lbp_code_create: row weight > 8 at row " + std::to_string(c));
+        for (int e = row_ptr[c]; e < row_ptr[c + 1]; ++e) {
+            if (col_idx[e] < 0 || col_idx[e] >= n)
+                return fail(LBP_EINVAL, "lbp_code_create: column index out of range in row " + std::to_string(c));
+            if (e > row_ptr[c] && col_idx[e] <= col_idx[e - 1])
+                return fail(LBP_EINVAL, "lbp_code_create: column indices not strictly increasing in row " + std::to_string(c));
+        }
+    }
+    for (int v = 0; v < n; ++v)
+        if (!(p[v] > 0.0 && p[v] < 1.0)) return fail(LBP_EINVAL, "lbp_code_create: prior outside (0,1) at column " + std::to_string(v));
+    const int nnz = row_ptr[m];
+    // column tables: slot positions c*DEG + k in ascending check order
+    std::vector<int> cw(n, 0);
+    std::vector<uint64_t> tab(n, ~0ull);
+    std::vector<uint16_t> cols((size_t)m * DEG, (uint16_t)NOPOS);
+    std::vector<uint8_t> deg(m);
+    for (int c = 0; c < m; ++c) {
+        deg[c] = (uint8_t)(row_ptr[c + 1] - row_ptr[c]);
+        for (int e = row_ptr[c]; e < row_ptr[c + 1]; ++e) {
+            int v = col_idx[e], k = e - row_ptr[c];
+            cols[(size_t)c * DEG + k] = (uint16_t)v;
+            if (cw[v] >= CDEG) return fail(LBP_EUNSUPPORTED, "lbp_code_create: column weight > 4 at column " + std::to_string(v));
+            uint64_t pos = (uint64_t)(c * DEG + k);
+            tab[v] &= ~(0xFFFFull << (16 * cw[v]));
+            tab[v] |= pos << (16 * cw[v]);
+            cw[v]++;
+        }
+    }
+    std::vector<float> mu32(n), mu16(n);
+    std::vector<int32_t> muq(n);
+    bool uniform = true;
+    for (int v = 0; v < n; ++v) {
+        double mu = std::log((1.0 - p[v]) / p[v]);  // Algorithm 1, line 1 (fp64, host)
+        mu32[v] = (float)mu;
+        mu16[v] = to_fp16_value(mu);
+        double q = std::nearbyint(16.0 * mu);
+        muq[v] = (int32_t)(q > 127 ? 127 : (q < -127 ? -127 : q));
+        if (p[v] != p[0]) uniform = false;
+    }
+    lbp_code code = new lbp_code_s();
+    code->m = m;
+    code->n = n;
+    code->nnz = nnz;
+    code->uniform = uniform;
+    hipGetDevice(&code->device);
+    size_t o_cols = 0, o_deg = align256(o_cols + cols.size() * 2), o_tab = align256(o_deg + (size_t)m),
+           o_m32 = align256(o_tab + (size_t)n * 8), o_m16 = align256(o_m32 + (size_t)n * 4),
+           o_mq = align256(o_m16 + (size_t)n * 4), total = align256(o_mq + (size_t)n * 4);
+    hipError_t e = hipMalloc(&code->dmem, total);
+    if (e != hipSuccess) {
+        delete code;
+        return fail(LBP_ENOMEM, std::string("lbp_code_create: hipMalloc: ") + hipGetErrorString(e));
+    }
+    char *b = (char *)code->dmem;
+    std::vector<char> host(total, 0);
+    std::memcpy(host.data() + o_cols, cols.data(), cols.size() * 2);
+    std::memcpy(host.data() + o_deg, deg.data(), (size_t)m);
+    std::memcpy(host.data() + o_tab, tab.data(), (size_t)n * 8);
+    std::memcpy(host.data() + o_m32, mu32.data(), (size_t)n * 4);
+    std::memcpy(host.data() + o_m16, mu16.data(), (size_t)n * 4);
+    std::memcpy(host.data() + o_mq, muq.data(), (size_t)n * 4);
+    e = hipMemcpy(code->dmem, host.data(), total, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        hipFree(code->dmem);
+        delete code;
+        return fail(LBP_EDEVICE, std::string("lbp_code_create: hipMemcpy: ") + hipGetErrorString(e));
+    }
+    DevCode &dc = code->dc;
+    dc.m = m;
+    dc.n = n;
+    dc.mw = (m + 31) / 32;
+    dc.nw = (n + 31) / 32;
+    dc.cn_cols = (const uint16_t *)(b + o_cols);
+    dc.cn_deg = (const uint8_t *)(b + o_deg);
+    dc.vn_tab = (const uint64_t *)(b + o_tab);
+    dc.mu_f32 = (const float *)(b + o_m32);
+    dc.mu_f16 = (const float *)(b + o_m16);
+    dc.mu_q = (const int32_t *)(b + o_mq);
+    *out = code;
+    return LBP_OK;
+}
+
+void lbp_code_destroy(lbp_code code) {
+    if (!code) return;
+    DeviceGuard g(code->device);
+    hipFree(code->dmem);
+    delete code;
+}
+
+int32_t lbp_code_rows(lbp_code code) { return code ? code->m : 0; }
+int32_t lbp_code_cols(lbp_code code) { return code ? code->n : 0; }
+
+static void free_decoder(lbp_decoder d) {
+    hipFree(d->d_counters);
+    hipFree(d->d_fail_list);
+    hipFree(d->d_list2);
+    hipFree(d->d_fail_llr);
+    hipFree(d->d_stage);
+    hipFree(d->d_gscratch);
+    if (d->h_count) hipHostFree(d->h_count);
+}
+
+lbp_status lbp_decoder_create(lbp_code code, const lbp_params *prm, int64_t max_batch, lbp_decoder *out) {
+    g_err.clear();
+    if (!code || !prm || !out) return fail(LBP_EINVAL, "lbp_decoder_create: NULL argument");
+    *out = nullptr;
+    if (max_batch < 1 || max_batch > (int64_t)1 << 31) return fail(LBP_EINVAL, "lbp_decoder_create: 1 <= max_batch <= 2^31");
+    if (prm->max_iter < 1) return fail(LBP_EINVAL, "lbp_decoder_create: max_iter must be >= 1");
+    if (prm->msg < 0 || prm->msg > 2) return fail(LBP_EINVAL, "lbp_decoder_create: unknown message format");
+    if (prm->scale_mode != 0 && prm->scale_mode != 1) return fail(LBP_EINVAL, "lbp_decoder_create: unknown scale mode");
+    if (prm->flip != 0 && prm->flip != 1) return fail(LBP_EINVAL, "lbp_decoder_create: unknown flip mode");
+    if (prm->osd < 0 || prm->osd > 2) return fail(LBP_EINVAL, "lbp_decoder_create: unknown OSD mode");
+    if (prm->lottery_skip < 0) return fail(LBP_EINVAL, "lbp_decoder_create: lottery_skip must be >= 0");
+    if (prm->osd == LBP_OSD_CS && prm->osd_order < 0) return fail(LBP_EINVAL, "lbp_decoder_create: osd_order must be >= 0");
+    if (prm->reserved != 0) return fail(LBP_EINVAL, "lbp_decoder_create: reserved field must be 0");
+    int k = 0;
+    if (prm->scale_mode == 1) {
+        if (!(prm->scale > 0.0f && prm->scale <= 1.0f)) return fail(LBP_EINVAL, "lbp_decoder_create: constant scale must be in (0,1]");
+        if (prm->msg == LBP_MSG_INT8) {
+            double kk = (double)prm->scale * 8.0;
+            k = (int)std::lround(kk);
+            if (std::fabs(kk - k) > 1e-6) return fail(LBP_EINVAL, "lbp_decoder_create: Int3.4 constant scale must be k/8");
+        }
+    }
+    if (prm->osd == LBP_OSD_CS && !code->uniform)
+        return fail(LBP_EUNSUPPORTED, "lbp_decoder_create: OSD-CS needs a uniform prior (Hamming-weight cost)");
+    DeviceGuard g(code->device);
+    lbp_decoder d = new lbp_decoder_s();
+    d->code = code;
+    d->prm = *prm;
+    d->max_batch = max_batch;
+    BpParams &bp = d->bp;
+    bp.max_iter = prm->max_iter;
+    bp.scale_mode = prm->scale_mode;
+    bp.scale_f = prm->scale;
+    bp.scale_k = k;
+    bp.lottery = prm->lottery ? 1 : 0;
+    bp.skip = prm->lottery_skip;
+    bp.flip = prm->flip;
+    bp.osd = prm->osd;
+    bp.seed = prm->seed;
+
+    int dev = code->device, ncu = 0, lds_block = 0;
+    auto cleanup_fail = [&](lbp_status s, const std::string &msg) {
+        free_decoder(d);
+        delete d;
+        return fail(s, msg);
+    };
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipDeviceGetAttribute(&lds_block, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+        return cleanup_fail(LBP_EDEVICE, "lbp_decoder_create: device query failed");
+    // ---- BP launch shape: the waves-per-block choice with the most resident waves per CU
+    d->wave_bytes = bp_wave_bytes(prm->msg, code->m, code->n);
+    if (d->wave_bytes > lds_block) return cleanup_fail(LBP_EUNSUPPORTED, "lbp_decoder_create: per-shot state exceeds LDS");
+    int best_waves = 0;
+    for (int wpb : {16, 8, 4, 2, 1}) {
+        int lds = d->wave_bytes * wpb;
+        if (lds > lds_block) continue;
+        int bpc = 0;
+        if (bp_max_blocks_per_cu(prm->msg, wpb, lds, &bpc) != hipSuccess) continue;
+        if (bpc * wpb > best_waves) {
+            best_waves = bpc * wpb;
+            d->wpb = wpb;
+            d->bp_blocks = bpc * ncu;
+        }
+    }
+    if (best_waves == 0) return cleanup_fail(LBP_EDEVICE, "lbp_decoder_create: no feasible BP launch shape");
+    // ---- OSD workspace
+    d->fail_cap = prm->osd ? std::min<int64_t>(max_batch, std::max<int64_t>(1024, ((int64_t)256 << 20) / ((int64_t)code->n * 8)))
+                           : 0;
+    // the OSD kernel also holds a little static LDS (block-wide reductions)
+    d->osd_lds = osd_block_bytes(code->m, code->n, lds_block - 1024, &d->g_in_lds, &d->mws, &d->sort_p);
+    if (d->osd_lds > lds_block - 1024) return cleanup_fail(LBP_EUNSUPPORTED, "lbp_decoder_create: OSD sort does not fit LDS");
+    d->osd_blocks = ncu;
+    hipError_t e;
+#define ALLOC(ptr, bytes)                                                                                     \
+    do {                                                                                                      \
+        e = hipMalloc((void **)&(ptr), (bytes) > 0 ? (bytes) : 16);                                            \
+        if (e != hipSuccess) return cleanup_fail(LBP_ENOMEM, std::string("lbp_decoder_create: hipMalloc: ") + \
+                                                                 hipGetErrorString(e));                        \
+    } while (0)
+    ALLOC(d->d_counters, 64);
+    ALLOC(d->d_stage, (size_t)d->bp_blocks * d->wpb * code->n * 8);
+    if (prm->osd) {
+        ALLOC(d->d_fail_list, (size_t)max_batch * 4);
+        ALLOC(d->d_list2, (size_t)max_batch * 4);
+        ALLOC(d->d_fail_llr, (size_t)d->fail_cap * code->n * 8);
+        if (!d->g_in_lds) ALLOC(d->d_gscratch, (size_t)d->osd_blocks * code->m * d->mws * 4);
+    }
+#undef ALLOC
+    e = hipHostMalloc((void **)&d->h_count, 64, hipHostMallocDefault);
+    if (e != hipSuccess) return cleanup_fail(LBP_ENOMEM, "lbp_decoder_create: hipHostMalloc failed");
+    *out = d;
+    return LBP_OK;
+}
+
+void lbp_decoder_destroy(lbp_decoder d) {
+    if (!d) return;
+    DeviceGuard g(d->code->device);
+    free_decoder(d);
+    delete d;
+}
+
+int64_t lbp_decoder_osd_capacity(lbp_decoder d) { return d ? d->fail_cap : 0; }
+
+lbp_status lbp_decoder_set_osd_capacity(lbp_decoder d, int64_t cap) {
+    if (!d) return fail(LBP_EINVAL, "lbp_decoder_set_osd_capacity: NULL decoder");
+    if (cap < 1 || cap > d->fail_cap) return fail(LBP_EINVAL, "lbp_decoder_set_osd_capacity: 1 <= cap <= current capacity");
+    d->fail_cap = cap;
+    return LBP_OK;
+}
+
+static lbp_status run_pass(lbp_decoder d, int64_t n_work, const int32_t *work_list, uint64_t first_shot_id,
+                           const uint32_t *syn, uint32_t *corr, uint8_t *flags, int32_t *iters, float *llr,
+                           hipStream_t s) {
+    lbp_code C = d->code;
+    HIPCHK(launch_reset(d->d_counters, 16, s));
+    BpArgs a{};
+    a.code = C->dc;
+    a.prm = d->bp;
+    a.n_work = n_work;
+    a.first_shot_id = first_shot_id;
+    a.work_list = work_list;
+    a.synd = syn;
+    a.corr = corr;
+    a.flags = flags;
+    a.iters = iters;
+    a.llr_out = llr;
+    a.counters = d->d_counters;
+    a.fail_list = d->d_fail_list;
+    a.fail_llr = d->d_fail_llr;
+    a.fail_cap = d->fail_cap;
+    a.stage = d->d_stage;
+    a.wave_bytes = d->wave_bytes;
+    int64_t need_blocks = (n_work + d->wpb - 1) / d->wpb;
+    int blocks = (int)std::min<int64_t>(d->bp_blocks, std::max<int64_t>(1, need_blocks));
+    HIPCHK(launch_bp(d->prm.msg, a, blocks, d->wpb, s));
+    if (d->prm.osd) {
+        OsdArgs o{};
+        o.m = C->m;
+        o.n = C->n;
+        o.mw = C->dc.mw;
+        o.nw = C->dc.nw;
+        o.mws = d->mws;
+        o.vn_tab = C->dc.vn_tab;
+        o.mode = d->prm.osd;
+        o.order = d->prm.osd_order;
+        o.synd = syn;
+        o.corr = corr;
+        o.flags = flags;
+        o.counters = d->d_counters;
+        o.fail_list = d->d_fail_list;
+        o.fail_llr = d->d_fail_llr;
+        o.fail_cap = d->fail_cap;
+        o.gscratch = d->d_gscratch;
+        o.sort_p = d->sort_p;
+        o.g_in_lds = d->g_in_lds;
+        o.has_lo = d->prm.msg == LBP_MSG_FP32;
+        HIPCHK(launch_osd(o, d->osd_blocks, d->osd_lds, s));
+    }
+    return LBP_OK;
+}
+
+lbp_status lbp_decode(lbp_decoder d, int64_t n_shots, uint64_t first_shot_id, const uint32_t *syndromes,
+                      uint32_t *corrections, uint8_t *flags, int32_t *iters, float *llr_out, void *stream) {
+    g_err.clear();
+    if (!d) return fail(LBP_EINVAL, "lbp_decode: NULL decoder");
+    if (n_shots < 0 || n_shots > d->max_batch) return fail(LBP_EINVAL, "lbp_decode: 0 <= n_shots <= max_batch");
+    if (n_shots == 0) return LBP_OK;
+    if (!syndromes || !corrections || !flags) return fail(LBP_EINVAL, "lbp_decode: NULL buffer");
+    DeviceGuard g(d->code->device);
+    hipStream_t s = (hipStream_t)stream;
+    lbp_status st = run_pass(d, n_shots, nullptr, first_shot_id, syndromes, corrections, flags, iters, llr_out, s);
+    if (st != LBP_OK || !d->prm.osd || n_shots <= d->fail_cap) return st;
+    // More shots may have failed BP than one OSD pass can stage: re-decode the
+    // overflow (BP is deterministic per shot) and run OSD on it, until done.
+    for (;;) {
+        HIPCHK(hipMemcpyAsync(d->h_count, d->d_counters + 1, 4, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        int64_t total = d->h_count[0];
+        if (total <= d->fail_cap) return LBP_OK;
+        int64_t rest = total - d->fail_cap;
+        HIPCHK(launch_gather_list(d->d_counters, d->d_fail_list, d->fail_cap, d->d_list2, rest, s));
+        st = run_pass(d, rest, d->d_list2, first_shot_id, syndromes, corrections, flags, iters, llr_out, s);
+        if (st != LBP_OK) return st;
+    }
+}
+
+lbp_status lbp_decode_host(lbp_decoder d, int64_t n_shots, uint64_t first_shot_id, const uint32_t *syndromes,
+                           uint32_t *corrections, uint8_t *flags, int32_t *iters, float *llr_out) {
+    g_err.clear();
+    if (!d) return fail(LBP_EINVAL, "lbp_decode_host: NULL decoder");
+    if (n_shots < 0 || n_shots > d->max_batch) return fail(LBP_EINVAL, "lbp_decode_host: 0 <= n_shots <= max_batch");
+    if (n_shots == 0) return LBP_OK;
+    if (!syndromes || !corrections || !flags) return fail(LBP_EINVAL, "lbp_decode_host: NULL buffer");
+    DeviceGuard g(d->code->device);
+    const size_t mw = d->code->dc.mw, nw = d->code->dc.nw, n = d->code->n;
+    uint32_t *ds = nullptr, *dc = nullptr;
+    uint8_t *df = nullptr;
+    int32_t *di = nullptr;
+    float *dl = nullptr;
+    hipStream_t s = nullptr;
+    lbp_status st = LBP_OK;
+    auto cleanup = [&]() {
+        if (s) hipStreamDestroy(s);
+        hipFree(ds); hipFree(dc); hipFree(df); hipFree(di); hipFree(dl);
+    };
+    auto chk = [&](hipError_t e, const char *what) {
+        if (e != hipSuccess && st == LBP_OK)
+            st = fail(e == hipErrorOutOfMemory ? LBP_ENOMEM : LBP_EDEVICE, std::string("lbp_decode_host: ") + what + ": " + hipGetErrorString(e));
+        return e == hipSuccess;
+    };
+    bool ok = chk(hipStreamCreateWithFlags(&s, hipStreamNonBlocking), "hipStreamCreate") &&
+              chk(hipMalloc(&ds, n_shots * mw * 4), "hipMalloc") && chk(hipMalloc(&dc, n_shots * nw * 4), "hipMalloc") &&
+              chk(hipMalloc(&df, n_shots), "hipMalloc") && (!iters || chk(hipMalloc(&di, n_shots * 4), "hipMalloc")) &&
+              (!llr_out || chk(hipMalloc(&dl, n_shots * n * 4), "hipMalloc")) &&
+              chk(hipMemcpyAsync(ds, syndromes, n_shots * mw * 4, hipMemcpyHostToDevice, s), "hipMemcpyAsync");
+    if (ok) {
+        st = lbp_decode(d, n_shots, first_shot_id, ds, dc, df, di, dl, s);
+        ok = st == LBP_OK && chk(hipMemcpyAsync(corrections, dc, n_shots * nw * 4, hipMemcpyDeviceToHost, s), "hipMemcpyAsync") &&
+             chk(hipMemcpyAsync(flags, df, n_shots, hipMemcpyDeviceToHost, s), "hipMemcpyAsync") &&
+             (!iters || chk(hipMemcpyAsync(iters, di, n_shots * 4, hipMemcpyDeviceToHost, s), "hipMemcpyAsync")) &&
+             (!llr_out || chk(hipMemcpyAsync(llr_out, dl, n_shots * n * 4, hipMemcpyDeviceToHost, s), "hipMemcpyAsync")) &&
+             chk(hipStreamSynchronize(s), "hipStreamSynchronize");
+    }
+    (void)ok;
+    cleanup();
+    return st;
+}
+
+}  // extern "C"
