@@ -1,0 +1,253 @@
+#!/usr/bin/env python
+"""Decoded syndromes/s and p99 latency on one MI355X: BB[[144,12,12]] phenomenological.
+
+Workload: the space-time matrix of BB[[144,12,12]] over 12 rounds (864 checks x
+2592 columns, 6840 edges), i.i.d. flips at p = 0.003, Lottery BP with at most
+200 iterations, then OSD-CS order 10 on the shots BP does not converge.  One
+step decodes the whole batch (10^6 syndromes by default) through the C ABI;
+inputs are resident in HBM before the timed region starts.
+
+Prints one JSON line (see the field list at the end of main()).
+"""
+from __future__ import annotations
+
+import argparse
+import concurrent.futures as cf
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from workloads import codes, sample  # noqa: E402
+from workloads.logical import LogicalChecker, failures_packed, wilson  # noqa: E402
+
+WORKLOAD = "bb144_phen"
+P_ERR = 0.003
+MAX_ITER = 200
+OSD_ORDER = 10
+DATA_SEED = 1004
+LOTTERY_SEED = 2004
+MSG_CODES = {"fp32": 0, "fp16": 1, "int8": 2}
+# VALU issue peak: 256 CUs x 4 SIMD16 x 16 lanes x 2.4 GHz (32-bit ops, no packing)
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+# Algorithmic 32-bit ALU operations per edge-update of NMS BP:
+# VN: add into lambda, subtract for alpha, saturate/round; CN: |alpha|, two
+# compares for min1/min2, sign xor, select min1/min2, sign apply; hard decision
+# and syndrome xor amortized to one more op.
+ALG_OPS_PER_EDGE = 10
+
+
+def _chunk_job(args):
+    k, n_total = args
+    h, _, _ = codes.workload_matrices(WORKLOAD)
+    lo = k * sample.CHUNK
+    hi = min(n_total, lo + sample.CHUNK)
+    e, syn = sample.make_batch(h, P_ERR, hi - lo, DATA_SEED, first_shot=lo)
+    return k, sample.pack_sparse(e), syn
+
+
+def make_inputs(shots: int, workers: int):
+    nchunks = (shots + sample.CHUNK - 1) // sample.CHUNK
+    errs = [None] * nchunks
+    syns = [None] * nchunks
+    with cf.ProcessPoolExecutor(max_workers=workers) as ex:
+        for k, e, s in ex.map(_chunk_job, [(k, shots) for k in range(nchunks)]):
+            errs[k] = e
+            syns[k] = s
+    return np.concatenate(errs), np.concatenate(syns)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def time_format(torch, h, syn_dev, msg: str, steps: int, warmup: int, shots: int):
+    from paper_2605_00038_amd import Code, Decoder, DecoderParams
+    prm = DecoderParams(max_iter=MAX_ITER, msg=MSG_CODES[msg], lottery=True, lottery_skip=6, osd=2,
+                        osd_order=OSD_ORDER, seed=LOTTERY_SEED)
+    dec = Decoder(Code.from_scipy(h, P_ERR), prm, shots)
+    corr = torch.empty((shots, dec.nw), dtype=torch.int32, device="cuda")
+    flags = torch.empty(shots, dtype=torch.uint8, device="cuda")
+    iters = torch.empty(shots, dtype=torch.int32, device="cuda")
+    out = (corr, flags, iters, None)
+    for _ in range(warmup):
+        dec.decode(syn_dev, out=out)
+    torch.cuda.synchronize()
+    dec.kernel_times()
+    dec.set_timing(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        dec.decode(syn_dev, out=out)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    dec.set_timing(False)
+    bp_ms, bp_n, osd_ms, osd_n = dec.kernel_times()
+    res = dict(seconds=t1 - t0, bp_ms=bp_ms, bp_launches=bp_n, osd_ms=osd_ms, osd_launches=osd_n,
+               corr=corr.cpu().numpy().view(np.uint32), flags=flags.cpu().numpy(), iters=iters.cpu().numpy())
+    return dec, res
+
+
+def latency(torch, dec, syn_dev, requests: int):
+    """Single-syndrome requests, each from the host call to stream completion."""
+    corr = torch.empty((1, dec.nw), dtype=torch.int32, device="cuda")
+    flags = torch.empty(1, dtype=torch.uint8, device="cuda")
+    out = (corr, flags, None, None)
+    for k in range(20):
+        dec.decode(syn_dev[k:k + 1], first_shot_id=k, out=out)
+    torch.cuda.synchronize()
+    lat = np.empty(requests)
+    for k in range(requests):
+        t0 = time.perf_counter()
+        dec.decode(syn_dev[k:k + 1], first_shot_id=k, out=out)
+        torch.cuda.synchronize()
+        lat[k] = time.perf_counter() - t0
+    return lat * 1e6
+
+
+def cpu_baseline(h, syn, seconds: float):
+    import oracle
+    threads = os.cpu_count() or 1
+    prm = oracle.OracleParams(max_iter=MAX_ITER, msg=oracle.INT8, lottery=True, lottery_skip=6,
+                              osd=oracle.OSD_CS, osd_order=OSD_ORDER, seed=LOTTERY_SEED)
+    cal = min(len(syn), 2000 * threads)
+    t0 = time.perf_counter()
+    oracle.decode(h, P_ERR, prm, syn[:cal], n_threads=threads)
+    rate = cal / (time.perf_counter() - t0)
+    n = int(min(len(syn), max(cal, rate * seconds)))
+    t0 = time.perf_counter()
+    oracle.decode(h, P_ERR, prm, syn[:n], n_threads=threads)
+    dt = time.perf_counter() - t0
+    return dict(value=n / dt, unit="syndromes/s", cores=threads, kind="oracle",
+                sample=f"first {n} shots of the benchmark batch, Int3.4 oracle with the same lottery "
+                       f"and OSD-CS(10), {threads} threads, {dt:.1f} s")
+
+
+def traffic_from_profiles(msg: str):
+    """HBM bytes per BP launch from the committed rocprofv3 PMC summary, or None
+    when that summary is missing or was taken on a different kernel source."""
+    path = os.path.join(ROOT, "profiles", f"bp_kernel_{WORKLOAD}_{msg}_pmc.md")
+    src = os.path.join(ROOT, "paper_2605_00038_amd", "csrc", "bp_kernel.hip")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m = re.search(r"source_sha256:\s*([0-9a-f]{64})", text)
+    b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not m or not b:
+        return None
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != m.group(1):
+        return None
+    return float(b.group(1))
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--shots", type=int, default=1_000_000)
+    ap.add_argument("--msg", default="int8", choices=list(MSG_CODES))
+    ap.add_argument("--formats", default="int8,fp16,fp32", help="formats timed besides --msg (LER comparison)")
+    ap.add_argument("--latency-requests", type=int, default=3000)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-ler", action="store_true")
+    ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: shots are independent, so N GPUs would each decode a disjoint "
+              "range of shots with no exchange; only --gpus 1 is supported here.", file=sys.stderr)
+        sys.exit(2)
+
+    h, hc, rounds = codes.workload_matrices(WORKLOAD)
+    m, n, E = h.shape[0], h.shape[1], h.nnz
+    # inputs are sampled by forked workers before this process touches the GPU
+    t0 = time.perf_counter()
+    err_p, syn = make_inputs(args.shots, args.workers)
+    log(f"sampled {args.shots} shots in {time.perf_counter() - t0:.1f} s")
+
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    import paper_2605_00038_amd  # noqa: F401  (fails loudly without liblbp.so)
+    syn_dev = torch.from_numpy(syn.view(np.int32)).cuda()
+    hx, hz = codes.bb144()
+    checker = LogicalChecker(hx, hz, rounds)
+
+    formats = [args.msg] + [f for f in args.formats.split(",") if f and f != args.msg]
+    per_fmt = {}
+    head_dec = None
+    for fmt in formats:
+        steps = args.steps if fmt == args.msg else max(1, min(args.steps, 2))
+        dec, r = time_format(torch, h, syn_dev, fmt, steps, args.warmup, args.shots)
+        rate = args.shots * steps / r["seconds"]
+        edges = float(r["iters"].astype(np.int64).sum()) * E
+        entry = dict(syndromes_per_s=rate, ms_per_step=1e3 * r["seconds"] / steps,
+                     bp_ms_per_launch=r["bp_ms"] / max(1, r["bp_launches"]),
+                     osd_ms_per_launch=r["osd_ms"] / max(1, r["osd_launches"]),
+                     mean_iters=float(r["iters"].mean()), osd_invoke_rate=float((r["flags"] & 2).mean()),
+                     edge_updates_per_step=edges, steps=steps)
+        if not args.no_ler:
+            sf, lf = failures_packed(checker, err_p, r["corr"], n)
+            k = int((sf | lf).sum())
+            lo, hi = wilson(k, args.shots)
+            entry.update(ler=k / args.shots, ler_ci95=[lo, hi], ler_synd_part=int(sf.sum()), ler_logical_part=int(lf.sum()))
+        per_fmt[fmt] = entry
+        log(fmt, json.dumps({k: v for k, v in entry.items()}))
+        if fmt == args.msg:
+            head_dec, head = dec, entry
+        else:
+            del dec
+        torch.cuda.empty_cache()
+
+    lat = latency(torch, head_dec, syn_dev, args.latency_requests) if args.latency_requests > 0 else None
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(h, syn, args.cpu_seconds)
+        log("cpu", json.dumps(cpu))
+
+    bp_s = head["bp_ms_per_launch"] / 1e3
+    ops = head["edge_updates_per_step"] * ALG_OPS_PER_EDGE
+    achieved = ops / bp_s / 1e12
+    traffic = traffic_from_profiles(args.msg)
+    line = {
+        "metric": "decoded syndromes/sec and p99 latency on 1 MI355X, BB-144 phenomenological",
+        "value": head["syndromes_per_s"],
+        "unit": "syndromes/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.msg,
+        "data": "synthetic: i.i.d. Bernoulli(p) flips on every column of H_st, seeded (PCG64, chunked)",
+        "config": {"workload": "BB[[144,12,12]] phenomenological, 12 rounds, H_st 864x2592 (6840 edges), "
+                               "p=0.003, Lottery BP I=200 K=6, OSD-CS(10)",
+                   "shots_per_step": args.shots, "data_seed": DATA_SEED, "lottery_seed": LOTTERY_SEED},
+        "p99_latency_us": float(np.percentile(lat, 99)) if lat is not None else None,
+        "latency_us": ({"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                        "p99.9": float(np.percentile(lat, 99.9)), "requests": int(len(lat)),
+                        "kind": "single-syndrome decode, host call to stream completion"}
+                       if lat is not None else None),
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
+                     "frac": achieved / VALU_PEAK_TOPS, "traffic": traffic,
+                     "kernel": f"bp_kernel<{args.msg}>", "launch_ms": head["bp_ms_per_launch"],
+                     "edge_updates_per_s": head["edge_updates_per_step"] / bp_s,
+                     "ops_per_edge_update": ALG_OPS_PER_EDGE},
+        "cpu_baseline": cpu,
+        "formats": per_fmt,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -136,6 +136,15 @@ int64_t lbp_decoder_osd_capacity(lbp_decoder dec);
 /* Testing aid: lower the staging capacity (>= 1) to exercise the overflow path. */
 lbp_status lbp_decoder_set_osd_capacity(lbp_decoder dec, int64_t cap);
 
+/* Kernel timing (tracing aid).  While enabled, lbp_decode records a pair of HIP
+ * events around every BP and every OSD kernel launch on the call's stream.
+ * lbp_decoder_kernel_times waits for the recorded events, returns the
+ * accumulated GPU milliseconds and launch counts since the last query, and
+ * resets them.  Any output pointer may be NULL. */
+lbp_status lbp_decoder_set_timing(lbp_decoder dec, int32_t enable);
+lbp_status lbp_decoder_kernel_times(lbp_decoder dec, double *bp_ms, int64_t *bp_launches, double *osd_ms,
+                                    int64_t *osd_launches);
+
 /* Thread-local description of the last error (empty string if none). */
 const char *lbp_last_error(void);
 /* Library version as major*10000 + minor*100 + patch. */

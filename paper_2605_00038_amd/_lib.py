@@ -58,6 +58,9 @@ SIGNATURES = {
     "lbp_decode_host": (_I32, [_VP, _I64, _U64, _VP, _VP, _VP, _VP, _VP]),
     "lbp_decoder_osd_capacity": (_I64, [_VP]),
     "lbp_decoder_set_osd_capacity": (_I32, [_VP, _I64]),
+    "lbp_decoder_set_timing": (_I32, [_VP, _I32]),
+    "lbp_decoder_kernel_times": (_I32, [_VP, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I64),
+                                        ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I64)]),
     "lbp_last_error": (ctypes.c_char_p, []),
     "lbp_version": (_I32, []),
 }

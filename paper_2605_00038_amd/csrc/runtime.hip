@@ -74,7 +74,26 @@ struct lbp_decoder_s {
     float *d_stage = nullptr;
     uint32_t *d_gscratch = nullptr;
     uint32_t *h_count = nullptr;  // pinned
+    // kernel timing: event pairs per launch, kind 0 = BP, 1 = OSD
+    bool timing = false;
+    struct Rec {
+        hipEvent_t a, b;
+        int kind;
+    };
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> pool;
 };
+
+static hipEvent_t take_event(lbp_decoder d) {
+    if (!d->pool.empty()) {
+        hipEvent_t e = d->pool.back();
+        d->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
 
 extern "C" {
 
@@ -201,6 +220,13 @@ int32_t lbp_code_rows(lbp_code code) { return code ? code->m : 0; }
 int32_t lbp_code_cols(lbp_code code) { return code ? code->n : 0; }
 
 static void free_decoder(lbp_decoder d) {
+    for (auto &r : d->recs) {
+        hipEventDestroy(r.a);
+        hipEventDestroy(r.b);
+    }
+    for (auto e : d->pool) hipEventDestroy(e);
+    d->recs.clear();
+    d->pool.clear();
     hipFree(d->d_counters);
     hipFree(d->d_fail_list);
     hipFree(d->d_list2);
@@ -344,7 +370,13 @@ static lbp_status run_pass(lbp_decoder d, int64_t n_work, const int32_t *work_li
     a.wave_bytes = d->wave_bytes;
     int64_t need_blocks = (n_work + d->wpb - 1) / d->wpb;
     int blocks = (int)std::min<int64_t>(d->bp_blocks, std::max<int64_t>(1, need_blocks));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (d->timing && (e0 = take_event(d)) && (e1 = take_event(d))) HIPCHK(hipEventRecord(e0, s));
     HIPCHK(launch_bp(d->prm.msg, a, blocks, d->wpb, s));
+    if (e1) {
+        HIPCHK(hipEventRecord(e1, s));
+        d->recs.push_back({e0, e1, 0});
+    }
     if (d->prm.osd) {
         OsdArgs o{};
         o.m = C->m;
@@ -366,8 +398,43 @@ static lbp_status run_pass(lbp_decoder d, int64_t n_work, const int32_t *work_li
         o.sort_p = d->sort_p;
         o.g_in_lds = d->g_in_lds;
         o.has_lo = d->prm.msg == LBP_MSG_FP32;
+        hipEvent_t f0 = nullptr, f1 = nullptr;
+        if (d->timing && (f0 = take_event(d)) && (f1 = take_event(d))) HIPCHK(hipEventRecord(f0, s));
         HIPCHK(launch_osd(o, d->osd_blocks, d->osd_lds, s));
+        if (f1) {
+            HIPCHK(hipEventRecord(f1, s));
+            d->recs.push_back({f0, f1, 1});
+        }
     }
+    return LBP_OK;
+}
+
+lbp_status lbp_decoder_set_timing(lbp_decoder d, int32_t enable) {
+    if (!d) return fail(LBP_EINVAL, "lbp_decoder_set_timing: NULL decoder");
+    d->timing = enable != 0;
+    return LBP_OK;
+}
+
+lbp_status lbp_decoder_kernel_times(lbp_decoder d, double *bp_ms, int64_t *bp_launches, double *osd_ms,
+                                    int64_t *osd_launches) {
+    if (!d) return fail(LBP_EINVAL, "lbp_decoder_kernel_times: NULL decoder");
+    DeviceGuard g(d->code->device);
+    double t[2] = {0, 0};
+    int64_t c[2] = {0, 0};
+    for (auto &r : d->recs) {
+        HIPCHK(hipEventSynchronize(r.b));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, r.a, r.b));
+        t[r.kind] += ms;
+        c[r.kind] += 1;
+        d->pool.push_back(r.a);
+        d->pool.push_back(r.b);
+    }
+    d->recs.clear();
+    if (bp_ms) *bp_ms = t[0];
+    if (bp_launches) *bp_launches = c[0];
+    if (osd_ms) *osd_ms = t[1];
+    if (osd_launches) *osd_launches = c[1];
     return LBP_OK;
 }
 

@@ -82,6 +82,17 @@ class Decoder:
     def set_osd_capacity(self, cap: int) -> None:
         check(load().lbp_decoder_set_osd_capacity(self._h, int(cap)))
 
+    def set_timing(self, enable: bool) -> None:
+        check(load().lbp_decoder_set_timing(self._h, int(enable)))
+
+    def kernel_times(self):
+        """(bp_ms, bp_launches, osd_ms, osd_launches) accumulated since the last call."""
+        a, c = ctypes.c_double(), ctypes.c_double()
+        b, d = ctypes.c_int64(), ctypes.c_int64()
+        check(load().lbp_decoder_kernel_times(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c),
+                                              ctypes.byref(d)))
+        return a.value, b.value, c.value, d.value
+
     def decode(self, syndromes, first_shot_id: int = 0, out=None, want_iters: bool = True,
                want_llr: bool = False, stream=None):
         """Decode a [shots, ceil(m/32)] int32/uint32 CUDA tensor of packed syndromes.

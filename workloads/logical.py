@@ -45,6 +45,31 @@ class LogicalChecker:
         return synd_fail, log_fail & ~synd_fail
 
 
+def failures_packed(checker: "LogicalChecker", err_packed: np.ndarray, corr_packed: np.ndarray, n_dec: int,
+                    chunk: int = 32768):
+    """Same as LogicalChecker.failures for packed error words (dense, chunked)."""
+    hT = checker.h.toarray().T.astype(np.float32)
+    kT = checker.k.toarray().T.astype(np.float32)
+    S = err_packed.shape[0]
+    sf = np.zeros(S, bool)
+    lf = np.zeros(S, bool)
+    span = checker.r * checker.n
+    for lo in range(0, S, chunk):
+        hi = min(S, lo + chunk)
+        diff = np.ascontiguousarray(err_packed[lo:hi] ^ corr_packed[lo:hi], dtype="<u4")
+        nz = diff.any(axis=1)
+        if not nz.any():
+            continue
+        bits = unpack_bits(diff[nz], n_dec)[:, :span]
+        R = np.bitwise_xor.reduce(bits.reshape(bits.shape[0], checker.r, checker.n), axis=1).astype(np.float32)
+        s_bad = (np.rint(R @ hT).astype(np.int64) & 1).any(axis=1)
+        l_bad = (np.rint(R @ kT).astype(np.int64) & 1).any(axis=1) & ~s_bad
+        idx = np.nonzero(nz)[0] + lo
+        sf[idx] = s_bad
+        lf[idx] = l_bad
+    return sf, lf
+
+
 def wilson(k: int, n: int, z: float = 1.959963984540054) -> tuple[float, float]:
     """Wilson score interval for a binomial proportion k/n (95% by default)."""
     if n == 0:

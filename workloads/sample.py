@@ -76,3 +76,13 @@ def make_batch(h: sp.csr_matrix, p: float, shots: int, seed: int, first_shot: in
     e = sample_errors(h.shape[1], p, shots, seed, first_shot)
     s = syndromes(h, e)
     return e, pack_bits(s)
+
+
+def pack_sparse(errors: sp.csr_matrix) -> np.ndarray:
+    """Sparse 0/1 rows -> packed uint32 words (same layout as pack_bits)."""
+    e = sp.csr_matrix(errors)
+    out = np.zeros((e.shape[0], words(e.shape[1])), dtype=np.uint32)
+    rows = np.repeat(np.arange(e.shape[0]), np.diff(e.indptr))
+    cols = e.indices.astype(np.int64)
+    np.bitwise_or.at(out, (rows, cols >> 5), (np.uint32(1) << (cols & 31).astype(np.uint32)))
+    return out
