@@ -71,7 +71,7 @@ struct OsdArgs {
     const int32_t *fail_list;
     const float *fail_llr;      // [fail_cap][2n]
     int64_t fail_cap;
-    uint32_t *gscratch;         // per-block G when it does not fit in LDS (else null)
+    uint32_t *gscratch;         // per-block scratch: G in global memory, or column ballots
     int32_t sort_p;             // power of two >= n
     int32_t g_in_lds;
     int32_t has_lo;             // lambda carries a non-zero low part (fp32 messages)
@@ -79,13 +79,18 @@ struct OsdArgs {
 
 // LDS bytes the BP kernel needs per wave for a code.
 int bp_wave_bytes(int msg, int m, int n);
-// LDS bytes per block of the OSD kernel (and whether G fits in LDS).
-int osd_block_bytes(int m, int n, int lds_limit, int *g_in_lds, int *mws, int *sort_p);
+// OSD kernel choice for a code: variant > 0 keeps G in registers (NW words per
+// row, m <= 1024), 0 keeps G in LDS, -1 in global memory.  Returns LDS bytes
+// per block; *threads is the block size.
+int osd_block_bytes(int m, int n, int lds_limit, int *variant, int *mws, int *sort_p, int *threads);
+// Per-block global scratch of the OSD kernel.
+size_t osd_scratch_bytes(int variant, int m, int mws);
+hipError_t osd_max_blocks_per_cu(int variant, int threads, int lds, int *out);
 
 hipError_t launch_reset(uint32_t *counters, int count, hipStream_t s);
 hipError_t launch_bp(int msg, const BpArgs &a, int blocks, int waves_per_block, hipStream_t s);
 hipError_t bp_max_blocks_per_cu(int msg, int waves_per_block, int lds_bytes, int *out);
-hipError_t launch_osd(const OsdArgs &a, int blocks, int lds_bytes, hipStream_t s);
+hipError_t launch_osd(const OsdArgs &a, int variant, int blocks, int threads, int lds_bytes, hipStream_t s);
 hipError_t launch_gather_list(const uint32_t *counters, const int32_t *fail_list, int64_t from, int32_t *out,
                               int64_t count, hipStream_t s);
 

@@ -101,24 +101,94 @@ __device__ __forceinline__ int col_rows(const uint64_t *vn_tab, int col, int *ro
 
 // Exclusive block scan of one int per thread; *total receives the sum.
 __device__ int block_excl_scan(int x, int *scr, int *total) {
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nwv = (int)(blockDim.x >> 6);
     int incl = wave_incl_scan(x, lane);
     if (lane == 63) scr[wid] = incl;
     __syncthreads();
     if (wid == 0) {
-        int v = lane < OSD_WAVES ? scr[lane] : 0;
+        int v = lane < nwv ? scr[lane] : 0;
         int vi = wave_incl_scan(v, lane);
-        if (lane < OSD_WAVES) scr[lane] = vi - v;
-        if (lane == OSD_WAVES - 1) scr[OSD_WAVES] = vi;
+        if (lane < nwv) scr[lane] = vi - v;
+        if (lane == nwv - 1) scr[16] = vi;
     }
     __syncthreads();
     int r = scr[wid] + incl - x;
-    *total = scr[OSD_WAVES];
+    *total = scr[16];
     __syncthreads();
     return r;
 }
 
-__global__ __launch_bounds__(OSD_THREADS) void osd_kernel(OsdArgs a) {
+// Step 1 (LLR sorting): perm[j] = j-th column in ascending (lambda, column)
+// order, lambda = hi + lo.  Bitonic sort of (orderable(hi) << 32 | column) in
+// `keys` (P entries), then each run of equal hi is ordered by lo with a stable
+// insertion sort (runs only exist with a non-zero lo, i.e. fp32 messages).
+__device__ void sort_columns(const float *lam, int n, int P, int has_lo, unsigned long long *keys, float *lo_s,
+                             uint16_t *perm) {
+    const int tid = threadIdx.x, nth = blockDim.x;
+    for (int j = tid; j < P; j += nth)
+        keys[j] = j < n ? (((unsigned long long)orderable(lam[j]) << 32) | (unsigned)j) : ~0ull;
+    if (has_lo)
+        for (int j = tid; j < n; j += nth) lo_s[j] = lam[n + j];
+    __syncthreads();
+    for (int k = 2; k <= P; k <<= 1) {
+        for (int jj = k >> 1; jj > 0; jj >>= 1) {
+            for (int t = tid; t < (P >> 1); t += nth) {
+                int i = ((t & ~(jj - 1)) << 1) | (t & (jj - 1));
+                int l = i + jj;
+                bool asc = (i & k) == 0;
+                unsigned long long x = keys[i], y = keys[l];
+                if ((x > y) == asc) { keys[i] = y; keys[l] = x; }
+            }
+            __syncthreads();
+        }
+    }
+    if (has_lo) {
+        for (int j = tid; j < n; j += nth) {
+            const uint32_t h = (uint32_t)(keys[j] >> 32);
+            if (j > 0 && (uint32_t)(keys[j - 1] >> 32) == h) continue;  // not the start of a run
+            int e = j + 1;
+            while (e < n && (uint32_t)(keys[e] >> 32) == h) ++e;
+            for (int x = j + 1; x < e; ++x) {
+                unsigned long long kx = keys[x];
+                uint32_t ox = orderable(lo_s[kx & 0xFFFFu]);
+                int y = x - 1;
+                while (y >= j && orderable(lo_s[keys[y] & 0xFFFFu]) > ox) {
+                    keys[y + 1] = keys[y];
+                    --y;
+                }
+                keys[y + 1] = kx;
+            }
+        }
+        __syncthreads();
+    }
+    for (int j = tid; j < n; j += nth) perm[j] = (uint16_t)(keys[j] & 0xFFFFu);
+    __syncthreads();
+}
+
+// Non-basis columns in sorted order -> tl[0..nt).
+__device__ int list_nonbasis(const uint8_t *isb, const uint16_t *perm, int n, uint16_t *tl, int *scr) {
+    const int nth = blockDim.x;
+    const int chunk = (n + nth - 1) / nth;
+    const int lo = threadIdx.x * chunk, hi = lo + chunk < n ? lo + chunk : n;
+    int cnt = 0;
+    for (int j = lo; j < hi; ++j) cnt += !isb[j];
+    int nt;
+    int off = block_excl_scan(cnt, scr, &nt);
+    for (int j = lo; j < hi; ++j)
+        if (!isb[j]) tl[off++] = perm[j];
+    __syncthreads();
+    return nt;
+}
+
+// Pair index -> (a, b), a < b < w, lexicographic.
+__device__ __forceinline__ void pair_of(int pi, int w, int &aa, int &bb) {
+    int rem = pi;
+    aa = 0;
+    while (rem >= w - 1 - aa) { rem -= w - 1 - aa; ++aa; }
+    bb = aa + 1 + rem;
+}
+
+__global__ __launch_bounds__(OSD_THREADS) void osd_lds_kernel(OsdArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int m = a.m, n = a.n, tid = threadIdx.x, lane = tid & 63;
     const int P = a.sort_p;
@@ -151,47 +221,8 @@ __global__ __launch_bounds__(OSD_THREADS) void osd_kernel(OsdArgs a) {
         const int64_t shot = a.fail_list[q];
         const float *lam = a.fail_llr + (size_t)q * 2 * n;  // hi[n] then lo[n]: lambda = hi + lo
 
-        // ---- 1. sort (lambda, column) ascending: bitonic on (hi, column), then
-        // runs of equal hi are ordered by lo (stable, so ties stay by column)
-        unsigned long long *keys = (unsigned long long *)smem;
-        for (int j = tid; j < P; j += OSD_THREADS)
-            keys[j] = j < n ? (((unsigned long long)orderable(lam[j]) << 32) | (unsigned)j) : ~0ull;
-        if (a.has_lo)
-            for (int j = tid; j < n; j += OSD_THREADS) lo_s[j] = lam[n + j];
-        __syncthreads();
-        for (int k = 2; k <= P; k <<= 1) {
-            for (int jj = k >> 1; jj > 0; jj >>= 1) {
-                for (int t = tid; t < (P >> 1); t += OSD_THREADS) {
-                    int i = ((t & ~(jj - 1)) << 1) | (t & (jj - 1));
-                    int l = i + jj;
-                    bool asc = (i & k) == 0;
-                    unsigned long long x = keys[i], y = keys[l];
-                    if ((x > y) == asc) { keys[i] = y; keys[l] = x; }
-                }
-                __syncthreads();
-            }
-        }
-        if (a.has_lo) {
-            for (int j = tid; j < n; j += OSD_THREADS) {
-                const uint32_t h = (uint32_t)(keys[j] >> 32);
-                if (j > 0 && (uint32_t)(keys[j - 1] >> 32) == h) continue;  // not the start of a run
-                int e = j + 1;
-                while (e < n && (uint32_t)(keys[e] >> 32) == h) ++e;
-                for (int x = j + 1; x < e; ++x) {  // insertion sort by lo (stable)
-                    unsigned long long kx = keys[x];
-                    uint32_t ox = orderable(lo_s[kx & 0xFFFFu]);
-                    int y = x - 1;
-                    while (y >= j && orderable(lo_s[keys[y] & 0xFFFFu]) > ox) {
-                        keys[y + 1] = keys[y];
-                        --y;
-                    }
-                    keys[y + 1] = kx;
-                }
-            }
-            __syncthreads();
-        }
-        for (int j = tid; j < n; j += OSD_THREADS) perm[j] = (uint16_t)(keys[j] & 0xFFFFu);
-        __syncthreads();
+        // ---- 1. sort (lambda, column) ascending
+        sort_columns(lam, n, P, a.has_lo, (unsigned long long *)smem, lo_s, perm);
 
         // ---- 2. G = I, s' = s
         const int mw = a.mw;
@@ -258,14 +289,7 @@ __global__ __launch_bounds__(OSD_THREADS) void osd_kernel(OsdArgs a) {
         // ---- 4. OSD-CS candidate sweep
         int t0 = -1, t1 = -1;
         if (a.mode == OSD_CS) {
-            const int chunk = (n + OSD_THREADS - 1) / OSD_THREADS;
-            const int lo = tid * chunk, hi = lo + chunk < n ? lo + chunk : n;
-            int cnt = 0;
-            for (int j = lo; j < hi; ++j) cnt += !isb[j];
-            int nt;
-            int off = block_excl_scan(cnt, scr, &nt);
-            for (int j = lo; j < hi; ++j)
-                if (!isb[j]) tl[off++] = perm[j];
+            const int nt = list_nonbasis(isb, perm, n, tl, scr);
             int w0 = 0;
             for (int r = tid; r < m; r += OSD_THREADS) w0 += sp[r];
             w0 = wave_sum(w0);
@@ -289,9 +313,8 @@ __global__ __launch_bounds__(OSD_THREADS) void osd_kernel(OsdArgs a) {
             const int w = a.order < nt ? a.order : nt;
             const int npairs = w * (w - 1) / 2;
             for (int pi = tid; pi < npairs; pi += OSD_THREADS) {
-                int aa = 0, rem = pi;
-                while (rem >= w - 1 - aa) { rem -= w - 1 - aa; ++aa; }
-                int bb = aa + 1 + rem;
+                int aa, bb;
+                pair_of(pi, w, aa, bb);
                 int ra[CDEG], rb[CDEG];
                 int na = col_rows(a.vn_tab, tl[aa], ra), nb = col_rows(a.vn_tab, tl[bb], rb);
                 unsigned long long cost = 2;
@@ -306,10 +329,10 @@ __global__ __launch_bounds__(OSD_THREADS) void osd_kernel(OsdArgs a) {
             if (idx >= 1 && idx <= (unsigned)nt) {
                 t0 = tl[idx - 1];
             } else if (idx > (unsigned)nt) {
-                int pi = (int)idx - 1 - nt, aa = 0, rem = pi;
-                while (rem >= w - 1 - aa) { rem -= w - 1 - aa; ++aa; }
+                int aa, bb;
+                pair_of((int)idx - 1 - nt, w, aa, bb);
                 t0 = tl[aa];
-                t1 = tl[aa + 1 + rem];
+                t1 = tl[bb];
             }
         }
 
@@ -339,35 +362,284 @@ __global__ __launch_bounds__(OSD_THREADS) void osd_kernel(OsdArgs a) {
     }
 }
 
+
+// ---------------------------------------------------------------------------
+// Register-resident variant for m <= 32*NW <= 1024: thread r owns row r of G as
+// an NW-word vector register, so the Gauss-Jordan XOR of a pivot row is NW
+// VALU ops against a broadcast LDS copy, and the bit of the reduced column is
+// read with a wave-uniform word index (indexed register move, no LDS).  Two
+// block barriers per pivot step, one per dependent column.  For OSD-CS each
+// wave turns every column c of G into a 64-bit ballot of its rows; the cost of
+// a candidate is then a popcount per wave.
+template <int NW>
+using vrow = uint32_t __attribute__((ext_vector_type(NW)));
+
+template <int NW>
+__device__ __forceinline__ uint32_t row_bit(const vrow<NW> &g, int c) {
+    return (g[c >> 5] >> (c & 31)) & 1u;  // c is wave-uniform
+}
+
+template <int NW>
+__device__ __forceinline__ uint32_t reduced_bit(const vrow<NW> &g, uint64_t tab) {
+    uint32_t x = 0;
+#pragma unroll
+    for (int j = 0; j < CDEG; ++j) {
+        uint32_t p = (uint32_t)(tab >> (16 * j)) & 0xFFFFu;
+        if (p != NOPOS) x ^= row_bit<NW>(g, __builtin_amdgcn_readfirstlane((int)(p / DEG)));
+    }
+    return x;
+}
+
+__device__ __forceinline__ uint64_t uniform_tab(const uint64_t *vn_tab, int col) {
+    col = __builtin_amdgcn_readfirstlane(col);
+    uint64_t t = vn_tab[col];
+    uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)t), hi = __builtin_amdgcn_readfirstlane((uint32_t)(t >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// popcount over the block's rows of (s' + reduced column(s)) using per-wave ballots
+__device__ __forceinline__ uint32_t ballot_cost(const unsigned long long *B, const unsigned long long *Y, int m,
+                                                int nwv, uint64_t ta, uint64_t tb) {
+    uint32_t cost = 0;
+    for (int w = 0; w < nwv; ++w) {
+        unsigned long long x = Y[w];
+#pragma unroll
+        for (int j = 0; j < CDEG; ++j) {
+            uint32_t p = (uint32_t)(ta >> (16 * j)) & 0xFFFFu;
+            if (p != NOPOS) x ^= B[(size_t)w * m + p / DEG];
+            uint32_t q = (uint32_t)(tb >> (16 * j)) & 0xFFFFu;
+            if (q != NOPOS) x ^= B[(size_t)w * m + q / DEG];
+        }
+        cost += __popcll(x);
+    }
+    return cost;
+}
+
+// Wave `w`'s 64-row mask of the XOR of the reduced columns named by ta and tb.
+__device__ __forceinline__ uint64_t ballot_cost_mask(const unsigned long long *B, int m, int w, uint64_t ta,
+                                                     uint64_t tb) {
+    unsigned long long x = 0;
+#pragma unroll
+    for (int j = 0; j < CDEG; ++j) {
+        uint32_t p = (uint32_t)(ta >> (16 * j)) & 0xFFFFu;
+        if (p != NOPOS) x ^= B[(size_t)w * m + p / DEG];
+        uint32_t q = (uint32_t)(tb >> (16 * j)) & 0xFFFFu;
+        if (q != NOPOS) x ^= B[(size_t)w * m + q / DEG];
+    }
+    return x;
+}
+
+template <int NW>
+__global__ __launch_bounds__(1024) void osd_reg_kernel(OsdArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int m = a.m, n = a.n, tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int nth = blockDim.x, nwv = nth >> 6;
+    const int P = a.sort_p;
+    const bool valid = tid < m;
+    unsigned char *q0 = smem + (((size_t)P * 8 + 15) & ~(size_t)15);
+    float *lo_s = (float *)q0;                       q0 += ((size_t)n * 4 + 15) & ~(size_t)15;
+    uint16_t *perm = (uint16_t *)q0;                 q0 += ((size_t)n * 2 + 15) & ~(size_t)15;
+    uint16_t *tl = (uint16_t *)q0;                   q0 += ((size_t)n * 2 + 15) & ~(size_t)15;
+    uint8_t *isb = q0;                               q0 += ((size_t)n + 15) & ~(size_t)15;
+    vrow<NW> *prow = (vrow<NW> *)q0;                 q0 += ((size_t)NW * 4 + 15) & ~(size_t)15;
+    uint32_t *cw = (uint32_t *)q0;                   q0 += ((size_t)a.nw * 4 + 15) & ~(size_t)15;
+    uint32_t *red = (uint32_t *)q0;                  q0 += 16 * 4;
+    int *scr = (int *)q0;                            q0 += 32 * 4;
+    unsigned long long *Y = (unsigned long long *)q0; q0 += 16 * 8;
+    unsigned long long *best64 = (unsigned long long *)q0;
+    unsigned long long *B = (unsigned long long *)a.gscratch + (size_t)blockIdx.x * 16 * m;
+
+    uint32_t nfail = a.counters[1];
+    if ((int64_t)nfail > a.fail_cap) nfail = (uint32_t)a.fail_cap;
+
+    for (uint32_t q = blockIdx.x; q < nfail; q += gridDim.x) {
+        const int64_t shot = a.fail_list[q];
+        const float *lam = a.fail_llr + (size_t)q * 2 * n;
+
+        // ---- 1. sort (lambda, column) ascending
+        sort_columns(lam, n, P, a.has_lo, (unsigned long long *)smem, lo_s, perm);
+
+        // ---- 2. G = I (row tid), s' = s
+        vrow<NW> g;
+#pragma unroll
+        for (int k = 0; k < NW; ++k) g[k] = (valid && k == (tid >> 5)) ? (1u << (tid & 31)) : 0u;
+        const uint32_t *sw = a.synd + shot * a.mw;
+        uint32_t sp = valid ? (sw[tid >> 5] >> (tid & 31)) & 1u : 0u;
+        bool piv = false;
+        int pcol = 0;
+        for (int j = tid; j < n; j += nth) isb[j] = 0;
+        if (tid < 3) red[tid] = 0xFFFFFFFFu;
+        __syncthreads();
+
+        // ---- 3. Gauss-Jordan in sorted column order
+        int rank = 0, step = 0;
+        for (int j = 0; j < n && rank < m; ++j) {
+            const int col = perm[j];
+            const uint64_t tab = uniform_tab(a.vn_tab, col);
+            const uint32_t x = reduced_bit<NW>(g, tab);
+            const int slot = step % 3;
+            if (tid == 0) red[(step + 1) % 3] = 0xFFFFFFFFu;
+            const uint64_t bal = __ballot(valid && x && !piv);
+            if (lane == 0 && bal) atomicMin(&red[slot], (uint32_t)(wid * 64 + __ffsll((unsigned long long)bal) - 1));
+            __syncthreads();
+            const int pv = (int)red[slot];
+            ++step;
+            if (pv == (int)0xFFFFFFFFu) continue;
+            if (tid == pv) {
+                *prow = g;
+                red[3] = sp;
+                piv = true;
+                pcol = col;
+            }
+            if (tid == 0) isb[j] = 1;
+            __syncthreads();
+            if (x && tid != pv) {
+                g ^= *prow;
+                sp ^= red[3];
+            }
+            ++rank;
+        }
+
+        // ---- consistency: a row with no pivot reduced to 0 = s'_r
+        if (__syncthreads_or(valid && !piv && sp)) {
+            if (tid == 0) a.flags[shot] = (uint8_t)(FLAG_OSD | FLAG_OSD_INCONSISTENT);
+            __syncthreads();
+            continue;
+        }
+
+        // ---- 4. OSD-CS candidate sweep on per-wave column ballots of G (G is dead afterwards)
+        int t0 = -1, t1 = -1;
+        uint32_t e = sp;
+        if (a.mode == OSD_CS) {
+            const int nt = list_nonbasis(isb, perm, n, tl, scr);
+            for (int c = 0; c < m; ++c) {
+                const uint64_t b = __ballot(valid && row_bit<NW>(g, c));
+                if (lane == 0) B[(size_t)wid * m + c] = b;
+            }
+            const uint64_t yb = __ballot(valid && sp);
+            if (lane == 0) Y[wid] = yb;
+            if (tid == 0) *best64 = ~0ull;
+            __syncthreads();
+            uint32_t cost0 = 0;
+            for (int w = 0; w < nwv; ++w) cost0 += __popcll(Y[w]);
+            unsigned long long best = (unsigned long long)cost0 << 32;
+            for (int ai = tid; ai < nt; ai += nth) {
+                unsigned long long cost = 1 + ballot_cost(B, Y, m, nwv, a.vn_tab[tl[ai]], ~0ull);
+                unsigned long long key = (cost << 32) | (unsigned long long)(1 + ai);
+                best = key < best ? key : best;
+            }
+            const int w = a.order < nt ? a.order : nt;
+            const int npairs = w * (w - 1) / 2;
+            for (int pi = tid; pi < npairs; pi += nth) {
+                int aa, bb;
+                pair_of(pi, w, aa, bb);
+                unsigned long long cost = 2 + ballot_cost(B, Y, m, nwv, a.vn_tab[tl[aa]], a.vn_tab[tl[bb]]);
+                unsigned long long key = (cost << 32) | (unsigned long long)(1 + nt + pi);
+                best = key < best ? key : best;
+            }
+            best = wave_min_u64(best);
+            if (lane == 0) atomicMin(best64, best);
+            __syncthreads();
+            const unsigned idx = (unsigned)(*best64 & 0xFFFFFFFFull);
+            if (idx >= 1 && idx <= (unsigned)nt) {
+                t0 = tl[idx - 1];
+            } else if (idx > (unsigned)nt) {
+                int aa, bb;
+                pair_of((int)idx - 1 - nt, w, aa, bb);
+                t0 = tl[aa];
+                t1 = tl[bb];
+            }
+            // this row's bit of the chosen candidate's reduced columns, from the ballots
+            const uint64_t tab0 = t0 >= 0 ? a.vn_tab[t0] : ~0ull, tab1 = t1 >= 0 ? a.vn_tab[t1] : ~0ull;
+            const uint64_t xb = ballot_cost_mask(B, m, wid, tab0, tab1);
+            e ^= (uint32_t)(xb >> lane) & 1u;
+        }
+
+        // ---- 5. e_S = s' + G H_T t on the basis, t on the rest; scatter to columns
+        for (int ww = tid; ww < a.nw; ww += nth) cw[ww] = 0u;
+        __syncthreads();
+        if (valid && piv && e) atomicOr(&cw[pcol >> 5], 1u << (pcol & 31));
+        if (tid == 0) {
+            if (t0 >= 0) atomicOr(&cw[t0 >> 5], 1u << (t0 & 31));
+            if (t1 >= 0) atomicOr(&cw[t1 >> 5], 1u << (t1 & 31));
+        }
+        __syncthreads();
+        for (int ww = tid; ww < a.nw; ww += nth) a.corr[shot * a.nw + ww] = cw[ww];
+        __syncthreads();
+    }
+}
+
 }  // namespace
 
-int osd_block_bytes(int m, int n, int lds_limit, int *g_in_lds, int *mws, int *sort_p) {
+int osd_block_bytes(int m, int n, int lds_limit, int *variant, int *mws, int *sort_p, int *threads) {
     int P = 1;
     while (P < n) P <<= 1;
     int mw = (m + 31) / 32;
     int s = mw | 1;
     auto al = [](size_t x) { return (x + 15) & ~(size_t)15; };
-    size_t rest = al((size_t)n * 4) + al((size_t)n * 2) * 2 + al((size_t)n) + al((size_t)m * 2) + al((size_t)m) * 2 +
-                  al((size_t)((n + 31) / 32) * 4) + 16 * 4 + 32 * 4 + 16;
+    *sort_p = P;
+    size_t common = al((size_t)n * 4) + al((size_t)n * 2) * 2 + al((size_t)n) + al((size_t)((n + 31) / 32) * 4) +
+                    16 * 4 + 32 * 4 + 16;
+    if (m <= 1024) {
+        int nw = m <= 256 ? 8 : (m <= 512 ? 16 : (m <= 896 ? 28 : 32));
+        *variant = nw;
+        *mws = mw;
+        *threads = 64 * ((m + 63) / 64);
+        return (int)(al((size_t)P * 8) + common + al((size_t)nw * 4) + 16 * 8);
+    }
+    *threads = OSD_THREADS;
+    size_t rest = common + al((size_t)m * 2) + al((size_t)m) * 2;
     size_t gb = (size_t)m * s * 4;
     size_t with_g = al(gb > (size_t)P * 8 ? gb : (size_t)P * 8) + rest;
-    size_t without = al((size_t)P * 8) + rest;
-    *sort_p = P;
     if ((int64_t)with_g <= lds_limit) {
-        *g_in_lds = 1;
+        *variant = 0;  // G in LDS
         *mws = s;
         return (int)with_g;
     }
-    *g_in_lds = 0;
+    *variant = -1;     // G in global memory
     *mws = mw;
-    return (int)without;
+    return (int)(al((size_t)P * 8) + rest);
 }
 
-hipError_t launch_osd(const OsdArgs &a, int blocks, int lds, hipStream_t s) {
-    hipError_t e = hipFuncSetAttribute((const void *)osd_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+size_t osd_scratch_bytes(int variant, int m, int mws) {
+    if (variant > 0) return (size_t)16 * m * 8;       // per-wave column ballots
+    if (variant < 0) return (size_t)m * mws * 4;      // G
+    return 0;
+}
+
+template <class K>
+static hipError_t launch_k(K kern, const OsdArgs &a, int blocks, int threads, int lds, hipStream_t s) {
+    hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(osd_kernel, dim3(blocks), dim3(OSD_THREADS), (size_t)lds, s, a);
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(threads), (size_t)lds, s, a);
     return hipGetLastError();
+}
+
+hipError_t launch_osd(const OsdArgs &a, int variant, int blocks, int threads, int lds, hipStream_t s) {
+    switch (variant) {
+    case 8: return launch_k(osd_reg_kernel<8>, a, blocks, threads, lds, s);
+    case 16: return launch_k(osd_reg_kernel<16>, a, blocks, threads, lds, s);
+    case 28: return launch_k(osd_reg_kernel<28>, a, blocks, threads, lds, s);
+    case 32: return launch_k(osd_reg_kernel<32>, a, blocks, threads, lds, s);
+    default: return launch_k(osd_lds_kernel, a, blocks, threads, lds, s);
+    }
+}
+
+template <class K>
+static hipError_t occ_k(K kern, int threads, int lds, int *out) {
+    hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e != hipSuccess) return e;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(out, kern, threads, (size_t)lds);
+}
+
+hipError_t osd_max_blocks_per_cu(int variant, int threads, int lds, int *out) {
+    switch (variant) {
+    case 8: return occ_k(osd_reg_kernel<8>, threads, lds, out);
+    case 16: return occ_k(osd_reg_kernel<16>, threads, lds, out);
+    case 28: return occ_k(osd_reg_kernel<28>, threads, lds, out);
+    case 32: return occ_k(osd_reg_kernel<32>, threads, lds, out);
+    default: return occ_k(osd_lds_kernel, threads, lds, out);
+    }
 }
 
 }  // namespace lbp

@@ -65,7 +65,7 @@ struct lbp_decoder_s {
     int64_t max_batch = 0;
     BpParams bp{};
     int wpb = 1, bp_blocks = 1, wave_bytes = 0;
-    int osd_blocks = 0, osd_lds = 0, g_in_lds = 1, mws = 1, sort_p = 1;
+    int osd_blocks = 0, osd_lds = 0, osd_variant = 0, osd_threads = 1024, mws = 1, sort_p = 1;
     int64_t fail_cap = 0;
     uint32_t *d_counters = nullptr;
     int32_t *d_fail_list = nullptr;
@@ -305,9 +305,13 @@ lbp_status lbp_decoder_create(lbp_code code, const lbp_params *prm, int64_t max_
     d->fail_cap = prm->osd ? std::min<int64_t>(max_batch, std::max<int64_t>(1024, ((int64_t)256 << 20) / ((int64_t)code->n * 8)))
                            : 0;
     // the OSD kernel also holds a little static LDS (block-wide reductions)
-    d->osd_lds = osd_block_bytes(code->m, code->n, lds_block - 1024, &d->g_in_lds, &d->mws, &d->sort_p);
+    d->osd_lds = osd_block_bytes(code->m, code->n, lds_block - 1024, &d->osd_variant, &d->mws, &d->sort_p,
+                                 &d->osd_threads);
     if (d->osd_lds > lds_block - 1024) return cleanup_fail(LBP_EUNSUPPORTED, "lbp_decoder_create: OSD sort does not fit LDS");
-    d->osd_blocks = ncu;
+    int obpc = 0;
+    if (prm->osd && (osd_max_blocks_per_cu(d->osd_variant, d->osd_threads, d->osd_lds, &obpc) != hipSuccess || obpc < 1))
+        return cleanup_fail(LBP_EDEVICE, "lbp_decoder_create: no feasible OSD launch shape");
+    d->osd_blocks = ncu * std::max(1, obpc);
     hipError_t e;
 #define ALLOC(ptr, bytes)                                                                                     \
     do {                                                                                                      \
@@ -321,7 +325,7 @@ lbp_status lbp_decoder_create(lbp_code code, const lbp_params *prm, int64_t max_
         ALLOC(d->d_fail_list, (size_t)max_batch * 4);
         ALLOC(d->d_list2, (size_t)max_batch * 4);
         ALLOC(d->d_fail_llr, (size_t)d->fail_cap * code->n * 8);
-        if (!d->g_in_lds) ALLOC(d->d_gscratch, (size_t)d->osd_blocks * code->m * d->mws * 4);
+        ALLOC(d->d_gscratch, (size_t)d->osd_blocks * osd_scratch_bytes(d->osd_variant, code->m, d->mws));
     }
 #undef ALLOC
     e = hipHostMalloc((void **)&d->h_count, 64, hipHostMallocDefault);
@@ -396,11 +400,11 @@ static lbp_status run_pass(lbp_decoder d, int64_t n_work, const int32_t *work_li
         o.fail_cap = d->fail_cap;
         o.gscratch = d->d_gscratch;
         o.sort_p = d->sort_p;
-        o.g_in_lds = d->g_in_lds;
+        o.g_in_lds = d->osd_variant == 0;
         o.has_lo = d->prm.msg == LBP_MSG_FP32;
         hipEvent_t f0 = nullptr, f1 = nullptr;
         if (d->timing && (f0 = take_event(d)) && (f1 = take_event(d))) HIPCHK(hipEventRecord(f0, s));
-        HIPCHK(launch_osd(o, d->osd_blocks, d->osd_lds, s));
+        HIPCHK(launch_osd(o, d->osd_variant, d->osd_blocks, d->osd_threads, d->osd_lds, s));
         if (f1) {
             HIPCHK(hipEventRecord(f1, s));
             d->recs.push_back({f0, f1, 1});

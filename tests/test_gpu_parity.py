@@ -174,3 +174,17 @@ def test_full_size_sampled_bb144():
         assert o["flags"][0] == g["flags"][k] and o["iters"][0] == g["iters"][k]
         assert (o["corr"][0] == g["corr"][k]).all(), k
     _say("  failed-BP shots", int((g["flags"] & 2).sum()), "of 65536")
+
+
+@pytest.mark.parametrize("name", ["surface13_phen", "surface17_phen"])
+def test_osd_large_codes(name):
+    """Codes with m > 1024 run OSD with G in LDS (d=13, 1092 checks) or in global
+    memory (d=17, 2448 checks); few BP iterations force many shots into OSD."""
+    h, e, syn = batch(name, 0.01, 24, 1010)
+    for osd_mode in (1, 2):
+        prm = _params(msg=2, max_iter=3, lottery=False, osd=osd_mode, osd_order=6)
+        g = gpu_decode(h, 0.01, prm, syn)
+        o = oracle.decode(h, 0.01, oracle_params(prm), syn, n_threads=8)
+        assert (g["flags"] & 2).sum() >= 8
+        assert (g["flags"] == o["flags"]).all()
+        assert (g["corr"] == o["corr"]).all()
