@@ -87,6 +87,14 @@ int osd_block_bytes(int m, int n, int lds_limit, int *variant, int *mws, int *so
 size_t osd_scratch_bytes(int variant, int m, int mws);
 hipError_t osd_max_blocks_per_cu(int variant, int threads, int lds, int *out);
 
+// Int3.4 check-centric kernel (codes with <= 1024 checks): slots per lane
+// (0 = not applicable), block-shared table bytes, per-wave LDS bytes.
+int bp_int8_slots(int m);
+int bp_int8_table_bytes(int slots);
+int bp_int8_wave_bytes(int m, int n);
+hipError_t launch_bp_int8(int slots, const BpArgs &a, int blocks, int waves_per_block, hipStream_t s);
+hipError_t bp_int8_max_blocks_per_cu(int slots, int waves_per_block, int lds_bytes, int *out);
+
 hipError_t launch_reset(uint32_t *counters, int count, hipStream_t s);
 hipError_t launch_bp(int msg, const BpArgs &a, int blocks, int waves_per_block, hipStream_t s);
 hipError_t bp_max_blocks_per_cu(int msg, int waves_per_block, int lds_bytes, int *out);

@@ -374,6 +374,9 @@ __global__ __launch_bounds__(OSD_THREADS) void osd_lds_kernel(OsdArgs a) {
 template <int NW>
 using vrow = uint32_t __attribute__((ext_vector_type(NW)));
 
+static_assert(sizeof(vrow<28>) == 128 && sizeof(vrow<32>) == 128 && sizeof(vrow<16>) == 64 && sizeof(vrow<8>) == 32,
+              "osd_block_bytes assumes power-of-two vector sizes");
+
 template <int NW>
 __device__ __forceinline__ uint32_t row_bit(const vrow<NW> &g, int c) {
     return (g[c >> 5] >> (c & 31)) & 1u;  // c is wave-uniform
@@ -441,7 +444,8 @@ __global__ __launch_bounds__(1024) void osd_reg_kernel(OsdArgs a) {
     uint16_t *perm = (uint16_t *)q0;                 q0 += ((size_t)n * 2 + 15) & ~(size_t)15;
     uint16_t *tl = (uint16_t *)q0;                   q0 += ((size_t)n * 2 + 15) & ~(size_t)15;
     uint8_t *isb = q0;                               q0 += ((size_t)n + 15) & ~(size_t)15;
-    vrow<NW> *prow = (vrow<NW> *)q0;                 q0 += ((size_t)NW * 4 + 15) & ~(size_t)15;
+    vrow<NW> *crow = (vrow<NW> *)q0;                 q0 += (32 * sizeof(vrow<NW>) + 15) & ~(size_t)15;
+    uint32_t *csp = (uint32_t *)q0;                  q0 += 32 * 4;
     uint32_t *cw = (uint32_t *)q0;                   q0 += ((size_t)a.nw * 4 + 15) & ~(size_t)15;
     uint32_t *red = (uint32_t *)q0;                  q0 += 16 * 4;
     int *scr = (int *)q0;                            q0 += 32 * 4;
@@ -459,6 +463,10 @@ __global__ __launch_bounds__(1024) void osd_reg_kernel(OsdArgs a) {
         // ---- 1. sort (lambda, column) ascending
         sort_columns(lam, n, P, a.has_lo, (unsigned long long *)smem, lo_s, perm);
 
+        // sorted column tables, staged over the dead sort keys: ptab[j] = vn_tab[perm[j]]
+        uint64_t *ptab = (uint64_t *)smem;
+        for (int j = tid; j < n; j += nth) ptab[j] = a.vn_tab[perm[j]];
+
         // ---- 2. G = I (row tid), s' = s
         vrow<NW> g;
 #pragma unroll
@@ -471,31 +479,42 @@ __global__ __launch_bounds__(1024) void osd_reg_kernel(OsdArgs a) {
         if (tid < 3) red[tid] = 0xFFFFFFFFu;
         __syncthreads();
 
-        // ---- 3. Gauss-Jordan in sorted column order
-        int rank = 0, step = 0;
+        // ---- 3. Gauss-Jordan in sorted column order, one block barrier per column:
+        // each wave publishes its first candidate row before the barrier, so the
+        // winner's row is already in LDS when the pivot is known.
+        int rank = 0;
+        int slot = 0, nslot = 1, buf = 0;  // reduction slot rotates over 3, row buffers over 2
+        uint64_t tab = n > 0 ? ptab[0] : ~0ull;
         for (int j = 0; j < n && rank < m; ++j) {
-            const int col = perm[j];
-            const uint64_t tab = uniform_tab(a.vn_tab, col);
-            const uint32_t x = reduced_bit<NW>(g, tab);
-            const int slot = step % 3;
-            if (tid == 0) red[(step + 1) % 3] = 0xFFFFFFFFu;
+            const uint64_t tu = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(tab >> 32)) << 32) |
+                                __builtin_amdgcn_readfirstlane((uint32_t)tab);
+            if (j + 1 < n) tab = ptab[j + 1];  // prefetch the next column's rows
+            const uint32_t x = reduced_bit<NW>(g, tu);
             const uint64_t bal = __ballot(valid && x && !piv);
-            if (lane == 0 && bal) atomicMin(&red[slot], (uint32_t)(wid * 64 + __ffsll((unsigned long long)bal) - 1));
+            if (tid == 0) red[nslot] = 0xFFFFFFFFu;
+            if (bal) {
+                const int first = __ffsll((unsigned long long)bal) - 1;
+                if (lane == first) {
+                    crow[buf * 16 + wid] = g;
+                    csp[buf * 16 + wid] = sp;
+                }
+                if (lane == 0) atomicMin(&red[slot], (uint32_t)(wid * 64 + first));
+            }
             __syncthreads();
             const int pv = (int)red[slot];
-            ++step;
+            const int pb = buf;
+            slot = nslot;
+            nslot = nslot == 2 ? 0 : nslot + 1;
+            buf ^= 1;
             if (pv == (int)0xFFFFFFFFu) continue;
             if (tid == pv) {
-                *prow = g;
-                red[3] = sp;
                 piv = true;
-                pcol = col;
+                pcol = perm[j];
             }
             if (tid == 0) isb[j] = 1;
-            __syncthreads();
             if (x && tid != pv) {
-                g ^= *prow;
-                sp ^= red[3];
+                g ^= crow[pb * 16 + (pv >> 6)];
+                sp ^= csp[pb * 16 + (pv >> 6)];
             }
             ++rank;
         }
@@ -585,7 +604,9 @@ int osd_block_bytes(int m, int n, int lds_limit, int *variant, int *mws, int *so
         *variant = nw;
         *mws = mw;
         *threads = 64 * ((m + 63) / 64);
-        return (int)(al((size_t)P * 8) + common + al((size_t)nw * 4) + 16 * 8);
+        size_t vb = 4;  // a vector of nw words occupies the next power of two bytes
+        while (vb < (size_t)nw * 4) vb <<= 1;
+        return (int)(al((size_t)P * 8) + common + al(32 * vb) + 32 * 4 + 16 * 8);
     }
     *threads = OSD_THREADS;
     size_t rest = common + al((size_t)m * 2) + al((size_t)m) * 2;

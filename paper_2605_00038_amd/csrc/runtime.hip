@@ -64,7 +64,7 @@ struct lbp_decoder_s {
     lbp_params prm{};
     int64_t max_batch = 0;
     BpParams bp{};
-    int wpb = 1, bp_blocks = 1, wave_bytes = 0;
+    int wpb = 1, bp_blocks = 1, wave_bytes = 0, int8_slots = 0, table_bytes = 0;
     int osd_blocks = 0, osd_lds = 0, osd_variant = 0, osd_threads = 1024, mws = 1, sort_p = 1;
     int64_t fail_cap = 0;
     uint32_t *d_counters = nullptr;
@@ -286,14 +286,19 @@ lbp_status lbp_decoder_create(lbp_code code, const lbp_params *prm, int64_t max_
         hipDeviceGetAttribute(&lds_block, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
         return cleanup_fail(LBP_EDEVICE, "lbp_decoder_create: device query failed");
     // ---- BP launch shape: the waves-per-block choice with the most resident waves per CU
-    d->wave_bytes = bp_wave_bytes(prm->msg, code->m, code->n);
-    if (d->wave_bytes > lds_block) return cleanup_fail(LBP_EUNSUPPORTED, "lbp_decoder_create: per-shot state exceeds LDS");
+    d->int8_slots = prm->msg == LBP_MSG_INT8 ? bp_int8_slots(code->m) : 0;
+    d->wave_bytes = d->int8_slots ? bp_int8_wave_bytes(code->m, code->n) : bp_wave_bytes(prm->msg, code->m, code->n);
+    d->table_bytes = d->int8_slots ? bp_int8_table_bytes(d->int8_slots) : 0;
+    if (d->table_bytes + d->wave_bytes > lds_block)
+        return cleanup_fail(LBP_EUNSUPPORTED, "lbp_decoder_create: per-shot state exceeds LDS");
     int best_waves = 0;
-    for (int wpb : {16, 8, 4, 2, 1}) {
-        int lds = d->wave_bytes * wpb;
+    for (int wpb : {16, 12, 8, 4, 2, 1}) {
+        int lds = d->table_bytes + d->wave_bytes * wpb;
         if (lds > lds_block) continue;
         int bpc = 0;
-        if (bp_max_blocks_per_cu(prm->msg, wpb, lds, &bpc) != hipSuccess) continue;
+        hipError_t oe = d->int8_slots ? bp_int8_max_blocks_per_cu(d->int8_slots, wpb, lds, &bpc)
+                                      : bp_max_blocks_per_cu(prm->msg, wpb, lds, &bpc);
+        if (oe != hipSuccess) continue;
         if (bpc * wpb > best_waves) {
             best_waves = bpc * wpb;
             d->wpb = wpb;
@@ -376,7 +381,8 @@ static lbp_status run_pass(lbp_decoder d, int64_t n_work, const int32_t *work_li
     int blocks = (int)std::min<int64_t>(d->bp_blocks, std::max<int64_t>(1, need_blocks));
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (d->timing && (e0 = take_event(d)) && (e1 = take_event(d))) HIPCHK(hipEventRecord(e0, s));
-    HIPCHK(launch_bp(d->prm.msg, a, blocks, d->wpb, s));
+    HIPCHK(d->int8_slots ? launch_bp_int8(d->int8_slots, a, blocks, d->wpb, s)
+                         : launch_bp(d->prm.msg, a, blocks, d->wpb, s));
     if (e1) {
         HIPCHK(hipEventRecord(e1, s));
         d->recs.push_back({e0, e1, 0});
