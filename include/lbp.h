@@ -32,13 +32,14 @@ typedef enum {
     LBP_EINVAL = -1,        /* malformed argument (bad CSR, prior outside (0,1), size, NULL) */
     LBP_ENOMEM = -2,        /* device or host allocation failed */
     LBP_EDEVICE = -3,       /* HIP runtime error (message says which call) */
-    LBP_EBUSY = -4,         /* admission refused (reserved for serving) */
-    LBP_ENOTREADY = -5,     /* result not available yet (reserved for serving) */
+    LBP_EBUSY = -4,         /* serving: admission refused, or no free slot */
+    LBP_ENOTREADY = -5,     /* serving: result not available yet */
     LBP_EUNSUPPORTED = -6   /* valid input outside what the kernels handle (see lbp_code_create) */
 } lbp_status;
 
 typedef struct lbp_code_s *lbp_code;       /* immutable Tanner graph + priors (device copy) */
 typedef struct lbp_decoder_s *lbp_decoder; /* parameters + device workspace for up to max_batch shots */
+typedef struct lbp_server_s *lbp_server;   /* continuous-batching serving loop (one device) */
 
 /* Message storage format.  INT8 is the paper's Int3.4 fixed point (Sec. VII-A):
  * signed 8-bit, LSB = 1/16, saturated symmetrically to +-127; column LLRs are
@@ -125,10 +126,22 @@ void lbp_decoder_destroy(lbp_decoder dec);
 lbp_status lbp_decode(lbp_decoder dec, int64_t n_shots, uint64_t first_shot_id, const uint32_t *syndromes,
                       uint32_t *corrections, uint8_t *flags, int32_t *iters, float *llr_out, void *stream);
 
-/* Same contract with HOST pointers; synchronous.  Allocates and frees device
- * staging buffers internally. */
+/* lbp_decode with a lottery key per shot instead of (params seed, first_shot_id + k):
+ * shot_keys [n_shots][2] (DEVICE) holds (seed, shot_id) of each shot, as
+ * Algorithm 3's random draw for shot k at iteration i uses Philox4x64-10 with
+ * key (seed, 0) and counter (shot_id, i, 0, 0).  Used to pack shots of
+ * different requests into one launch without changing any result. */
+lbp_status lbp_decode_keyed(lbp_decoder dec, int64_t n_shots, const uint64_t *shot_keys, const uint32_t *syndromes,
+                            uint32_t *corrections, uint8_t *flags, int32_t *iters, float *llr_out, void *stream);
+
+/* Same contract as lbp_decode with HOST pointers; synchronous.  Allocates and
+ * frees device staging buffers internally. */
 lbp_status lbp_decode_host(lbp_decoder dec, int64_t n_shots, uint64_t first_shot_id, const uint32_t *syndromes,
                            uint32_t *corrections, uint8_t *flags, int32_t *iters, float *llr_out);
+
+/* Device bytes held by the decoder's workspace, and its max_batch. */
+int64_t lbp_decoder_device_bytes(lbp_decoder dec);
+int64_t lbp_decoder_max_batch(lbp_decoder dec);
 
 /* Number of failed shots whose lambda one OSD pass can stage; failures beyond
  * it are re-decoded (BP is deterministic) and handled in further passes. */
@@ -144,6 +157,68 @@ lbp_status lbp_decoder_set_osd_capacity(lbp_decoder dec, int64_t cap);
 lbp_status lbp_decoder_set_timing(lbp_decoder dec, int32_t enable);
 lbp_status lbp_decoder_kernel_times(lbp_decoder dec, double *bp_ms, int64_t *bp_launches, double *osd_ms,
                                     int64_t *osd_launches);
+
+/* ---- Serving (real-time decoding of a stream of requests, Sec. I and VI-B:
+ * the decoder must keep up with syndromes as they arrive, and its tail
+ * latency matters).  A server owns one worker thread on the device current
+ * at creation, its queues and all device buffers; the caller owns its host
+ * arrays.  lbp_server_* calls are thread-safe.
+ *
+ * Continuous batching: every code slot has 3 batch buffers (stream + decoder
+ * workspace + pinned staging).  Whenever one is free, the worker packs the
+ * slot's queued shots into it, first come first served, splitting a request
+ * across batches when it is larger than a batch, and launches it.  A request
+ * is complete once all of its shots are back.  Each shot is decoded with the
+ * key (seed, first_shot_id + j) of its request, so results are identical to a
+ * lone lbp_decode of the request with that seed, whatever else shares the
+ * batch. */
+
+/* device_mem_budget_bytes: cap on the device memory all slots may hold (0 =
+ * 4 GiB); max_slots: number of codes (1..64). */
+lbp_status lbp_server_create(int64_t device_mem_budget_bytes, int32_t max_slots, lbp_server *out);
+/* Register a code with its decoding parameters (params.seed is ignored: each
+ * request brings its own).  Picks the largest batch size (power of two <=
+ * 8192) whose three buffers fit the remaining budget: LBP_ENOMEM if none does,
+ * LBP_EBUSY if all slots are taken.  The code must outlive the server. */
+lbp_status lbp_server_add_code(lbp_server srv, lbp_code code, const lbp_params *prm, int32_t *code_slot);
+/* Queue n_shots >= 1 syndromes (HOST, [n_shots][ceil(m/32)], copied before
+ * return).  Admission: LBP_EBUSY when the slot already holds 64 batches'
+ * worth of queued shots.  *ticket identifies the request. */
+lbp_status lbp_server_submit(lbp_server srv, int32_t code_slot, int64_t n_shots, uint64_t seed,
+                             uint64_t first_shot_id, const uint32_t *host_syndromes, uint64_t *ticket);
+/* LBP_ENOTREADY while the request is pending.  Once complete, copies the
+ * results into the HOST arrays (corrections [n_shots][ceil(n/32)], flags
+ * [n_shots], iters [n_shots]; any may be NULL), releases the ticket and
+ * returns LBP_OK (or the error that stopped the request).  Unknown or
+ * released ticket: LBP_EINVAL. */
+lbp_status lbp_server_poll(lbp_server srv, uint64_t ticket, uint32_t *corrections, uint8_t *flags, int32_t *iters);
+/* lbp_server_poll that blocks up to timeout_us microseconds (< 0: no limit). */
+lbp_status lbp_server_wait(lbp_server srv, uint64_t ticket, int64_t timeout_us, uint32_t *corrections,
+                           uint8_t *flags, int32_t *iters);
+/* Drop a request: its queued shots are never launched, results of shots
+ * already in flight are discarded, and the ticket is released. */
+lbp_status lbp_server_cancel(lbp_server srv, uint64_t ticket);
+/* Slot statistics: batch size, batches and shots launched, largest batch,
+ * shots queued now.  Any output may be NULL. */
+lbp_status lbp_server_slot_info(lbp_server srv, int32_t code_slot, int64_t *tick_shots, int64_t *batches,
+                                int64_t *shots, int64_t *max_fill, int64_t *queued_shots);
+/* Benchmarking aid: drive the server with an open-loop stream of n_requests
+ * requests of shots_per_request syndromes each.  Request q goes to
+ * code_slots[k], k uniform in [0, n_codes) (request_code[q] = k, may be
+ * NULL), and takes the next shots_per_request rows of host_syndromes[k]
+ * ([pool[k]][ceil(m_k/32)], HOST, cycled), with lottery key (seed,
+ * q * shots_per_request + j).  Arrivals form a Poisson process of rate
+ * requests_per_s (0: submit back to back, retrying while admission refuses:
+ * the saturation load).  latency_us[q] = time from request q's scheduled
+ * arrival to the moment its result is visible to lbp_server_poll;
+ * *elapsed_s (may be NULL) = first arrival to last completion.  Returns when
+ * every request has completed. */
+lbp_status lbp_server_run_load(lbp_server srv, int32_t n_codes, const int32_t *code_slots,
+                               const uint32_t *const *host_syndromes, const int64_t *pool, int64_t n_requests,
+                               int64_t shots_per_request, double requests_per_s, uint64_t seed,
+                               int32_t *request_code, double *latency_us, double *elapsed_s);
+/* Stop the worker (pending requests are dropped) and free everything. */
+void lbp_server_destroy(lbp_server srv);
 
 /* Thread-local description of the last error (empty string if none). */
 const char *lbp_last_error(void);

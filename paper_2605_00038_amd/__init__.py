@@ -8,5 +8,6 @@ from ._lib import (  # noqa: F401
     OSD_NONE, OSD_0, OSD_CS, FLAG_CONVERGED, FLAG_OSD, FLAG_OSD_INCONSISTENT,
 )
 from .decoder import Code, Decoder, DecoderParams  # noqa: F401
+from .server import Server  # noqa: F401
 
 __version__ = "0.1.0"

@@ -61,6 +61,19 @@ SIGNATURES = {
     "lbp_decoder_set_timing": (_I32, [_VP, _I32]),
     "lbp_decoder_kernel_times": (_I32, [_VP, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I64),
                                         ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I64)]),
+    "lbp_decode_keyed": (_I32, [_VP, _I64, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
+    "lbp_decoder_device_bytes": (_I64, [_VP]),
+    "lbp_decoder_max_batch": (_I64, [_VP]),
+    "lbp_server_create": (_I32, [_I64, _I32, ctypes.POINTER(_VP)]),
+    "lbp_server_add_code": (_I32, [_VP, _VP, ctypes.POINTER(Params), ctypes.POINTER(_I32)]),
+    "lbp_server_submit": (_I32, [_VP, _I32, _I64, _U64, _U64, _VP, ctypes.POINTER(_U64)]),
+    "lbp_server_poll": (_I32, [_VP, _U64, _VP, _VP, _VP]),
+    "lbp_server_wait": (_I32, [_VP, _U64, _I64, _VP, _VP, _VP]),
+    "lbp_server_cancel": (_I32, [_VP, _U64]),
+    "lbp_server_slot_info": (_I32, [_VP, _I32] + [ctypes.POINTER(_I64)] * 5),
+    "lbp_server_run_load": (_I32, [_VP, _I32, _VP, _VP, _VP, _I64, _I64, ctypes.c_double, _U64, _VP, _VP,
+                                   ctypes.POINTER(ctypes.c_double)]),
+    "lbp_server_destroy": (None, [_VP]),
     "lbp_last_error": (ctypes.c_char_p, []),
     "lbp_version": (_I32, []),
 }

@@ -82,7 +82,7 @@ __device__ __forceinline__ int scale_q(const BpParams &P, int i, int mag) {
 }
 
 // Lottery selection (Algorithm 3), U from the previous syndrome estimate SHp.
-__device__ int lottery_pick_q(const DevCode &C, const BpParams &P, uint64_t shot_id, int i, const uint16_t *L,
+__device__ int lottery_pick_q(const DevCode &C, uint64_t seed, uint64_t shot_id, int i, const uint16_t *L,
                               const uint32_t *S, const uint32_t *SHp, int lane) {
     int N = 0;
     for (int w0 = 0; w0 < C.mw; w0 += 64) {
@@ -90,7 +90,7 @@ __device__ int lottery_pick_q(const DevCode &C, const BpParams &P, uint64_t shot
         N += wave_sum(__popc(w < C.mw ? (SHp[w] ^ S[w]) : 0u));
     }
     if (N == 0) return -1;
-    const uint64_t x = philox_w0(P.seed, shot_id, (uint64_t)i);
+    const uint64_t x = philox_w0(seed, shot_id, (uint64_t)i);
     uint32_t k = (uint32_t)(((x >> 32) * (uint64_t)N) >> 32);
     int cstar = 0;
     for (int w0 = 0; w0 < C.mw; w0 += 64) {
@@ -179,7 +179,8 @@ __global__ __launch_bounds__(1024) void bp_int8_kernel(BpArgs a) {
         item = __builtin_amdgcn_readfirstlane(item);
         if ((int64_t)item >= a.n_work) break;
         const int64_t shot = a.work_list ? (int64_t)a.work_list[item] : (int64_t)item;
-        const uint64_t shot_id = a.first_shot_id + (uint64_t)shot;
+        const uint64_t seed = a.shot_keys ? a.shot_keys[2 * shot] : P.seed;
+        const uint64_t shot_id = a.shot_keys ? a.shot_keys[2 * shot + 1] : a.first_shot_id + (uint64_t)shot;
         float *llr_row = a.llr_out ? a.llr_out + shot * n : nullptr;
 
         for (int w = lane; w < C.mw; w += 64) {
@@ -303,7 +304,7 @@ __global__ __launch_bounds__(1024) void bp_int8_kernel(BpArgs a) {
             }
             fv = -1;
             if (P.lottery && i >= P.skip && i <= P.max_iter - 2)
-                fv = lottery_pick_q(C, P, shot_id, i, Ln16, S, SHp, lane);
+                fv = lottery_pick_q(C, seed, shot_id, i, Ln16, S, SHp, lane);
             uint32_t *t = Lc;
             Lc = Ln;
             Ln = t;

@@ -289,7 +289,7 @@ __device__ void cn_half(const DevCode &C, const BpParams &P, int i, typename Fmt
 // SHp; lambda^(i) of the candidates is rebuilt from the C2V messages of
 // iteration i still held in E, with the same arithmetic as the VN half.
 template <int MSG>
-__device__ int lottery_select(const DevCode &C, const BpParams &P, uint64_t shot_id, int i,
+__device__ int lottery_select(const DevCode &C, const BpParams &P, uint64_t seed, uint64_t shot_id, int i,
                               const typename Fmt<MSG>::T *E, const uint32_t *S, const uint32_t *SHp, int lane) {
     using F = Fmt<MSG>;
     int N = 0;
@@ -299,7 +299,7 @@ __device__ int lottery_select(const DevCode &C, const BpParams &P, uint64_t shot
         N += wave_sum(__popc(u));
     }
     if (N == 0) return -1;
-    const uint64_t x = philox_word0(P.seed, shot_id, (uint64_t)i);
+    const uint64_t x = philox_word0(seed, shot_id, (uint64_t)i);
     uint32_t k = (uint32_t)(((x >> 32) * (uint64_t)N) >> 32);  // floor(r * N)
     int cstar = -1;
     for (int w0 = 0; w0 < C.mw; w0 += 64) {
@@ -466,10 +466,11 @@ __global__ __launch_bounds__(1024) void bp_kernel(BpArgs a) {
     for (;;) {
         uint32_t item = 0;
         if (lane == 0) item = atomicAdd(&a.counters[0], 1u);
-        item = __shfl(item, 0, 64);
+        item = __builtin_amdgcn_readfirstlane(item);
         if ((int64_t)item >= a.n_work) break;
         const int64_t shot = a.work_list ? (int64_t)a.work_list[item] : (int64_t)item;
-        const uint64_t shot_id = a.first_shot_id + (uint64_t)shot;
+        const uint64_t seed = a.shot_keys ? a.shot_keys[2 * shot] : P.seed;
+        const uint64_t shot_id = a.shot_keys ? a.shot_keys[2 * shot + 1] : a.first_shot_id + (uint64_t)shot;
         float *llr_row = a.llr_out ? a.llr_out + shot * C.n : nullptr;
 
         // padding bits of the last word are ignored (they could otherwise name checks >= m)
@@ -504,7 +505,7 @@ __global__ __launch_bounds__(1024) void bp_kernel(BpArgs a) {
             cn_half<MSG>(C, P, i, E, S, lane);
             wave_sync();
             int fv = -1;
-            if (P.lottery && i >= P.skip && i <= P.max_iter - 2) fv = lottery_select<MSG>(C, P, shot_id, i, E, S, SHp, lane);
+            if (P.lottery && i >= P.skip && i <= P.max_iter - 2) fv = lottery_select<MSG>(C, P, seed, shot_id, i, E, S, SHp, lane);
             for (int w = lane; w < C.mw; w += 64) SHc[w] = 0u;
             wave_sync();
             const bool last = i == P.max_iter - 1;
@@ -528,7 +529,7 @@ __global__ __launch_bounds__(1024) void bp_kernel(BpArgs a) {
         if (!converged && P.osd != OSD_NONE) {
             uint32_t q = 0;
             if (lane == 0) q = atomicAdd(&a.counters[1], 1u);
-            q = __shfl(q, 0, 64);
+            q = __builtin_amdgcn_readfirstlane(q);
             if (lane == 0) a.fail_list[q] = (int32_t)shot;
             if ((int64_t)q < a.fail_cap) {
                 float *dst = a.fail_llr + (size_t)q * 2 * C.n;

@@ -46,6 +46,7 @@ struct BpArgs {
     BpParams prm;
     int64_t n_work;             // work items in this launch
     uint64_t first_shot_id;
+    const uint64_t *shot_keys;  // nullable: [shots][2] = (lottery seed, shot_id) per shot
     const int32_t *work_list;   // nullable: work item -> shot index
     const uint32_t *synd;       // [shots][mw]
     uint32_t *corr;             // [shots][nw]
@@ -76,6 +77,9 @@ struct OsdArgs {
     int32_t g_in_lds;
     int32_t has_lo;             // lambda carries a non-zero low part (fp32 messages)
 };
+
+// Set the thread-local message returned by lbp_last_error.
+void set_error(const char *msg);
 
 // LDS bytes the BP kernel needs per wave for a code.
 int bp_wave_bytes(int msg, int m, int n);

@@ -52,6 +52,8 @@ float to_fp16_value(double x) {
 
 }  // namespace
 
+void lbp::set_error(const char *msg) { g_err = msg ? msg : ""; }
+
 struct lbp_code_s {
     int m = 0, n = 0, nnz = 0, device = 0;
     bool uniform = true;
@@ -67,6 +69,7 @@ struct lbp_decoder_s {
     int wpb = 1, bp_blocks = 1, wave_bytes = 0, int8_slots = 0, table_bytes = 0;
     int osd_blocks = 0, osd_lds = 0, osd_variant = 0, osd_threads = 1024, mws = 1, sort_p = 1;
     int64_t fail_cap = 0;
+    int64_t dev_bytes = 0;  // device workspace held by the decoder
     uint32_t *d_counters = nullptr;
     int32_t *d_fail_list = nullptr;
     int32_t *d_list2 = nullptr;
@@ -320,6 +323,7 @@ lbp_status lbp_decoder_create(lbp_code code, const lbp_params *prm, int64_t max_
     hipError_t e;
 #define ALLOC(ptr, bytes)                                                                                     \
     do {                                                                                                      \
+        d->dev_bytes += (int64_t)align256((bytes) > 0 ? (bytes) : 16);                                          \
         e = hipMalloc((void **)&(ptr), (bytes) > 0 ? (bytes) : 16);                                            \
         if (e != hipSuccess) return cleanup_fail(LBP_ENOMEM, std::string("lbp_decoder_create: hipMalloc: ") + \
                                                                  hipGetErrorString(e));                        \
@@ -356,8 +360,8 @@ lbp_status lbp_decoder_set_osd_capacity(lbp_decoder d, int64_t cap) {
 }
 
 static lbp_status run_pass(lbp_decoder d, int64_t n_work, const int32_t *work_list, uint64_t first_shot_id,
-                           const uint32_t *syn, uint32_t *corr, uint8_t *flags, int32_t *iters, float *llr,
-                           hipStream_t s) {
+                           const uint64_t *keys, const uint32_t *syn, uint32_t *corr, uint8_t *flags, int32_t *iters,
+                           float *llr, hipStream_t s) {
     lbp_code C = d->code;
     HIPCHK(launch_reset(d->d_counters, 16, s));
     BpArgs a{};
@@ -365,6 +369,7 @@ static lbp_status run_pass(lbp_decoder d, int64_t n_work, const int32_t *work_li
     a.prm = d->bp;
     a.n_work = n_work;
     a.first_shot_id = first_shot_id;
+    a.shot_keys = keys;
     a.work_list = work_list;
     a.synd = syn;
     a.corr = corr;
@@ -448,16 +453,17 @@ lbp_status lbp_decoder_kernel_times(lbp_decoder d, double *bp_ms, int64_t *bp_la
     return LBP_OK;
 }
 
-lbp_status lbp_decode(lbp_decoder d, int64_t n_shots, uint64_t first_shot_id, const uint32_t *syndromes,
-                      uint32_t *corrections, uint8_t *flags, int32_t *iters, float *llr_out, void *stream) {
+static lbp_status decode_impl(const char *who, lbp_decoder d, int64_t n_shots, uint64_t first_shot_id,
+                              const uint64_t *keys, const uint32_t *syndromes, uint32_t *corrections, uint8_t *flags,
+                              int32_t *iters, float *llr_out, void *stream) {
     g_err.clear();
-    if (!d) return fail(LBP_EINVAL, "lbp_decode: NULL decoder");
-    if (n_shots < 0 || n_shots > d->max_batch) return fail(LBP_EINVAL, "lbp_decode: 0 <= n_shots <= max_batch");
+    if (!d) return fail(LBP_EINVAL, std::string(who) + ": NULL decoder");
+    if (n_shots < 0 || n_shots > d->max_batch) return fail(LBP_EINVAL, std::string(who) + ": 0 <= n_shots <= max_batch");
     if (n_shots == 0) return LBP_OK;
-    if (!syndromes || !corrections || !flags) return fail(LBP_EINVAL, "lbp_decode: NULL buffer");
+    if (!syndromes || !corrections || !flags) return fail(LBP_EINVAL, std::string(who) + ": NULL buffer");
     DeviceGuard g(d->code->device);
     hipStream_t s = (hipStream_t)stream;
-    lbp_status st = run_pass(d, n_shots, nullptr, first_shot_id, syndromes, corrections, flags, iters, llr_out, s);
+    lbp_status st = run_pass(d, n_shots, nullptr, first_shot_id, keys, syndromes, corrections, flags, iters, llr_out, s);
     if (st != LBP_OK || !d->prm.osd || n_shots <= d->fail_cap) return st;
     // More shots may have failed BP than one OSD pass can stage: re-decode the
     // overflow (BP is deterministic per shot) and run OSD on it, until done.
@@ -468,10 +474,26 @@ lbp_status lbp_decode(lbp_decoder d, int64_t n_shots, uint64_t first_shot_id, co
         if (total <= d->fail_cap) return LBP_OK;
         int64_t rest = total - d->fail_cap;
         HIPCHK(launch_gather_list(d->d_counters, d->d_fail_list, d->fail_cap, d->d_list2, rest, s));
-        st = run_pass(d, rest, d->d_list2, first_shot_id, syndromes, corrections, flags, iters, llr_out, s);
+        st = run_pass(d, rest, d->d_list2, first_shot_id, keys, syndromes, corrections, flags, iters, llr_out, s);
         if (st != LBP_OK) return st;
     }
 }
+
+lbp_status lbp_decode(lbp_decoder d, int64_t n_shots, uint64_t first_shot_id, const uint32_t *syndromes,
+                      uint32_t *corrections, uint8_t *flags, int32_t *iters, float *llr_out, void *stream) {
+    return decode_impl("lbp_decode", d, n_shots, first_shot_id, nullptr, syndromes, corrections, flags, iters, llr_out,
+                       stream);
+}
+
+lbp_status lbp_decode_keyed(lbp_decoder d, int64_t n_shots, const uint64_t *shot_keys, const uint32_t *syndromes,
+                            uint32_t *corrections, uint8_t *flags, int32_t *iters, float *llr_out, void *stream) {
+    if (n_shots > 0 && !shot_keys) return fail(LBP_EINVAL, "lbp_decode_keyed: NULL shot_keys");
+    return decode_impl("lbp_decode_keyed", d, n_shots, 0, shot_keys, syndromes, corrections, flags, iters, llr_out,
+                       stream);
+}
+
+int64_t lbp_decoder_device_bytes(lbp_decoder d) { return d ? d->dev_bytes : 0; }
+int64_t lbp_decoder_max_batch(lbp_decoder d) { return d ? d->max_batch : 0; }
 
 lbp_status lbp_decode_host(lbp_decoder d, int64_t n_shots, uint64_t first_shot_id, const uint32_t *syndromes,
                            uint32_t *corrections, uint8_t *flags, int32_t *iters, float *llr_out) {

@@ -119,6 +119,30 @@ class Decoder:
                                 llr.data_ptr() if llr is not None else None, s.cuda_stream))
         return corr, flags, iters, llr
 
+    def decode_keyed(self, syndromes, shot_keys, out=None, stream=None):
+        """lbp_decode_keyed: shot_keys is a CUDA int64/uint64 tensor [shots, 2] of (seed, shot_id)."""
+        import torch
+        assert syndromes.is_cuda and syndromes.dim() == 2 and syndromes.shape[1] == self.mw
+        assert syndromes.is_contiguous() and shot_keys.is_contiguous() and shot_keys.is_cuda
+        assert shot_keys.shape == (syndromes.shape[0], 2) and shot_keys.element_size() == 8
+        shots = syndromes.shape[0]
+        dev = syndromes.device
+        if out is None:
+            corr = torch.empty((shots, self.nw), dtype=torch.int32, device=dev)
+            flags = torch.empty(shots, dtype=torch.uint8, device=dev)
+            iters = torch.empty(shots, dtype=torch.int32, device=dev)
+        else:
+            corr, flags, iters = out
+        s = stream if stream is not None else torch.cuda.current_stream(dev)
+        check(load().lbp_decode_keyed(self._h, shots, shot_keys.data_ptr(), syndromes.data_ptr(), corr.data_ptr(),
+                                      flags.data_ptr(), iters.data_ptr() if iters is not None else None, None,
+                                      s.cuda_stream))
+        return corr, flags, iters
+
+    @property
+    def device_bytes(self) -> int:
+        return int(load().lbp_decoder_device_bytes(self._h))
+
     def decode_host(self, syndromes: np.ndarray, first_shot_id: int = 0, want_llr: bool = False):
         """Synchronous decode of host arrays (numpy uint32 [shots, ceil(m/32)])."""
         syn = np.ascontiguousarray(syndromes, dtype=np.uint32)

@@ -78,3 +78,27 @@ def test_null_handles_are_rejected():
     assert lib.lbp_decoder_set_osd_capacity(None, 5) == L.LBP_EINVAL
     assert lib.lbp_decoder_osd_capacity(None) == 0
     assert "NULL" in lib.lbp_last_error().decode()
+
+
+def test_server_and_keyed_calls_reject_bad_arguments_before_device_use():
+    L, lib = _lib()
+    h = ctypes.c_void_p()
+    assert lib.lbp_server_create(0, 0, ctypes.byref(h)) == L.LBP_EINVAL      # max_slots < 1
+    assert lib.lbp_server_create(0, 65, ctypes.byref(h)) == L.LBP_EINVAL     # max_slots > 64
+    assert lib.lbp_server_create(-1, 4, ctypes.byref(h)) == L.LBP_EINVAL     # negative budget
+    assert lib.lbp_server_create(0, 4, None) == L.LBP_EINVAL
+    slot = ctypes.c_int32()
+    t = ctypes.c_uint64()
+    p = L.Params()
+    lib.lbp_params_default(ctypes.byref(p))
+    assert lib.lbp_server_add_code(None, None, ctypes.byref(p), ctypes.byref(slot)) == L.LBP_EINVAL
+    assert lib.lbp_server_submit(None, 0, 1, 0, 0, None, ctypes.byref(t)) == L.LBP_EINVAL
+    assert lib.lbp_server_poll(None, 1, None, None, None) == L.LBP_EINVAL
+    assert lib.lbp_server_wait(None, 1, 0, None, None, None) == L.LBP_EINVAL
+    assert lib.lbp_server_cancel(None, 1) == L.LBP_EINVAL
+    assert lib.lbp_server_slot_info(None, 0, None, None, None, None, None) == L.LBP_EINVAL
+    assert lib.lbp_server_run_load(None, 1, None, None, None, 1, 1, 0.0, 0, None, None, None) == L.LBP_EINVAL
+    lib.lbp_server_destroy(None)
+    assert lib.lbp_decode_keyed(None, 1, None, None, None, None, None, None, None) == L.LBP_EINVAL
+    assert lib.lbp_decoder_device_bytes(None) == 0
+    assert lib.lbp_decoder_max_batch(None) == 0
