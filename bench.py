@@ -111,6 +111,26 @@ def latency(torch, dec, syn_dev, requests: int):
     return lat * 1e6
 
 
+def baseline_row(torch, h, syn_dev, shots: int, warmup: int):
+    """The plain global-memory FP32 path (lbp_decode_baseline) on the first `shots` syndromes."""
+    from paper_2605_00038_amd import Code, Decoder, DecoderParams
+    prm = DecoderParams(max_iter=MAX_ITER, msg=0, lottery=True, lottery_skip=6, osd=2, osd_order=OSD_ORDER,
+                        seed=LOTTERY_SEED)
+    dec = Decoder(Code.from_scipy(h, P_ERR), prm, shots)
+    s = syn_dev[:shots]
+    for _ in range(max(1, warmup)):
+        dec.decode_baseline(s)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    corr, flags, iters = dec.decode_baseline(s)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    out = dict(corr=corr.cpu().numpy().view(np.uint32), flags=flags.cpu().numpy(), iters=iters.cpu().numpy())
+    del dec
+    torch.cuda.empty_cache()
+    return dt, out
+
+
 def serving(h, syn, n_requests: int, shots_per_request: int = 1):
     """Serving loop (continuous batching) under single-syndrome requests: the
     saturation rate (requests submitted back to back), then Poisson arrivals at
@@ -189,6 +209,8 @@ def main():
     ap.add_argument("--msg", default="int8", choices=list(MSG_CODES))
     ap.add_argument("--formats", default="int8,fp16,fp32", help="formats timed besides --msg (LER comparison)")
     ap.add_argument("--latency-requests", type=int, default=3000)
+    ap.add_argument("--baseline-shots", type=int, default=262_144,
+                    help="shots for the plain global-memory FP32 comparison row (0 = skip)")
     ap.add_argument("--serve-requests", type=int, default=200_000,
                     help="single-syndrome requests per serving-loop run (0 = skip)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -256,6 +278,20 @@ def main():
             del dec
         torch.cuda.empty_cache()
 
+    base = None
+    if args.baseline_shots > 0:
+        B = min(args.baseline_shots, args.shots)
+        dt, r = baseline_row(torch, h, syn_dev, B, args.warmup)
+        base = dict(kind="plain FP32 path: messages in global memory, one thread per check/column, "
+                         "a launch per half-iteration (lbp_decode_baseline)",
+                    shots=B, seconds=dt, syndromes_per_s=B / dt, mean_iters=float(r["iters"].mean()),
+                    osd_invoke_rate=float(((r["flags"] & 2) != 0).mean()))
+        if not args.no_ler:
+            sf, lf = failures_packed(checker, err_p[:B], r["corr"], n)
+            k = int((sf | lf).sum())
+            base.update(ler=k / B, ler_ci95=list(wilson(k, B)))
+        base["speedup_of_headline"] = head["syndromes_per_s"] / base["syndromes_per_s"]
+        log("baseline", json.dumps(base))
     lat = latency(torch, head_dec, syn_dev, args.latency_requests) if args.latency_requests > 0 else None
     del head_dec
     torch.cuda.empty_cache()
@@ -304,6 +340,7 @@ def main():
                      "edge_updates_per_s": head["edge_updates_per_step"] / bp_s,
                      "ops_per_edge_update": ALG_OPS_PER_EDGE},
         "cpu_baseline": cpu,
+        "gpu_plain_fp32_baseline": base,
         "formats": per_fmt,
     }
     print(json.dumps(line), flush=True)

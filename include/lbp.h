@@ -134,6 +134,19 @@ lbp_status lbp_decode(lbp_decoder dec, int64_t n_shots, uint64_t first_shot_id, 
 lbp_status lbp_decode_keyed(lbp_decoder dec, int64_t n_shots, const uint64_t *shot_keys, const uint32_t *syndromes,
                             uint32_t *corrections, uint8_t *flags, int32_t *iters, float *llr_out, void *stream);
 
+/* Comparison path: the same decoding as lbp_decode (FP32 or FP16 message
+ * storage; LBP_EUNSUPPORTED for INT8) written the plain way, with every
+ * message in global memory, one thread per check or per column and a kernel
+ * launch per half-iteration (Algorithm 1's CN update, then LLR update + hard
+ * decision + next VN update, then syndrome check + Algorithm 3).  Sums are
+ * taken in fp64 in ascending check order and rounded once to the storage
+ * format.  Same arguments and outputs as lbp_decode (no llr_out).  Allocates
+ * its message arrays on first use (n_shots * (8*m*8 + 8*n) bytes, kept until
+ * the decoder is destroyed) and synchronizes `stream` every 4 iterations to
+ * stop once all shots have finished. */
+lbp_status lbp_decode_baseline(lbp_decoder dec, int64_t n_shots, uint64_t first_shot_id, const uint32_t *syndromes,
+                               uint32_t *corrections, uint8_t *flags, int32_t *iters, void *stream);
+
 /* Same contract as lbp_decode with HOST pointers; synchronous.  Allocates and
  * frees device staging buffers internally. */
 lbp_status lbp_decode_host(lbp_decoder dec, int64_t n_shots, uint64_t first_shot_id, const uint32_t *syndromes,

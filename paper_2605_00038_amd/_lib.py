@@ -62,6 +62,7 @@ SIGNATURES = {
     "lbp_decoder_kernel_times": (_I32, [_VP, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I64),
                                         ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I64)]),
     "lbp_decode_keyed": (_I32, [_VP, _I64, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
+    "lbp_decode_baseline": (_I32, [_VP, _I64, _U64, _VP, _VP, _VP, _VP, _VP]),
     "lbp_decoder_device_bytes": (_I64, [_VP]),
     "lbp_decoder_max_batch": (_I64, [_VP]),
     "lbp_server_create": (_I32, [_I64, _I32, ctypes.POINTER(_VP)]),

@@ -1,0 +1,307 @@
+// Plain global-memory Lottery BP: the comparison path for the fused kernels.
+//
+// The same decoding as lbp_decode for FP32 / FP16 message storage, written the
+// way a straightforward GPU port is: every message lives in HBM
+// ([shots][m][DEG] alpha and beta, [shots][n] lambda), one thread per check or
+// per column, and one kernel launch per half-iteration:
+//   cn    (shot, check):  alpha -> beta           (Algorithm 1, CN update)
+//   col   (shot, column): beta -> lambda, e_hat, next alpha (LLR update, hard
+//                          decision, VN update of the next iteration)
+//   check (wave per shot): syndrome estimate, termination, lottery
+//                          (Algorithm 3), failure list for OSD
+// Sums run in fp64 in ascending check order and are rounded once to the
+// storage format, so lambda and the messages carry the exact arithmetic of the
+// method's reading; nothing is kept on chip between launches.
+#include <hip/hip_fp16.h>
+
+#include "lbp_internal.h"
+
+namespace lbp {
+namespace {
+
+__device__ __forceinline__ float store_msg(int msg, double x) {
+    if (msg == MSG_FP16) {
+        // double -> float with round-to-odd, then float -> half to nearest even:
+        // the odd sticky bit makes the two steps round like one
+        float t = (float)x;
+        if ((double)t != x && (__float_as_uint(t) & 1u) == 0u) {
+            // step one ulp toward x (the neighbour on x's side has the odd last bit)
+            uint32_t u = __float_as_uint(t);
+            if (t == 0.0f) u = (x < 0 ? 0x80000000u : 0u) | 1u;
+            else if (((double)t < x) == (t > 0.0f)) u += 1u;  // away from zero
+            else u -= 1u;                                      // toward zero
+            t = __uint_as_float(u);
+        }
+        __half h = __float2half_rn(t);
+        if (__hisinf(h)) return x > 0 ? 65504.0f : -65504.0f;
+        return __half2float(h);
+    }
+    float f = (float)x;
+    if (__builtin_isinf(f)) return x > 0 ? 3.402823466e38f : -3.402823466e38f;
+    return f;
+}
+
+__device__ __forceinline__ double mu_of(const DevCode &C, int msg, int v) {
+    return msg == MSG_FP16 ? (double)C.mu_f16[v] : (double)C.mu_f32[v];
+}
+
+__device__ __forceinline__ double sigma_of(const BpParams &P, int i) {
+    if (P.scale_mode == 1) return (double)P.scale_f;
+    return i >= 24 ? 1.0 : 1.0 - __builtin_ldexp(1.0, -(i + 1));  // fl32(1 - 2^-(i+1)), exact
+}
+
+__device__ uint64_t philox_w0(uint64_t k0, uint64_t c0, uint64_t c1) {
+    uint64_t x0 = c0, x1 = c1, x2 = 0, x3 = 0, ka = k0, kb = 0;
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t h0 = __umul64hi(0xD2E7470EE14C6C93ULL, x0), l0 = 0xD2E7470EE14C6C93ULL * x0;
+        const uint64_t h1 = __umul64hi(0xCA5A826395121157ULL, x2), l1 = 0xCA5A826395121157ULL * x2;
+        const uint64_t y0 = h1 ^ x1 ^ ka, y2 = h0 ^ x3 ^ kb;
+        x0 = y0;
+        x1 = l1;
+        x2 = y2;
+        x3 = l0;
+        ka += 0x9E3779B97F4A7C15ULL;
+        kb += 0xBB67AE8584CAA73BULL;
+    }
+    return x0;
+}
+
+// alpha^(0) = mu on every real slot, +inf (never a minimum) on padding slots.
+__global__ void bl_init(BlArgs a) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t slots = (int64_t)a.code.m * DEG;
+    if (t >= a.shots * slots) return;
+    const int64_t shot = t / slots;
+    const int e = (int)(t - shot * slots);
+    const uint32_t v = a.code.cn_cols[e];
+    a.alpha[t] = v == NOPOS ? __builtin_inff() : store_msg(a.msg, mu_of(a.code, a.msg, (int)v));
+    if (e == 0) {
+        a.active[shot] = 1;
+        a.flipv[shot] = -1;
+    }
+    if (e < 2 * a.code.mw) a.shat[shot * 2 * a.code.mw + e] = 0u;
+}
+
+// Check-node update of iteration i for every active shot.
+__global__ void bl_cn(BlArgs a, int i) {
+    const int64_t shot = blockIdx.x;
+    const int c = blockIdx.y * blockDim.x + threadIdx.x;
+    const DevCode &C = a.code;
+    if (c >= C.m || !a.active[shot]) return;
+    const int64_t base = (shot * C.m + c) * DEG;
+    const int deg = C.cn_deg[c];
+    const int fv = a.flipv[shot];
+    const bool llr = a.prm.flip == FLIP_LLR && i > 0;
+    float x[DEG];
+    double m1 = __builtin_inf(), m2 = __builtin_inf();
+    int arg = -1, par = (a.synd[shot * C.mw + (c >> 5)] >> (c & 31)) & 1u;
+    for (int k = 0; k < DEG; ++k) {
+        const uint32_t v = C.cn_cols[c * DEG + k];
+        if (k >= deg) break;
+        float al;
+        if (llr) al = store_msg(a.msg, a.lam[shot * C.n + v] - (double)a.beta[base + k]);
+        else al = a.alpha[base + k];
+        if (!llr && (int)v == fv) al = -al;  // message flip (Algorithm 3)
+        x[k] = al;
+        const double mag = __builtin_fabs((double)al);
+        if (mag < m1) {
+            m2 = m1;
+            m1 = mag;
+            arg = k;
+        } else if (mag < m2) {
+            m2 = mag;
+        }
+        par ^= al < 0.f;
+    }
+    if (deg == 1) m2 = CAP_FLOAT;
+    const double sig = sigma_of(a.prm, i);
+    for (int k = 0; k < deg; ++k) {
+        const double b = sig * (k == arg ? m2 : m1);
+        const int neg = par ^ (x[k] < 0.f);
+        a.beta[base + k] = store_msg(a.msg, neg ? -b : b);
+    }
+}
+
+// lambda^(i), e_hat^(i) and (message-flip mode) alpha^(i+1) of every column.
+__global__ void bl_col(BlArgs a) {
+    const int64_t shot = blockIdx.x;
+    const int v = blockIdx.y * blockDim.x + threadIdx.x;
+    const DevCode &C = a.code;
+    if (!a.active[shot]) return;  // uniform per block
+    const bool valid = v < C.n;
+    double b[CDEG];
+    uint32_t pos[CDEG];
+    double lam = 0.0, mu = 0.0;
+    if (valid) {
+        const uint64_t tab = C.vn_tab[v];
+        mu = mu_of(C, a.msg, v);
+        lam = mu;
+        for (int j = 0; j < CDEG; ++j) {
+            pos[j] = (uint32_t)(tab >> (16 * j)) & 0xFFFFu;
+            b[j] = pos[j] != NOPOS ? (double)a.beta[shot * C.m * DEG + pos[j]] : 0.0;
+            lam += b[j];
+        }
+        a.lam[shot * C.n + v] = lam;
+        if (a.prm.flip == FLIP_MSG) {
+            for (int j = 0; j < CDEG; ++j) {
+                if (pos[j] == NOPOS) continue;
+                double x = mu;
+                for (int t = 0; t < CDEG; ++t)
+                    if (t != j && pos[t] != NOPOS) x += b[t];
+                a.alpha[shot * C.m * DEG + pos[j]] = store_msg(a.msg, x);
+            }
+        }
+    }
+    const uint64_t bal = __ballot(valid && lam <= (double)TAU_FLOAT);
+    if ((threadIdx.x & 63) == 0 && v < C.n) {
+        const int w = v >> 5;
+        a.ehat[shot * C.nw + w] = (uint32_t)bal;
+        if (w + 1 < C.nw) a.ehat[shot * C.nw + w + 1] = (uint32_t)(bal >> 32);
+    }
+}
+
+// Syndrome estimate, termination and lottery of iteration i: one wave per shot.
+__global__ void bl_check(BlArgs a, int i) {
+    const DevCode &C = a.code;
+    const BpParams &P = a.prm;
+    const int lane = threadIdx.x & 63;
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+    const uint32_t last_mask = (C.m & 31) ? ((1u << (C.m & 31)) - 1u) : ~0u;
+    for (int64_t shot = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); shot < a.shots;
+         shot += waves) {
+        if (!a.active[shot]) continue;
+        const uint32_t *S = a.synd + shot * C.mw;
+        uint32_t *SHc = a.shat + (shot * 2 + (i & 1)) * C.mw;
+        const uint32_t *SHp = a.shat + (shot * 2 + ((i + 1) & 1)) * C.mw;
+        const uint32_t *EH = a.ehat + shot * C.nw;
+        bool mism = false;
+        for (int w = lane; w < C.mw; w += 64) {
+            uint32_t x = 0;
+            for (int bit = 0; bit < 32; ++bit) {
+                const int c = w * 32 + bit;
+                if (c >= C.m) break;
+                uint32_t p = 0;
+                for (int k = 0; k < C.cn_deg[c]; ++k) {
+                    const uint32_t v = C.cn_cols[c * DEG + k];
+                    p ^= (EH[v >> 5] >> (v & 31)) & 1u;
+                }
+                x |= p << bit;
+            }
+            SHc[w] = x;
+            const uint32_t s = w == C.mw - 1 ? (S[w] & last_mask) : S[w];
+            mism |= x != s;
+        }
+        const bool conv = __ballot(mism) == 0ull;
+        if (conv || i == P.max_iter - 1) {
+            for (int w = lane; w < C.nw; w += 64) a.corr[shot * C.nw + w] = EH[w];
+            if (lane == 0) {
+                a.active[shot] = 0;
+                a.flags[shot] = conv ? (uint8_t)FLAG_CONVERGED : (uint8_t)(P.osd != OSD_NONE ? FLAG_OSD : 0);
+                if (a.iters) a.iters[shot] = i + 1;
+                if (!conv && P.osd != OSD_NONE) {
+                    const uint32_t q = atomicAdd(&a.counters[1], 1u);
+                    a.fail_list[q] = (int32_t)shot;
+                }
+            }
+            continue;
+        }
+        if (lane == 0) atomicAdd(&a.counters[0], 1u);
+        int fv = -1;
+        if (P.lottery && i >= P.skip && i <= P.max_iter - 2) {
+            // U = checks whose previous estimate differs from s, ascending
+            int N = 0;
+            for (int w = lane; w < C.mw; w += 64) {
+                const uint32_t s = w == C.mw - 1 ? (S[w] & last_mask) : S[w];
+                N += __popc(SHp[w] ^ s);
+            }
+            for (int o = 32; o > 0; o >>= 1) N += __shfl_xor(N, o, 64);
+            if (N > 0) {
+                const uint64_t seed = a.shot_keys ? a.shot_keys[2 * shot] : P.seed;
+                const uint64_t sid = a.shot_keys ? a.shot_keys[2 * shot + 1] : a.first_shot_id + (uint64_t)shot;
+                const uint64_t x = philox_w0(seed, sid, (uint64_t)i);
+                int k = (int)(((x >> 32) * (uint64_t)N) >> 32);
+                int cstar = -1;
+                for (int w = 0; w < C.mw && cstar < 0; ++w) {  // uniform scan: clarity over speed
+                    const uint32_t s = w == C.mw - 1 ? (S[w] & last_mask) : S[w];
+                    uint32_t u = SHp[w] ^ s;
+                    const int cnt = __popc(u);
+                    if (k < cnt) {
+                        for (int q = 0; q < k; ++q) u &= u - 1;
+                        cstar = w * 32 + __ffs(u) - 1;
+                    }
+                    k -= cnt;
+                }
+                int best_v = -1, best_cnt = -1;
+                long long best_q = 0;
+                for (int e = 0; e < C.cn_deg[cstar]; ++e) {
+                    const int v = C.cn_cols[cstar * DEG + e];
+                    const uint64_t tab = C.vn_tab[v];
+                    int cnt = 0;
+                    for (int j = 0; j < CDEG; ++j) {
+                        const uint32_t p = (uint32_t)(tab >> (16 * j)) & 0xFFFFu;
+                        if (p == NOPOS) continue;
+                        const int c = (int)(p / DEG);
+                        const uint32_t s = (S[c >> 5] >> (c & 31)) & 1u;
+                        cnt += (int)(((SHp[c >> 5] >> (c & 31)) & 1u) ^ s);
+                    }
+                    const double qa = __builtin_fabs(a.lam[shot * C.n + v]) * 4096.0;
+                    const long long q = qa >= 4.0e18 ? (long long)4.0e18 : (long long)__builtin_floor(qa);
+                    if (best_v < 0 || cnt > best_cnt || (cnt == best_cnt && (q < best_q || (q == best_q && v < best_v)))) {
+                        best_v = v;
+                        best_cnt = cnt;
+                        best_q = q;
+                    }
+                }
+                fv = best_v;
+            }
+        }
+        if (lane == 0) {
+            if (P.flip == FLIP_LLR) {
+                if (fv >= 0) a.lam[shot * C.n + fv] = -a.lam[shot * C.n + fv];
+                a.flipv[shot] = -1;
+            } else {
+                a.flipv[shot] = fv;
+            }
+        }
+    }
+}
+
+// lambda of failed shots [from, from + count) into the OSD staging format.
+__global__ void bl_stage(BlArgs a, int64_t from, int64_t count, float *dst, uint32_t *ocounters) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int n = a.code.n;
+    if (t == 0) ocounters[1] = (uint32_t)count;
+    if (t >= count * n) return;
+    const int64_t q = t / n;
+    const int v = (int)(t - q * n);
+    const double l = a.lam[(int64_t)a.fail_list[from + q] * n + v];
+    const float hi = (float)l;
+    dst[q * 2 * n + v] = hi;
+    dst[q * 2 * n + n + v] = (float)(l - (double)hi);
+}
+
+}  // namespace
+
+hipError_t baseline_init(const BlArgs &a, hipStream_t s) {
+    const int64_t total = a.shots * a.code.m * DEG;
+    hipLaunchKernelGGL(bl_init, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t baseline_iteration(const BlArgs &a, int i, hipStream_t s) {
+    hipLaunchKernelGGL(bl_cn, dim3((unsigned)a.shots, (unsigned)((a.code.m + 255) / 256)), dim3(256), 0, s, a, i);
+    hipLaunchKernelGGL(bl_col, dim3((unsigned)a.shots, (unsigned)((a.code.n + 255) / 256)), dim3(256), 0, s, a);
+    const int64_t blocks = std::min<int64_t>((a.shots + 3) / 4, 65536);
+    hipLaunchKernelGGL(bl_check, dim3((unsigned)blocks), dim3(256), 0, s, a, i);
+    return hipGetLastError();
+}
+
+hipError_t baseline_stage(const BlArgs &a, int64_t from, int64_t count, float *dst, uint32_t *ocounters,
+                          hipStream_t s) {
+    const int64_t total = std::max<int64_t>(1, count * a.code.n);
+    hipLaunchKernelGGL(bl_stage, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, a, from, count, dst,
+                       ocounters);
+    return hipGetLastError();
+}
+
+}  // namespace lbp

@@ -78,6 +78,32 @@ struct OsdArgs {
     int32_t has_lo;             // lambda carries a non-zero low part (fp32 messages)
 };
 
+// Global-memory comparison path (one launch per half-iteration).
+struct BlArgs {
+    DevCode code;
+    BpParams prm;
+    int32_t msg;                // MSG_FP32 or MSG_FP16 storage
+    int64_t shots;
+    uint64_t first_shot_id;
+    const uint64_t *shot_keys;  // nullable, as in BpArgs
+    const uint32_t *synd;       // [shots][mw]
+    uint32_t *corr;             // [shots][nw]
+    uint8_t *flags;             // [shots]
+    int32_t *iters;             // [shots] or null
+    float *alpha, *beta;        // [shots][m*DEG]
+    double *lam;                // [shots][n]
+    uint32_t *ehat;             // [shots][nw]
+    uint32_t *shat;             // [shots][2][mw]: estimate of iteration i in slot i&1
+    int32_t *flipv;             // [shots] column whose messages the next CN update negates, or -1
+    uint8_t *active;            // [shots]
+    uint32_t *counters;         // [0] shots still running after an iteration, [1] failed shots
+    int32_t *fail_list;         // [shots]
+};
+hipError_t baseline_init(const BlArgs &a, hipStream_t s);
+hipError_t baseline_iteration(const BlArgs &a, int i, hipStream_t s);
+hipError_t baseline_stage(const BlArgs &a, int64_t from, int64_t count, float *dst, uint32_t *ocounters,
+                          hipStream_t s);
+
 // Set the thread-local message returned by lbp_last_error.
 void set_error(const char *msg);
 

@@ -77,6 +77,13 @@ struct lbp_decoder_s {
     float *d_stage = nullptr;
     uint32_t *d_gscratch = nullptr;
     uint32_t *h_count = nullptr;  // pinned
+    // global-memory comparison path, allocated on first use
+    int64_t bl_cap = 0;
+    float *bl_alpha = nullptr, *bl_beta = nullptr;
+    double *bl_lam = nullptr;
+    uint32_t *bl_ehat = nullptr, *bl_shat = nullptr;
+    int32_t *bl_flipv = nullptr;
+    uint8_t *bl_active = nullptr;
     // kernel timing: event pairs per launch, kind 0 = BP, 1 = OSD
     bool timing = false;
     struct Rec {
@@ -237,6 +244,13 @@ static void free_decoder(lbp_decoder d) {
     hipFree(d->d_stage);
     hipFree(d->d_gscratch);
     if (d->h_count) hipHostFree(d->h_count);
+    hipFree(d->bl_alpha);
+    hipFree(d->bl_beta);
+    hipFree(d->bl_lam);
+    hipFree(d->bl_ehat);
+    hipFree(d->bl_shat);
+    hipFree(d->bl_flipv);
+    hipFree(d->bl_active);
 }
 
 lbp_status lbp_decoder_create(lbp_code code, const lbp_params *prm, int64_t max_batch, lbp_decoder *out) {
@@ -490,6 +504,99 @@ lbp_status lbp_decode_keyed(lbp_decoder d, int64_t n_shots, const uint64_t *shot
     if (n_shots > 0 && !shot_keys) return fail(LBP_EINVAL, "lbp_decode_keyed: NULL shot_keys");
     return decode_impl("lbp_decode_keyed", d, n_shots, 0, shot_keys, syndromes, corrections, flags, iters, llr_out,
                        stream);
+}
+
+lbp_status lbp_decode_baseline(lbp_decoder d, int64_t n_shots, uint64_t first_shot_id, const uint32_t *syndromes,
+                               uint32_t *corrections, uint8_t *flags, int32_t *iters, void *stream) {
+    g_err.clear();
+    if (!d) return fail(LBP_EINVAL, "lbp_decode_baseline: NULL decoder");
+    if (n_shots < 0 || n_shots > d->max_batch) return fail(LBP_EINVAL, "lbp_decode_baseline: 0 <= n_shots <= max_batch");
+    if (d->prm.msg == LBP_MSG_INT8)
+        return fail(LBP_EUNSUPPORTED, "lbp_decode_baseline: FP32 or FP16 message storage only");
+    if (n_shots == 0) return LBP_OK;
+    if (!syndromes || !corrections || !flags) return fail(LBP_EINVAL, "lbp_decode_baseline: NULL buffer");
+    DeviceGuard g(d->code->device);
+    hipStream_t s = (hipStream_t)stream;
+    lbp_code C = d->code;
+    const size_t slots = (size_t)C->m * DEG;
+    if (d->bl_cap < n_shots) {
+        HIPCHK(hipStreamSynchronize(s));
+        hipFree(d->bl_alpha); hipFree(d->bl_beta); hipFree(d->bl_lam); hipFree(d->bl_ehat);
+        hipFree(d->bl_shat); hipFree(d->bl_flipv); hipFree(d->bl_active);
+        d->bl_alpha = d->bl_beta = nullptr; d->bl_lam = nullptr; d->bl_ehat = d->bl_shat = nullptr;
+        d->bl_flipv = nullptr; d->bl_active = nullptr;
+        d->bl_cap = 0;
+        const size_t S = (size_t)n_shots;
+        HIPCHK(hipMalloc((void **)&d->bl_alpha, S * slots * 4));
+        HIPCHK(hipMalloc((void **)&d->bl_beta, S * slots * 4));
+        HIPCHK(hipMalloc((void **)&d->bl_lam, S * C->n * 8));
+        HIPCHK(hipMalloc((void **)&d->bl_ehat, S * C->dc.nw * 4));
+        HIPCHK(hipMalloc((void **)&d->bl_shat, S * 2 * C->dc.mw * 4));
+        HIPCHK(hipMalloc((void **)&d->bl_flipv, S * 4));
+        HIPCHK(hipMalloc((void **)&d->bl_active, S));
+        d->bl_cap = n_shots;
+    }
+    BlArgs a{};
+    a.code = C->dc;
+    a.prm = d->bp;
+    a.msg = d->prm.msg;
+    a.shots = n_shots;
+    a.first_shot_id = first_shot_id;
+    a.synd = syndromes;
+    a.corr = corrections;
+    a.flags = flags;
+    a.iters = iters;
+    a.alpha = d->bl_alpha;
+    a.beta = d->bl_beta;
+    a.lam = d->bl_lam;
+    a.ehat = d->bl_ehat;
+    a.shat = d->bl_shat;
+    a.flipv = d->bl_flipv;
+    a.active = d->bl_active;
+    a.counters = d->d_counters;
+    a.fail_list = d->d_fail_list;
+    HIPCHK(launch_reset(d->d_counters, 16, s));
+    HIPCHK(baseline_init(a, s));
+    for (int i = 0; i < d->prm.max_iter; ++i) {
+        HIPCHK(launch_reset(d->d_counters, 1, s));
+        HIPCHK(baseline_iteration(a, i, s));
+        if ((i & 3) == 3 && i + 1 < d->prm.max_iter) {  // stop launching once every shot has finished
+            HIPCHK(hipMemcpyAsync(d->h_count, d->d_counters, 4, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            if (d->h_count[0] == 0) break;
+        }
+    }
+    if (!d->prm.osd) return LBP_OK;
+    HIPCHK(hipMemcpyAsync(d->h_count, d->d_counters + 1, 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    const int64_t total = d->h_count[0];
+    for (int64_t from = 0; from < total; from += d->fail_cap) {
+        const int64_t cnt = std::min<int64_t>(d->fail_cap, total - from);
+        uint32_t *oc = d->d_counters + 8;
+        HIPCHK(baseline_stage(a, from, cnt, d->d_fail_llr, oc, s));
+        OsdArgs o{};
+        o.m = C->m;
+        o.n = C->n;
+        o.mw = C->dc.mw;
+        o.nw = C->dc.nw;
+        o.mws = d->mws;
+        o.vn_tab = C->dc.vn_tab;
+        o.mode = d->prm.osd;
+        o.order = d->prm.osd_order;
+        o.synd = syndromes;
+        o.corr = corrections;
+        o.flags = flags;
+        o.counters = oc;
+        o.fail_list = d->d_fail_list + from;
+        o.fail_llr = d->d_fail_llr;
+        o.fail_cap = d->fail_cap;
+        o.gscratch = d->d_gscratch;
+        o.sort_p = d->sort_p;
+        o.g_in_lds = d->osd_variant == 0;
+        o.has_lo = 1;
+        HIPCHK(launch_osd(o, d->osd_variant, d->osd_blocks, d->osd_threads, d->osd_lds, s));
+    }
+    return LBP_OK;
 }
 
 int64_t lbp_decoder_device_bytes(lbp_decoder d) { return d ? d->dev_bytes : 0; }

@@ -139,6 +139,21 @@ class Decoder:
                                       s.cuda_stream))
         return corr, flags, iters
 
+    def decode_baseline(self, syndromes, first_shot_id: int = 0, stream=None):
+        """lbp_decode_baseline (global-memory comparison path); returns (corr, flags, iters)."""
+        import torch
+        assert syndromes.is_cuda and syndromes.dim() == 2 and syndromes.shape[1] == self.mw
+        assert syndromes.is_contiguous()
+        shots = syndromes.shape[0]
+        dev = syndromes.device
+        corr = torch.empty((shots, self.nw), dtype=torch.int32, device=dev)
+        flags = torch.empty(shots, dtype=torch.uint8, device=dev)
+        iters = torch.empty(shots, dtype=torch.int32, device=dev)
+        s = stream if stream is not None else torch.cuda.current_stream(dev)
+        check(load().lbp_decode_baseline(self._h, shots, first_shot_id & 0xFFFFFFFFFFFFFFFF, syndromes.data_ptr(),
+                                         corr.data_ptr(), flags.data_ptr(), iters.data_ptr(), s.cuda_stream))
+        return corr, flags, iters
+
     @property
     def device_bytes(self) -> int:
         return int(load().lbp_decoder_device_bytes(self._h))
