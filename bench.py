@@ -132,26 +132,42 @@ def baseline_row(torch, h, syn_dev, shots: int, warmup: int):
 
 
 def serving(h, syn, n_requests: int, shots_per_request: int = 1):
-    """Serving loop (continuous batching) under single-syndrome requests: the
-    saturation rate (requests submitted back to back), then Poisson arrivals at
-    50% and 90% of it; latency from scheduled arrival to poll-visible result."""
+    """Serving loop under single-syndrome Poisson requests (latency from the
+    scheduled arrival to the poll-visible result).  Saturation is the highest
+    offered rate the server sustains: achieved >= 97% of offered with a median
+    latency under 2 ms (no backlog).  The rates tried are fractions of the
+    back-to-back (flood) rate; p50/p99 are then reported at 50% and 90% of
+    the sustained saturation rate."""
     from paper_2605_00038_amd import Code, DecoderParams, Server
     prm = DecoderParams(max_iter=MAX_ITER, msg=2, lottery=True, lottery_skip=6, osd=2, osd_order=OSD_ORDER)
     srv = Server(max_slots=1)
     slot = srv.add_code(Code.from_scipy(h, P_ERR), prm)
     pool = syn[: min(len(syn), 1 << 18)]
-    srv.run_load([slot], [pool], min(n_requests, 20000), shots_per_request, 0.0, LOTTERY_SEED)  # warm-up
-    lat, _, el = srv.run_load([slot], [pool], n_requests, shots_per_request, 0.0, LOTTERY_SEED)
-    sat = n_requests / el
-    out = dict(requests=n_requests, shots_per_request=shots_per_request, saturation_requests_per_s=sat,
-               saturation_syndromes_per_s=sat * shots_per_request,
-               saturation_p50_us=float(np.percentile(lat, 50)), saturation_p99_us=float(np.percentile(lat, 99)))
-    for frac in (0.5, 0.9):
-        lat, _, el = srv.run_load([slot], [pool], n_requests, shots_per_request, frac * sat, LOTTERY_SEED + 1)
-        out[f"load{int(frac * 100)}"] = dict(offered_requests_per_s=frac * sat, achieved_requests_per_s=n_requests / el,
-                                            p50_us=float(np.percentile(lat, 50)), p99_us=float(np.percentile(lat, 99)),
-                                            p999_us=float(np.percentile(lat, 99.9)))
-    out["tick"] = srv.slot_info(slot)
+
+    def run(rate, n, seed):
+        lat, _, el = srv.run_load([slot], [pool], n, shots_per_request, rate, seed)
+        return dict(offered_requests_per_s=rate, achieved_requests_per_s=n / el, requests=n,
+                    p50_us=float(np.percentile(lat, 50)), p99_us=float(np.percentile(lat, 99)),
+                    p999_us=float(np.percentile(lat, 99.9)))
+
+    run(0.0, min(n_requests, 20000), LOTTERY_SEED)  # warm-up
+    flood = run(0.0, n_requests, LOTTERY_SEED)
+    sweep, sat = [], None
+    for k, frac in enumerate((0.05, 0.1, 0.2, 0.3, 0.4, 0.5, 0.6, 0.7, 0.8, 0.9)):
+        rate = frac * flood["achieved_requests_per_s"]
+        r = run(rate, int(max(20000, min(n_requests, rate * 0.5))), LOTTERY_SEED + 1 + k)
+        sweep.append(r)
+        if r["achieved_requests_per_s"] >= 0.97 * rate and r["p50_us"] < 2000.0:
+            sat = rate
+        else:
+            break
+    out = dict(shots_per_request=shots_per_request, flood=flood, sweep=sweep, saturation_requests_per_s=sat,
+               saturation_syndromes_per_s=(sat or 0.0) * shots_per_request)
+    if sat:
+        for frac in (0.5, 0.9):
+            out[f"load{int(frac * 100)}"] = run(frac * sat, int(max(20000, min(n_requests, frac * sat * 1.0))),
+                                                LOTTERY_SEED + 20 + int(frac * 10))
+    out["slot"] = srv.slot_info(slot)
     srv.close()
     return out
 
@@ -324,7 +340,7 @@ def main():
         "config": {"workload": "BB[[144,12,12]] phenomenological, 12 rounds, H_st 864x2592 (6840 edges), "
                                "p=0.003, Lottery BP I=200 K=6, OSD-CS(10)",
                    "shots_per_step": args.shots, "data_seed": DATA_SEED, "lottery_seed": LOTTERY_SEED},
-        "p99_latency_us": (serve["load50"]["p99_us"] if serve is not None
+        "p99_latency_us": (serve["load50"]["p99_us"] if serve is not None and "load50" in serve
                            else float(np.percentile(lat, 99)) if lat is not None else None),
         "p99_latency_kind": ("serving loop, single-syndrome Poisson requests at 50% of saturation, "
                              "arrival to poll-visible result" if serve is not None

@@ -177,25 +177,29 @@ lbp_status lbp_decoder_kernel_times(lbp_decoder dec, double *bp_ms, int64_t *bp_
  * at creation, its queues and all device buffers; the caller owns its host
  * arrays.  lbp_server_* calls are thread-safe.
  *
- * Continuous batching: every code slot has 3 batch buffers (stream + decoder
- * workspace + pinned staging).  Whenever one is free, the worker packs the
- * slot's queued shots into it, first come first served, splitting a request
- * across batches when it is larger than a batch, and launches it.  A request
- * is complete once all of its shots are back.  Each shot is decoded with the
- * key (seed, first_shot_id + j) of its request, so results are identical to a
- * lone lbp_decode of the request with that seed, whatever else shares the
- * batch. */
+ * Streaming: every code slot has a ring of R shots in pinned host memory and
+ * a persistent BP grid that claims published shots one per wavefront, so each
+ * shot's result is visible as soon as that shot is done (no batch
+ * boundaries).  Shots whose BP run fails are handed to OSD launches on the
+ * CUs the BP grid leaves free (3/8 of them).  The worker publishes queued
+ * shots first come first served, splitting large requests, with at most R
+ * shots in flight per slot; a request completes when all of its shots have.
+ * Each shot is decoded with the key (seed, first_shot_id + j) of its request,
+ * so results equal a lone lbp_decode of the request with that seed, whatever
+ * else is in flight.  The BP grid exits after 2 ms without work and is
+ * relaunched when shots arrive. */
 
 /* device_mem_budget_bytes: cap on the device memory all slots may hold (0 =
- * 4 GiB); max_slots: number of codes (1..64). */
+ * 16 GiB); max_slots: number of codes (1..64). */
 lbp_status lbp_server_create(int64_t device_mem_budget_bytes, int32_t max_slots, lbp_server *out);
 /* Register a code with its decoding parameters (params.seed is ignored: each
- * request brings its own).  Picks the largest batch size (power of two <=
- * 8192) whose three buffers fit the remaining budget: LBP_ENOMEM if none does,
- * LBP_EBUSY if all slots are taken.  The code must outlive the server. */
+ * request brings its own).  Picks the largest ring (power of two, 1024 ..
+ * 65536 shots; 8n bytes of device memory per shot) that fits the remaining
+ * budget: LBP_ENOMEM if none does, LBP_EBUSY if all slots are taken.  The
+ * code must outlive the server. */
 lbp_status lbp_server_add_code(lbp_server srv, lbp_code code, const lbp_params *prm, int32_t *code_slot);
 /* Queue n_shots >= 1 syndromes (HOST, [n_shots][ceil(m/32)], copied before
- * return).  Admission: LBP_EBUSY when the slot already holds 64 batches'
+ * return).  Admission: LBP_EBUSY when the slot would hold more than 16 rings'
  * worth of queued shots.  *ticket identifies the request. */
 lbp_status lbp_server_submit(lbp_server srv, int32_t code_slot, int64_t n_shots, uint64_t seed,
                              uint64_t first_shot_id, const uint32_t *host_syndromes, uint64_t *ticket);
@@ -208,13 +212,13 @@ lbp_status lbp_server_poll(lbp_server srv, uint64_t ticket, uint32_t *correction
 /* lbp_server_poll that blocks up to timeout_us microseconds (< 0: no limit). */
 lbp_status lbp_server_wait(lbp_server srv, uint64_t ticket, int64_t timeout_us, uint32_t *corrections,
                            uint8_t *flags, int32_t *iters);
-/* Drop a request: its queued shots are never launched, results of shots
+/* Drop a request: its queued shots are never published, results of shots
  * already in flight are discarded, and the ticket is released. */
 lbp_status lbp_server_cancel(lbp_server srv, uint64_t ticket);
-/* Slot statistics: batch size, batches and shots launched, largest batch,
- * shots queued now.  Any output may be NULL. */
-lbp_status lbp_server_slot_info(lbp_server srv, int32_t code_slot, int64_t *tick_shots, int64_t *batches,
-                                int64_t *shots, int64_t *max_fill, int64_t *queued_shots);
+/* Slot statistics: ring size, BP grid launches, shots completed, most shots
+ * in flight at once, shots queued now.  Any output may be NULL. */
+lbp_status lbp_server_slot_info(lbp_server srv, int32_t code_slot, int64_t *ring_items, int64_t *bp_launches,
+                                int64_t *shots, int64_t *max_inflight, int64_t *queued_shots);
 /* Benchmarking aid: drive the server with an open-loop stream of n_requests
  * requests of shots_per_request syndromes each.  Request q goes to
  * code_slots[k], k uniform in [0, n_codes) (request_code[q] = k, may be

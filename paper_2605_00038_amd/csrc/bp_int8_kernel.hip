@@ -174,17 +174,28 @@ __global__ __launch_bounds__(1024) void bp_int8_kernel(BpArgs a) {
     const int nvs = (n + 63) >> 6;
 
     for (;;) {
-        uint32_t item = 0;
-        if (lane == 0) item = atomicAdd(&a.counters[0], 1u);
-        item = __builtin_amdgcn_readfirstlane(item);
-        if ((int64_t)item >= a.n_work) break;
-        const int64_t shot = a.work_list ? (int64_t)a.work_list[item] : (int64_t)item;
-        const uint64_t seed = a.shot_keys ? a.shot_keys[2 * shot] : P.seed;
-        const uint64_t shot_id = a.shot_keys ? a.shot_keys[2 * shot + 1] : a.first_shot_id + (uint64_t)shot;
+        int64_t item = 0;
+        if (a.ring) {
+            if (lane == 0) item = serve_claim(*a.ring);
+            item = uniform64(item);
+            if (item < 0) break;
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");  // the host's writes of this ring slot
+        } else {
+            uint32_t it0 = 0;
+            if (lane == 0) it0 = atomicAdd(&a.counters[0], 1u);
+            item = (int64_t)__builtin_amdgcn_readfirstlane(it0);
+            if (item >= a.n_work) break;
+        }
+        // a ring item lives in slot item & mask; a batch item names its shot
+        const int64_t shot = a.ring ? (item & a.ring->mask) : a.work_list ? (int64_t)a.work_list[item] : item;
+        const uint64_t *keys = a.ring ? a.ring->keys : a.shot_keys;
+        const uint64_t seed = keys ? keys[2 * shot] : P.seed;
+        const uint64_t shot_id = keys ? keys[2 * shot + 1] : a.first_shot_id + (uint64_t)shot;
         float *llr_row = a.llr_out ? a.llr_out + shot * n : nullptr;
+        const uint32_t *syn_row = (a.ring ? a.ring->syn : a.synd) + shot * C.mw;
 
         for (int w = lane; w < C.mw; w += 64) {
-            uint32_t x = a.synd[shot * C.mw + w];
+            uint32_t x = syn_row[w];
             S[w] = w == C.mw - 1 ? (x & last_mask) : x;
         }
         // lambda^(-1) = mu in both buffers (Algorithm 1, line 4: alpha^(0) = mu)
@@ -311,6 +322,23 @@ __global__ __launch_bounds__(1024) void bp_int8_kernel(BpArgs a) {
             wave_sync();
         }
 
+        if (a.ring) {
+            const ServeRing &R = *a.ring;
+            uint32_t *corr_row = R.corr + shot * C.nw;
+            for (int w = lane; w < C.nw; w += 64) corr_row[w] = EH[w];
+            const bool osd = !converged && P.osd != OSD_NONE;
+            if (osd) {
+                float *dst = R.llr + shot * 2 * n;
+                for (int v = lane; v < 2 * n; v += 64) dst[v] = stage[v];
+            }
+            if (lane == 0) {
+                R.flags[shot] = converged ? (uint8_t)FLAG_CONVERGED : osd ? (uint8_t)(FLAG_OSD | FLAG_OSD_PENDING) : 0;
+                R.iters[shot] = it;
+            }
+            serve_publish(R, item, lane);
+            wave_sync();
+            continue;
+        }
         for (int w = lane; w < C.nw; w += 64) a.corr[shot * C.nw + w] = EH[w];
         const uint8_t fl = converged ? (uint8_t)FLAG_CONVERGED : (uint8_t)(P.osd != OSD_NONE ? FLAG_OSD : 0);
         if (lane == 0) {

@@ -41,6 +41,29 @@ struct BpParams {
     uint64_t seed;
 };
 
+// Serving rings of one code slot.  Host memory is pinned, fine-grained
+// (coherent) and read or written by the kernels directly.
+struct ServeRing {
+    const uint32_t *syn;            // host [R][mw]: syndrome of item k in slot k & mask
+    const uint64_t *keys;           // host [R][2]: (lottery seed, shot_id)
+    const uint64_t *host_tail;      // host: number of items published
+    const uint32_t *host_stop;      // host: nonzero asks idle waves to exit
+    uint32_t *corr;                 // host [R][nw]
+    uint8_t *flags;                 // host [R]
+    int32_t *iters;                 // host [R]
+    uint64_t *cq;                   // host [R]: completion queue; position p holds cq_entry(p, item)
+    unsigned long long *cq_tail;    // device: next completion-queue position
+    unsigned long long *head;       // device: next item to claim
+    unsigned long long *tail;       // device: copy of host_tail (raised by the polling wave)
+    uint32_t *token;                // device: 1 while a wave polls host memory
+    unsigned long long *last_claim; // device: clock of the latest claim by any wave
+    float *llr;                     // device [R][2n]: lambda (hi, lo) of items left to OSD
+    int64_t mask;                   // R - 1 (R a power of two)
+    uint64_t idle_ticks;            // the grid exits after this long without a claim (100 MHz ticks)
+};
+// flags bit of a ring item whose BP failed and whose OSD has not run yet
+constexpr uint8_t FLAG_OSD_PENDING = 0x80;
+
 struct BpArgs {
     DevCode code;
     BpParams prm;
@@ -59,7 +82,73 @@ struct BpArgs {
     int64_t fail_cap;
     float *stage;               // [grid waves][2n]
     int32_t wave_bytes;         // LDS bytes per wave
+    const ServeRing *ring;      // device copy; non-null: take items from the ring, not the batch arrays
 };
+
+// Claim the next published ring item for the calling lane (call from one lane
+// per wave).  Returns -1 when the host asked to stop, or once no wave of the
+// grid has claimed anything for idle_ticks (the grid winds down as a whole, so
+// a busy stream never loses waves).  Only the wave holding the token reads
+// host memory; the others watch the device copy of the tail.
+__device__ inline int64_t serve_claim(const ServeRing &r) {
+    const uint64_t t_start = __builtin_amdgcn_s_memrealtime();
+    int idle_rounds = 0;
+    for (;;) {
+        unsigned long long t = __hip_atomic_load(r.tail, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        unsigned long long h = __hip_atomic_load(r.head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        while (h < t) {
+            const unsigned long long old = atomicCAS(r.head, h, h + 1);
+            if (old == h) {
+                __hip_atomic_fetch_max(r.last_claim, (unsigned long long)__builtin_amdgcn_s_memrealtime(),
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                return (int64_t)h;
+            }
+            h = old;
+        }
+        // test before test-and-set: idle waves mostly read, and only one polls the host
+        if (__hip_atomic_load(r.token, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u &&
+            atomicCAS(r.token, 0u, 1u) == 0u) {
+            const uint64_t ht = __hip_atomic_load(r.host_tail, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+            const uint32_t stop = __hip_atomic_load(r.host_stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            if (ht > t) __hip_atomic_fetch_max(r.tail, (unsigned long long)ht, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            atomicExch(r.token, 0u);
+            if (ht > t) continue;
+            if (stop) return -1;
+        }
+        const uint64_t now = __builtin_amdgcn_s_memrealtime();
+        const uint64_t last = __hip_atomic_load(r.last_claim, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (now - (last > t_start ? last : t_start) > r.idle_ticks) return -1;
+        // back off while nothing arrives (s_sleep k waits about 64 k cycles)
+        if (idle_rounds < 6) ++idle_rounds;
+        for (int z = 0; z < (1 << idle_rounds); ++z) __builtin_amdgcn_s_sleep(2);
+    }
+}
+
+// A completion-queue entry names its position's lap and the item in one word,
+// so the reader can tell a fresh entry from an old one with a single load.
+constexpr int CQ_ITEM_BITS = 40;
+__host__ __device__ inline uint64_t cq_entry(uint64_t pos, uint64_t item, int64_t mask) {
+    return ((pos / ((uint64_t)mask + 1) + 1) << CQ_ITEM_BITS) | (item & ((1ull << CQ_ITEM_BITS) - 1));
+}
+
+// Publish a finished ring item: every lane's stores first, then an entry of
+// the completion queue (at most R items are in flight, so it never laps the
+// host's reader).
+__device__ inline void serve_publish(const ServeRing &r, int64_t item, int lane) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+    __builtin_amdgcn_wave_barrier();
+    if (lane == 0) {
+        const unsigned long long p = atomicAdd(r.cq_tail, 1ull);
+        __hip_atomic_store(r.cq + (p & r.mask), cq_entry(p, (uint64_t)item, r.mask), __ATOMIC_RELEASE,
+                           __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+}
+
+__device__ inline int64_t uniform64(int64_t x) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(uint64_t)x);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)x >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
 
 struct OsdArgs {
     int32_t m, n, mw, nw, mws;  // mws: G row stride in words (odd)
@@ -76,6 +165,7 @@ struct OsdArgs {
     int32_t sort_p;             // power of two >= n
     int32_t g_in_lds;
     int32_t has_lo;             // lambda carries a non-zero low part (fp32 messages)
+    int32_t llr_by_shot;        // fail_llr indexed by the shot (ring slot) instead of the list position
 };
 
 // Global-memory comparison path (one launch per half-iteration).

@@ -219,7 +219,7 @@ __global__ __launch_bounds__(OSD_THREADS) void osd_lds_kernel(OsdArgs a) {
 
     for (uint32_t q = blockIdx.x; q < nfail; q += gridDim.x) {
         const int64_t shot = a.fail_list[q];
-        const float *lam = a.fail_llr + (size_t)q * 2 * n;  // hi[n] then lo[n]: lambda = hi + lo
+        const float *lam = a.fail_llr + (size_t)(a.llr_by_shot ? shot : (int64_t)q) * 2 * n;  // hi[n] then lo[n]
 
         // ---- 1. sort (lambda, column) ascending
         sort_columns(lam, n, P, a.has_lo, (unsigned long long *)smem, lo_s, perm);
@@ -358,6 +358,7 @@ __global__ __launch_bounds__(OSD_THREADS) void osd_lds_kernel(OsdArgs a) {
         }
         __syncthreads();
         for (int ww = tid; ww < a.nw; ww += OSD_THREADS) a.corr[shot * a.nw + ww] = cw[ww];
+        if (tid == 0) a.flags[shot] = (uint8_t)FLAG_OSD;  // clears a serving ring's pending bit
         __syncthreads();
     }
 }
@@ -458,7 +459,7 @@ __global__ __launch_bounds__(1024) void osd_reg_kernel(OsdArgs a) {
 
     for (uint32_t q = blockIdx.x; q < nfail; q += gridDim.x) {
         const int64_t shot = a.fail_list[q];
-        const float *lam = a.fail_llr + (size_t)q * 2 * n;
+        const float *lam = a.fail_llr + (size_t)(a.llr_by_shot ? shot : (int64_t)q) * 2 * n;
 
         // ---- 1. sort (lambda, column) ascending
         sort_columns(lam, n, P, a.has_lo, (unsigned long long *)smem, lo_s, perm);
@@ -584,6 +585,7 @@ __global__ __launch_bounds__(1024) void osd_reg_kernel(OsdArgs a) {
         }
         __syncthreads();
         for (int ww = tid; ww < a.nw; ww += nth) a.corr[shot * a.nw + ww] = cw[ww];
+        if (tid == 0) a.flags[shot] = (uint8_t)FLAG_OSD;  // clears a serving ring's pending bit
         __syncthreads();
     }
 }

@@ -1,5 +1,6 @@
 // Host runtime of the C ABI in include/lbp.h: validation, device tables,
 // workspace sizing, launch configuration and the OSD overflow loop.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -8,6 +9,7 @@
 
 #include "../../include/lbp.h"
 #include "lbp_internal.h"
+#include "serve_internal.h"
 
 using namespace lbp;
 
@@ -103,6 +105,59 @@ static hipEvent_t take_event(lbp_decoder d) {
     hipEvent_t e = nullptr;
     if (hipEventCreate(&e) != hipSuccess) return nullptr;
     return e;
+}
+
+lbp_status lbp::serve_shape(lbp_decoder d, double osd_fraction, ServeShape *out) {
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, d->code->device) != hipSuccess)
+        return fail(LBP_EDEVICE, "serve_shape: device query failed");
+    const int bpc = std::max(1, d->bp_blocks / std::max(1, ncu));
+    const int osd_cus = d->prm.osd ? std::max(1, (int)(ncu * osd_fraction)) : 0;
+    out->bp_blocks = std::max(1, std::min(d->bp_blocks, bpc * (ncu - osd_cus)));
+    out->osd_blocks = d->prm.osd ? std::max(1, std::min(d->osd_blocks, osd_cus * std::max(1, d->osd_blocks / ncu))) : 0;
+    return LBP_OK;
+}
+
+lbp_status lbp::serve_launch_bp(lbp_decoder d, const ServeRing *ring_dev, int blocks, hipStream_t s) {
+    BpArgs a{};
+    a.code = d->code->dc;
+    a.prm = d->bp;
+    a.ring = ring_dev;
+    a.stage = d->d_stage;
+    a.wave_bytes = d->wave_bytes;
+    blocks = std::max(1, std::min(blocks, d->bp_blocks));  // d_stage holds bp_blocks * wpb waves
+    HIPCHK(d->int8_slots ? launch_bp_int8(d->int8_slots, a, blocks, d->wpb, s)
+                         : launch_bp(d->prm.msg, a, blocks, d->wpb, s));
+    return LBP_OK;
+}
+
+lbp_status lbp::serve_launch_osd(lbp_decoder d, const ServeRing &ring, const int32_t *d_list,
+                                 const uint32_t *d_counters, int blocks, hipStream_t s) {
+    lbp_code C = d->code;
+    OsdArgs o{};
+    o.m = C->m;
+    o.n = C->n;
+    o.mw = C->dc.mw;
+    o.nw = C->dc.nw;
+    o.mws = d->mws;
+    o.vn_tab = C->dc.vn_tab;
+    o.mode = d->prm.osd;
+    o.order = d->prm.osd_order;
+    o.synd = ring.syn;
+    o.corr = ring.corr;
+    o.flags = ring.flags;
+    o.counters = d_counters;
+    o.fail_list = d_list;
+    o.fail_llr = ring.llr;
+    o.fail_cap = (int64_t)1 << 40;
+    o.gscratch = d->d_gscratch;
+    o.sort_p = d->sort_p;
+    o.g_in_lds = d->osd_variant == 0;
+    o.has_lo = d->prm.msg == LBP_MSG_FP32;
+    o.llr_by_shot = 1;
+    blocks = std::max(1, std::min(blocks, d->osd_blocks));  // d_gscratch holds osd_blocks blocks
+    HIPCHK(launch_osd(o, d->osd_variant, blocks, d->osd_threads, d->osd_lds, s));
+    return LBP_OK;
 }
 
 extern "C" {

@@ -1,15 +1,19 @@
-// Serving loop of the C ABI (lbp_server_*): continuous batching of decode
-// requests for several codes on one device.
+// Serving loop of the C ABI (lbp_server_*): per-shot streaming decode of
+// request queues for several codes on one device.
 //
-// One worker thread per server.  Each code slot owns `kInflight` batch
-// buffers; each buffer has its own stream, decoder workspace, device arrays
-// and pinned host staging.  Whenever a buffer is free and requests of that
-// slot are queued, the worker packs queued shots (FIFO, splitting large
-// requests) into it, copies them in, decodes with per-shot lottery keys
-// (seed, shot_id) and copies the results out.  A batch in flight is polled
-// with hipEventQuery; its results are scattered back into the requests, and a
-// request becomes visible to lbp_server_poll once all of its shots are back.
-// Per-shot keys make every result independent of how requests were packed.
+// Each code slot owns a ring of R items in pinned, coherent host memory
+// (syndrome + lottery key in; correction, flags and iterations out, plus a
+// completion queue of finished items) and a persistent BP grid that claims published items one shot per
+// wave.  A shot's result is visible as soon as that shot has finished: there
+// are no batch boundaries, so a converging shot never waits behind a slow one.
+// Shots whose BP run fails leave their lambda in device memory and are marked
+// OSD-pending; the worker gathers them and launches OSD on the CUs the BP
+// grid leaves free.  The BP grid exits after a short idle period (and on
+// destroy); the worker relaunches it when new items are published.
+//
+// One worker thread per server moves requests from the slot queues into the
+// rings (first come first served, at most R items in flight), reads the
+// completion queue, starts OSD launches and completes requests.
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
@@ -25,15 +29,20 @@
 
 #include "../../include/lbp.h"
 #include "lbp_internal.h"
+#include "serve_internal.h"
 
 namespace {
 
 using Clock = std::chrono::steady_clock;
 
-constexpr int kInflight = 3;             // batch buffers per code slot
-constexpr int64_t kDefaultBudget = (int64_t)4 << 30;
-constexpr int64_t kMaxTick = 8192;       // shots per batch (upper bound)
-constexpr int64_t kQueueFactor = 64;     // admission: queued shots per slot <= kQueueFactor * tick
+constexpr int64_t kMaxRing = 65536;        // items in flight per slot (upper bound, power of two)
+constexpr int64_t kMinRing = 1024;
+constexpr int64_t kQueueFactor = 16;       // admission: queued shots per slot <= kQueueFactor * R
+constexpr int64_t kOsdList = 4096;         // failed shots per OSD launch
+constexpr uint64_t kIdleTicks = 200000;    // the BP grid exits after 2 ms without a claim (100 MHz clock)
+constexpr double kOsdFraction = 0.375;     // CUs left to OSD launches
+constexpr int64_t kDefaultBudget = (int64_t)16 << 30;
+constexpr auto kQueryGap = std::chrono::microseconds(20);
 
 lbp_status sfail(lbp_status s, const std::string &m) {
     lbp::set_error(m.c_str());
@@ -49,8 +58,8 @@ struct Request {
     std::vector<uint32_t> corr;
     std::vector<uint8_t> flags;
     std::vector<int32_t> iters;
-    int64_t dispatched = 0;   // shots handed to batches
-    int64_t outstanding = 0;  // shots in batches not yet completed
+    int64_t dispatched = 0;   // shots placed in the ring
+    int64_t outstanding = 0;  // shots in the ring not yet complete
     bool cancelled = false;
     bool done = false;
     lbp_status status = LBP_OK;
@@ -59,39 +68,51 @@ struct Request {
 };
 using ReqPtr = std::shared_ptr<Request>;
 
-struct Segment {
-    ReqPtr req;
-    int64_t req_off, batch_off, count;
-};
+enum : uint8_t { S_FREE = 0, S_BP = 1, S_OSD_WAIT = 2, S_OSD_RUN = 3, S_DONE = 4 };
 
-struct Batch {
-    hipStream_t stream = nullptr;
-    hipEvent_t done = nullptr;
-    lbp_decoder dec = nullptr;
-    uint32_t *d_syn = nullptr, *d_corr = nullptr;
-    uint8_t *d_flags = nullptr;
-    int32_t *d_iters = nullptr;
-    uint64_t *d_keys = nullptr;
-    uint32_t *h_syn = nullptr, *h_corr = nullptr;
-    uint8_t *h_flags = nullptr;
-    int32_t *h_iters = nullptr;
-    uint64_t *h_keys = nullptr;
-    bool busy = false;
-    int64_t shots = 0;
-    lbp_status status = LBP_OK;
-    std::string err;
-    std::vector<Segment> segs;
+// What submit needs of a slot without taking the server lock.
+struct SlotInfo {
+    int mw = 0, nw = 0;
+    int64_t R = 0;
+    std::atomic<int64_t> queued{0};  // shots submitted and not yet in the ring
 };
 
 struct Slot {
     lbp_code code = nullptr;
-    int mw = 0, nw = 0;
-    int64_t tick = 0;
-    Batch b[kInflight];
+    lbp_decoder dec = nullptr;
+    int mw = 0, nw = 0, n = 0;
+    int64_t R = 0;
+    lbp::ServeShape shape{};
+    // host rings (pinned, coherent)
+    uint32_t *h_syn = nullptr;
+    uint64_t *h_keys = nullptr, *h_tail = nullptr, *h_cq = nullptr;
+    uint32_t *h_stop = nullptr, *h_corr = nullptr, *h_ocount = nullptr;
+    uint8_t *h_flags = nullptr;
+    int32_t *h_iters = nullptr, *h_list = nullptr;
+    // device
+    lbp::ServeRing ring{};
+    lbp::ServeRing *d_ring = nullptr;
+    unsigned long long *d_ctl = nullptr;  // head, tail, token, last claim, completion-queue tail
+    float *d_llr = nullptr;
+    int32_t *d_list = nullptr;
+    uint32_t *d_ocount = nullptr;
+    hipStream_t s_bp = nullptr, s_osd = nullptr;
+    hipEvent_t e_bp = nullptr, e_osd = nullptr;
+    bool bp_running = false, osd_running = false;
+    Clock::time_point next_query{};  // event queries are runtime calls: at most one round per kQueryGap
+    // item bookkeeping
+    uint64_t published = 0, done_upto = 0;
+    std::vector<ReqPtr> ref_req;  // request of each occupied ring slot (keeps it alive)
+    std::vector<int64_t> ref_off;
+    std::vector<uint8_t> state;
+    std::vector<uint64_t> osd_wait, osd_run;
+    uint64_t cq_head = 0;  // next completion-queue position to read
+    uint64_t bp_done = 0;  // items through BP (published - bp_done are still in BP)
     std::deque<ReqPtr> queue;
-    int64_t queued_shots = 0;
+    SlotInfo *info = nullptr;
+    int64_t dev_bytes = 0;
     // statistics
-    int64_t batches = 0, shots = 0, max_fill = 0;
+    int64_t bp_launches = 0, shots = 0, max_inflight = 0, osd_launches = 0;
 };
 
 }  // namespace
@@ -100,178 +121,324 @@ struct lbp_server_s {
     int device = 0;
     int64_t budget = 0, used = 0;
     int max_slots = 0;
-    std::vector<std::unique_ptr<Slot>> slots;
+    // mu: slots, tickets and request progress (worker, poll, wait, cancel)
     std::mutex mu;
-    std::condition_variable cv_work, cv_done;
-    std::thread worker;
-    bool stop = false;
+    std::vector<std::unique_ptr<Slot>> slots;
     std::unordered_map<uint64_t, ReqPtr> tickets;
-    uint64_t next_ticket = 1;
+    std::condition_variable cv_done;
+    std::string dead_msg;
+    // in_mu: the inbox of submitted requests and the worker's sleep (lock order: mu, then in_mu)
+    std::mutex in_mu;
+    std::vector<ReqPtr> inbox;
+    std::atomic<int64_t> inbox_n{0};  // inbox.size(), readable without in_mu
+    std::condition_variable cv_work;
+    bool idle = false, stop = false;
+    std::atomic<bool> stop_seen{false};  // stop, readable without in_mu
+    // lock-free
+    SlotInfo info[64];
+    std::atomic<int> n_slots{0};
+    std::atomic<uint64_t> next_ticket{1};
+    std::atomic<int> dead{LBP_OK};  // a device error stops the server
+    std::thread worker;
 };
 
 namespace {
 
-void free_batch(Batch &b) {
-    if (b.stream) hipStreamSynchronize(b.stream);
-    if (b.dec) lbp_decoder_destroy(b.dec);
-    hipFree(b.d_syn);
-    hipFree(b.d_corr);
-    hipFree(b.d_flags);
-    hipFree(b.d_iters);
-    hipFree(b.d_keys);
-    if (b.h_syn) hipHostFree(b.h_syn);
-    if (b.h_corr) hipHostFree(b.h_corr);
-    if (b.h_flags) hipHostFree(b.h_flags);
-    if (b.h_iters) hipHostFree(b.h_iters);
-    if (b.h_keys) hipHostFree(b.h_keys);
-    if (b.done) hipEventDestroy(b.done);
-    if (b.stream) hipStreamDestroy(b.stream);
-    b = Batch{};
+void free_slot(Slot &sl) {
+    if (sl.h_stop) __atomic_store_n(sl.h_stop, 1u, __ATOMIC_RELEASE);
+    if (sl.s_bp) (void)hipStreamSynchronize(sl.s_bp);
+    if (sl.s_osd) (void)hipStreamSynchronize(sl.s_osd);
+    if (sl.dec) lbp_decoder_destroy(sl.dec);
+    for (void *p : {(void *)sl.h_syn, (void *)sl.h_keys, (void *)sl.h_tail, (void *)sl.h_cq, (void *)sl.h_stop,
+                    (void *)sl.h_corr, (void *)sl.h_ocount, (void *)sl.h_flags, (void *)sl.h_iters, (void *)sl.h_list})
+        if (p) (void)hipHostFree(p);
+    for (void *p : {(void *)sl.d_ring, (void *)sl.d_ctl, (void *)sl.d_llr, (void *)sl.d_list, (void *)sl.d_ocount})
+        if (p) (void)hipFree(p);
+    if (sl.e_bp) (void)hipEventDestroy(sl.e_bp);
+    if (sl.e_osd) (void)hipEventDestroy(sl.e_osd);
+    if (sl.s_bp) (void)hipStreamDestroy(sl.s_bp);
+    if (sl.s_osd) (void)hipStreamDestroy(sl.s_osd);
 }
 
-// Launch one batch (worker thread, server lock NOT held: the batch's segments
-// reference requests that only the worker mutates while they are dispatched).
-void launch_batch(Slot &sl, Batch &b) {
-    const int64_t S = b.shots;
-    for (const Segment &g : b.segs) {
-        const Request &r = *g.req;
-        std::memcpy(b.h_syn + g.batch_off * sl.mw, r.syn.data() + g.req_off * sl.mw, (size_t)g.count * sl.mw * 4);
-        for (int64_t j = 0; j < g.count; ++j) {
-            b.h_keys[2 * (g.batch_off + j)] = r.seed;
-            b.h_keys[2 * (g.batch_off + j) + 1] = r.first_id + (uint64_t)(g.req_off + j);
-        }
-    }
-    b.status = LBP_OK;
-    hipError_t e = hipMemcpyAsync(b.d_syn, b.h_syn, (size_t)S * sl.mw * 4, hipMemcpyHostToDevice, b.stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(b.d_keys, b.h_keys, (size_t)S * 16, hipMemcpyHostToDevice, b.stream);
-    if (e != hipSuccess) {
-        b.status = LBP_EDEVICE;
-        b.err = std::string("server: hipMemcpyAsync: ") + hipGetErrorString(e);
-        return;
-    }
-    lbp_status st = lbp_decode_keyed(b.dec, S, b.d_keys, b.d_syn, b.d_corr, b.d_flags, b.d_iters, nullptr, b.stream);
-    if (st != LBP_OK) {
-        b.status = st;
-        b.err = lbp_last_error();
-        return;
-    }
-    e = hipMemcpyAsync(b.h_corr, b.d_corr, (size_t)S * sl.nw * 4, hipMemcpyDeviceToHost, b.stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(b.h_flags, b.d_flags, (size_t)S, hipMemcpyDeviceToHost, b.stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(b.h_iters, b.d_iters, (size_t)S * 4, hipMemcpyDeviceToHost, b.stream);
-    if (e == hipSuccess) e = hipEventRecord(b.done, b.stream);
-    if (e != hipSuccess) {
-        b.status = LBP_EDEVICE;
-        b.err = std::string("server: ") + hipGetErrorString(e);
-    }
+// Allocate the rings and device state of a slot with R items.
+lbp_status setup_slot(Slot &sl, int64_t R) {
+    sl.R = R;
+    hipError_t e = hipSuccess;
+    auto chk = [&](hipError_t x) {
+        if (e == hipSuccess) e = x;
+    };
+    const unsigned hf = hipHostMallocCoherent | hipHostMallocMapped;
+    chk(hipHostMalloc((void **)&sl.h_syn, (size_t)R * sl.mw * 4, hf));
+    chk(hipHostMalloc((void **)&sl.h_keys, (size_t)R * 16, hf));
+    chk(hipHostMalloc((void **)&sl.h_tail, 64, hf));
+    chk(hipHostMalloc((void **)&sl.h_stop, 64, hf));
+    chk(hipHostMalloc((void **)&sl.h_corr, (size_t)R * sl.nw * 4, hf));
+    chk(hipHostMalloc((void **)&sl.h_flags, (size_t)R, hf));
+    chk(hipHostMalloc((void **)&sl.h_iters, (size_t)R * 4, hf));
+    chk(hipHostMalloc((void **)&sl.h_cq, (size_t)R * 8, hf));
+    chk(hipHostMalloc((void **)&sl.h_list, (size_t)kOsdList * 4, hipHostMallocDefault));
+    chk(hipHostMalloc((void **)&sl.h_ocount, 64, hipHostMallocDefault));
+    chk(hipMalloc((void **)&sl.d_ring, sizeof(lbp::ServeRing)));
+    chk(hipMalloc((void **)&sl.d_ctl, 64));
+    chk(hipMalloc((void **)&sl.d_llr, (size_t)R * 2 * sl.n * 4));
+    chk(hipMalloc((void **)&sl.d_list, (size_t)kOsdList * 4));
+    chk(hipMalloc((void **)&sl.d_ocount, 64));
+    chk(hipStreamCreateWithFlags(&sl.s_bp, hipStreamNonBlocking));
+    chk(hipStreamCreateWithFlags(&sl.s_osd, hipStreamNonBlocking));
+    chk(hipEventCreateWithFlags(&sl.e_bp, hipEventDisableTiming));
+    chk(hipEventCreateWithFlags(&sl.e_osd, hipEventDisableTiming));
+    if (e != hipSuccess)
+        return sfail(e == hipErrorOutOfMemory ? LBP_ENOMEM : LBP_EDEVICE,
+                     std::string("lbp_server_add_code: ") + hipGetErrorString(e));
+    std::memset(sl.h_cq, 0, (size_t)R * 8);  // lap field 0: no entry yet
+    *sl.h_tail = 0;
+    *sl.h_stop = 0;
+    std::memset(sl.h_ocount, 0, 64);
+    unsigned long long zero[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    chk(hipMemcpy(sl.d_ctl, zero, 64, hipMemcpyHostToDevice));
+    chk(hipMemcpy(sl.d_ocount, zero, 64, hipMemcpyHostToDevice));
+    lbp::ServeRing &r = sl.ring;
+    r.syn = sl.h_syn;
+    r.keys = sl.h_keys;
+    r.host_tail = sl.h_tail;
+    r.host_stop = sl.h_stop;
+    r.corr = sl.h_corr;
+    r.flags = sl.h_flags;
+    r.iters = sl.h_iters;
+    r.cq = sl.h_cq;
+    r.cq_tail = sl.d_ctl + 4;
+    r.head = sl.d_ctl;
+    r.tail = sl.d_ctl + 1;
+    r.token = (uint32_t *)(sl.d_ctl + 2);
+    r.last_claim = sl.d_ctl + 3;
+    r.llr = sl.d_llr;
+    r.mask = R - 1;
+    r.idle_ticks = kIdleTicks;
+    chk(hipMemcpy(sl.d_ring, &r, sizeof(r), hipMemcpyHostToDevice));
+    if (e != hipSuccess) return sfail(LBP_EDEVICE, std::string("lbp_server_add_code: ") + hipGetErrorString(e));
+    sl.ref_req.assign((size_t)R, ReqPtr());
+    sl.ref_off.assign((size_t)R, 0);
+    sl.state.assign((size_t)R, S_FREE);
+    sl.dev_bytes = (int64_t)R * 2 * sl.n * 4 + lbp_decoder_device_bytes(sl.dec) + 4096;
+    return LBP_OK;
 }
 
-// Fill a free batch from the slot's queue (lock held).  Returns false if empty.
-bool pack_batch(Slot &sl, Batch &b) {
-    b.segs.clear();
-    b.shots = 0;
-    while (!sl.queue.empty() && b.shots < sl.tick) {
+void finish_request(lbp_server srv, Request &r, Clock::time_point now) {
+    r.done = true;
+    r.t_done = now;
+    if (r.cancelled) srv->tickets.erase(r.ticket);
+}
+
+// One shot finished (lock held): copy its outputs and release its ring slot.
+void complete_item(lbp_server srv, Slot &sl, uint64_t item, Clock::time_point now) {
+    const int64_t k = (int64_t)(item & (uint64_t)(sl.R - 1));
+    Request *r = sl.ref_req[k].get();
+    const int64_t off = sl.ref_off[k];
+    if (!r->cancelled) {
+        std::memcpy(r->corr.data() + off * sl.nw, sl.h_corr + k * sl.nw, (size_t)sl.nw * 4);
+        r->flags[off] = sl.h_flags[k];
+        r->iters[off] = sl.h_iters[k];
+    }
+    sl.state[k] = S_DONE;
+    sl.shots += 1;
+    if (--r->outstanding == 0 && (r->dispatched == r->n || r->cancelled)) finish_request(srv, *r, now);
+    sl.ref_req[k].reset();
+}
+
+// Move queued shots into the ring (lock held).  Returns true if any moved.
+bool publish(Slot &sl) {
+    const uint64_t start = sl.published;
+    while (!sl.queue.empty() && (int64_t)(sl.published - sl.done_upto) < sl.R) {
         ReqPtr r = sl.queue.front();
-        if (r->cancelled || r->status != LBP_OK) {  // never dispatched further
-            sl.queued_shots -= r->n - r->dispatched;
-            sl.queue.pop_front();
+        if (r->cancelled) {
+            sl.queue.pop_front();  // its undispatched shots left the count when it was cancelled
             continue;
         }
-        const int64_t take = std::min(r->n - r->dispatched, sl.tick - b.shots);
-        b.segs.push_back({r, r->dispatched, b.shots, take});
-        r->dispatched += take;
-        r->outstanding += take;
-        b.shots += take;
-        sl.queued_shots -= take;
+        while (r->dispatched < r->n && (int64_t)(sl.published - sl.done_upto) < sl.R) {
+            const uint64_t item = sl.published++;
+            const int64_t k = (int64_t)(item & (uint64_t)(sl.R - 1));
+            const int64_t off = r->dispatched++;
+            std::memcpy(sl.h_syn + k * sl.mw, r->syn.data() + off * sl.mw, (size_t)sl.mw * 4);
+            sl.h_keys[2 * k] = r->seed;
+            sl.h_keys[2 * k + 1] = r->first_id + (uint64_t)off;
+            sl.ref_req[k] = r;
+            sl.ref_off[k] = off;
+            sl.state[k] = S_BP;
+            r->outstanding += 1;
+            sl.info->queued.fetch_sub(1, std::memory_order_relaxed);
+        }
         if (r->dispatched == r->n) sl.queue.pop_front();
     }
-    return b.shots > 0;
+    if (sl.published == start) return false;
+    __atomic_store_n(sl.h_tail, sl.published, __ATOMIC_RELEASE);
+    sl.max_inflight = std::max<int64_t>(sl.max_inflight, (int64_t)(sl.published - sl.done_upto));
+    return true;
 }
 
-// Scatter the results of a finished batch into its requests (lock held).
-void complete_batch(lbp_server srv, Slot &sl, Batch &b) {
+// Advance the reuse bound past finished items.
+void retire(Slot &sl) {
+    while (sl.done_upto < sl.published && sl.state[sl.done_upto & (uint64_t)(sl.R - 1)] == S_DONE) {
+        sl.state[sl.done_upto & (uint64_t)(sl.R - 1)] = S_FREE;
+        ++sl.done_upto;
+    }
+}
+
+// One pass over a slot (lock held).  Returns true if anything progressed.
+bool service(lbp_server srv, Slot &sl, bool &busy) {
+    bool progressed = publish(sl);
     const auto now = Clock::now();
-    for (const Segment &g : b.segs) {
-        Request &r = *g.req;
-        if (b.status != LBP_OK && r.status == LBP_OK) {
-            r.status = b.status;
-            r.err = b.err;
+    // BP results, in completion-queue order
+    const uint64_t item_mask = (1ull << lbp::CQ_ITEM_BITS) - 1;
+    for (;;) {
+        const int64_t q = (int64_t)(sl.cq_head & (uint64_t)(sl.R - 1));
+        const uint64_t e = __atomic_load_n(sl.h_cq + q, __ATOMIC_ACQUIRE);
+        if ((e >> lbp::CQ_ITEM_BITS) != (lbp::cq_entry(sl.cq_head, 0, sl.R - 1) >> lbp::CQ_ITEM_BITS)) break;
+        // the item in flight whose low bits the entry carries
+        const uint64_t item = sl.done_upto + (((e & item_mask) - sl.done_upto) & item_mask);
+        const int64_t k = (int64_t)(item & (uint64_t)(sl.R - 1));
+        if (item >= sl.published || sl.state[k] != S_BP || !sl.ref_req[k]) {
+            srv->dead_msg = "server: completion queue names item " + std::to_string(item) + " (in flight: " +
+                            std::to_string(sl.done_upto) + ".." + std::to_string(sl.published) + ")";
+            srv->dead = LBP_EDEVICE;
+            return true;
         }
-        if (!r.cancelled && b.status == LBP_OK) {
-            std::memcpy(r.corr.data() + g.req_off * sl.nw, b.h_corr + g.batch_off * sl.nw, (size_t)g.count * sl.nw * 4);
-            std::memcpy(r.flags.data() + g.req_off, b.h_flags + g.batch_off, (size_t)g.count);
-            std::memcpy(r.iters.data() + g.req_off, b.h_iters + g.batch_off, (size_t)g.count * 4);
-        }
-        r.outstanding -= g.count;
-        if (r.outstanding == 0 && (r.dispatched == r.n || r.cancelled || r.status != LBP_OK)) {
-            r.done = true;
-            r.t_done = now;
-            if (r.cancelled) srv->tickets.erase(r.ticket);
+        ++sl.cq_head;
+        ++sl.bp_done;
+        progressed = true;
+        if (sl.h_flags[k] & lbp::FLAG_OSD_PENDING) {
+            sl.state[k] = S_OSD_WAIT;
+            sl.osd_wait.push_back(item);
+        } else {
+            complete_item(srv, sl, item, now);
         }
     }
-    sl.batches += 1;
-    sl.shots += b.shots;
-    sl.max_fill = std::max(sl.max_fill, b.shots);
-    b.segs.clear();
-    b.busy = false;
+    const bool query = now >= sl.next_query;
+    if (query) sl.next_query = now + kQueryGap;
+    // OSD launches
+    if (query && sl.osd_running && hipEventQuery(sl.e_osd) == hipSuccess) {
+        sl.osd_running = false;
+        for (uint64_t item : sl.osd_run) complete_item(srv, sl, item, now);
+        sl.osd_run.clear();
+        progressed = true;
+    }
+    if (!sl.osd_running && !sl.osd_wait.empty()) {
+        const size_t cnt = std::min<size_t>(sl.osd_wait.size(), (size_t)kOsdList);
+        for (size_t q = 0; q < cnt; ++q) {
+            const uint64_t item = sl.osd_wait[q];
+            sl.h_list[q] = (int32_t)(item & (uint64_t)(sl.R - 1));
+            sl.state[sl.h_list[q]] = S_OSD_RUN;
+            sl.osd_run.push_back(item);
+        }
+        sl.osd_wait.erase(sl.osd_wait.begin(), sl.osd_wait.begin() + (long)cnt);
+        sl.h_ocount[1] = (uint32_t)cnt;
+        hipError_t e = hipMemcpyAsync(sl.d_list, sl.h_list, cnt * 4, hipMemcpyHostToDevice, sl.s_osd);
+        if (e == hipSuccess) e = hipMemcpyAsync(sl.d_ocount, sl.h_ocount, 8, hipMemcpyHostToDevice, sl.s_osd);
+        lbp_status st = e == hipSuccess ? lbp::serve_launch_osd(sl.dec, sl.ring, sl.d_list, sl.d_ocount,
+                                                                sl.shape.osd_blocks, sl.s_osd)
+                                        : LBP_EDEVICE;
+        if (st == LBP_OK && hipEventRecord(sl.e_osd, sl.s_osd) == hipSuccess) {
+            sl.osd_running = true;
+            sl.osd_launches += 1;
+        } else {
+            srv->dead_msg = std::string("server: OSD launch failed: ") + lbp_last_error();
+            srv->dead = LBP_EDEVICE;
+        }
+        progressed = true;
+    }
+    // keep a BP grid running while items wait for it
+    if (query && sl.bp_running && hipEventQuery(sl.e_bp) == hipSuccess) sl.bp_running = false;
+    const bool bp_waiting = sl.bp_done < sl.published;
+    if (!sl.bp_running && bp_waiting && srv->dead.load() == LBP_OK) {
+        lbp_status st = lbp::serve_launch_bp(sl.dec, sl.d_ring, sl.shape.bp_blocks, sl.s_bp);
+        if (st == LBP_OK && hipEventRecord(sl.e_bp, sl.s_bp) == hipSuccess) {
+            sl.bp_running = true;
+            sl.bp_launches += 1;
+        } else {
+            srv->dead_msg = std::string("server: BP launch failed: ") + lbp_last_error();
+            srv->dead = LBP_EDEVICE;
+        }
+        progressed = true;
+    }
+    retire(sl);
+    busy = busy || bp_waiting || sl.osd_running || !sl.osd_wait.empty() || !sl.queue.empty();
+    return progressed;
+}
+
+// A device error ends every pending request with that error (mu held).
+void fail_all(lbp_server srv) {
+    const auto now = Clock::now();
+    std::vector<ReqPtr> in;
+    {
+        std::lock_guard<std::mutex> il(srv->in_mu);
+        in.swap(srv->inbox);
+        srv->inbox_n.store(0);
+    }
+    for (auto &r : in) srv->tickets[r->ticket] = r;
+    for (auto &kv : srv->tickets) {
+        Request &r = *kv.second;
+        if (r.done) continue;
+        r.status = (lbp_status)srv->dead.load();
+        r.err = srv->dead_msg;
+        r.done = true;
+        r.t_done = now;
+    }
+    for (auto &sp : srv->slots) {
+        sp->queue.clear();
+        sp->info->queued.store(0);
+    }
+}
+
+// Move submitted requests into the ticket table and slot queues (mu held).
+// Returns false when the server is stopping.
+bool drain_inbox(lbp_server srv) {
+    std::vector<ReqPtr> in;
+    if (srv->inbox_n.load(std::memory_order_acquire) > 0 || srv->stop_seen.load(std::memory_order_acquire)) {
+        std::lock_guard<std::mutex> il(srv->in_mu);
+        if (srv->stop) return false;
+        in.swap(srv->inbox);
+        srv->inbox_n.store(0, std::memory_order_relaxed);
+    }
+    for (auto &r : in) {
+        srv->tickets[r->ticket] = r;
+        srv->slots[r->slot]->queue.push_back(r);
+    }
+    return true;
 }
 
 void worker_main(lbp_server srv) {
-    hipSetDevice(srv->device);
+    (void)hipSetDevice(srv->device);
     std::unique_lock<std::mutex> lk(srv->mu);
-    size_t rr = 0;
-    while (!srv->stop) {
-        bool progressed = false, any_busy = false;
-        // 1. completions
-        for (auto &sp : srv->slots) {
-            for (Batch &b : sp->b) {
-                if (!b.busy) continue;
-                if (b.status != LBP_OK || hipEventQuery(b.done) == hipSuccess) {
-                    complete_batch(srv, *sp, b);
-                    progressed = true;
-                } else {
-                    any_busy = true;
-                }
-            }
+    while (drain_inbox(srv)) {
+        bool busy = false, progressed = false;
+        for (auto &sp : srv->slots) progressed |= service(srv, *sp, busy);
+        if (srv->dead.load() != LBP_OK) {
+            fail_all(srv);
+            srv->cv_done.notify_all();
+            lk.unlock();
+            std::unique_lock<std::mutex> il(srv->in_mu);
+            srv->cv_work.wait(il, [&] { return srv->stop; });
+            return;
         }
         if (progressed) srv->cv_done.notify_all();
-        // 2. dispatch, round robin over slots
-        const size_t ns = srv->slots.size();
-        for (size_t k = 0; k < ns; ++k) {
-            Slot &sl = *srv->slots[(rr + k) % ns];
-            for (Batch &b : sl.b) {
-                if (b.busy || sl.queue.empty()) continue;
-                if (!pack_batch(sl, b)) continue;
-                b.busy = true;
-                any_busy = true;
-                progressed = true;
-                lk.unlock();
-                launch_batch(sl, b);
-                lk.lock();
-            }
-        }
-        rr = ns ? (rr + 1) % ns : 0;
-        if (progressed) continue;
-        if (any_busy) {
-            lk.unlock();
-            std::this_thread::yield();
-            lk.lock();
+        lk.unlock();
+        if (progressed || busy) {  // let pollers in between passes
+            if (!progressed)
+                for (int k = 0; k < 64; ++k) __builtin_ia32_pause();
         } else {
-            srv->cv_work.wait(lk, [&] {
-                if (srv->stop) return true;
-                for (auto &sp : srv->slots)
-                    if (!sp->queue.empty()) return true;
-                return false;
-            });
+            std::unique_lock<std::mutex> il(srv->in_mu);
+            srv->idle = true;
+            srv->cv_work.wait(il, [&] { return srv->stop || !srv->inbox.empty(); });
+            srv->idle = false;
         }
+        lk.lock();
     }
 }
 
-lbp_status copy_out(const Slot &sl, const Request &r, uint32_t *corrections, uint8_t *flags, int32_t *iters) {
+lbp_status copy_out(const Request &r, uint32_t *corrections, uint8_t *flags, int32_t *iters) {
     if (r.status != LBP_OK) return sfail(r.status, r.err);
     if (corrections) std::memcpy(corrections, r.corr.data(), r.corr.size() * 4);
     if (flags) std::memcpy(flags, r.flags.data(), r.flags.size());
     if (iters) std::memcpy(iters, r.iters.data(), r.iters.size() * 4);
-    (void)sl;
     return LBP_OK;
 }
 
@@ -305,138 +472,140 @@ lbp_status lbp_server_create(int64_t device_mem_budget_bytes, int32_t max_slots,
 lbp_status lbp_server_add_code(lbp_server srv, lbp_code code, const lbp_params *prm, int32_t *code_slot) {
     lbp::set_error("");
     if (!srv || !code || !prm || !code_slot) return sfail(LBP_EINVAL, "lbp_server_add_code: NULL argument");
-    {
-        std::lock_guard<std::mutex> lk(srv->mu);
-        if ((int)srv->slots.size() >= srv->max_slots) return sfail(LBP_EBUSY, "lbp_server_add_code: all slots in use");
-    }
-    int prev = 0;
-    hipGetDevice(&prev);
-    hipSetDevice(srv->device);
-    auto sl = std::make_unique<Slot>();
-    sl->code = code;
-    const int m = lbp_code_rows(code), n = lbp_code_cols(code);
-    sl->mw = (m + 31) / 32;
-    sl->nw = (n + 31) / 32;
-    lbp_status st = LBP_OK;
-    int64_t bytes = 0;
-    // largest tick (power of two <= kMaxTick) whose buffers fit what is left of the budget
     int64_t left;
     {
         std::lock_guard<std::mutex> lk(srv->mu);
+        if ((int)srv->slots.size() >= srv->max_slots) return sfail(LBP_EBUSY, "lbp_server_add_code: all slots in use");
         left = srv->budget - srv->used;
     }
-    for (int64_t tick = kMaxTick; tick >= 1; tick /= 2) {
-        for (Batch &b : sl->b) free_batch(b);
-        bytes = 0;
-        st = LBP_OK;
-        for (Batch &b : sl->b) {
-            st = lbp_decoder_create(code, prm, tick, &b.dec);
-            if (st != LBP_OK) break;
-            bytes += lbp_decoder_device_bytes(b.dec);
-            const size_t io = (size_t)tick * (sl->mw * 4 + sl->nw * 4 + 1 + 4 + 16);
-            bytes += (int64_t)io;
-            hipError_t e = hipSuccess;
-            auto chk = [&](hipError_t x) {
-                if (e == hipSuccess) e = x;
-            };
-            chk(hipStreamCreateWithFlags(&b.stream, hipStreamNonBlocking));
-            chk(hipEventCreateWithFlags(&b.done, hipEventDisableTiming));
-            chk(hipMalloc((void **)&b.d_syn, (size_t)tick * sl->mw * 4));
-            chk(hipMalloc((void **)&b.d_corr, (size_t)tick * sl->nw * 4));
-            chk(hipMalloc((void **)&b.d_flags, (size_t)tick));
-            chk(hipMalloc((void **)&b.d_iters, (size_t)tick * 4));
-            chk(hipMalloc((void **)&b.d_keys, (size_t)tick * 16));
-            chk(hipHostMalloc((void **)&b.h_syn, (size_t)tick * sl->mw * 4, hipHostMallocDefault));
-            chk(hipHostMalloc((void **)&b.h_corr, (size_t)tick * sl->nw * 4, hipHostMallocDefault));
-            chk(hipHostMalloc((void **)&b.h_flags, (size_t)tick, hipHostMallocDefault));
-            chk(hipHostMalloc((void **)&b.h_iters, (size_t)tick * 4, hipHostMallocDefault));
-            chk(hipHostMalloc((void **)&b.h_keys, (size_t)tick * 16, hipHostMallocDefault));
-            if (e != hipSuccess) {
-                st = e == hipErrorOutOfMemory ? LBP_ENOMEM : LBP_EDEVICE;
-                lbp::set_error((std::string("lbp_server_add_code: ") + hipGetErrorString(e)).c_str());
-                break;
-            }
-        }
-        if (st == LBP_OK && bytes <= left) {
-            sl->tick = tick;
-            break;
-        }
-        if (st != LBP_OK && st != LBP_ENOMEM) break;  // parameters or device error: no smaller tick helps
-    }
-    if (st != LBP_OK || sl->tick == 0) {
+    int prev = 0;
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(srv->device);
+    auto sl = std::make_unique<Slot>();
+    sl->code = code;
+    const int m = lbp_code_rows(code);
+    sl->n = lbp_code_cols(code);
+    sl->mw = (m + 31) / 32;
+    sl->nw = (sl->n + 31) / 32;
+    lbp_status st = lbp_decoder_create(code, prm, kOsdList, &sl->dec);
+    if (st == LBP_OK) st = lbp::serve_shape(sl->dec, kOsdFraction, &sl->shape);
+    if (st != LBP_OK) {
         std::string msg = lbp_last_error();
-        for (Batch &b : sl->b) free_batch(b);
-        hipSetDevice(prev);
-        if (st != LBP_OK && st != LBP_ENOMEM) return sfail(st, msg);
+        free_slot(*sl);
+        (void)hipSetDevice(prev);
+        return sfail(st, msg);
+    }
+    // the largest ring whose lambda staging (R * 8n bytes) fits the budget left
+    const int64_t fixed = lbp_decoder_device_bytes(sl->dec) + 4096;
+    int64_t R = kMaxRing;
+    while (R > kMinRing && fixed + R * 8 * (int64_t)sl->n > left) R /= 2;
+    if (fixed + R * 8 * (int64_t)sl->n > left) {
+        free_slot(*sl);
+        (void)hipSetDevice(prev);
         return sfail(LBP_ENOMEM, "lbp_server_add_code: the code's buffers do not fit the device memory budget");
     }
-    hipSetDevice(prev);
+    st = setup_slot(*sl, R);
+    (void)hipSetDevice(prev);
+    if (st != LBP_OK) {
+        std::string msg = lbp_last_error();
+        free_slot(*sl);
+        return sfail(st, msg);
+    }
     std::lock_guard<std::mutex> lk(srv->mu);
-    if ((int)srv->slots.size() >= srv->max_slots || srv->used + bytes > srv->budget) {
-        for (Batch &b : sl->b) free_batch(b);
+    if ((int)srv->slots.size() >= srv->max_slots || srv->used + sl->dev_bytes > srv->budget) {
+        free_slot(*sl);
         return sfail(LBP_EBUSY, "lbp_server_add_code: slots or budget taken concurrently");
     }
-    srv->used += bytes;
-    *code_slot = (int32_t)srv->slots.size();
+    srv->used += sl->dev_bytes;
+    const int idx = (int)srv->slots.size();
+    SlotInfo &inf = srv->info[idx];
+    inf.mw = sl->mw;
+    inf.nw = sl->nw;
+    inf.R = sl->R;
+    inf.queued.store(0);
+    sl->info = &inf;
     srv->slots.push_back(std::move(sl));
+    srv->n_slots.store(idx + 1, std::memory_order_release);  // submit may use the slot from here on
+    *code_slot = (int32_t)idx;
     return LBP_OK;
 }
 
+static lbp_status submit_impl(lbp_server srv, int32_t code_slot, int64_t n_shots, uint64_t seed, uint64_t first_shot_id,
+                       const uint32_t *host_syndromes, uint64_t *ticket, ReqPtr *out_req);
+
 lbp_status lbp_server_submit(lbp_server srv, int32_t code_slot, int64_t n_shots, uint64_t seed,
                              uint64_t first_shot_id, const uint32_t *host_syndromes, uint64_t *ticket) {
+    return submit_impl(srv, code_slot, n_shots, seed, first_shot_id, host_syndromes, ticket, nullptr);
+}
+
+static lbp_status submit_impl(lbp_server srv, int32_t code_slot, int64_t n_shots, uint64_t seed, uint64_t first_shot_id,
+                       const uint32_t *host_syndromes, uint64_t *ticket, ReqPtr *out_req) {
     lbp::set_error("");
     if (!srv || !ticket) return sfail(LBP_EINVAL, "lbp_server_submit: NULL argument");
     if (n_shots < 1) return sfail(LBP_EINVAL, "lbp_server_submit: n_shots must be >= 1");
     if (!host_syndromes) return sfail(LBP_EINVAL, "lbp_server_submit: NULL syndromes");
-    auto r = std::make_shared<Request>();
-    int mw, nw;
-    {
-        std::lock_guard<std::mutex> lk(srv->mu);
-        if (code_slot < 0 || code_slot >= (int)srv->slots.size()) return sfail(LBP_EINVAL, "lbp_server_submit: unknown code slot");
-        Slot &sl = *srv->slots[code_slot];
-        if (sl.queued_shots + n_shots > kQueueFactor * sl.tick)
-            return sfail(LBP_EBUSY, "lbp_server_submit: queue full (admission refused)");
-        mw = sl.mw;
-        nw = sl.nw;
+    if (code_slot < 0 || code_slot >= srv->n_slots.load(std::memory_order_acquire))
+        return sfail(LBP_EINVAL, "lbp_server_submit: unknown code slot");
+    if (srv->dead.load() != LBP_OK) return sfail((lbp_status)srv->dead.load(), "lbp_server_submit: server stopped after a device error");
+    SlotInfo &inf = srv->info[code_slot];
+    // admission: reserve the shots in the slot's queue count
+    if (inf.queued.fetch_add(n_shots) + n_shots > kQueueFactor * inf.R) {
+        inf.queued.fetch_sub(n_shots);
+        return sfail(LBP_EBUSY, "lbp_server_submit: queue full (admission refused)");
     }
+    auto r = std::make_shared<Request>();
     r->slot = code_slot;
     r->n = n_shots;
     r->seed = seed;
     r->first_id = first_shot_id;
     try {
-        r->syn.assign(host_syndromes, host_syndromes + (size_t)n_shots * mw);
-        r->corr.resize((size_t)n_shots * nw);
+        r->syn.assign(host_syndromes, host_syndromes + (size_t)n_shots * inf.mw);
+        r->corr.resize((size_t)n_shots * inf.nw);
         r->flags.resize((size_t)n_shots);
         r->iters.resize((size_t)n_shots);
     } catch (...) {
+        inf.queued.fetch_sub(n_shots);
         return sfail(LBP_ENOMEM, "lbp_server_submit: host allocation failed");
     }
+    r->ticket = srv->next_ticket.fetch_add(1);
+    r->t_submit = Clock::now();
+    *ticket = r->ticket;
+    if (out_req) *out_req = r;
+    bool wake;
     {
-        std::lock_guard<std::mutex> lk(srv->mu);
-        Slot &sl = *srv->slots[code_slot];
-        if (sl.queued_shots + n_shots > kQueueFactor * sl.tick)
-            return sfail(LBP_EBUSY, "lbp_server_submit: queue full (admission refused)");
-        r->ticket = srv->next_ticket++;
-        r->t_submit = Clock::now();
-        srv->tickets[r->ticket] = r;
-        sl.queue.push_back(r);
-        sl.queued_shots += n_shots;
-        *ticket = r->ticket;
+        std::lock_guard<std::mutex> il(srv->in_mu);
+        srv->inbox.push_back(std::move(r));
+        srv->inbox_n.fetch_add(1, std::memory_order_release);
+        wake = srv->idle;
     }
-    srv->cv_work.notify_one();
+    if (wake) srv->cv_work.notify_one();
     return LBP_OK;
+}
+
+// The request of a ticket, from the ticket table or the inbox (mu held).
+static ReqPtr find_ticket(lbp_server srv, uint64_t ticket, bool *in_inbox) {
+    *in_inbox = false;
+    auto it = srv->tickets.find(ticket);
+    if (it != srv->tickets.end()) return it->second;
+    std::lock_guard<std::mutex> il(srv->in_mu);
+    for (auto &r : srv->inbox)
+        if (r->ticket == ticket) {
+            *in_inbox = true;
+            return r;
+        }
+    return nullptr;
 }
 
 lbp_status lbp_server_poll(lbp_server srv, uint64_t ticket, uint32_t *corrections, uint8_t *flags, int32_t *iters) {
     lbp::set_error("");
     if (!srv) return sfail(LBP_EINVAL, "lbp_server_poll: NULL server");
     std::lock_guard<std::mutex> lk(srv->mu);
-    auto it = srv->tickets.find(ticket);
-    if (it == srv->tickets.end()) return sfail(LBP_EINVAL, "lbp_server_poll: unknown ticket");
-    ReqPtr r = it->second;
-    if (!r->done) return LBP_ENOTREADY;
-    srv->tickets.erase(it);
-    return copy_out(*srv->slots[r->slot], *r, corrections, flags, iters);
+    bool in_inbox;
+    ReqPtr r = find_ticket(srv, ticket, &in_inbox);
+    if (!r) return sfail(LBP_EINVAL, "lbp_server_poll: unknown ticket");
+    if (in_inbox || !r->done) return LBP_ENOTREADY;
+    srv->tickets.erase(ticket);
+    return copy_out(*r, corrections, flags, iters);
 }
 
 lbp_status lbp_server_wait(lbp_server srv, uint64_t ticket, int64_t timeout_us, uint32_t *corrections, uint8_t *flags,
@@ -444,51 +613,62 @@ lbp_status lbp_server_wait(lbp_server srv, uint64_t ticket, int64_t timeout_us, 
     lbp::set_error("");
     if (!srv) return sfail(LBP_EINVAL, "lbp_server_wait: NULL server");
     std::unique_lock<std::mutex> lk(srv->mu);
-    auto it = srv->tickets.find(ticket);
-    if (it == srv->tickets.end()) return sfail(LBP_EINVAL, "lbp_server_wait: unknown ticket");
-    ReqPtr r = it->second;
+    bool in_inbox;
+    ReqPtr r = find_ticket(srv, ticket, &in_inbox);
+    if (!r) return sfail(LBP_EINVAL, "lbp_server_wait: unknown ticket");
     auto ready = [&] { return r->done; };
     if (timeout_us < 0) srv->cv_done.wait(lk, ready);
     else if (!srv->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us), ready)) return LBP_ENOTREADY;
-    srv->tickets.erase(r->ticket);
-    return copy_out(*srv->slots[r->slot], *r, corrections, flags, iters);
+    srv->tickets.erase(ticket);
+    return copy_out(*r, corrections, flags, iters);
 }
 
 lbp_status lbp_server_cancel(lbp_server srv, uint64_t ticket) {
     lbp::set_error("");
     if (!srv) return sfail(LBP_EINVAL, "lbp_server_cancel: NULL server");
     std::lock_guard<std::mutex> lk(srv->mu);
-    auto it = srv->tickets.find(ticket);
-    if (it == srv->tickets.end()) return sfail(LBP_EINVAL, "lbp_server_cancel: unknown ticket");
-    ReqPtr r = it->second;
+    bool in_inbox;
+    ReqPtr r = find_ticket(srv, ticket, &in_inbox);
+    if (!r) return sfail(LBP_EINVAL, "lbp_server_cancel: unknown ticket");
+    if (in_inbox) {
+        std::lock_guard<std::mutex> il(srv->in_mu);
+        for (auto q = srv->inbox.begin(); q != srv->inbox.end(); ++q)
+            if (q->get() == r.get()) {
+                srv->inbox.erase(q);
+                srv->inbox_n.fetch_sub(1);
+                break;
+            }
+        srv->info[r->slot].queued.fetch_sub(r->n);
+        return LBP_OK;
+    }
     if (!r->done) {
         r->cancelled = true;
-        if (r->outstanding > 0) return LBP_OK;  // dropped when its batches complete
-        // still queued in full or in part: drop the undispatched rest now
         Slot &sl = *srv->slots[r->slot];
+        // shots not yet in the ring are never published
         for (auto q = sl.queue.begin(); q != sl.queue.end(); ++q)
             if (q->get() == r.get()) {
-                sl.queued_shots -= r->n - r->dispatched;
                 sl.queue.erase(q);
                 break;
             }
+        sl.info->queued.fetch_sub(r->n - r->dispatched);
+        if (r->outstanding > 0) r->dispatched = r->n;  // shots in the ring complete (and are discarded) later
     }
-    srv->tickets.erase(it);
+    srv->tickets.erase(ticket);
     return LBP_OK;
 }
 
-lbp_status lbp_server_slot_info(lbp_server srv, int32_t code_slot, int64_t *tick_shots, int64_t *batches,
-                                int64_t *shots, int64_t *max_fill, int64_t *queued_shots) {
+lbp_status lbp_server_slot_info(lbp_server srv, int32_t code_slot, int64_t *ring_items, int64_t *bp_launches,
+                                int64_t *shots, int64_t *max_inflight, int64_t *queued_shots) {
     lbp::set_error("");
     if (!srv) return sfail(LBP_EINVAL, "lbp_server_slot_info: NULL server");
     std::lock_guard<std::mutex> lk(srv->mu);
     if (code_slot < 0 || code_slot >= (int)srv->slots.size()) return sfail(LBP_EINVAL, "lbp_server_slot_info: unknown code slot");
     const Slot &sl = *srv->slots[code_slot];
-    if (tick_shots) *tick_shots = sl.tick;
-    if (batches) *batches = sl.batches;
+    if (ring_items) *ring_items = sl.R;
+    if (bp_launches) *bp_launches = sl.bp_launches;
     if (shots) *shots = sl.shots;
-    if (max_fill) *max_fill = sl.max_fill;
-    if (queued_shots) *queued_shots = sl.queued_shots;
+    if (max_inflight) *max_inflight = sl.max_inflight;
+    if (queued_shots) *queued_shots = sl.info->queued.load();
     return LBP_OK;
 }
 
@@ -502,15 +682,12 @@ lbp_status lbp_server_run_load(lbp_server srv, int32_t n_codes, const int32_t *c
     if (n_codes < 1 || n_requests < 1 || shots_per_request < 1 || !(requests_per_s >= 0.0))
         return sfail(LBP_EINVAL, "lbp_server_run_load: bad sizes or rate");
     std::vector<int> mw(n_codes);
-    {
-        std::lock_guard<std::mutex> lk(srv->mu);
-        for (int k = 0; k < n_codes; ++k) {
-            if (code_slots[k] < 0 || code_slots[k] >= (int)srv->slots.size())
-                return sfail(LBP_EINVAL, "lbp_server_run_load: unknown code slot");
-            if (pool[k] < shots_per_request || !host_syndromes[k])
-                return sfail(LBP_EINVAL, "lbp_server_run_load: syndrome pool smaller than one request");
-            mw[k] = srv->slots[code_slots[k]]->mw;
-        }
+    for (int k = 0; k < n_codes; ++k) {
+        if (code_slots[k] < 0 || code_slots[k] >= srv->n_slots.load(std::memory_order_acquire))
+            return sfail(LBP_EINVAL, "lbp_server_run_load: unknown code slot");
+        if (pool[k] < shots_per_request || !host_syndromes[k])
+            return sfail(LBP_EINVAL, "lbp_server_run_load: syndrome pool smaller than one request");
+        mw[k] = srv->info[code_slots[k]].mw;
     }
     std::mt19937_64 rng(seed);
     std::exponential_distribution<double> gap(requests_per_s > 0 ? requests_per_s : 1.0);
@@ -536,12 +713,10 @@ lbp_status lbp_server_run_load(lbp_server srv, int32_t n_codes, const int32_t *c
         }
         uint64_t ticket = 0;
         lbp_status st;
-        while ((st = lbp_server_submit(srv, code_slots[k], shots_per_request, seed, (uint64_t)q * shots_per_request,
-                                       syn, &ticket)) == LBP_EBUSY)
+        while ((st = submit_impl(srv, code_slots[k], shots_per_request, seed, (uint64_t)q * shots_per_request, syn,
+                                 &ticket, &reqs[q])) == LBP_EBUSY)
             std::this_thread::yield();
         if (st != LBP_OK) return st;
-        std::lock_guard<std::mutex> lk(srv->mu);
-        reqs[q] = srv->tickets[ticket];
     }
     Clock::time_point t_last = t0;
     for (int64_t q = 0; q < n_requests; ++q) {
@@ -557,17 +732,17 @@ lbp_status lbp_server_run_load(lbp_server srv, int32_t n_codes, const int32_t *c
 void lbp_server_destroy(lbp_server srv) {
     if (!srv) return;
     {
-        std::lock_guard<std::mutex> lk(srv->mu);
+        std::lock_guard<std::mutex> il(srv->in_mu);
         srv->stop = true;
+        srv->stop_seen.store(true, std::memory_order_release);
     }
     srv->cv_work.notify_all();
     if (srv->worker.joinable()) srv->worker.join();
     int prev = 0;
-    hipGetDevice(&prev);
-    hipSetDevice(srv->device);
-    for (auto &sp : srv->slots)
-        for (Batch &b : sp->b) free_batch(b);
-    hipSetDevice(prev);
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(srv->device);
+    for (auto &sp : srv->slots) free_slot(*sp);
+    (void)hipSetDevice(prev);
     delete srv;
 }
 

@@ -10,7 +10,7 @@ from .decoder import Code, DecoderParams
 
 
 class Server:
-    """Continuous-batching server on the current HIP device."""
+    """Streaming decode server (lbp_server_*) on the current HIP device."""
 
     def __init__(self, device_mem_budget: int = 0, max_slots: int = 8):
         h = ctypes.c_void_p()
@@ -66,7 +66,7 @@ class Server:
     def slot_info(self, slot: int) -> dict:
         v = [ctypes.c_int64() for _ in range(5)]
         check(load().lbp_server_slot_info(self._h, int(slot), *[ctypes.byref(x) for x in v]))
-        return dict(zip(("tick_shots", "batches", "shots", "max_fill", "queued_shots"), (x.value for x in v)))
+        return dict(zip(("ring_items", "bp_launches", "shots", "max_inflight", "queued_shots"), (x.value for x in v)))
 
     def run_load(self, slots, pools, n_requests: int, shots_per_request: int, rate: float, seed: int):
         """Open-loop Poisson load (rate requests/s; 0 = saturation) over the given slots.

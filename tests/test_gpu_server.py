@@ -76,10 +76,10 @@ def test_server_mix_equals_lone_decodes():
         data.append((h, p, kw, syn))
     info = srv.slot_info(slots[0])
     _say("bb144 slot", info)
-    assert info["tick_shots"] >= 1
-    # requests: sizes 1..40, one larger than a batch (split), random codes, seeds, shot ids
+    assert info["ring_items"] >= 1024
+    # requests: sizes 1..40, one of 10123 shots, random codes, seeds, shot ids
     reqs = []
-    big = info["tick_shots"] + 123
+    big = 10123
     plan = [(0, big)] + [(int(rng.integers(0, 3)), int(rng.integers(1, 41))) for _ in range(300)]
     for k, (ci, size) in enumerate(plan):
         syn = data[ci][3]
@@ -120,9 +120,9 @@ def test_server_cancel_admission_and_tickets():
     h, e, syn = batch(name, p, 2000, 900)
     srv = Server(max_slots=1)
     slot = srv.add_code(_code(h, p), _params(**kw))
-    tick = srv.slot_info(slot)["tick_shots"]
+    ring = srv.slot_info(slot)["ring_items"]
     with pytest.raises(LbpError) as ei:   # more than the admission bound in one request
-        srv.submit(slot, np.zeros((64 * tick + 1, syn.shape[1]), np.uint32), 1)
+        srv.submit(slot, np.zeros((16 * ring + 1, syn.shape[1]), np.uint32), 1)
     assert ei.value.status == LBP_EBUSY
     with pytest.raises(LbpError) as ei:   # a second slot does not exist
         srv.add_code(_code(h, p), _params(**kw))
@@ -144,7 +144,7 @@ def test_server_cancel_admission_and_tickets():
     srv.close()
 
 
-def test_server_memory_budget_limits_batch_size():
+def test_server_memory_budget_limits_ring_size():
     from paper_2605_00038_amd import Server
     from paper_2605_00038_amd._lib import LbpError, LBP_ENOMEM
     name, p, kw = CODES[0]
@@ -153,8 +153,8 @@ def test_server_memory_budget_limits_batch_size():
     small = Server(device_mem_budget=400 << 20, max_slots=1)
     s1 = big.add_code(_code(h, p), _params(**kw))
     s2 = small.add_code(_code(h, p), _params(**kw))
-    t1, t2 = big.slot_info(s1)["tick_shots"], small.slot_info(s2)["tick_shots"]
-    _say("ticks", t1, t2)
+    t1, t2 = big.slot_info(s1)["ring_items"], small.slot_info(s2)["ring_items"]
+    _say("rings", t1, t2)
     assert t2 < t1
     r1 = big.wait(big.submit(s1, syn, 4), s1, 64)
     r2 = small.wait(small.submit(s2, syn, 4), s2, 64)
