@@ -131,6 +131,22 @@ def baseline_row(torch, h, syn_dev, shots: int, warmup: int):
     return dt, out
 
 
+def host_buffer_rate(h, syn, shots: int):
+    """lbp_decode_host: host arrays in and out (PCIe copies and device staging
+    allocation included); reported beside the HBM-resident value, never as it."""
+    from paper_2605_00038_amd import Code, Decoder, DecoderParams
+    prm = DecoderParams(max_iter=MAX_ITER, msg=2, lottery=True, lottery_skip=6, osd=2, osd_order=OSD_ORDER,
+                        seed=LOTTERY_SEED)
+    dec = Decoder(Code.from_scipy(h, P_ERR), prm, shots)
+    part = np.ascontiguousarray(syn[:shots])
+    dec.decode_host(part[:1024])  # warm-up
+    t0 = time.perf_counter()
+    dec.decode_host(part)
+    dt = time.perf_counter() - t0
+    return dict(kind="lbp_decode_host: host syndromes in, host corrections/flags/iters out", shots=shots,
+                seconds=dt, syndromes_per_s=shots / dt)
+
+
 def serving(h, syn, n_requests: int, shots_per_request: int = 1):
     """Serving loop under single-syndrome Poisson requests (latency from the
     scheduled arrival to the poll-visible result).  Saturation is the highest
@@ -227,6 +243,8 @@ def main():
     ap.add_argument("--latency-requests", type=int, default=3000)
     ap.add_argument("--baseline-shots", type=int, default=262_144,
                     help="shots for the plain global-memory FP32 comparison row (0 = skip)")
+    ap.add_argument("--no-host-rate", dest="host_rate", action="store_false",
+                    help="skip the PCIe-inclusive lbp_decode_host rate")
     ap.add_argument("--serve-requests", type=int, default=200_000,
                     help="single-syndrome requests per serving-loop run (0 = skip)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -310,6 +328,9 @@ def main():
         log("baseline", json.dumps(base))
     lat = latency(torch, head_dec, syn_dev, args.latency_requests) if args.latency_requests > 0 else None
     del head_dec
+    pcie = host_buffer_rate(h, syn, min(args.shots, 262_144)) if args.host_rate else None
+    if pcie:
+        log("pcie", json.dumps(pcie))
     torch.cuda.empty_cache()
     serve = None
     if args.serve_requests > 0:
@@ -357,6 +378,7 @@ def main():
                      "ops_per_edge_update": ALG_OPS_PER_EDGE},
         "cpu_baseline": cpu,
         "gpu_plain_fp32_baseline": base,
+        "pcie_inclusive": pcie,
         "formats": per_fmt,
     }
     print(json.dumps(line), flush=True)

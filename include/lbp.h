@@ -93,7 +93,7 @@ void lbp_params_default(lbp_params *p);
  * increasing column indices per row; p[n] (host): error probability of each
  * column, 0 < p < 1.  The library copies everything; the caller may free its
  * arrays on return.  The prior LLR mu_v = ln((1-p_v)/p_v) is evaluated in
- * fp64 on the host (Algorithm 1, line 1).
+ * fp64 on the host (Algorithm 1, prior).
  * Limits (LBP_EUNSUPPORTED otherwise): 1 <= row weight <= 8, column weight
  * <= 4, m <= 8191, n <= 65535.  Empty rows and malformed CSR: LBP_EINVAL.
  * The code lives on the device that is current when it is created. */

@@ -223,14 +223,14 @@ static void bp_float(const ocode *C, const orc_params *P, const double *prior, u
                      const uint8_t *s, uint8_t *ehat, int *iters, int *conv, double *lam_out, work *W) {
     const int m = C->m, n = C->n, fmt = P->msg, I = P->max_iter;
     double *mu = W->mu, *alpha = W->alpha, *beta = W->beta, *lam = W->lam;
-    for (int v = 0; v < n; ++v) mu[v] = orc_store(fmt, log((1.0 - prior[v]) / prior[v])); /* Alg.1 l.1 */
+    for (int v = 0; v < n; ++v) mu[v] = orc_store(fmt, log((1.0 - prior[v]) / prior[v])); /* Algorithm 1: prior LLR */
     for (int e = 0; e < C->nnz; ++e) beta[e] = 0.0;
     for (int v = 0; v < n; ++v) lam[v] = mu[v];
     int flip_v = -1;
     *conv = 0;
     *iters = I;
     for (int i = 0; i < I; ++i) {
-        /* VN update (Alg.1 l.3-6) */
+        /* VN update (Algorithm 1) */
         for (int c = 0; c < m; ++c)
             for (int e = C->rp[c]; e < C->rp[c + 1]; ++e) {
                 int v = C->ci[e];
@@ -244,7 +244,7 @@ static void bp_float(const ocode *C, const orc_params *P, const double *prior, u
                 if (P->flip == ORC_FLIP_MSG && v == flip_v) a = -a;
                 alpha[e] = orc_store(fmt, a);
             }
-        /* CN update (l.7) */
+        /* CN update (Algorithm 1) */
         double sig = sigma_float(P, i);
         for (int c = 0; c < m; ++c) {
             int deg = C->rp[c + 1] - C->rp[c];
@@ -264,7 +264,7 @@ static void bp_float(const ocode *C, const orc_params *P, const double *prior, u
                 beta[e] = orc_store(fmt, neg ? -b : b);
             }
         }
-        /* LLR update (l.8), hard decision (l.9), syndrome (l.10) */
+        /* LLR update, hard decision, syndrome estimate (Algorithm 1) */
         for (int v = 0; v < n; ++v) {
             double l = mu[v];
             for (int t = C->cp[v]; t < C->cp[v + 1]; ++t) l += beta[C->ce[t]];
@@ -278,13 +278,13 @@ static void bp_float(const ocode *C, const orc_params *P, const double *prior, u
             W->shat[c] = (uint8_t)x;
             if (x != s[c]) match = 0;
         }
-        if (match && P->early_stop) { /* l.11-12 */
+        if (match && P->early_stop) { /* early termination (Algorithm 1) */
             *conv = 1;
             *iters = i + 1;
             break;
         }
         *conv = match;
-        /* lottery (l.13, Algorithm 3) */
+        /* lottery (Algorithm 3) */
         flip_v = -1;
         if (P->lottery && i >= P->lottery_skip && i <= I - 2) {
             int vs = lottery_pick(C, P, shot_id, i, s, W->sprev, W->ulist, lam, NULL);
@@ -405,11 +405,11 @@ static int osd_shot(const ocode *C, int mode, int order, const double *lam, cons
     uint8_t *eperm = (uint8_t *)calloc((size_t)n, 1);
     int ret = 0;
 
-    /* l.1: sort lambda ascending (stable: ties by column index) */
+    /* sort lambda ascending (stable: ties by column index) */
     for (int v = 0; v < n; ++v) { kc[v].l = lam[v] == 0.0 ? 0.0 : lam[v]; kc[v].col = v; }
     qsort(kc, (size_t)n, sizeof(keycol), cmp_keycol);
     for (int j = 0; j < n; ++j) { pi[j] = kc[j].col; pos[kc[j].col] = j; }
-    /* l.2: permuted columns, augmented with s in column n */
+    /* permuted columns, augmented with s in column n */
     for (int c = 0; c < m; ++c) {
         uint64_t *row = A + (size_t)c * W;
         for (int e = C->rp[c]; e < C->rp[c + 1]; ++e) {
@@ -418,7 +418,7 @@ static int osd_shot(const ocode *C, int mode, int order, const double *lam, cons
         }
         if (s[c]) row[n >> 6] |= 1ULL << (n & 63);
     }
-    /* l.3-6: Gauss-Jordan elimination in permuted column order; the pivots are
+    /* Gauss-Jordan elimination in permuted column order; the pivots are
      * the first rank(H) independent columns */
     int rank = 0;
     for (int j = 0; j < n && rank < m; ++j) {
@@ -473,7 +473,7 @@ static int osd_shot(const ocode *C, int mode, int order, const double *lam, cons
                     if (cost < best_cost) { best_cost = cost; best_a = a; best_b = b; }
                 }
         }
-        /* l.7: e' = (e_S, t); l.8: map back through pi */
+        /* e' = (e_S, t), mapped back through pi */
         for (int k = 0; k < rank; ++k) {
             const uint64_t *row = A + (size_t)k * W;
             int x = getbit(row, n);

@@ -198,7 +198,7 @@ __global__ __launch_bounds__(1024) void bp_int8_kernel(BpArgs a) {
             uint32_t x = syn_row[w];
             S[w] = w == C.mw - 1 ? (x & last_mask) : x;
         }
-        // lambda^(-1) = mu in both buffers (Algorithm 1, line 4: alpha^(0) = mu)
+        // lambda^(-1) = mu in both buffers (Algorithm 1 initialisation: alpha^(0) = mu)
         for (int v = lane; v < n; v += 64) {
             const uint16_t mb = (uint16_t)(C.mu_q[v] + BIAS);
             ((uint16_t *)LA)[v] = mb;

@@ -204,8 +204,8 @@ __device__ __forceinline__ bool hard_decision(const Lam<typename Fmt<MSG>::A> &l
     else return l.hi < TAU_FLOAT || (l.hi == TAU_FLOAT && l.lo <= 0.f);
 }
 
-// Q(|lambda|): |lambda| for Int3.4, floor(|lambda| * 2^12) for float (exact,
-// saturating at 2^62).
+// Q(|lambda|): |lambda| for Int3.4, floor(|lambda| * 2^12) for float (exact),
+// capped at 4e18 (a value no real lambda reaches; the cap only keeps Q finite).
 template <int MSG>
 __device__ __forceinline__ uint64_t quantized_abs(const Lam<typename Fmt<MSG>::A> &l) {
     if constexpr (MSG == MSG_INT8) {
@@ -214,7 +214,7 @@ __device__ __forceinline__ uint64_t quantized_abs(const Lam<typename Fmt<MSG>::A
         float hi = l.hi, lo = l.lo;
         if (hi < 0.f || (hi == 0.f && lo < 0.f)) { hi = -hi; lo = -lo; }
         float H = hi * 4096.0f, L = lo * 4096.0f;  // exact scalings
-        if (!(H < 4.6116860e18f)) return (uint64_t)1 << 62;
+        if (!((double)H + (double)L < 4.0e18)) return 4000000000000000000ull;
         float fh = __builtin_floorf(H);
         if (fh == H) {
             // H integral: floor(H + L) = H + floor(L)
@@ -490,7 +490,7 @@ __global__ __launch_bounds__(1024) void bp_kernel(BpArgs a) {
             uint32_t x = syn_row[w];
             S[w] = w == C.mw - 1 ? (x & last_mask) : x;
         }
-        // Algorithm 1, line 4: alpha^(0) = mu; padding slots get the sentinel.
+        // alpha^(0) = mu (Algorithm 1 initialisation); padding slots get the sentinel.
         for (int c = lane; c < C.m; c += 64) {
             const int deg = C.cn_deg[c];
 #pragma unroll

@@ -224,7 +224,7 @@ lbp_status lbp_code_create(int32_t m, int32_t n, const int32_t *row_ptr, const i
     std::vector<int32_t> muq(n);
     bool uniform = true;
     for (int v = 0; v < n; ++v) {
-        double mu = std::log((1.0 - p[v]) / p[v]);  // Algorithm 1, line 1 (fp64, host)
+        double mu = std::log((1.0 - p[v]) / p[v]);  // prior LLR of Algorithm 1 (fp64, host)
         mu32[v] = (float)mu;
         mu16[v] = to_fp16_value(mu);
         double q = std::nearbyint(16.0 * mu);
