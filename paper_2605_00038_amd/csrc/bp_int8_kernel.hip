@@ -1,26 +1,41 @@
 // Int3.4 Lottery BP for codes with at most 64*16 checks: one wavefront per
-// shot, check-centric.
+// shot, check-centric, two edges per VALU instruction.
 //
 // Per shot the wave keeps
 //   * beta (C2V, int8) of every edge in VGPRs: lane L owns checks L + 64*s,
-//     s < SLOTS, and holds their 8 padded slots packed in one u64 per check;
-//   * lambda of every column twice in its LDS slice (current / next), as
-//     biased 16-bit values packed in pairs (|lambda| <= 5*127 fits).
+//     s < SLOTS, and holds their 8 padded slots packed in two u32 per check;
+//   * lambda of every column in its LDS slice as one u32 per column holding
+//     two biased 16-bit values (value + 2^15): the lambda of the previous
+//     iteration ("current") and the sum being built for this one ("next").
+//     The halves swap roles every iteration.  |lambda| <= 5*127 keeps every
+//     partial sum inside its half, so halves never carry into each other.
 // Int3.4 arithmetic is exact, so lambda^(i) = mu + sum of beta^(i) is built
-// with integer LDS atomic adds into `next` (order-independent): one fused pass
-// per check gathers lambda^(i-1) from `current`, forms
-// alpha = sat(lambda - beta_old) (== mu + the other C2V messages), runs
-// min1/min2/argmin/sign parity, stores the new beta in VGPRs and adds it to
-// `next`.  A second pass over columns takes the hard decision (ballot into the
-// correction words), forms the syndrome estimate by LDS atomic XOR (only
-// columns with e = 1) and resets `current` to mu for the next iteration.
-// There is no variable-node gather.  Padding slots point at column n, whose
-// `current` value is reset to 254 each iteration: it always yields
-// alpha = +127, the sentinel that never wins a minimum.
+// with integer LDS atomic adds into the next half (order-independent): one
+// fused pass per check gathers lambda^(i-1) from the current halves, forms
+// alpha = lambda - beta_old (== mu + the other C2V messages), runs
+// min1/min2/argmin/sign parity, keeps the new beta in VGPRs and adds it to
+// the next halves.  A second pass over columns takes the hard decision (ballot
+// into the correction words), forms the syndrome estimate by LDS atomic XOR
+// (only columns with e = 1) and resets the consumed half to mu.  There is no
+// variable-node gather.
+//
+// The check pass works on pairs of edges in packed 16-bit registers (the
+// v_pk_* integer instructions): the two lambda values of a pair are gathered
+// into the two halves of a register, and the int8 beta of four edges is
+// unpacked into two pairs with one byte-permute each, whose selectors also
+// sign-extend.  Each check's slots are paired (1,3), (0,2), (5,7), (4,6).
+//
+// Padding slots point at pad columns (after column n-1) whose current half is
+// reset to 254 each iteration: alpha >= +127 there, a key that never wins a
+// minimum.  Pads are spread over PAD_COLS columns so that their sums cannot
+// leave a 16-bit half either.
 //
 // The lottery (Algorithm 3) runs after the column pass with U from the
 // previous syndrome estimate and lambda^(i) read from LDS; the flip acts on
-// the next iteration's alpha (message flip) or on lambda_v* (LLR flip).
+// the next iteration's alpha (message flip) or on lambda_v* (LLR flip), inside
+// a wave-uniform branch taken only by the slots that hold a check of v*.
+#include <climits>
+
 #include "lbp_internal.h"
 
 namespace lbp {
@@ -28,6 +43,10 @@ namespace {
 
 constexpr int BIAS = 32768;
 constexpr int PAD_LAMBDA = 254;
+constexpr int PAD_COLS = 48;
+
+typedef short v2i16 __attribute__((ext_vector_type(2)));
+typedef unsigned short v2u16 __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -65,25 +84,20 @@ __device__ uint64_t philox_w0(uint64_t k0, uint64_t c0, uint64_t c1) {
     return x0;
 }
 
-__device__ __forceinline__ int sbyte(uint64_t w, int k) { return (int)(int8_t)(uint8_t)(w >> (8 * k)); }
+__device__ __forceinline__ v2i16 as_i16(uint32_t x) { return __builtin_bit_cast(v2i16, x); }
+__device__ __forceinline__ v2u16 as_u16(uint32_t x) { return __builtin_bit_cast(v2u16, x); }
+__device__ __forceinline__ uint32_t as_u32(v2i16 x) { return __builtin_bit_cast(uint32_t, x); }
+__device__ __forceinline__ uint32_t as_u32(v2u16 x) { return __builtin_bit_cast(uint32_t, x); }
 
-__device__ __forceinline__ int med3i(int a, int b, int c) {
-    const int lo = a < b ? a : b, hi = a < b ? b : a;
-    const int t = hi < c ? hi : c;
-    return lo > t ? lo : t;
-}
-
-__device__ __forceinline__ int sat127(int x) { return x > 127 ? 127 : (x < -127 ? -127 : x); }
-
-__device__ __forceinline__ int scale_q(const BpParams &P, int i, int mag) {
-    if (P.scale_mode == 1) return (P.scale_k * mag) >> 3;
-    int sh = i + 1 > 30 ? 30 : i + 1;
-    return mag - (mag >> sh);
+// lambda^(i) of column v: the half that received this iteration's sum.
+__device__ __forceinline__ int lambda_next(const uint32_t *L, int v, int nxt_hi) {
+    const uint32_t w = L[v];
+    return (int)(nxt_hi ? (w >> 16) : (w & 0xFFFFu)) - BIAS;
 }
 
 // Lottery selection (Algorithm 3), U from the previous syndrome estimate SHp.
-__device__ int lottery_pick_q(const DevCode &C, uint64_t seed, uint64_t shot_id, int i, const uint16_t *L,
-                              const uint32_t *S, const uint32_t *SHp, int lane) {
+__device__ int lottery_pick_q(const DevCode &C, uint64_t seed, uint64_t shot_id, int i, const uint32_t *L,
+                              int nxt_hi, const uint32_t *S, const uint32_t *SHp, int lane) {
     int N = 0;
     for (int w0 = 0; w0 < C.mw; w0 += 64) {
         int w = w0 + lane;
@@ -128,7 +142,7 @@ __device__ int lottery_pick_q(const DevCode &C, uint64_t seed, uint64_t shot_id,
                     cnt += ((SHp[c >> 5] ^ S[c >> 5]) >> (c & 31)) & 1u;
                 }
             }
-            int l = (int)L[v] - BIAS;
+            int l = lambda_next(L, v, nxt_hi);
             q = l < 0 ? -l : l;
         }
     }
@@ -146,6 +160,143 @@ __device__ int lottery_pick_q(const DevCode &C, uint64_t seed, uint64_t shot_id,
     return bv;
 }
 
+// Byte-permute selectors (byte i of the result = byte sel_i of {src0, src1},
+// src1 the low word; 8 / 10 = sign of byte 1 of src1 / src0, 9 / 11 = of byte 3):
+// (b1, b3) and (b0, b2) of a word of four int8, sign-extended to int16 pairs,
+// and the inverse (pairs back to four bytes).
+constexpr uint32_t SEL_13 = 0x09030801u;    // src1 = w: b1, sign(b1), b3, sign(b3)
+constexpr uint32_t SEL_02 = 0x0B020A00u;    // src0 = w << 8, src1 = w: b0, sign(b0), b2, sign(b2)
+constexpr uint32_t SEL_PACK = 0x06020400u;  // src0 = (b1, b3), src1 = (b0, b2) -> b0 b1 b2 b3
+
+// One check of the check pass on its four slot pairs.  PAR: which half holds
+// the current lambda (0: low, 1: high); the sum for this iteration goes to the
+// other half.  FLIP: the wave-uniform flip path (fo = v*'s offset in both halves).
+template <int PAR, bool FLIP, bool LLR_FLIP>
+__device__ __forceinline__ void check_update(const uint4 cw, uint32_t &bw0, uint32_t &bw1, uint32_t syn_bit,
+                                             unsigned char *Lb, uint32_t base, int sh, int scale_mode, int scale_k,
+                                             uint32_t fo) {
+    const uint32_t T[4] = {cw.x, cw.y, cw.z, cw.w};  // (off1,off3) (off0,off2) (off5,off7) (off4,off6)
+    // ---- gather lambda^(i-1) of the eight columns into four pairs
+    uint32_t lam[4];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+        const uint32_t a0 = base + (T[p] & 0xFFFFu), a1 = base + (T[p] >> 16);
+        const uint32_t l0 = *(const uint16_t *)(Lb + a0 + 2 * PAR);
+        const uint32_t l1 = *(const uint16_t *)(Lb + a1 + 2 * PAR);
+        lam[p] = l0 | (l1 << 16);
+    }
+    // ---- beta_old pairs
+    const uint32_t b[4] = {__builtin_amdgcn_perm(bw0, bw0, SEL_13), __builtin_amdgcn_perm(bw0 << 8, bw0, SEL_02),
+                           __builtin_amdgcn_perm(bw1, bw1, SEL_13), __builtin_amdgcn_perm(bw1 << 8, bw1, SEL_02)};
+    // ---- alpha, keys, min1/min2 per half, sign parity (stage by stage over the
+    // four pairs, so that dependent packed instructions are never adjacent)
+    v2i16 l[4], x[4], mg[4];
+    v2u16 key[4];
+    const v2u16 kslot[4] = {{1, 3}, {0, 2}, {5, 7}, {4, 6}};
+#pragma unroll
+    for (int p = 0; p < 4; ++p) l[p] = as_i16(lam[p] ^ 0x80008000u);  // biased -> signed lambda
+    if constexpr (FLIP) {
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            // per half: d == 0 exactly where the slot names v*; (d | -d) has its top bit clear only there
+            const v2u16 d = as_u16(T[p]) - as_u16(fo);
+            const v2u16 nz = (d | ((v2u16){0, 0} - d)) >> (v2u16){15, 15};
+            const v2i16 fm = as_i16(as_u32(nz - (v2u16){1, 1}));  // -1 in the halves naming v*
+            if constexpr (LLR_FLIP) l[p] = (l[p] ^ fm) - fm;  // lambda_v* negated
+            x[p] = l[p] - as_i16(b[p]);
+            if constexpr (!LLR_FLIP) x[p] = (x[p] ^ fm) - fm;  // messages of v* negated
+        }
+    } else {
+#pragma unroll
+        for (int p = 0; p < 4; ++p) x[p] = l[p] - as_i16(b[p]);
+    }
+    // |alpha| saturated at 127 (the sign of alpha is the sign of its saturated value)
+#pragma unroll
+    for (int p = 0; p < 4; ++p) mg[p] = (v2i16){0, 0} - x[p];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) mg[p] = __builtin_elementwise_max(x[p], mg[p]);
+#pragma unroll
+    for (int p = 0; p < 4; ++p) mg[p] = __builtin_elementwise_min(mg[p], (v2i16){127, 127});
+#pragma unroll
+    for (int p = 0; p < 4; ++p) key[p] = (as_u16(as_u32(mg[p])) << (v2u16){3, 3}) | kslot[p];  // |alpha| << 3 | slot
+    const uint32_t px = as_u32(x[0]) ^ as_u32(x[1]) ^ as_u32(x[2]) ^ as_u32(x[3]);
+    v2u16 m1 = __builtin_elementwise_min(key[0], key[1]);
+    v2u16 m2 = __builtin_elementwise_max(key[0], key[1]);
+    const v2u16 m1b = __builtin_elementwise_min(key[2], key[3]);
+    const v2u16 m2b = __builtin_elementwise_max(key[2], key[3]);
+    m2 = __builtin_elementwise_min(__builtin_elementwise_max(m1, m1b), __builtin_elementwise_min(m2, m2b));
+    m1 = __builtin_elementwise_min(m1, m1b);
+    // merge the two halves: minimum and second minimum over all eight keys
+    const uint32_t m1a = m1.x, m1c = m1.y, m2a = m2.x, m2c = m2.y;
+    const uint32_t k1 = m1a < m1c ? m1a : m1c;
+    const uint32_t hi1 = m1a < m1c ? m1c : m1a;
+    const uint32_t m2m = m2a < m2c ? m2a : m2c;
+    const uint32_t k2 = hi1 < m2m ? hi1 : m2m;
+    const uint32_t par = (((px ^ (px >> 16)) >> 15) & 1u) ^ syn_bit;
+    const int g1 = (int)(k1 >> 3), g2 = (int)(k2 >> 3);
+    int s1, s2;
+    if (scale_mode == 1) {
+        s1 = (scale_k * g1) >> 3;
+        s2 = (scale_k * g2) >> 3;
+    } else {
+        s1 = g1 - (g1 >> sh);
+        s2 = g2 - (g2 >> sh);
+    }
+    const v2u16 k1p = {(unsigned short)(k1 + 1), (unsigned short)(k1 + 1)};
+    const uint32_t s1p = (uint32_t)s1 | ((uint32_t)s1 << 16);
+    const uint32_t dxp = (uint32_t)(s1 ^ s2) | ((uint32_t)(s1 ^ s2) << 16);
+    const uint32_t pp = par ? 0x80008000u : 0u;
+    uint32_t nb[4];
+    v2i16 eq[4], sm[4];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) eq[p] = as_i16(as_u32(key[p] - k1p));  // per half: negative only at the argmin
+#pragma unroll
+    for (int p = 0; p < 4; ++p) eq[p] = eq[p] >> (v2i16){15, 15};                 // -1 at the argmin slot
+#pragma unroll
+    for (int p = 0; p < 4; ++p) sm[p] = as_i16(as_u32(x[p]) ^ pp) >> (v2i16){15, 15};  // -1 where beta < 0
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+        const uint32_t mag = s1p ^ (dxp & as_u32(eq[p]));  // s2 at the argmin, s1 elsewhere
+        nb[p] = as_u32((as_i16(mag) ^ sm[p]) - sm[p]);
+    }
+    // ---- add the new beta to the other half of each column word
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+        const uint32_t a0 = base + (T[p] & 0xFFFFu), a1 = base + (T[p] >> 16);
+        uint32_t v0, v1;
+        if constexpr (PAR == 0) {  // the sum goes to the high halves
+            v0 = nb[p] << 16;
+            v1 = nb[p] & 0xFFFF0000u;
+        } else {                   // the sum goes to the low halves (sign-extended: no borrow leaves the half)
+            v0 = (uint32_t)(((int32_t)(nb[p] << 16)) >> 16);
+            v1 = (uint32_t)(((int32_t)nb[p]) >> 16);
+        }
+        __hip_atomic_fetch_add((uint32_t *)(Lb + a0), v0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        __hip_atomic_fetch_add((uint32_t *)(Lb + a1), v1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+    bw0 = __builtin_amdgcn_perm(nb[0], nb[1], SEL_PACK);
+    bw1 = __builtin_amdgcn_perm(nb[2], nb[3], SEL_PACK);
+}
+
+// The check pass of one iteration over all of the lane's checks.
+template <int SLOTS, int PAR, bool LLR_FLIP>
+__device__ __forceinline__ void check_pass(const uint4 *cidx4, uint32_t (&bq)[SLOTS][2], uint32_t srow,
+                                           unsigned char *Lb, uint32_t base, int lane, int sh, int scale_mode,
+                                           int scale_k, uint32_t flipslots, uint32_t fo) {
+#pragma unroll
+    for (int s = 0; s < SLOTS; ++s) {
+        const uint4 cw = cidx4[s * 64 + lane];
+        const uint32_t sb = (srow >> s) & 1u;
+        if (flipslots & (1u << s))
+            check_update<PAR, true, LLR_FLIP>(cw, bq[s][0], bq[s][1], sb, Lb, base, sh, scale_mode, scale_k, fo);
+        else
+            check_update<PAR, false, LLR_FLIP>(cw, bq[s][0], bq[s][1], sb, Lb, base, sh, scale_mode, scale_k, fo);
+        // opaque to the optimiser: otherwise it forwards unpacked values to the next
+        // iteration and keeps several registers per check
+        asm volatile("" : "+v"(bq[s][0]), "+v"(bq[s][1]));
+    }
+}
+
 template <int SLOTS, bool LLR_FLIP>
 __global__ __launch_bounds__(1024) void bp_int8_kernel(BpArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -153,25 +304,37 @@ __global__ __launch_bounds__(1024) void bp_int8_kernel(BpArgs a) {
     const BpParams &P = a.prm;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int n = C.n, m = C.m;
-    // block-shared column index of every padded slot: cidx[(s*64 + lane)*DEG + k],
-    // read as one 16-byte vector per check
-    uint16_t *cidx = (uint16_t *)smem;
-    for (int t = threadIdx.x; t < SLOTS * DEG * 64; t += blockDim.x) {
-        const int c = t / DEG, k = t % DEG;
-        uint32_t v = c < m ? C.cn_cols[c * DEG + k] : NOPOS;
-        cidx[t] = (uint16_t)(v == NOPOS ? n : v);
+    // block-shared byte offsets (4 * column) of every padded slot, paired as
+    // cidx4[s*64 + lane] = {(o1,o3), (o0,o2), (o5,o7), (o4,o6)} of check lane + 64 s
+    uint32_t *cidx = (uint32_t *)smem;
+    for (int t = threadIdx.x; t < SLOTS * 64 * 4; t += blockDim.x) {
+        const int c = t >> 2, w = t & 3;
+        const int k0 = (w & 2) * 2 + ((w & 1) ? 0 : 1);  // slot of the low half: 1, 0, 5, 4
+        uint32_t off[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int k = k0 + 2 * h;
+            uint32_t v = c < m ? C.cn_cols[c * DEG + k] : NOPOS;
+            if (v == NOPOS) v = (uint32_t)n + (uint32_t)((c * DEG + k) % PAD_COLS);
+            off[h] = 4u * v;
+        }
+        cidx[t] = off[0] | (off[1] << 16);
     }
     __syncthreads();
-    unsigned char *base = smem + (((size_t)SLOTS * DEG * 64 * 2 + 15) & ~(size_t)15) + (size_t)wv * a.wave_bytes;
-    const size_t lwords = (size_t)(n + 3) / 2;  // (n + 2) biased 16-bit lambda values, padded to pairs
-    uint32_t *LA = (uint32_t *)base;
-    uint32_t *LB = LA + lwords;
-    uint32_t *S = (uint32_t *)(base + ((2 * lwords * 4 + 15) & ~(size_t)15));
+    const uint4 *cidx4 = (const uint4 *)smem;
+    unsigned char *base_p = smem + (size_t)SLOTS * 64 * 16 + (size_t)wv * a.wave_bytes;
+    uint32_t *L = (uint32_t *)base_p;  // [n + PAD_COLS] column words
+    unsigned char *Lb = smem;
+    const uint32_t base = (uint32_t)(base_p - smem);
+    const int nl = n + PAD_COLS;
+    uint32_t *S = (uint32_t *)(base_p + (((size_t)nl * 4 + 15) & ~(size_t)15));
     uint32_t *SH0 = S + C.mw, *SH1 = SH0 + C.mw, *EH = SH1 + C.mw;
     const int gwave = blockIdx.x * (blockDim.x >> 6) + wv;
     float *stage = a.stage + (size_t)gwave * 2 * n;
     const uint32_t last_mask = (m & 31) ? ((1u << (m & 31)) - 1u) : ~0u;
     const int nvs = (n + 63) >> 6;
+    const bool mu_uniform = C.mu_q_uniform != INT32_MIN;
+    const uint32_t pad_b = (uint32_t)(PAD_LAMBDA + BIAS);
 
     for (;;) {
         int64_t item = 0;
@@ -198,17 +361,15 @@ __global__ __launch_bounds__(1024) void bp_int8_kernel(BpArgs a) {
             uint32_t x = syn_row[w];
             S[w] = w == C.mw - 1 ? (x & last_mask) : x;
         }
-        // lambda^(-1) = mu in both buffers (Algorithm 1 initialisation: alpha^(0) = mu)
-        for (int v = lane; v < n; v += 64) {
-            const uint16_t mb = (uint16_t)(C.mu_q[v] + BIAS);
-            ((uint16_t *)LA)[v] = mb;
-            ((uint16_t *)LB)[v] = mb;
+        // lambda^(-1) = mu in both halves (Algorithm 1 initialisation: alpha^(0) = mu)
+        for (int v = lane; v < nl; v += 64) {
+            const uint32_t mb = v < n ? (uint32_t)((mu_uniform ? C.mu_q_uniform : C.mu_q[v]) + BIAS) : pad_b;
+            L[v] = mb | (mb << 16);
         }
-        if (lane < 2) ((uint16_t *)LA)[n + lane] = (uint16_t)(PAD_LAMBDA + BIAS);
         wave_sync();
-        uint64_t bq[SLOTS];  // beta of the previous iteration, packed int8
+        uint32_t bq[SLOTS][2];  // beta of the previous iteration, int8, slots 0-3 and 4-7
 #pragma unroll
-        for (int s = 0; s < SLOTS; ++s) bq[s] = 0;
+        for (int s = 0; s < SLOTS; ++s) bq[s][0] = bq[s][1] = 0u;
         // bit s: measured syndrome of check lane + 64 s (S is zero beyond m)
         uint32_t srow = 0;
 #pragma unroll 1
@@ -217,67 +378,31 @@ __global__ __launch_bounds__(1024) void bp_int8_kernel(BpArgs a) {
             if (w < C.mw) srow |= ((S[w] >> (lane & 31)) & 1u) << s;
         }
 
-        int it = 0, fv = -1;
+        int it = 0;
         bool converged = false;
-        uint32_t *Lc = LA, *Ln = LB;
+        uint32_t flipslots = 0, fo = 0;
         for (int i = 0; i < P.max_iter; ++i) {
             uint32_t *SHc = (i & 1) ? SH1 : SH0;
             uint32_t *SHp = (i & 1) ? SH0 : SH1;
-            const uint16_t *Lc16 = (const uint16_t *)Lc;
+            const int par = i & 1;  // half holding lambda^(i-1)
+            const int sh = i + 1 > 30 ? 30 : i + 1;
             // ---- check-node pass: alpha from lambda^(i-1), beta^(i), lambda^(i) += beta^(i)
-#pragma unroll
-            for (int s = 0; s < SLOTS; ++s) {
-                int al[DEG], vv[DEG], lr[DEG];
-                int m1 = 1 << 20, m2 = 1 << 20, px = -(int)((srow >> s) & 1);
-                const uint4 cw = ((const uint4 *)cidx)[s * 64 + lane];
-                const uint32_t cws[4] = {cw.x, cw.y, cw.z, cw.w};
-#pragma unroll
-                for (int k = 0; k < DEG; ++k) vv[k] = (int)((cws[k >> 1] >> (16 * (k & 1))) & 0xFFFFu);
-#pragma unroll
-                for (int k = 0; k < DEG; ++k) lr[k] = Lc16[vv[k]];
-#pragma unroll
-                for (int k = 0; k < DEG; ++k) {
-                    const int v = vv[k];
-                    const int lam = lr[k] - BIAS;
-                    const int b0 = sbyte(bq[s], k);
-                    int x = sat127(lam - b0);
-                    // flip (fv = -1 matches nothing): negated alpha, or alpha from -lambda
-                    const int xf = LLR_FLIP ? sat127(-lam - b0) : -x;
-                    x = v == fv ? xf : x;
-                    al[k] = x;
-                    const int key = ((x < 0 ? -x : x) << 3) | k;  // |alpha|, first index on ties
-                    m2 = med3i(key, m1, m2);  // second smallest (m1 <= m2)
-                    m1 = key < m1 ? key : m1;
-                    px ^= x;  // sign bit: parity of the syndrome bit and the negative alphas
-                }
-                const int par = px < 0;
-                const int arg = m1 & 7;
-                const int s1 = scale_q(P, i, m1 >> 3), s2 = scale_q(P, i, m2 >> 3);
-                uint64_t packed = 0;
-#pragma unroll
-                for (int k = 0; k < DEG; ++k) {
-                    const int mag = k == arg ? s2 : s1;
-                    const int b = (par ^ (al[k] < 0)) ? -mag : mag;
-                    const int v = vv[k];
-                    // biased 16-bit halves: the sum never leaves [0, 65535], so no carry crosses halves
-                    atomicAdd(&Ln[v >> 1], (uint32_t)(b << ((v & 1) * 16)));
-                    packed |= (uint64_t)(uint8_t)b << (8 * k);
-                }
-                // opaque to the optimiser: otherwise it forwards the 8 unpacked
-                // values to the next iteration and keeps 8 registers per check
-                asm volatile("" : "+v"(packed));
-                bq[s] = packed;
-            }
+            if (par == 0)
+                check_pass<SLOTS, 0, LLR_FLIP>(cidx4, bq, srow, Lb, base, lane, sh, P.scale_mode, P.scale_k,
+                                               flipslots, fo);
+            else
+                check_pass<SLOTS, 1, LLR_FLIP>(cidx4, bq, srow, Lb, base, lane, sh, P.scale_mode, P.scale_k,
+                                               flipslots, fo);
             for (int w = lane; w < C.mw; w += 64) SHc[w] = 0u;
             wave_sync();
             // ---- column pass: hard decision, corrections, syndrome estimate, reset
             const bool last = i == P.max_iter - 1;
-            const uint16_t *Ln16 = (const uint16_t *)Ln;
-            uint16_t *Lc16w = (uint16_t *)Lc;
+            const int nxt_hi = par == 0;
+            uint16_t *Lh = (uint16_t *)L;
             for (int vs = 0; vs < nvs; ++vs) {
                 const int v = vs * 64 + lane;
                 const bool valid = v < n;
-                const int l = valid ? (int)Ln16[v] - BIAS : 1;
+                const int l = valid ? lambda_next(L, v, nxt_hi) : 1;
                 const bool e = valid && l <= 0;
                 const uint64_t bal = __ballot(e);
                 if (lane == 0) {
@@ -296,7 +421,8 @@ __global__ __launch_bounds__(1024) void bp_int8_kernel(BpArgs a) {
                     }
                 }
                 if (valid) {
-                    Lc16w[v] = (uint16_t)(C.mu_q[v] + BIAS);  // accumulation base of iteration i+1
+                    // the consumed half becomes the accumulation base of iteration i+1
+                    Lh[2 * v + par] = (uint16_t)((mu_uniform ? C.mu_q_uniform : C.mu_q[v]) + BIAS);
                     if (llr_row) llr_row[v] = (float)l;
                     if (last) {
                         stage[v] = (float)l;
@@ -304,7 +430,9 @@ __global__ __launch_bounds__(1024) void bp_int8_kernel(BpArgs a) {
                     }
                 }
             }
-            if (lane < 2) ((uint16_t *)Ln)[n + lane] = (uint16_t)(PAD_LAMBDA + BIAS);
+            // pads: re-arm the half that just collected this iteration's pad sums (it is
+            // read next iteration); the other half collects the next sums from 254
+            if (lane < PAD_COLS) Lh[2 * (n + lane) + (par ^ 1)] = (uint16_t)pad_b;
             wave_sync();
             bool mism = false;
             for (int w = lane; w < C.mw; w += 64) mism |= SHc[w] != S[w];
@@ -313,12 +441,22 @@ __global__ __launch_bounds__(1024) void bp_int8_kernel(BpArgs a) {
                 converged = true;
                 break;
             }
-            fv = -1;
-            if (P.lottery && i >= P.skip && i <= P.max_iter - 2)
-                fv = lottery_pick_q(C, seed, shot_id, i, Ln16, S, SHp, lane);
-            uint32_t *t = Lc;
-            Lc = Ln;
-            Ln = t;
+            flipslots = 0;
+            if (P.lottery && i >= P.skip && i <= P.max_iter - 2) {
+                const int fv = lottery_pick_q(C, seed, shot_id, i, L, nxt_hi, S, SHp, lane);
+                if (fv >= 0) {
+                    // slots holding a check of v*: its column table names them
+                    const uint64_t tab = C.vn_tab[__builtin_amdgcn_readfirstlane(fv)];
+#pragma unroll
+                    for (int j = 0; j < CDEG; ++j) {
+                        const uint32_t p = (uint32_t)(tab >> (16 * j)) & 0xFFFFu;
+                        if (p != NOPOS) flipslots |= 1u << ((p / DEG) >> 6);
+                    }
+                    flipslots = __builtin_amdgcn_readfirstlane(flipslots);
+                    fo = 4u * (uint32_t)fv;
+                    fo = fo | (fo << 16);
+                }
+            }
             wave_sync();
         }
 
@@ -361,20 +499,20 @@ __global__ __launch_bounds__(1024) void bp_int8_kernel(BpArgs a) {
 
 }  // namespace
 
-int bp_int8_slots(int m) {
+int bp_int8_slots(int m, int n) {
+    if ((int64_t)(n + PAD_COLS) * 4 > 65535) return 0;  // column offsets are 16-bit
     const int need = (m + 63) / 64;
     for (int s : {1, 2, 4, 8, 14, 16})
         if (need <= s) return s;
     return 0;
 }
 
-int bp_int8_table_bytes(int slots) { return (int)(((size_t)slots * DEG * 64 * 2 + 15) & ~(size_t)15); }
+int bp_int8_table_bytes(int slots) { return slots * 64 * 16; }
 
 int bp_int8_wave_bytes(int m, int n) {
     size_t mw = (size_t)(m + 31) / 32;
     size_t eh = 2 * (size_t)((n + 63) / 64);
-    size_t lwords = (size_t)(n + 3) / 2;
-    size_t tot = ((2 * lwords * 4 + 15) & ~(size_t)15) + 4 * (3 * mw + eh);
+    size_t tot = (((size_t)(n + PAD_COLS) * 4 + 15) & ~(size_t)15) + 4 * (3 * mw + eh);
     return (int)((tot + 15) & ~(size_t)15);
 }
 

@@ -30,6 +30,7 @@ struct DevCode {
     const float *mu_f32;      // [n]       prior LLR rounded to fp32
     const float *mu_f16;      // [n]       prior LLR rounded to fp16 (held as float)
     const int32_t *mu_q;      // [n]       Int3.4 prior
+    int32_t mu_q_uniform;     // the Int3.4 prior when every column has the same one, else INT32_MIN
 };
 
 struct BpParams {
@@ -209,7 +210,7 @@ hipError_t osd_max_blocks_per_cu(int variant, int threads, int lds, int *out);
 
 // Int3.4 check-centric kernel (codes with <= 1024 checks): slots per lane
 // (0 = not applicable), block-shared table bytes, per-wave LDS bytes.
-int bp_int8_slots(int m);
+int bp_int8_slots(int m, int n);
 int bp_int8_table_bytes(int slots);
 int bp_int8_wave_bytes(int m, int n);
 hipError_t launch_bp_int8(int slots, const BpArgs &a, int blocks, int waves_per_block, hipStream_t s);

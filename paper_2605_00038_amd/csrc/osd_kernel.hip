@@ -513,9 +513,14 @@ __global__ __launch_bounds__(1024) void osd_reg_kernel(OsdArgs a) {
                 pcol = perm[j];
             }
             if (tid == 0) isb[j] = 1;
-            if (x && tid != pv) {
-                g ^= crow[pb * 16 + (pv >> 6)];
-                sp ^= csp[pb * 16 + (pv >> 6)];
+            // reduced columns are sparse early on: waves with no row to update skip the row read
+            if (__ballot(x && tid != pv)) {
+                const vrow<NW> pr = crow[pb * 16 + (pv >> 6)];
+                const uint32_t ps = csp[pb * 16 + (pv >> 6)];
+                if (x && tid != pv) {
+                    g ^= pr;
+                    sp ^= ps;
+                }
             }
             ++rank;
         }

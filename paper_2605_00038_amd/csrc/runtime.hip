@@ -1,6 +1,7 @@
 // Host runtime of the C ABI in include/lbp.h: validation, device tables,
 // workspace sizing, launch configuration and the OSD overflow loop.
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -270,6 +271,7 @@ lbp_status lbp_code_create(int32_t m, int32_t n, const int32_t *row_ptr, const i
     dc.mu_f32 = (const float *)(b + o_m32);
     dc.mu_f16 = (const float *)(b + o_m16);
     dc.mu_q = (const int32_t *)(b + o_mq);
+    dc.mu_q_uniform = uniform ? muq[0] : INT32_MIN;
     *out = code;
     return LBP_OK;
 }
@@ -358,7 +360,7 @@ lbp_status lbp_decoder_create(lbp_code code, const lbp_params *prm, int64_t max_
         hipDeviceGetAttribute(&lds_block, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
         return cleanup_fail(LBP_EDEVICE, "lbp_decoder_create: device query failed");
     // ---- BP launch shape: the waves-per-block choice with the most resident waves per CU
-    d->int8_slots = prm->msg == LBP_MSG_INT8 ? bp_int8_slots(code->m) : 0;
+    d->int8_slots = prm->msg == LBP_MSG_INT8 ? bp_int8_slots(code->m, code->n) : 0;
     d->wave_bytes = d->int8_slots ? bp_int8_wave_bytes(code->m, code->n) : bp_wave_bytes(prm->msg, code->m, code->n);
     d->table_bytes = d->int8_slots ? bp_int8_table_bytes(d->int8_slots) : 0;
     if (d->table_bytes + d->wave_bytes > lds_block)
