@@ -84,6 +84,7 @@ typedef struct {
     int32_t osd;
     int32_t osd_order;
     int32_t early_stop; /* 1 normally; 0 keeps iterating (test hook) */
+    int32_t policy;     /* lottery design-space variant: CN rule in bits 0-1, VN rule in bits 4-5 */
     uint64_t seed;
 } orc_params;
 
@@ -172,10 +173,13 @@ static int scale_int8(const orc_params *P, int i, int mag) {
     return mag - (mag >> sh);
 }
 
-static uint64_t lottery_draw(uint64_t seed, uint64_t shot_id, int i) {
+/* Words 0 and 1 of the Philox block of (shot, iteration): word 0 picks the
+ * check, word 1 the neighbour when that choice is random too. */
+static void lottery_draw(uint64_t seed, uint64_t shot_id, int i, uint64_t *w0, uint64_t *w1) {
     uint64_t ctr[4] = {shot_id, (uint64_t)i, 0, 0}, key[2] = {seed, 0}, out[4];
     orc_philox4x64_10(ctr, key, out);
-    return out[0];
+    *w0 = out[0];
+    *w1 = out[1];
 }
 
 /* ------------------------------------------------------------------ BP */
@@ -188,17 +192,52 @@ typedef struct {
 } work;
 
 /* Lottery (Algorithm 3) for iteration i.  U uses the previous iteration's
- * syndrome estimate.  Returns v* or -1 when U is empty. */
+ * syndrome estimate.  Returns v* or -1 when U is empty.
+ *
+ * Design space of the selection (Sec. III-B, Table I), P->policy:
+ *   CN rule (bits 0-1): 0 = a random check of U (Algorithm 3);
+ *                       1 = worst check: the check of U with the most
+ *                           neighbours in the current hard decision, the
+ *                           smallest index among equals.
+ *   VN rule (bits 4-5): 0 = the proposed key: most neighbouring checks in U,
+ *                           then smallest Q(|lambda|), then smallest column
+ *                           (Algorithm 3 and Sec. IV-B);
+ *                       1 = the same two criteria in the other order
+ *                           (smallest Q first, then most checks in U), as
+ *                           Sec. III-B words the proposed policy;
+ *                       2 = unreliable neighbour: smallest Q, then column;
+ *                       3 = a random neighbour.
+ * Random draws: r0 = (word 0 >> 32) / 2^32 picks the check, index
+ * floor(r0 |U|); r1 = (word 1 >> 32) / 2^32 picks the neighbour among the
+ * check's columns in ascending order. */
 static int lottery_pick(const ocode *C, const orc_params *P, uint64_t shot_id, int i,
                         const uint8_t *s, const uint8_t *sprev, int *ulist,
-                        const double *lamf, const long *lami) {
+                        const double *lamf, const long *lami, const uint8_t *ehat) {
+    const int cn_rule = P->policy & 3, vn_rule = (P->policy >> 4) & 3;
     int N = 0;
     for (int c = 0; c < C->m; ++c)
         if (sprev[c] != s[c]) ulist[N++] = c;
     if (N == 0) return -1;
-    uint64_t x = lottery_draw(P->seed, shot_id, i);
-    uint64_t k = ((x >> 32) * (uint64_t)N) >> 32; /* floor(r * N) */
-    int cstar = ulist[k];
+    uint64_t x0, x1;
+    lottery_draw(P->seed, shot_id, i, &x0, &x1);
+    int cstar;
+    if (cn_rule == 1) {
+        int best = -1;
+        cstar = -1;
+        for (int u = 0; u < N; ++u) {
+            int c = ulist[u], cnt = 0;
+            for (int e = C->rp[c]; e < C->rp[c + 1]; ++e) cnt += ehat[C->ci[e]];
+            if (cnt > best) { best = cnt; cstar = c; }   /* ascending c: first maximum wins */
+        }
+    } else {
+        uint64_t k = ((x0 >> 32) * (uint64_t)N) >> 32; /* floor(r * N) */
+        cstar = ulist[k];
+    }
+    if (vn_rule == 3) {
+        const int deg = C->rp[cstar + 1] - C->rp[cstar];
+        uint64_t k = ((x1 >> 32) * (uint64_t)deg) >> 32;
+        return C->ci[C->rp[cstar] + (int)k];
+    }
     int best_v = -1, best_cnt = -1;
     long long best_q = 0;
     for (int e = C->rp[cstar]; e < C->rp[cstar + 1]; ++e) {
@@ -212,7 +251,11 @@ static int lottery_pick(const ocode *C, const orc_params *P, uint64_t shot_id, i
             double a = fabs(lamf[v]) * 4096.0;
             q = a >= 4.0e18 ? (long long)4.0e18 : (long long)floor(a);
         }
-        int better = best_v < 0 || cnt > best_cnt || (cnt == best_cnt && (q < best_q || (q == best_q && v < best_v)));
+        int better;
+        if (best_v < 0) better = 1;
+        else if (vn_rule == 0) better = cnt > best_cnt || (cnt == best_cnt && (q < best_q || (q == best_q && v < best_v)));
+        else if (vn_rule == 1) better = q < best_q || (q == best_q && (cnt > best_cnt || (cnt == best_cnt && v < best_v)));
+        else better = q < best_q || (q == best_q && v < best_v);
         if (better) { best_v = v; best_cnt = cnt; best_q = q; }
     }
     return best_v;
@@ -287,7 +330,7 @@ static void bp_float(const ocode *C, const orc_params *P, const double *prior, u
         /* lottery (Algorithm 3) */
         flip_v = -1;
         if (P->lottery && i >= P->lottery_skip && i <= I - 2) {
-            int vs = lottery_pick(C, P, shot_id, i, s, W->sprev, W->ulist, lam, NULL);
+            int vs = lottery_pick(C, P, shot_id, i, s, W->sprev, W->ulist, lam, NULL, ehat);
             if (vs >= 0) {
                 if (P->flip == ORC_FLIP_MSG) flip_v = vs;
                 else lam[vs] = -lam[vs];
@@ -362,7 +405,7 @@ static void bp_int8(const ocode *C, const orc_params *P, const double *prior, ui
         *conv = match;
         flip_v = -1;
         if (P->lottery && i >= P->lottery_skip && i <= I - 2) {
-            int vs = lottery_pick(C, P, shot_id, i, s, W->sprev, W->ulist, NULL, lam);
+            int vs = lottery_pick(C, P, shot_id, i, s, W->sprev, W->ulist, NULL, lam, ehat);
             if (vs >= 0) {
                 if (P->flip == ORC_FLIP_MSG) flip_v = vs;
                 else lam[vs] = -lam[vs];
@@ -611,16 +654,17 @@ int orc_decode(int32_t m, int32_t n, const int32_t *row_ptr, const int32_t *col_
  * s, sprev: m bytes; lam: n values (Int3.4 when is_int8).  Returns v* or -1. */
 int orc_lottery_pick(int32_t m, int32_t n, const int32_t *row_ptr, const int32_t *col_idx, uint64_t seed,
                      uint64_t shot_id, int32_t i, const uint8_t *s, const uint8_t *sprev, const double *lam,
-                     int32_t is_int8) {
+                     int32_t is_int8, int32_t policy, const uint8_t *ehat) {
     ocode C;
     if (build_code(m, n, row_ptr, col_idx, &C) != 0) return -2;
     orc_params P;
     memset(&P, 0, sizeof P);
     P.seed = seed;
+    P.policy = policy;
     int *ulist = malloc(sizeof(int) * (size_t)(m + 1));
     long *li = malloc(sizeof(long) * (size_t)(n + 1));
     for (int v = 0; v < n; ++v) li[v] = (long)lam[v];
-    int r = lottery_pick(&C, &P, shot_id, i, s, sprev, ulist, is_int8 ? NULL : lam, is_int8 ? li : NULL);
+    int r = lottery_pick(&C, &P, shot_id, i, s, sprev, ulist, is_int8 ? NULL : lam, is_int8 ? li : NULL, ehat);
     free(ulist); free(li);
     free_code(&C);
     return r;

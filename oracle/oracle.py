@@ -31,6 +31,7 @@ class _Params(ctypes.Structure):
         ("osd", ctypes.c_int32),
         ("osd_order", ctypes.c_int32),
         ("early_stop", ctypes.c_int32),
+        ("policy", ctypes.c_int32),
         ("seed", ctypes.c_uint64),
     ]
 
@@ -47,12 +48,13 @@ class OracleParams:
     osd: int = OSD_NONE
     osd_order: int = 10
     early_stop: bool = True
+    policy: int = 0              # lottery variant: CN rule | VN rule << 4 (see lottery_pick)
     seed: int = 0
 
     def c(self) -> _Params:
         return _Params(self.max_iter, self.scale_mode, self.scale, self.msg, int(self.lottery),
                        self.lottery_skip, self.flip, self.osd, self.osd_order, int(self.early_stop),
-                       self.seed & 0xFFFFFFFFFFFFFFFF)
+                       self.policy, self.seed & 0xFFFFFFFFFFFFFFFF)
 
 
 def build(force: bool = False) -> str:
@@ -89,7 +91,8 @@ def _get():
         lib.orc_osd.restype = ctypes.c_int
         lib.orc_lottery_pick.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
                                          ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int32, ctypes.c_void_p,
-                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32]
+                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                         ctypes.c_void_p]
         lib.orc_lottery_pick.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -159,11 +162,24 @@ def osd(h, llr: np.ndarray, syndrome: np.ndarray, mode: int = OSD_0, order: int 
     return corr, int(flag[0])
 
 
-def lottery_pick(h, seed: int, shot_id: int, i: int, s, sprev, lam, is_int8: bool = False) -> int:
-    """Algorithm 3's selection on explicit state; returns v* (or -1 if no check is unsatisfied)."""
+# Lottery design-space rules (Sec. III-B, Table I); policy = CN rule | VN rule << 4.
+CN_RANDOM, CN_WORST = 0, 1
+VN_PROPOSED, VN_Q_FIRST, VN_UNRELIABLE, VN_RANDOM = 0, 1, 2, 3
+
+
+def policy_code(cn: int = CN_RANDOM, vn: int = VN_PROPOSED) -> int:
+    return cn | (vn << 4)
+
+
+def lottery_pick(h, seed: int, shot_id: int, i: int, s, sprev, lam, is_int8: bool = False,
+                 policy: int = 0, ehat=None) -> int:
+    """Algorithm 3's selection on explicit state; returns v* (or -1 if no check is unsatisfied).
+
+    ehat (n bytes, the current hard decision) is read only by the worst-check rule."""
     m, n, rp, ci = _csr(h)
     s8 = np.ascontiguousarray(s, dtype=np.uint8)
     p8 = np.ascontiguousarray(sprev, dtype=np.uint8)
     lam = np.ascontiguousarray(lam, dtype=np.float64)
+    e8 = np.ascontiguousarray(ehat if ehat is not None else np.zeros(n), dtype=np.uint8)
     return _get().orc_lottery_pick(m, n, _ptr(rp), _ptr(ci), seed, shot_id, i, _ptr(s8), _ptr(p8), _ptr(lam),
-                                   int(is_int8))
+                                   int(is_int8), int(policy), _ptr(e8))

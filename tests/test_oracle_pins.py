@@ -217,6 +217,111 @@ def test_lottery_selection_hand_traced():
     assert oracle.lottery_pick(h, 123, 0, 7, s, sprev, [5, -3, 3, 2, 1, 1, 3], is_int8=True) == 1  # tie
 
 
+def _pin_graph():
+    rows = [[0, 1, 2], [1, 3], [2, 3, 4, 5], [5, 6]]
+    data = [(r, c) for r, row in enumerate(rows) for c in row]
+    return rows, sp.csr_matrix((np.ones(len(data), np.uint8), ([a for a, _ in data], [b for _, b in data])),
+                               shape=(4, 7))
+
+
+def test_lottery_worst_check_rule():
+    """Worst check (Sec. III-B): among U, the check with the most neighbours in the
+    current hard decision; checks outside U never count; equal counts -> smaller index.
+    Same graph as above, U = {c0, c1, c2}; the VN rule then picks inside that check."""
+    rows, h = _pin_graph()
+    s, sprev = [1, 0, 1, 0], [0, 1, 0, 0]
+    lam = [5.0, -1.5, 1.0002, 1.0001, 0.1, 0.2, 3.0]
+    worst = oracle.policy_code(cn=oracle.CN_WORST)
+    unrel = oracle.policy_code(cn=oracle.CN_WORST, vn=oracle.VN_UNRELIABLE)
+    cases = [([0, 1, 0, 1, 1, 1, 0], 2),    # c0:1 c1:2 c2:3
+             ([1, 1, 0, 0, 0, 0, 0], 0),    # c0:2 c1:1 c2:0
+             ([0, 1, 0, 0, 0, 0, 0], 0),    # c0:1 c1:1 -> smaller index
+             ([0, 0, 0, 0, 0, 1, 1], 2),    # c3 has two but is satisfied; c2:1
+             ([0, 0, 0, 0, 0, 0, 0], 0)]    # all zero -> first check of U
+    # the proposed key inside each check (counts: col 1,2,3 see two checks of U)
+    vn_in = {0: 2, 1: 3, 2: 2}
+    # unreliable inside each check: smallest quantized |lambda|, then column
+    unrel_in = {0: 2, 1: 3, 2: 4}
+    for ehat, c in cases:
+        for shot in range(4):               # the draw must not matter
+            assert oracle.lottery_pick(h, 9, shot, 7, s, sprev, lam, policy=worst, ehat=ehat) == vn_in[c]
+            assert oracle.lottery_pick(h, 9, shot, 7, s, sprev, lam, policy=unrel, ehat=ehat) == unrel_in[c]
+
+
+def test_lottery_neighbour_rules():
+    """The neighbour rules on c2 = {2,3,4,5} with U = all four checks, so the
+    unsatisfied counts of columns 2..5 are 2, 2, 1, 2 (c3 now counts for column 5):
+      A: Q = 4096, 2048, 204, 409 -> proposed (count, then Q) picks 5; Q-first and
+         unreliable pick 4 (smallest Q).
+      B: Q = 4096, 2048, 409, 409 -> proposed 5; Q-first breaks the Q tie by the
+         larger count -> 5; unreliable breaks it by the smaller column -> 4.
+    Worst-check rule with ehat on columns 3,4,5 fixes c* = c2."""
+    rows, h = _pin_graph()
+    s, sprev = [1, 0, 1, 0], [0, 1, 0, 1]
+    ehat = [0, 0, 0, 1, 1, 1, 0]
+    lam_a = [5.0, -1.5, 1.0, 0.5, 0.05, 0.1, 3.0]
+    lam_b = [5.0, -1.5, 1.0, 0.5, 0.1, -0.1, 3.0]
+    expect = {oracle.VN_PROPOSED: (5, 5), oracle.VN_Q_FIRST: (4, 5), oracle.VN_UNRELIABLE: (4, 4)}
+    for vn, (ea, eb) in expect.items():
+        pol = oracle.policy_code(cn=oracle.CN_WORST, vn=vn)
+        assert oracle.lottery_pick(h, 5, 0, 9, s, sprev, lam_a, policy=pol, ehat=ehat) == ea
+        assert oracle.lottery_pick(h, 5, 0, 9, s, sprev, lam_b, policy=pol, ehat=ehat) == eb
+    # Int3.4: the same comparisons on |lambda| itself
+    pol = oracle.policy_code(cn=oracle.CN_WORST, vn=oracle.VN_Q_FIRST)
+    assert oracle.lottery_pick(h, 5, 0, 9, s, sprev, [80, -24, 16, 8, 2, -2, 48], is_int8=True,
+                               policy=pol, ehat=ehat) == 5
+    pol = oracle.policy_code(cn=oracle.CN_WORST, vn=oracle.VN_UNRELIABLE)
+    assert oracle.lottery_pick(h, 5, 0, 9, s, sprev, [80, -24, 16, 8, 2, -2, 48], is_int8=True,
+                               policy=pol, ehat=ehat) == 4
+
+
+def test_lottery_random_neighbour_draw():
+    """Random neighbour: word 1 of the same Philox block, r1 = (w1 >> 32) / 2^32,
+    picks column floor(r1 deg) of the check in ascending order; the check comes from
+    word 0 (random rule) or from the worst-check rule.  Every neighbour must occur."""
+    rows, h = _pin_graph()
+    s, sprev = [1, 0, 1, 0], [0, 1, 0, 0]
+    lam = [5.0, -1.5, 1.0002, 1.0001, 0.1, 0.2, 3.0]
+    seen = set()
+    for shot in range(64):
+        w = numpy_philox([shot, 4, 0, 0], [77, 0])
+        c = [0, 1, 2][((w[0] >> 32) * 3) >> 32]
+        v = rows[c][((w[1] >> 32) * len(rows[c])) >> 32]
+        seen.add(v)
+        pol = oracle.policy_code(cn=oracle.CN_RANDOM, vn=oracle.VN_RANDOM)
+        assert oracle.lottery_pick(h, 77, shot, 4, s, sprev, lam, policy=pol) == v
+        ehat = [0, 0, 0, 1, 1, 1, 0]                              # worst check c2
+        v2 = rows[2][((w[1] >> 32) * 4) >> 32]
+        pol = oracle.policy_code(cn=oracle.CN_WORST, vn=oracle.VN_RANDOM)
+        assert oracle.lottery_pick(h, 77, shot, 4, s, sprev, lam, policy=pol, ehat=ehat) == v2
+    assert seen == {0, 1, 2, 3, 4, 5}
+    # no unsatisfied check: no flip under every rule
+    for pol in range(0, 0x40, 0x10):
+        for cn in (0, 1):
+            assert oracle.lottery_pick(h, 77, 0, 4, s, s, lam, policy=pol | cn, ehat=[1] * 7) == -1
+
+
+@pytest.mark.parametrize("msg", [oracle.FP64, oracle.INT8])
+def test_lottery_policies_keep_decoder_outputs_valid(msg):
+    """Every rule runs through the whole decoder: a shot flagged converged has a
+    correction whose syndrome matches, and each rule other than the proposed one
+    changes some shot's iteration count (so the policy reaches the lottery)."""
+    h, _, _ = codes.workload_matrices("bb144_cc")
+    _, syn = sample.make_batch(h, 0.05, 96, seed=11)
+    n = h.shape[1]
+    base = None
+    for pol in [0, 0x01, 0x10, 0x20, 0x30, 0x21]:
+        r = oracle.decode(h, 0.05, oracle.OracleParams(max_iter=40, msg=msg, policy=pol, seed=2), syn)
+        corr = sample.unpack_bits(r["corr"], n)
+        ok = (r["flags"] & oracle.FLAG_CONVERGED) != 0
+        assert ok.sum() > 10
+        assert np.array_equal(sample.pack_bits((corr[ok].astype(np.int64) @ h.T.toarray()) % 2), syn[ok])
+        if base is None:
+            base = r["iters"]
+        else:
+            assert not np.array_equal(r["iters"], base), pol
+
+
 # ------------------------------------------------------------------------ OSD
 
 def _span_rank(cols):
