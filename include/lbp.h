@@ -60,6 +60,25 @@ typedef enum { LBP_SCALE_PAPER = 0, LBP_SCALE_CONST = 1 } lbp_scale;
  * itself is negated before the next VN update (the literal Algorithm 3). */
 typedef enum { LBP_FLIP_MSG = 0, LBP_FLIP_LLR = 1 } lbp_flip;
 
+/* Lottery selection rule (the design space of Sec. III-B and Table I):
+ * lottery_rule = CN rule | (VN rule << 4).  Let r0 and r1 be the upper 32 bits
+ * of words 0 and 1 of the Philox block of (shot_id, i), divided by 2^32.
+ *   LBP_CN_RANDOM: c* = the floor(r0 |U|)-th check of U in ascending order
+ *                  (Algorithm 3).
+ *   LBP_CN_WORST:  c* = the check of U with the most neighbours whose current
+ *                  hard decision is 1; the smallest index among equals.
+ *   LBP_VN_PROPOSED:   v* = the neighbour of c* with the most checks in U, then
+ *                      the smallest Q(|lambda|), then the smallest column
+ *                      (Algorithm 3, Sec. IV-B).
+ *   LBP_VN_Q_FIRST:    smallest Q first, then most checks in U, then column (the
+ *                      order in which Sec. III-B words the proposed key).
+ *   LBP_VN_UNRELIABLE: smallest Q, then smallest column.
+ *   LBP_VN_RANDOM:     the floor(r1 deg(c*))-th neighbour of c* in ascending order.
+ * Q(|lambda|) is |lambda| for INT8 and floor(|lambda| 2^12) for float formats. */
+enum { LBP_CN_RANDOM = 0, LBP_CN_WORST = 1 };
+enum { LBP_VN_PROPOSED = 0, LBP_VN_Q_FIRST = 1, LBP_VN_UNRELIABLE = 2, LBP_VN_RANDOM = 3 };
+#define LBP_LOTTERY_RULE(cn, vn) ((cn) | ((vn) << 4))
+
 /* Fallback for shots whose BP run ends without matching the syndrome. */
 typedef enum { LBP_OSD_NONE = 0, LBP_OSD_0 = 1, LBP_OSD_CS = 2 } lbp_osd;
 
@@ -73,7 +92,7 @@ typedef struct {
     int32_t flip;         /* lbp_flip */
     int32_t osd;          /* lbp_osd */
     int32_t osd_order;    /* OSD-CS: weight-2 patterns among the first osd_order non-basis columns */
-    int32_t reserved;     /* must be 0 */
+    int32_t lottery_rule; /* LBP_LOTTERY_RULE(cn, vn); 0 = Algorithm 3; other values rejected (LBP_EINVAL) */
     uint64_t seed;        /* lottery key: Philox4x64-10, key (seed, 0), counter (shot_id, i, 0, 0) */
 } lbp_params;
 
@@ -85,7 +104,7 @@ enum {
 };
 
 /* Fill *p with the defaults: I = 100, PAPER scale, INT8, lottery on, K = 6,
- * MSG flip, OSD-0, order 10, seed 0. */
+ * MSG flip, OSD-0, order 10, rule 0 (Algorithm 3), seed 0. */
 void lbp_params_default(lbp_params *p);
 
 /* Load a parity-check matrix and per-column priors (Algorithm 1 inputs H and p).
@@ -107,7 +126,9 @@ int32_t lbp_code_cols(lbp_code code);
 /* Create a decoder for `code` with parameters *prm, able to decode up to
  * max_batch shots per call.  Allocates the device workspace (on the code's
  * device).  OSD-CS requires a uniform prior (LBP_EUNSUPPORTED otherwise): its
- * candidate cost is the Hamming weight.  The code must outlive the decoder. */
+ * candidate cost is the Hamming weight.  The decoder holds a reference to the
+ * code: lbp_code_destroy may come before lbp_decoder_destroy (in any order);
+ * the code's device memory is released with its last user. */
 lbp_status lbp_decoder_create(lbp_code code, const lbp_params *prm, int64_t max_batch, lbp_decoder *out);
 void lbp_decoder_destroy(lbp_decoder dec);
 
@@ -196,7 +217,7 @@ lbp_status lbp_server_create(int64_t device_mem_budget_bytes, int32_t max_slots,
  * request brings its own).  Picks the largest ring (power of two, 1024 ..
  * 65536 shots; 8n bytes of device memory per shot) that fits the remaining
  * budget: LBP_ENOMEM if none does, LBP_EBUSY if all slots are taken.  The
- * code must outlive the server. */
+ * slot holds a reference to the code (as a decoder does). */
 lbp_status lbp_server_add_code(lbp_server srv, lbp_code code, const lbp_params *prm, int32_t *code_slot);
 /* Queue n_shots >= 1 syndromes (HOST, [n_shots][ceil(m/32)], copied before
  * return).  Admission: LBP_EBUSY when the slot would hold more than 16 rings'

@@ -16,6 +16,13 @@ MSG_FP32, MSG_FP16, MSG_INT8 = 0, 1, 2
 SCALE_PAPER, SCALE_CONST = 0, 1
 FLIP_MSG, FLIP_LLR = 0, 1
 OSD_NONE, OSD_0, OSD_CS = 0, 1, 2
+CN_RANDOM, CN_WORST = 0, 1
+VN_PROPOSED, VN_Q_FIRST, VN_UNRELIABLE, VN_RANDOM = 0, 1, 2, 3
+
+
+def lottery_rule(cn: int = CN_RANDOM, vn: int = VN_PROPOSED) -> int:
+    """lbp_params.lottery_rule for a check rule and a neighbour rule (LBP_LOTTERY_RULE)."""
+    return cn | (vn << 4)
 FLAG_CONVERGED, FLAG_OSD, FLAG_OSD_INCONSISTENT = 1, 2, 4
 
 _STATUS = {0: "LBP_OK", -1: "LBP_EINVAL", -2: "LBP_ENOMEM", -3: "LBP_EDEVICE", -4: "LBP_EBUSY",
@@ -39,7 +46,7 @@ class Params(ctypes.Structure):
         ("flip", ctypes.c_int32),
         ("osd", ctypes.c_int32),
         ("osd_order", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("lottery_rule", ctypes.c_int32),
         ("seed", ctypes.c_uint64),
     ]
 

@@ -50,7 +50,9 @@ __device__ __forceinline__ double sigma_of(const BpParams &P, int i) {
     return i >= 24 ? 1.0 : 1.0 - __builtin_ldexp(1.0, -(i + 1));  // fl32(1 - 2^-(i+1)), exact
 }
 
-__device__ uint64_t philox_w0(uint64_t k0, uint64_t c0, uint64_t c1) {
+// Philox4x64-10 (Salmon et al., SC'11): words 0 (returned) and 1 (w1) for
+// counter (c0, c1, 0, 0), key (k0, 0).
+__device__ uint64_t philox_w01(uint64_t k0, uint64_t c0, uint64_t c1, uint64_t &w1) {
     uint64_t x0 = c0, x1 = c1, x2 = 0, x3 = 0, ka = k0, kb = 0;
     for (int r = 0; r < 10; ++r) {
         const uint64_t h0 = __umul64hi(0xD2E7470EE14C6C93ULL, x0), l0 = 0xD2E7470EE14C6C93ULL * x0;
@@ -63,6 +65,7 @@ __device__ uint64_t philox_w0(uint64_t k0, uint64_t c0, uint64_t c1) {
         ka += 0x9E3779B97F4A7C15ULL;
         kb += 0xBB67AE8584CAA73BULL;
     }
+    w1 = x1;
     return x0;
 }
 
@@ -218,18 +221,38 @@ __global__ void bl_check(BlArgs a, int i) {
             if (N > 0) {
                 const uint64_t seed = a.shot_keys ? a.shot_keys[2 * shot] : P.seed;
                 const uint64_t sid = a.shot_keys ? a.shot_keys[2 * shot + 1] : a.first_shot_id + (uint64_t)shot;
-                const uint64_t x = philox_w0(seed, sid, (uint64_t)i);
-                int k = (int)(((x >> 32) * (uint64_t)N) >> 32);
+                uint64_t x1;
+                const uint64_t x = philox_w01(seed, sid, (uint64_t)i, x1);
+                const int cn_rule = P.rule & 3, vn_rule = (P.rule >> 4) & 3;
                 int cstar = -1;
-                for (int w = 0; w < C.mw && cstar < 0; ++w) {  // uniform scan: clarity over speed
-                    const uint32_t s = w == C.mw - 1 ? (S[w] & last_mask) : S[w];
-                    uint32_t u = SHp[w] ^ s;
-                    const int cnt = __popc(u);
-                    if (k < cnt) {
-                        for (int q = 0; q < k; ++q) u &= u - 1;
-                        cstar = w * 32 + __ffs(u) - 1;
+                if (cn_rule == LOT_CN_WORST) {
+                    // the check of U with the most neighbours in the hard decision, first of equals
+                    int best = -1;
+                    for (int c = 0; c < C.m; ++c) {  // uniform scan: clarity over speed
+                        const uint32_t s = (S[c >> 5] >> (c & 31)) & 1u;
+                        if (!(((SHp[c >> 5] >> (c & 31)) & 1u) ^ s)) continue;
+                        int cnt = 0;
+                        for (int k = 0; k < C.cn_deg[c]; ++k) {
+                            const uint32_t v = C.cn_cols[c * DEG + k];
+                            cnt += (int)((EH[v >> 5] >> (v & 31)) & 1u);
+                        }
+                        if (cnt > best) {
+                            best = cnt;
+                            cstar = c;
+                        }
                     }
-                    k -= cnt;
+                } else {
+                    int k = (int)(((x >> 32) * (uint64_t)N) >> 32);
+                    for (int w = 0; w < C.mw && cstar < 0; ++w) {  // uniform scan: clarity over speed
+                        const uint32_t s = w == C.mw - 1 ? (S[w] & last_mask) : S[w];
+                        uint32_t u = SHp[w] ^ s;
+                        const int cnt = __popc(u);
+                        if (k < cnt) {
+                            for (int q = 0; q < k; ++q) u &= u - 1;
+                            cstar = w * 32 + __ffs(u) - 1;
+                        }
+                        k -= cnt;
+                    }
                 }
                 int best_v = -1, best_cnt = -1;
                 long long best_q = 0;
@@ -246,13 +269,15 @@ __global__ void bl_check(BlArgs a, int i) {
                     }
                     const double qa = __builtin_fabs(a.lam[shot * C.n + v]) * 4096.0;
                     const long long q = qa >= 4.0e18 ? (long long)4.0e18 : (long long)__builtin_floor(qa);
-                    if (best_v < 0 || cnt > best_cnt || (cnt == best_cnt && (q < best_q || (q == best_q && v < best_v)))) {
+                    if (best_v < 0 || lottery_key_less(vn_rule, cnt, q, v, best_cnt, best_q, best_v)) {
                         best_v = v;
                         best_cnt = cnt;
                         best_q = q;
                     }
                 }
                 fv = best_v;
+                if (vn_rule == LOT_VN_RANDOM)
+                    fv = C.cn_cols[cstar * DEG + (int)(((x1 >> 32) * (uint64_t)C.cn_deg[cstar]) >> 32)];
             }
         }
         if (lane == 0) {

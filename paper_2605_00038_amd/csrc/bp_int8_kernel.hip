@@ -69,8 +69,8 @@ __device__ __forceinline__ int wave_incl_scan(int x, int lane) {
     return x;
 }
 
-// Philox4x64-10 (Salmon et al., SC'11), word 0 for counter (c0, c1, 0, 0), key (k0, 0).
-__device__ uint64_t philox_w0(uint64_t k0, uint64_t c0, uint64_t c1) {
+// Philox4x64-10 (Salmon et al., SC'11): words 0 and 1 for counter (c0, c1, 0, 0), key (k0, 0).
+__device__ uint64_t philox_w01(uint64_t k0, uint64_t c0, uint64_t c1, uint64_t &w1) {
     uint64_t x0 = c0, x1 = c1, x2 = 0, x3 = 0, ka = k0, kb = 0;
 #pragma unroll 1
     for (int r = 0; r < 10; ++r) {
@@ -81,6 +81,7 @@ __device__ uint64_t philox_w0(uint64_t k0, uint64_t c0, uint64_t c1) {
         ka += 0x9E3779B97F4A7C15ULL;
         kb += 0xBB67AE8584CAA73BULL;
     }
+    w1 = x1;
     return x0;
 }
 
@@ -95,37 +96,75 @@ __device__ __forceinline__ int lambda_next(const uint32_t *L, int v, int nxt_hi)
     return (int)(nxt_hi ? (w >> 16) : (w & 0xFFFFu)) - BIAS;
 }
 
-// Lottery selection (Algorithm 3), U from the previous syndrome estimate SHp.
-__device__ int lottery_pick_q(const DevCode &C, uint64_t seed, uint64_t shot_id, int i, const uint32_t *L,
-                              int nxt_hi, const uint32_t *S, const uint32_t *SHp, int lane) {
+// Worst check of U (Sec. III-B): the most neighbours in the hard decision EH,
+// the smallest index among equals.  One check per lane, wave-wide maximum.
+__device__ int worst_check(const DevCode &C, const uint32_t *S, const uint32_t *SHp, const uint32_t *EH, int lane) {
+    unsigned long long best = 0;
+    for (int c0 = 0; c0 < C.m; c0 += 64) {
+        const int c = c0 + lane;
+        if (c < C.m && (((SHp[c >> 5] ^ S[c >> 5]) >> (c & 31)) & 1u)) {
+            int cnt = 0;
+            const int deg = C.cn_deg[c];
+            for (int k = 0; k < deg; ++k) {
+                const uint32_t v = C.cn_cols[c * DEG + k];
+                cnt += (EH[v >> 5] >> (v & 31)) & 1u;
+            }
+            const unsigned long long key = ((unsigned long long)(cnt + 1) << 32) | (0xFFFFFFFFu - (uint32_t)c);
+            best = key > best ? key : best;
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long y = __shfl_xor(best, o, 64);
+        best = y > best ? y : best;
+    }
+    return (int)(0xFFFFFFFFu - (uint32_t)best);
+}
+
+// Lottery selection (Algorithm 3), U from the previous syndrome estimate SHp,
+// under the design-space rule `rule` (CN rule | VN rule << 4, Sec. III-B):
+// random or worst check; proposed key (count, Q, column), Q-first (Q, count,
+// column), unreliable (Q, column) or a random neighbour.  Q = |lambda|.
+__device__ int lottery_pick_q(const DevCode &C, int rule, uint64_t seed, uint64_t shot_id, int i, const uint32_t *L,
+                              int nxt_hi, const uint32_t *S, const uint32_t *SHp, const uint32_t *EH, int lane) {
     int N = 0;
     for (int w0 = 0; w0 < C.mw; w0 += 64) {
         int w = w0 + lane;
         N += wave_sum(__popc(w < C.mw ? (SHp[w] ^ S[w]) : 0u));
     }
     if (N == 0) return -1;
-    const uint64_t x = philox_w0(seed, shot_id, (uint64_t)i);
-    uint32_t k = (uint32_t)(((x >> 32) * (uint64_t)N) >> 32);
+    const int cn_rule = rule & 3, vn_rule = (rule >> 4) & 3;
+    uint64_t x1;
+    const uint64_t x = philox_w01(seed, shot_id, (uint64_t)i, x1);
     int cstar = 0;
-    for (int w0 = 0; w0 < C.mw; w0 += 64) {
-        int w = w0 + lane;
-        uint32_t u = w < C.mw ? (SHp[w] ^ S[w]) : 0u;
-        int cnt = __popc(u);
-        int incl = wave_incl_scan(cnt, lane);
-        int tot = __shfl(incl, 63, 64);
-        if ((int)k < tot) {
-            int excl = incl - cnt;
-            bool here = (int)k >= excl && (int)k < incl;
-            int pos = 0;
-            if (here) {
-                uint32_t t = u;
-                for (int q = (int)k - excl; q > 0; --q) t &= t - 1;
-                pos = w * 32 + __ffs(t) - 1;
+    if (cn_rule == LOT_CN_WORST) {
+        cstar = __builtin_amdgcn_readfirstlane(worst_check(C, S, SHp, EH, lane));
+    } else {
+        uint32_t k = (uint32_t)(((x >> 32) * (uint64_t)N) >> 32);
+        for (int w0 = 0; w0 < C.mw; w0 += 64) {
+            int w = w0 + lane;
+            uint32_t u = w < C.mw ? (SHp[w] ^ S[w]) : 0u;
+            int cnt = __popc(u);
+            int incl = wave_incl_scan(cnt, lane);
+            int tot = __shfl(incl, 63, 64);
+            if ((int)k < tot) {
+                int excl = incl - cnt;
+                bool here = (int)k >= excl && (int)k < incl;
+                int pos = 0;
+                if (here) {
+                    uint32_t t = u;
+                    for (int q = (int)k - excl; q > 0; --q) t &= t - 1;
+                    pos = w * 32 + __ffs(t) - 1;
+                }
+                cstar = __shfl(pos, __ffsll((unsigned long long)__ballot(here)) - 1, 64);
+                break;
             }
-            cstar = __shfl(pos, __ffsll((unsigned long long)__ballot(here)) - 1, 64);
-            break;
+            k -= (uint32_t)tot;
         }
-        k -= (uint32_t)tot;
+    }
+    if (vn_rule == LOT_VN_RANDOM) {
+        const uint32_t k = (uint32_t)(((x1 >> 32) * (uint64_t)C.cn_deg[cstar]) >> 32);
+        return C.cn_cols[cstar * DEG + (int)k];
     }
     int cnt = -1, v = 0x7FFFFFFF, q = 0;
     if (lane < DEG) {
@@ -151,7 +190,7 @@ __device__ int lottery_pick_q(const DevCode &C, uint64_t seed, uint64_t shot_id,
     for (int kk = 0; kk < DEG; ++kk) {
         int ck = __shfl(cnt, kk, 64), vk = __shfl(v, kk, 64), qk = __shfl(q, kk, 64);
         if (ck < 0) continue;
-        if (bv < 0 || ck > bc || (ck == bc && (qk < bq || (qk == bq && vk < bv)))) {
+        if (bv < 0 || lottery_key_less(vn_rule, ck, qk, vk, bc, bq, bv)) {
             bc = ck;
             bq = qk;
             bv = vk;
@@ -352,8 +391,10 @@ __global__ __launch_bounds__(1024) void bp_int8_kernel(BpArgs a) {
         // a ring item lives in slot item & mask; a batch item names its shot
         const int64_t shot = a.ring ? (item & a.ring->mask) : a.work_list ? (int64_t)a.work_list[item] : item;
         const uint64_t *keys = a.ring ? a.ring->keys : a.shot_keys;
-        const uint64_t seed = keys ? keys[2 * shot] : P.seed;
-        const uint64_t shot_id = keys ? keys[2 * shot + 1] : a.first_shot_id + (uint64_t)shot;
+        // wave-uniform: the lottery's Philox rounds then run on the scalar unit
+        const uint64_t seed = (uint64_t)uniform64((int64_t)(keys ? keys[2 * shot] : P.seed));
+        const uint64_t shot_id =
+            (uint64_t)uniform64((int64_t)(keys ? keys[2 * shot + 1] : a.first_shot_id + (uint64_t)shot));
         float *llr_row = a.llr_out ? a.llr_out + shot * n : nullptr;
         const uint32_t *syn_row = (a.ring ? a.ring->syn : a.synd) + shot * C.mw;
 
@@ -443,7 +484,7 @@ __global__ __launch_bounds__(1024) void bp_int8_kernel(BpArgs a) {
             }
             flipslots = 0;
             if (P.lottery && i >= P.skip && i <= P.max_iter - 2) {
-                const int fv = lottery_pick_q(C, seed, shot_id, i, L, nxt_hi, S, SHp, lane);
+                const int fv = lottery_pick_q(C, P.rule, seed, shot_id, i, L, nxt_hi, S, SHp, EH, lane);
                 if (fv >= 0) {
                     // slots holding a check of v*: its column table names them
                     const uint64_t tab = C.vn_tab[__builtin_amdgcn_readfirstlane(fv)];

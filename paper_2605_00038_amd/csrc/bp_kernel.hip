@@ -65,9 +65,9 @@ __device__ __forceinline__ uint64_t wave_min_u64(uint64_t x) {
     return x;
 }
 
-// Philox4x64-10 (Salmon et al., SC'11): word 0 of the block for counter
-// (ctr0, ctr1, 0, 0) under key (k0, 0).
-__device__ uint64_t philox_word0(uint64_t k0, uint64_t ctr0, uint64_t ctr1) {
+// Philox4x64-10 (Salmon et al., SC'11): words 0 (returned) and 1 (w1) of the
+// block for counter (ctr0, ctr1, 0, 0) under key (k0, 0).
+__device__ uint64_t philox_word01(uint64_t k0, uint64_t ctr0, uint64_t ctr1, uint64_t &w1) {
     uint64_t x0 = ctr0, x1 = ctr1, x2 = 0, x3 = 0, ka = k0, kb = 0;
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
@@ -78,6 +78,7 @@ __device__ uint64_t philox_word0(uint64_t k0, uint64_t ctr0, uint64_t ctr1) {
         ka += 0x9E3779B97F4A7C15ULL;
         kb += 0xBB67AE8584CAA73BULL;
     }
+    w1 = x1;
     return x0;
 }
 
@@ -285,9 +286,41 @@ __device__ void cn_half(const DevCode &C, const BpParams &P, int i, typename Fmt
 
 // ------------------------------------------------------------ lottery selection
 
+// Worst check of U (Sec. III-B): the most neighbours whose hard decision on
+// lambda^(i) (rebuilt from E) is 1, the smallest index among equals.
+template <int MSG>
+__device__ int worst_check(const DevCode &C, const typename Fmt<MSG>::T *E, const uint32_t *S, const uint32_t *SHp,
+                           int lane) {
+    unsigned long long best = 0;
+    for (int c0 = 0; c0 < C.m; c0 += 64) {
+        const int c = c0 + lane;
+        if (c < C.m && (((SHp[c >> 5] ^ S[c >> 5]) >> (c & 31)) & 1u)) {
+            int cnt = 0;
+            const int deg = C.cn_deg[c];
+            for (int k = 0; k < deg; ++k) {
+                const int v = C.cn_cols[c * DEG + k];
+                typename Fmt<MSG>::A b[CDEG];
+                uint32_t mask;
+                cnt += hard_decision<MSG>(column_lambda<MSG>(C, v, C.vn_tab[v], E, b, mask)) ? 1 : 0;
+            }
+            const unsigned long long key = ((unsigned long long)(cnt + 1) << 32) | (0xFFFFFFFFu - (uint32_t)c);
+            best = key > best ? key : best;
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long y = __shfl_xor(best, o, 64);
+        best = y > best ? y : best;
+    }
+    return (int)(0xFFFFFFFFu - (uint32_t)best);
+}
+
 // Algorithm 3 with U taken from the previous iteration's syndrome estimate
 // SHp; lambda^(i) of the candidates is rebuilt from the C2V messages of
 // iteration i still held in E, with the same arithmetic as the VN half.
+// P.rule picks the design-space variant (Sec. III-B): random or worst check;
+// proposed key (count, Q, column), Q-first, unreliable (Q, column) or a
+// random neighbour drawn from word 1 of the same Philox block.
 template <int MSG>
 __device__ int lottery_select(const DevCode &C, const BpParams &P, uint64_t seed, uint64_t shot_id, int i,
                               const typename Fmt<MSG>::T *E, const uint32_t *S, const uint32_t *SHp, int lane) {
@@ -299,31 +332,41 @@ __device__ int lottery_select(const DevCode &C, const BpParams &P, uint64_t seed
         N += wave_sum(__popc(u));
     }
     if (N == 0) return -1;
-    const uint64_t x = philox_word0(seed, shot_id, (uint64_t)i);
-    uint32_t k = (uint32_t)(((x >> 32) * (uint64_t)N) >> 32);  // floor(r * N)
+    const int cn_rule = P.rule & 3, vn_rule = (P.rule >> 4) & 3;
+    uint64_t x1;
+    const uint64_t x = philox_word01(seed, shot_id, (uint64_t)i, x1);
     int cstar = -1;
-    for (int w0 = 0; w0 < C.mw; w0 += 64) {
-        int w = w0 + lane;
-        uint32_t u = w < C.mw ? (SHp[w] ^ S[w]) : 0u;
-        int cnt = __popc(u);
-        int incl = wave_incl_scan(cnt, lane);
-        int tot = __shfl(incl, 63, 64);
-        if ((int)k < tot) {
-            int excl = incl - cnt;
-            bool here = (int)k >= excl && (int)k < incl;
-            int pos = 0;
-            if (here) {
-                uint32_t t = u;
-                for (int q = (int)k - excl; q > 0; --q) t &= t - 1;
-                pos = w * 32 + __ffs(t) - 1;
+    if (cn_rule == LOT_CN_WORST) {
+        cstar = __builtin_amdgcn_readfirstlane(worst_check<MSG>(C, E, S, SHp, lane));
+    } else {
+        uint32_t k = (uint32_t)(((x >> 32) * (uint64_t)N) >> 32);  // floor(r * N)
+        for (int w0 = 0; w0 < C.mw; w0 += 64) {
+            int w = w0 + lane;
+            uint32_t u = w < C.mw ? (SHp[w] ^ S[w]) : 0u;
+            int cnt = __popc(u);
+            int incl = wave_incl_scan(cnt, lane);
+            int tot = __shfl(incl, 63, 64);
+            if ((int)k < tot) {
+                int excl = incl - cnt;
+                bool here = (int)k >= excl && (int)k < incl;
+                int pos = 0;
+                if (here) {
+                    uint32_t t = u;
+                    for (int q = (int)k - excl; q > 0; --q) t &= t - 1;
+                    pos = w * 32 + __ffs(t) - 1;
+                }
+                uint64_t b = __ballot(here);
+                cstar = __shfl(pos, __ffsll((unsigned long long)b) - 1, 64);
+                break;
             }
-            uint64_t b = __ballot(here);
-            cstar = __shfl(pos, __ffsll((unsigned long long)b) - 1, 64);
-            break;
+            k -= (uint32_t)tot;
         }
-        k -= (uint32_t)tot;
     }
-    // candidates v in V(c*): (most unsatisfied checks, smallest Q(|lambda|), smallest v)
+    if (vn_rule == LOT_VN_RANDOM) {
+        const uint32_t k = (uint32_t)(((x1 >> 32) * (uint64_t)C.cn_deg[cstar]) >> 32);
+        return C.cn_cols[cstar * DEG + (int)k];
+    }
+    // candidates v in V(c*), ordered by the neighbour rule
     int cnt = -1, v = 0x7FFFFFFF;
     uint64_t q = 0;
     if (lane < DEG) {
@@ -353,7 +396,7 @@ __device__ int lottery_select(const DevCode &C, const BpParams &P, uint64_t seed
         int ck = __shfl(cnt, k, 64), vk = __shfl(v, k, 64);
         uint64_t qk = __shfl(q, k, 64);
         if (ck < 0) continue;
-        if (bv < 0 || ck > bc || (ck == bc && (qk < bq || (qk == bq && vk < bv)))) {
+        if (bv < 0 || lottery_key_less(vn_rule, ck, qk, vk, bc, bq, bv)) {
             bc = ck;
             bq = qk;
             bv = vk;
@@ -479,8 +522,10 @@ __global__ __launch_bounds__(1024) void bp_kernel(BpArgs a) {
         // a ring item lives in slot item & mask; a batch item names its shot
         const int64_t shot = a.ring ? (item & a.ring->mask) : a.work_list ? (int64_t)a.work_list[item] : item;
         const uint64_t *keys = a.ring ? a.ring->keys : a.shot_keys;
-        const uint64_t seed = keys ? keys[2 * shot] : P.seed;
-        const uint64_t shot_id = keys ? keys[2 * shot + 1] : a.first_shot_id + (uint64_t)shot;
+        // wave-uniform: the lottery's Philox rounds then run on the scalar unit
+        const uint64_t seed = (uint64_t)uniform64((int64_t)(keys ? keys[2 * shot] : P.seed));
+        const uint64_t shot_id =
+            (uint64_t)uniform64((int64_t)(keys ? keys[2 * shot + 1] : a.first_shot_id + (uint64_t)shot));
         float *llr_row = a.llr_out ? a.llr_out + shot * C.n : nullptr;
         const uint32_t *syn_row = (a.ring ? a.ring->syn : a.synd) + shot * C.mw;
 

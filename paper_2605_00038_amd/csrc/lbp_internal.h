@@ -39,8 +39,24 @@ struct BpParams {
     float scale_f;       // constant (float modes)
     int32_t scale_k;     // constant k of k/8 (Int3.4)
     int32_t lottery, skip, flip, osd;
+    int32_t rule;        // lottery selection rule: CN rule | VN rule << 4
     uint64_t seed;
 };
+
+// Lottery selection rules (Sec. III-B, Table I).
+enum { LOT_CN_RANDOM = 0, LOT_CN_WORST = 1 };
+enum { LOT_VN_PROPOSED = 0, LOT_VN_Q_FIRST = 1, LOT_VN_UNRELIABLE = 2, LOT_VN_RANDOM = 3 };
+
+// Candidate order of the neighbour rules: is (cnt, q, v) ahead of (bc, bq, bv)?
+// PROPOSED: more checks in U, then smaller Q, then smaller column; Q_FIRST:
+// smaller Q, then more checks in U, then column; UNRELIABLE: smaller Q, then column.
+template <typename Q>
+__device__ __forceinline__ bool lottery_key_less(int vn_rule, int cnt, Q q, int v, int bc, Q bq, int bv) {
+    if (vn_rule == LOT_VN_Q_FIRST)
+        return q < bq || (q == bq && (cnt > bc || (cnt == bc && v < bv)));
+    if (vn_rule == LOT_VN_UNRELIABLE) return q < bq || (q == bq && v < bv);
+    return cnt > bc || (cnt == bc && (q < bq || (q == bq && v < bv)));
+}
 
 // Serving rings of one code slot.  Host memory is pinned, fine-grained
 // (coherent) and read or written by the kernels directly.

@@ -1,6 +1,7 @@
 // Host runtime of the C ABI in include/lbp.h: validation, device tables,
 // workspace sizing, launch configuration and the OSD overflow loop.
 #include <algorithm>
+#include <atomic>
 #include <climits>
 #include <cmath>
 #include <cstdio>
@@ -62,6 +63,7 @@ struct lbp_code_s {
     bool uniform = true;
     void *dmem = nullptr;
     DevCode dc{};
+    std::atomic<int> refs{1};  // the creator's reference plus one per decoder using the code
 };
 
 struct lbp_decoder_s {
@@ -276,11 +278,15 @@ lbp_status lbp_code_create(int32_t m, int32_t n, const int32_t *row_ptr, const i
     return LBP_OK;
 }
 
-void lbp_code_destroy(lbp_code code) {
-    if (!code) return;
+static void code_release(lbp_code code) {
+    if (code->refs.fetch_sub(1, std::memory_order_acq_rel) != 1) return;
     DeviceGuard g(code->device);
     hipFree(code->dmem);
     delete code;
+}
+
+void lbp_code_destroy(lbp_code code) {
+    if (code) code_release(code);
 }
 
 int32_t lbp_code_rows(lbp_code code) { return code ? code->m : 0; }
@@ -308,6 +314,8 @@ static void free_decoder(lbp_decoder d) {
     hipFree(d->bl_shat);
     hipFree(d->bl_flipv);
     hipFree(d->bl_active);
+    if (d->code) code_release(d->code);
+    d->code = nullptr;
 }
 
 lbp_status lbp_decoder_create(lbp_code code, const lbp_params *prm, int64_t max_batch, lbp_decoder *out) {
@@ -322,7 +330,8 @@ lbp_status lbp_decoder_create(lbp_code code, const lbp_params *prm, int64_t max_
     if (prm->osd < 0 || prm->osd > 2) return fail(LBP_EINVAL, "lbp_decoder_create: unknown OSD mode");
     if (prm->lottery_skip < 0) return fail(LBP_EINVAL, "lbp_decoder_create: lottery_skip must be >= 0");
     if (prm->osd == LBP_OSD_CS && prm->osd_order < 0) return fail(LBP_EINVAL, "lbp_decoder_create: osd_order must be >= 0");
-    if (prm->reserved != 0) return fail(LBP_EINVAL, "lbp_decoder_create: reserved field must be 0");
+    if ((prm->lottery_rule & ~0x33) != 0 || (prm->lottery_rule & 3) > LBP_CN_WORST)
+        return fail(LBP_EINVAL, "lbp_decoder_create: unknown lottery_rule");
     int k = 0;
     if (prm->scale_mode == 1) {
         if (!(prm->scale > 0.0f && prm->scale <= 1.0f)) return fail(LBP_EINVAL, "lbp_decoder_create: constant scale must be in (0,1]");
@@ -337,6 +346,7 @@ lbp_status lbp_decoder_create(lbp_code code, const lbp_params *prm, int64_t max_
     DeviceGuard g(code->device);
     lbp_decoder d = new lbp_decoder_s();
     d->code = code;
+    code->refs.fetch_add(1, std::memory_order_relaxed);
     d->prm = *prm;
     d->max_batch = max_batch;
     BpParams &bp = d->bp;
@@ -348,6 +358,7 @@ lbp_status lbp_decoder_create(lbp_code code, const lbp_params *prm, int64_t max_
     bp.skip = prm->lottery_skip;
     bp.flip = prm->flip;
     bp.osd = prm->osd;
+    bp.rule = prm->lottery_rule;
     bp.seed = prm->seed;
 
     int dev = code->device, ncu = 0, lds_block = 0;

@@ -22,11 +22,12 @@ class DecoderParams:
     flip: int = _lib.FLIP_MSG
     osd: int = _lib.OSD_0
     osd_order: int = 10
+    lottery_rule: int = 0        # lottery_rule(cn, vn); 0 = Algorithm 3
     seed: int = 0
 
     def c(self) -> _lib.Params:
         return _lib.Params(self.max_iter, self.scale_mode, self.scale, self.msg, int(self.lottery),
-                           self.lottery_skip, self.flip, self.osd, self.osd_order, 0,
+                           self.lottery_skip, self.flip, self.osd, self.osd_order, self.lottery_rule,
                            self.seed & 0xFFFFFFFFFFFFFFFF)
 
 

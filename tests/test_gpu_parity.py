@@ -188,3 +188,26 @@ def test_osd_large_codes(name):
         assert (g["flags"] & 2).sum() >= 8
         assert (g["flags"] == o["flags"]).all()
         assert (g["corr"] == o["corr"]).all()
+
+
+def test_code_released_before_decoder():
+    """A decoder keeps its code alive: destroying the code handle first (as Python's
+    cycle collector may do) leaves the decoder working and the HIP state clean."""
+    import ctypes
+    import torch
+    from paper_2605_00038_amd import Code, Decoder
+    h, e, syn = batch("surface5_cc", 0.05, 300, 1001)
+    prm = _params(msg=2, max_iter=50, lottery=True, osd=1, seed=2001)
+    code = Code.from_scipy(h, 0.05)
+    dec = Decoder(code, prm, syn.shape[0])
+    code.__del__()                                  # lbp_code_destroy while the decoder lives
+    assert code.handle is None
+    s = torch.from_numpy(np.ascontiguousarray(syn).view(np.int32)).cuda()
+    corr, flags, iters, _ = dec.decode(s, first_shot_id=0)
+    o = oracle.decode(h, 0.05, oracle_params(prm), syn, n_threads=8)
+    assert (corr.cpu().numpy().view(np.uint32) == o["corr"]).all()
+    del dec, code
+    hip = ctypes.CDLL("libamdhip64.so")
+    assert hip.hipPeekAtLastError() == 0
+    t = torch.empty(64 << 20, dtype=torch.uint8, device="cuda")  # a fresh segment from the allocator
+    del t
