@@ -232,6 +232,150 @@ def traffic_from_profiles(msg: str):
     return float(b.group(1))
 
 
+# ---------------------------------------------------------------- experiments
+# The paper's ablations and accuracy studies on synthetic phenomenological
+# inputs: lottery rules (Sec. III-B, Table I), the skip-K sweep, iteration
+# histograms, LER and OSD invoke rate vs p (Sec. VI), LLR vs message flip.
+# Each prints one JSON object with every point; progress goes to stderr.
+
+def _sample_job(args):
+    name, p, seed, lo, hi = args
+    h, _, _ = codes.workload_matrices(name)
+    e, syn = sample.make_batch(h, p, hi - lo, seed, first_shot=lo)
+    return lo, sample.pack_sparse(e), syn
+
+
+def sample_workload(name: str, p: float, shots: int, seed: int, workers: int):
+    """Errors (packed) and syndromes for `shots` shots, chunked by sample.CHUNK."""
+    jobs = [(name, p, seed, lo, min(shots, lo + sample.CHUNK)) for lo in range(0, shots, sample.CHUNK)]
+    parts = {}
+    with cf.ProcessPoolExecutor(max_workers=workers) as ex:
+        for lo, e, s in ex.map(_sample_job, jobs):
+            parts[lo] = (e, s)
+    keys = sorted(parts)
+    return np.concatenate([parts[k][0] for k in keys]), np.concatenate([parts[k][1] for k in keys])
+
+
+def checker_for(name: str):
+    h, hc, r = codes.workload_matrices(name)
+    single = h[: h.shape[0] // r, : hc.shape[1]]
+    return h, LogicalChecker(single, hc, r)
+
+
+def decode_point(torch, h, checker, p, err, syn, prm, batch: int = 1 << 20):
+    """Decode every shot (in device batches) and summarize accuracy and iterations."""
+    from paper_2605_00038_amd import Code, Decoder
+    shots = syn.shape[0]
+    dec = Decoder(Code.from_scipy(h, p), prm, min(batch, shots))
+    corr = np.empty((shots, dec.nw), np.uint32)
+    flags = np.empty(shots, np.uint8)
+    iters = np.empty(shots, np.int32)
+    t0 = time.perf_counter()
+    for lo in range(0, shots, batch):
+        hi = min(shots, lo + batch)
+        s = torch.from_numpy(np.ascontiguousarray(syn[lo:hi]).view(np.int32)).cuda()
+        c, f, it, _ = dec.decode(s, first_shot_id=lo)
+        corr[lo:hi] = c.cpu().numpy().view(np.uint32)
+        flags[lo:hi] = f.cpu().numpy()
+        iters[lo:hi] = it.cpu().numpy()
+    gpu_s = time.perf_counter() - t0
+    del dec
+    sf, lf = failures_packed(checker, err, corr, h.shape[1])
+    k = int((sf | lf).sum())
+    conv = (flags & 1) != 0
+    hist = np.bincount(iters, minlength=prm.max_iter + 1)
+    return dict(shots=shots, failures=k, ler=k / shots, ler_ci95=list(wilson(k, shots)),
+                synd_fail=int(sf.sum()), logical_fail=int(lf.sum()),
+                not_converged=float((~conv).mean()), osd_invoke_rate=float(((flags & 2) != 0).mean()),
+                mean_iters=float(iters.mean()), max_iter_hits=int((~conv).sum()),
+                iter_hist={int(i): int(c) for i, c in enumerate(hist) if c}, decode_s=gpu_s)
+
+
+def run_experiment(args):
+    import torch
+    assert torch.cuda.is_available(), "experiments need a GPU"
+    from paper_2605_00038_amd import DecoderParams, lottery_rule, CN_RANDOM, CN_WORST, VN_PROPOSED, \
+        VN_Q_FIRST, VN_UNRELIABLE, VN_RANDOM
+    rules = {"proposed": lottery_rule(CN_RANDOM, VN_PROPOSED),
+             "proposed_q_first": lottery_rule(CN_RANDOM, VN_Q_FIRST),
+             "worst_cn+unreliable_vn": lottery_rule(CN_WORST, VN_UNRELIABLE),
+             "worst_cn+random_vn": lottery_rule(CN_WORST, VN_RANDOM),
+             "random_cn+unreliable_vn": lottery_rule(CN_RANDOM, VN_UNRELIABLE),
+             "random_cn+random_vn": lottery_rule(CN_RANDOM, VN_RANDOM)}
+    osd_modes = {"none": 0, "osd_cs10": 2}
+    shots = args.exp_shots
+    grid = []  # (workload, p, label, params)
+
+    def prm(**kw):
+        base = dict(max_iter=args.exp_max_iter, msg=MSG_CODES[args.msg], lottery=True, lottery_skip=6, osd=0,
+                    osd_order=OSD_ORDER, seed=LOTTERY_SEED)
+        base.update(kw)
+        return DecoderParams(**base)
+
+    ps = [float(x) for x in args.exp_p.split(",")] if args.exp_p else None
+    sd9 = args.exp_surface
+    if args.experiment == "policies":      # Table I / Fig. 5a: surface d = 9
+        for p in ps or [0.5e-3, 1e-3, 2e-3]:
+            for o, om in osd_modes.items():
+                grid.append((sd9, p, f"plain_bp/{o}", prm(lottery=False, osd=om)))
+                for r, code in rules.items():
+                    grid.append((sd9, p, f"{r}/{o}", prm(lottery_rule=code, osd=om)))
+    elif args.experiment == "skip":        # Fig. 5b: when to start the lottery
+        for p in ps or [0.5e-3, 1e-3, 2e-3]:
+            for k in (0, 1, 2, 4, 6, 8, 12, 16):
+                grid.append((sd9, p, f"skip{k}", prm(lottery_skip=k)))
+    elif args.experiment == "iters":       # Fig. 6: iteration distribution at p = 1e-4
+        for name in (sd9, args.exp_bb):
+            for p in ps or [1e-4]:
+                grid.append((name, p, "plain_bp", prm(lottery=False)))
+                grid.append((name, p, "lottery_bp", prm()))
+    elif args.experiment == "ler":         # Fig. 13 / Fig. 14: LER and OSD invoke rate on H_st
+        for name in args.exp_workloads.split(","):
+            for p in ps or [1e-3, 2e-3, 3e-3, 5e-3]:
+                for o, om in osd_modes.items():
+                    grid.append((name, p, f"plain_bp/{o}", prm(lottery=False, osd=om)))
+                    grid.append((name, p, f"lottery_bp/{o}", prm(osd=om)))
+    elif args.experiment == "flip":        # what the lottery negates: next messages or lambda itself
+        for name in (sd9, args.exp_bb):
+            for p in ps or [1e-3, 3e-3]:
+                for o, om in osd_modes.items():
+                    grid.append((name, p, f"msg_flip/{o}", prm(flip=0, osd=om)))
+                    grid.append((name, p, f"llr_flip/{o}", prm(flip=1, osd=om)))
+    else:
+        raise SystemExit(f"unknown experiment {args.experiment}")
+
+    inputs = {}
+    points = []
+    t_start = time.perf_counter()
+    for name, p, label, pr in grid:
+        key = (name, p)
+        if key not in inputs:
+            inputs.clear()
+            t0 = time.perf_counter()
+            err, syn = sample_workload(name, p, shots, DATA_SEED, args.workers)
+            h, checker = checker_for(name)
+            inputs[key] = (h, checker, err, syn)
+            log(f"[{args.experiment}] sampled {name} p={p} shots={shots} in {time.perf_counter() - t0:.1f} s")
+        h, checker, err, syn = inputs[key]
+        r = decode_point(torch, h, checker, p, err, syn, pr)
+        r.update(workload=name, p=p, label=label, max_iter=pr.max_iter, lottery=bool(pr.lottery),
+                 lottery_skip=pr.lottery_skip, lottery_rule=pr.lottery_rule, flip=pr.flip, osd=pr.osd,
+                 msg=args.msg)
+        points.append(r)
+        log(f"[{args.experiment}] {name} p={p} {label}: LER {r['ler']:.3e} "
+            f"[{r['ler_ci95'][0]:.2e},{r['ler_ci95'][1]:.2e}] not-conv {r['not_converged']:.3e} "
+            f"mean-iter {r['mean_iters']:.2f} ({r['decode_s']:.1f} s)")
+        torch.cuda.empty_cache()
+    out = dict(experiment=args.experiment, shots_per_point=shots, data_seed=DATA_SEED, lottery_seed=LOTTERY_SEED,
+               data="synthetic: i.i.d. Bernoulli(p) flips on every column of H_st, seeded (PCG64, chunked)",
+               seconds=time.perf_counter() - t_start, points=points)
+    text = json.dumps(out)
+    if args.exp_out:
+        with open(args.exp_out, "w") as f:
+            f.write(text + "\n")
+    print(text, flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -251,6 +395,16 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-ler", action="store_true")
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
+    ap.add_argument("--experiment", choices=["policies", "skip", "iters", "ler", "flip"],
+                    help="run one of the paper's ablations instead of the benchmark (prints a JSON table)")
+    ap.add_argument("--exp-shots", type=int, default=1 << 20, help="shots per experiment point")
+    ap.add_argument("--exp-p", default="", help="comma-separated physical error rates (default: per experiment)")
+    ap.add_argument("--exp-max-iter", type=int, default=300, help="BP iteration limit in experiments")
+    ap.add_argument("--exp-workloads", default="surface5_phenpf,surface9_phenpf,surface13_phenpf,bb144_phenpf",
+                    help="workloads of the ler experiment")
+    ap.add_argument("--exp-surface", default="surface9_phenpf", help="surface-code workload of the ablations")
+    ap.add_argument("--exp-bb", default="bb144_phenpf", help="BB-code workload of the ablations")
+    ap.add_argument("--exp-out", default="", help="also write the experiment's JSON to this file")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (HBM counter calibration)")
     args = ap.parse_args()
@@ -271,6 +425,9 @@ def main():
         print("bench.py measures one GPU: shots are independent, so N GPUs would each decode a disjoint "
               "range of shots with no exchange; only --gpus 1 is supported here.", file=sys.stderr)
         sys.exit(2)
+    if args.experiment:
+        run_experiment(args)
+        return
 
     h, hc, rounds = codes.workload_matrices(WORKLOAD)
     m, n, E = h.shape[0], h.shape[1], h.nnz

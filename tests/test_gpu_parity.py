@@ -35,6 +35,9 @@ INT8_CASES = [
     ("bb144_phen", 0.003, 3000, 1004, dict(max_iter=200, lottery=True, osd=2, osd_order=10, seed=2004)),
     ("bb144_phen", 0.01, 300, 1005, dict(max_iter=60, lottery=True, osd=2, osd_order=10, seed=7, flip=1)),
     ("surface5_phen", 0.02, 2000, 1006, dict(max_iter=40, lottery=True, lottery_skip=2, osd=0, seed=11)),
+    # H_st with the noiseless final read-out: weight-1 rows, every measurement column of weight 2
+    ("surface9_phenpf", 0.003, 2000, 1007, dict(max_iter=100, lottery=True, osd=2, osd_order=10, seed=12)),
+    ("bb144_phenpf", 0.004, 1000, 1008, dict(max_iter=100, lottery=True, osd=1, seed=13)),
 ]
 
 
@@ -72,6 +75,7 @@ FLOAT_CASES = [
     ("bb144_phen", 0.003, 3000, 1004, dict(max_iter=200, lottery=True, osd=2, seed=2004)),
     ("bb144_cc", 0.04, 3000, 1032, dict(max_iter=100, lottery=True, osd=1, seed=2032)),
     ("surface5_cc", 0.05, 3000, 1001, dict(max_iter=50, scale_mode=1, scale=0.625, lottery=False, osd=1)),
+    ("surface9_phenpf", 0.003, 3000, 1007, dict(max_iter=100, lottery=True, osd=2, seed=12)),
 ]
 
 

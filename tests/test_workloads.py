@@ -1,4 +1,6 @@
 """Shapes and invariants of the synthetic workloads (harness, no decoding)."""
+import math
+
 import numpy as np
 import scipy.sparse as sp
 
@@ -75,6 +77,32 @@ def test_table2_column_counts():
     h = codes.unrotated_surface_x(9)
     assert 9 * h.nnz + 2 * 9 * h.shape[0] == 3744
     assert codes.spacetime(h, 9).nnz == 9 * h.nnz + 17 * h.shape[0]
+
+
+def test_table2_with_final_round():
+    """Table II, d = 3 ... 27 (columns, nonzeros as printed, K = 10^3 rounded to three
+    figures): reproduced by the d-round H_st with the noiseless final read-out rows."""
+    table = {3: (57, 96), 9: (1.95e3, 3.74e3), 15: (9.47e3, 18.5e3), 21: (26.5e3, 52.1e3), 27: (56.9e3, 112e3)}
+    for d, (cols, nnz) in table.items():
+        h = codes.unrotated_surface_x(d)
+        st = codes.spacetime(h, d, final_round=True)
+        for got, printed in ((st.shape[1], cols), (st.nnz, nnz)):   # three figures, half rounded up
+            half = 0.5 * 10 ** (math.floor(math.log10(printed)) - 2)
+            assert printed - half <= got < printed + half, (d, got, printed)
+        assert st.shape[0] == (d + 1) * h.shape[0]
+        assert st.sum(axis=0).max() == 2 and st[: d * h.shape[0]].nnz + h.shape[0] == st.nnz
+
+
+def test_final_round_makes_last_measurement_errors_visible():
+    """A lone measurement error in the last round has a zero syndrome on the r-row
+    H_st only through its one row, while the final read-out adds a second one; a
+    decoder matching every detector then leaves a residual with no data syndrome."""
+    hx, hz = codes.rotated_surface(3)
+    r, m, n = 3, hz.shape[0], hz.shape[1]
+    plain, pf = codes.spacetime(hz, r), codes.spacetime(hz, r, final_round=True)
+    col = r * n + (r - 1) * m                                   # measurement column of round r-1, check 0
+    assert plain[:, col].nnz == 1 and pf[:, col].nnz == 2
+    assert pf[r * m, col] == 1                                   # the final read-out row of check 0
 
 
 def test_pack_roundtrip_and_chunk_independence():

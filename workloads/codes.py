@@ -95,17 +95,28 @@ def bb288() -> tuple[sp.csr_matrix, sp.csr_matrix]:
     return bb_code(12, 12, [(3, 0), (0, 2), (0, 7)], [(0, 3), (1, 0), (2, 0)])
 
 
-def spacetime(h: sp.csr_matrix, r: int) -> sp.csr_matrix:
+def spacetime(h: sp.csr_matrix, r: int, final_round: bool = False) -> sp.csr_matrix:
     """H_st = [I_r (x) H | D (x) I_m] of Eq. 1; D[t][t] = D[t][t-1] = 1.
 
     Columns: r blocks of n data columns (round t), then r blocks of m
     measurement columns.  Shape (r*m) x (r*n + r*m).
+
+    final_round=True appends the detectors of a noiseless final read-out of
+    the data qubits: m more rows [0 | 0 ... 0 I], which compare that read-out
+    with round r-1 and so see only round r-1's measurement errors.  Every
+    measurement column then has weight 2, the structure whose nonzero counts
+    Table II lists.
     """
     h = sp.csr_matrix(h, dtype=np.uint8)
     mm = h.shape[0]
     D = sp.eye(r, dtype=np.uint8, format="csr") + sp.eye(r, k=-1, dtype=np.uint8, format="csr")
     left = sp.kron(sp.eye(r, dtype=np.uint8), h, format="csr")
     right = sp.kron(D, sp.eye(mm, dtype=np.uint8), format="csr")
+    if final_round:
+        last = sp.csr_matrix((np.ones(mm, np.uint8), (np.arange(mm), (r - 1) * mm + np.arange(mm))),
+                             shape=(mm, r * mm))
+        left = sp.vstack([left, sp.csr_matrix((mm, left.shape[1]), dtype=np.uint8)], format="csr")
+        right = sp.vstack([right, last], format="csr")
     out = sp.hstack([left, right], format="csr").astype(np.uint8)
     out.sort_indices()
     out.sum_duplicates()
@@ -214,6 +225,10 @@ def workload_matrices(name: str) -> tuple[sp.csr_matrix, sp.csr_matrix, int]:
         d = int(name[len("surface"):-len("_phen")])
         hx, hz = rotated_surface(d)
         return spacetime(hz, d), hx, d
+    if name.startswith("surface") and name.endswith("_phenpf"):
+        d = int(name[len("surface"):-len("_phenpf")])
+        hx, hz = rotated_surface(d)
+        return spacetime(hz, d, final_round=True), hx, d
     if name == "bb144_cc":
         hx, hz = bb144()
         return hx, hz, 1
@@ -223,4 +238,7 @@ def workload_matrices(name: str) -> tuple[sp.csr_matrix, sp.csr_matrix, int]:
     if name == "bb288_phen":
         hx, hz = bb288()
         return spacetime(hx, 18), hz, 18
+    if name == "bb144_phenpf":
+        hx, hz = bb144()
+        return spacetime(hx, 12, final_round=True), hz, 12
     raise KeyError(name)
