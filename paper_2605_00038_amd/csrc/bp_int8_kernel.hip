@@ -339,9 +339,11 @@ __device__ __forceinline__ void check_pass(const uint4 *cidx4, uint32_t (&bq)[SL
 template <int SLOTS, bool LLR_FLIP>
 __global__ __launch_bounds__(1024) void bp_int8_kernel(BpArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ uint32_t claim_lock;  // serving: the wave of this block that polls the ring
     const DevCode &C = a.code;
     const BpParams &P = a.prm;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (threadIdx.x == 0) claim_lock = 0u;
     const int n = C.n, m = C.m;
     // block-shared byte offsets (4 * column) of every padded slot, paired as
     // cidx4[s*64 + lane] = {(o1,o3), (o0,o2), (o5,o7), (o4,o6)} of check lane + 64 s
@@ -378,8 +380,7 @@ __global__ __launch_bounds__(1024) void bp_int8_kernel(BpArgs a) {
     for (;;) {
         int64_t item = 0;
         if (a.ring) {
-            if (lane == 0) item = serve_claim(*a.ring);
-            item = uniform64(item);
+            item = serve_claim_block(*a.ring, &claim_lock, lane);
             if (item < 0) break;
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");  // the host's writes of this ring slot
         } else {

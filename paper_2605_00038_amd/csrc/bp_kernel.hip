@@ -492,10 +492,13 @@ __global__ __launch_bounds__(1024) void bp_kernel(BpArgs a) {
     using F = Fmt<MSG>;
     using T = typename F::T;
     extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ uint32_t claim_lock;  // serving: the wave of this block that polls the ring
     const DevCode &C = a.code;
     const BpParams &P = a.prm;
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
+    if (threadIdx.x == 0) claim_lock = 0u;
+    __syncthreads();
     unsigned char *base = smem + (size_t)wv * a.wave_bytes;
     T *E = (T *)base;
     size_t off = ((size_t)C.m * DEG * sizeof(T) + 15) & ~(size_t)15;
@@ -509,8 +512,7 @@ __global__ __launch_bounds__(1024) void bp_kernel(BpArgs a) {
     for (;;) {
         int64_t item = 0;
         if (a.ring) {
-            if (lane == 0) item = serve_claim(*a.ring);
-            item = uniform64(item);
+            item = serve_claim_block(*a.ring, &claim_lock, lane);
             if (item < 0) break;
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");  // the host's writes of this ring slot
         } else {

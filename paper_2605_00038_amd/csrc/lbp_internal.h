@@ -74,6 +74,7 @@ struct ServeRing {
     unsigned long long *tail;       // device: copy of host_tail (raised by the polling wave)
     uint32_t *token;                // device: 1 while a wave polls host memory
     unsigned long long *last_claim; // device: clock of the latest claim by any wave
+    uint32_t *exiting;              // device: set by the first wave that finds the ring idle; every wave then exits
     float *llr;                     // device [R][2n]: lambda (hi, lo) of items left to OSD
     int64_t mask;                   // R - 1 (R a power of two)
     uint64_t idle_ticks;            // the grid exits after this long without a claim (100 MHz ticks)
@@ -104,13 +105,17 @@ struct BpArgs {
 
 // Claim the next published ring item for the calling lane (call from one lane
 // per wave).  Returns -1 when the host asked to stop, or once no wave of the
-// grid has claimed anything for idle_ticks (the grid winds down as a whole, so
-// a busy stream never loses waves).  Only the wave holding the token reads
-// host memory; the others watch the device copy of the tail.
+// grid has claimed anything for idle_ticks.  The grid winds down as a whole:
+// the first wave to see the ring idle raises `exiting`, and every wave stops
+// claiming once it is raised, so a grid never keeps serving with part of its
+// waves gone (the host relaunches a full grid when items wait and the old
+// one has drained).  Only the wave holding the token reads host memory; the
+// others watch the device copy of the tail.
 __device__ inline int64_t serve_claim(const ServeRing &r) {
     const uint64_t t_start = __builtin_amdgcn_s_memrealtime();
     int idle_rounds = 0;
     for (;;) {
+        if (__hip_atomic_load(r.exiting, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) return -1;
         unsigned long long t = __hip_atomic_load(r.tail, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
         unsigned long long h = __hip_atomic_load(r.head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         while (h < t) {
@@ -134,11 +139,32 @@ __device__ inline int64_t serve_claim(const ServeRing &r) {
         }
         const uint64_t now = __builtin_amdgcn_s_memrealtime();
         const uint64_t last = __hip_atomic_load(r.last_claim, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (now - (last > t_start ? last : t_start) > r.idle_ticks) return -1;
+        // signed: the real-time counters of different XCDs need not agree, and a
+        // claim stamped on an XCD whose clock runs ahead must not read as idle time
+        if ((int64_t)(now - (last > t_start ? last : t_start)) > (int64_t)r.idle_ticks) {
+            atomicExch(r.exiting, 1u);
+            return -1;
+        }
         // back off while nothing arrives (s_sleep k waits about 64 k cycles)
         if (idle_rounds < 6) ++idle_rounds;
         for (int z = 0; z < (1 << idle_rounds); ++z) __builtin_amdgcn_s_sleep(2);
     }
+}
+
+// Claim for one wave through its workgroup: one wave of the block at a time
+// talks to the ring (an LDS lock), the others wait on the CU.  This keeps the
+// polling and the head CAS to one wave per block instead of every resident
+// wave.  Call from every lane; returns the item (wave-uniform) or -1.
+__device__ inline int64_t serve_claim_block(const ServeRing &r, uint32_t *lds_lock, int lane) {
+    int64_t item = 0;
+    if (lane == 0) {
+        while (atomicCAS(lds_lock, 0u, 1u) != 0u) __builtin_amdgcn_s_sleep(1);
+        item = serve_claim(r);
+        __hip_atomic_store(lds_lock, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(uint64_t)item);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)item >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
 // A completion-queue entry names its position's lap and the item in one word,

@@ -121,7 +121,9 @@ lbp_status lbp::serve_shape(lbp_decoder d, double osd_fraction, ServeShape *out)
     return LBP_OK;
 }
 
-lbp_status lbp::serve_launch_bp(lbp_decoder d, const ServeRing *ring_dev, int blocks, hipStream_t s) {
+lbp_status lbp::serve_launch_bp(lbp_decoder d, const ServeRing *ring_dev, uint32_t *exiting, int blocks,
+                                hipStream_t s) {
+    HIPCHK(launch_reset(exiting, 1, s));  // the previous grid has drained: stream order
     BpArgs a{};
     a.code = d->code->dc;
     a.prm = d->bp;
@@ -379,7 +381,7 @@ lbp_status lbp_decoder_create(lbp_code code, const lbp_params *prm, int64_t max_
     int best_waves = 0;
     for (int wpb : {16, 12, 8, 4, 2, 1}) {
         int lds = d->table_bytes + d->wave_bytes * wpb;
-        if (lds > lds_block) continue;
+        if (lds + 64 > lds_block) continue;  // plus the kernels' static LDS
         int bpc = 0;
         hipError_t oe = d->int8_slots ? bp_int8_max_blocks_per_cu(d->int8_slots, wpb, lds, &bpc)
                                       : bp_max_blocks_per_cu(prm->msg, wpb, lds, &bpc);

@@ -15,7 +15,8 @@ struct ServeShape {
 // osd_fraction of the CUs are left to OSD.
 lbp_status serve_shape(lbp_decoder d, double osd_fraction, ServeShape *out);
 // Persistent BP kernel over the ring described by ring_dev (device copy).
-lbp_status serve_launch_bp(lbp_decoder d, const ServeRing *ring_dev, int blocks, hipStream_t s);
+// Clears `exiting` (stream-ordered) and launches the persistent BP grid.
+lbp_status serve_launch_bp(lbp_decoder d, const ServeRing *ring_dev, uint32_t *exiting, int blocks, hipStream_t s);
 // OSD of the ring slots d_list[0 .. d_counters[1]) (lambda in ring.llr, by slot).
 lbp_status serve_launch_osd(lbp_decoder d, const ServeRing &ring, const int32_t *d_list, const uint32_t *d_counters,
                             int blocks, hipStream_t s);

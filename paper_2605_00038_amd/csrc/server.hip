@@ -92,7 +92,7 @@ struct Slot {
     // device
     lbp::ServeRing ring{};
     lbp::ServeRing *d_ring = nullptr;
-    unsigned long long *d_ctl = nullptr;  // head, tail, token, last claim, completion-queue tail
+    unsigned long long *d_ctl = nullptr;  // head, tail, token, last claim, completion-queue tail, exiting
     float *d_llr = nullptr;
     int32_t *d_list = nullptr;
     uint32_t *d_ocount = nullptr;
@@ -211,6 +211,7 @@ lbp_status setup_slot(Slot &sl, int64_t R) {
     r.tail = sl.d_ctl + 1;
     r.token = (uint32_t *)(sl.d_ctl + 2);
     r.last_claim = sl.d_ctl + 3;
+    r.exiting = (uint32_t *)(sl.d_ctl + 5);
     r.llr = sl.d_llr;
     r.mask = R - 1;
     r.idle_ticks = kIdleTicks;
@@ -349,7 +350,7 @@ bool service(lbp_server srv, Slot &sl, bool &busy) {
     if (query && sl.bp_running && hipEventQuery(sl.e_bp) == hipSuccess) sl.bp_running = false;
     const bool bp_waiting = sl.bp_done < sl.published;
     if (!sl.bp_running && bp_waiting && srv->dead.load() == LBP_OK) {
-        lbp_status st = lbp::serve_launch_bp(sl.dec, sl.d_ring, sl.shape.bp_blocks, sl.s_bp);
+        lbp_status st = lbp::serve_launch_bp(sl.dec, sl.d_ring, sl.ring.exiting, sl.shape.bp_blocks, sl.s_bp);
         if (st == LBP_OK && hipEventRecord(sl.e_bp, sl.s_bp) == hipSuccess) {
             sl.bp_running = true;
             sl.bp_launches += 1;
