@@ -262,7 +262,7 @@ def checker_for(name: str):
     return h, LogicalChecker(single, hc, r)
 
 
-def decode_point(torch, h, checker, p, err, syn, prm, batch: int = 1 << 20):
+def decode_point(torch, h, checker, p, err, syn, prm, batch: int = 1 << 18):
     """Decode every shot (in device batches) and summarize accuracy and iterations."""
     from paper_2605_00038_amd import Code, Decoder
     shots = syn.shape[0]
@@ -270,7 +270,7 @@ def decode_point(torch, h, checker, p, err, syn, prm, batch: int = 1 << 20):
     corr = np.empty((shots, dec.nw), np.uint32)
     flags = np.empty(shots, np.uint8)
     iters = np.empty(shots, np.int32)
-    t0 = time.perf_counter()
+    t0 = t_say = time.perf_counter()
     for lo in range(0, shots, batch):
         hi = min(shots, lo + batch)
         s = torch.from_numpy(np.ascontiguousarray(syn[lo:hi]).view(np.int32)).cuda()
@@ -278,6 +278,9 @@ def decode_point(torch, h, checker, p, err, syn, prm, batch: int = 1 << 20):
         corr[lo:hi] = c.cpu().numpy().view(np.uint32)
         flags[lo:hi] = f.cpu().numpy()
         iters[lo:hi] = it.cpu().numpy()
+        if time.perf_counter() - t_say > 20.0:   # long OSD-heavy points: show progress
+            t_say = time.perf_counter()
+            log(f"    {hi}/{shots} shots decoded, {t_say - t0:.0f} s")
     gpu_s = time.perf_counter() - t0
     del dec
     sf, lf = failures_packed(checker, err, corr, h.shape[1])
