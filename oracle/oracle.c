@@ -70,7 +70,6 @@
 #define ORC_FLAG_OSD_INCONSISTENT 4
 
 #define CAP_FLOAT 1024.0
-#define CAP_INT8 127
 #define TAU_FLOAT (1.0 / 4096.0)
 
 typedef struct {
@@ -85,6 +84,8 @@ typedef struct {
     int32_t osd_order;
     int32_t early_stop; /* 1 normally; 0 keeps iterating (test hook) */
     int32_t policy;     /* lottery design-space variant: CN rule in bits 0-1, VN rule in bits 4-5 */
+    int32_t fx_int;     /* fixed point Int x.y (ORC_INT8): x integer bits ... */
+    int32_t fx_frac;    /* ... and y fraction bits plus a sign bit; 0, 0 means Int3.4 */
     uint64_t seed;
 } orc_params;
 
@@ -148,16 +149,25 @@ double orc_store(int fmt, double x) {
     return x;
 }
 
-/* Int3.4: 16 * mu rounded to nearest even, saturated symmetrically to +-127. */
-int orc_prior_int8(double p) {
+/* Fixed point Int x.y (Sec. VII-A, quantization study): a sign bit, x integer
+ * and y fraction bits, i.e. integers in units of 2^-y saturated symmetrically
+ * to +-(2^(x+y) - 1).  The prior is 2^y mu rounded to nearest even, then
+ * saturated.  Int3.4 (8 bits, LSB 1/16, +-127) is the paper's choice. */
+int orc_prior_fixed(double p, int x, int y) {
+    const double qmax = (double)((1 << (x + y)) - 1);
     double mu = log((1.0 - p) / p);
-    double q = nearbyint(16.0 * mu);
-    if (q > CAP_INT8) q = CAP_INT8;
-    if (q < -CAP_INT8) q = -CAP_INT8;
+    double q = nearbyint(ldexp(mu, y));
+    if (q > qmax) q = qmax;
+    if (q < -qmax) q = -qmax;
     return (int)q;
 }
 
-static int sat8(long x) { return x > CAP_INT8 ? CAP_INT8 : (x < -CAP_INT8 ? -CAP_INT8 : (int)x); }
+int orc_prior_int8(double p) { return orc_prior_fixed(p, 3, 4); }
+
+static int fx_x(const orc_params *P) { return (P->fx_int | P->fx_frac) ? P->fx_int : 3; }
+static int fx_y(const orc_params *P) { return (P->fx_int | P->fx_frac) ? P->fx_frac : 4; }
+
+static int satq(long x, long qmax) { return x > qmax ? (int)qmax : (x < -qmax ? (int)-qmax : (int)x); }
 
 static double sigma_float(const orc_params *P, int i) {
     if (P->scale_mode == 1) return (double)(float)P->scale;
@@ -341,12 +351,14 @@ static void bp_float(const ocode *C, const orc_params *P, const double *prior, u
     if (lam_out) memcpy(lam_out, lam, sizeof(double) * (size_t)n);
 }
 
-/* One shot, Int3.4 messages: exact integer arithmetic. */
+/* One shot, fixed-point messages (Int x.y, Int3.4 by default): exact integer arithmetic. */
 static void bp_int8(const ocode *C, const orc_params *P, const double *prior, uint64_t shot_id,
                     const uint8_t *s, uint8_t *ehat, int *iters, int *conv, double *lam_out, work *W) {
     const int m = C->m, n = C->n, I = P->max_iter;
     long *mu = W->imu, *alpha = W->ialpha, *beta = W->ibeta, *lam = W->ilam;
-    for (int v = 0; v < n; ++v) mu[v] = orc_prior_int8(prior[v]);
+    const int fx = fx_x(P), fy = fx_y(P);
+    const long qmax = (1L << (fx + fy)) - 1;
+    for (int v = 0; v < n; ++v) mu[v] = orc_prior_fixed(prior[v], fx, fy);
     for (int e = 0; e < C->nnz; ++e) beta[e] = 0;
     for (int v = 0; v < n; ++v) lam[v] = mu[v];
     int flip_v = -1;
@@ -364,7 +376,7 @@ static void bp_int8(const ocode *C, const orc_params *P, const double *prior, ui
                         if (C->cr[t] != c) a += beta[C->ce[t]];
                 } else a = lam[v] - beta[e];
                 if (P->flip == ORC_FLIP_MSG && v == flip_v) a = -a;
-                alpha[e] = sat8(a);
+                alpha[e] = satq(a, qmax);
             }
         for (int c = 0; c < m; ++c) {
             int deg = C->rp[c + 1] - C->rp[c];
@@ -376,7 +388,7 @@ static void bp_int8(const ocode *C, const orc_params *P, const double *prior, ui
                 else if (x < m2) m2 = x;
                 par ^= (alpha[e] < 0);
             }
-            if (deg == 1) m2 = CAP_INT8;
+            if (deg == 1) m2 = qmax;
             for (int e = C->rp[c]; e < C->rp[c + 1]; ++e) {
                 int mag = (int)((e == arg) ? m2 : m1);
                 int neg = s[c] ^ par ^ (alpha[e] < 0);
@@ -628,6 +640,9 @@ int orc_decode(int32_t m, int32_t n, const int32_t *row_ptr, const int32_t *col_
     if (P->max_iter < 1 || P->msg < 0 || P->msg > 3) return -1;
     for (int v = 0; v < n; ++v)
         if (!(prior[v] > 0.0 && prior[v] < 1.0)) return -1;
+    if (P->msg == ORC_INT8 && (P->fx_int | P->fx_frac) &&
+        (P->fx_int < 0 || P->fx_frac < 0 || P->fx_int + P->fx_frac < 1 || P->fx_int + P->fx_frac > 7))
+        return -1;
     if (P->msg == ORC_INT8 && P->scale_mode == 1) {
         double k = P->scale * 8.0;
         if (fabs(k - nearbyint(k)) > 1e-12 || k < 1 || k > 8) return -1;

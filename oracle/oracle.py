@@ -32,6 +32,8 @@ class _Params(ctypes.Structure):
         ("osd_order", ctypes.c_int32),
         ("early_stop", ctypes.c_int32),
         ("policy", ctypes.c_int32),
+        ("fx_int", ctypes.c_int32),
+        ("fx_frac", ctypes.c_int32),
         ("seed", ctypes.c_uint64),
     ]
 
@@ -49,12 +51,14 @@ class OracleParams:
     osd_order: int = 10
     early_stop: bool = True
     policy: int = 0              # lottery variant: CN rule | VN rule << 4 (see lottery_pick)
+    fx_int: int = 3              # INT8 messages are fixed point Int x.y: x integer bits,
+    fx_frac: int = 4             # y fraction bits and a sign bit (Int3.4 by default)
     seed: int = 0
 
     def c(self) -> _Params:
         return _Params(self.max_iter, self.scale_mode, self.scale, self.msg, int(self.lottery),
                        self.lottery_skip, self.flip, self.osd, self.osd_order, int(self.early_stop),
-                       self.policy, self.seed & 0xFFFFFFFFFFFFFFFF)
+                       self.policy, self.fx_int, self.fx_frac, self.seed & 0xFFFFFFFFFFFFFFFF)
 
 
 def build(force: bool = False) -> str:
@@ -80,6 +84,8 @@ def _get():
         lib.orc_store.restype = ctypes.c_double
         lib.orc_prior_int8.argtypes = [ctypes.c_double]
         lib.orc_prior_int8.restype = ctypes.c_int
+        lib.orc_prior_fixed.argtypes = [ctypes.c_double, ctypes.c_int, ctypes.c_int]
+        lib.orc_prior_fixed.restype = ctypes.c_int
         lib.orc_decode.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
                                    ctypes.c_void_p, P(_Params), ctypes.c_int64, ctypes.c_uint64,
                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
@@ -124,6 +130,11 @@ def store(fmt: int, x: float) -> float:
 
 def prior_int8(p: float) -> int:
     return _get().orc_prior_int8(float(p))
+
+
+def prior_fixed(p: float, x: int, y: int) -> int:
+    """Int x.y prior: 2^y ln((1-p)/p) rounded to nearest even, saturated to +-(2^(x+y) - 1)."""
+    return _get().orc_prior_fixed(float(p), int(x), int(y))
 
 
 def decode(h, prior, params: OracleParams, syndromes: np.ndarray, first_shot_id: int = 0,

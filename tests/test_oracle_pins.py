@@ -71,6 +71,17 @@ def test_int34_priors():
     assert [oracle.prior_int8(p) for p in (0.05, 0.01, 0.003, 0.001, 1e-4)] == [47, 74, 93, 111, 127]
 
 
+def test_fixed_point_priors():
+    """Int x.y: 2^y ln((1-p)/p) to the nearest integer, saturated at 2^(x+y) - 1.
+    ln 9 = 2.1972, ln 99 = 4.5951, ln 999 = 6.9068; 7-bit formats saturate at 63,
+    8-bit ones at 127."""
+    table = {(2, 4): [35, 63, 63], (3, 3): [18, 37, 55], (4, 2): [9, 18, 28], (2, 5): [70, 127, 127],
+             (4, 3): [18, 37, 55], (3, 4): [35, 74, 111]}
+    for (x, y), want in table.items():
+        assert [oracle.prior_fixed(p, x, y) for p in (0.1, 0.01, 0.001)] == want, (x, y)
+    assert oracle.prior_fixed(0.001, 3, 4) == oracle.prior_int8(0.001)
+
+
 # ---------------------------------------------------------- closed-form BP schedules
 
 def _lam_after(h, prior, prm, s_bits, iters):
@@ -107,6 +118,41 @@ def test_sigma_schedule_int34():
         assert lam[1] == qb - (qa - (qa >> (i + 1)))
     lam = _lam_after(h, [0.1, 0.2], oracle.OracleParams(msg=oracle.INT8, scale_mode=1, scale=0.625), [1], 2)
     assert lam[0] == 35 - ((5 * 22) >> 3) and lam[1] == 22 - ((5 * 35) >> 3)
+
+
+@pytest.mark.parametrize("fx", [(2, 4), (3, 3), (4, 3)])
+def test_sigma_schedule_fixed_point(fx):
+    """The Int3.4 schedule in other formats, with the 7-bit saturation at 63: one
+    check on two variables (s = 1), lambda_a = q_a - (q_b - (q_b >> (i+1)))."""
+    x, y = fx
+    h = sp.csr_matrix(np.array([[1, 1]], dtype=np.uint8))
+    qa, qb = oracle.prior_fixed(0.001, x, y), oracle.prior_fixed(0.1, x, y)   # 63/35, 55/18, 55/18
+    for i in range(0, 8):
+        lam = _lam_after(h, [0.001, 0.1], oracle.OracleParams(msg=oracle.INT8, fx_int=x, fx_frac=y), [1], i + 1)
+        assert lam[0] == qa - (qb - (qb >> (i + 1)))
+        assert lam[1] == qb - (qa - (qa >> (i + 1)))
+
+
+@pytest.mark.parametrize("fx,qmax", [((3, 4), 127), ((3, 3), 63), ((2, 4), 63), ((1, 1), 3)])
+def test_degree_one_check_sends_the_format_maximum(fx, qmax):
+    """A check on one variable has no other input: it sends the largest magnitude
+    of the format, scaled, with the sign of the syndrome bit:
+    lambda = q - (qmax - (qmax >> 1)) after one iteration with s = 1."""
+    x, y = fx
+    h = sp.csr_matrix(np.array([[1]], dtype=np.uint8))
+    q = oracle.prior_fixed(0.3, x, y)
+    lam = _lam_after(h, [0.3], oracle.OracleParams(msg=oracle.INT8, fx_int=x, fx_frac=y), [1], 1)
+    assert lam[0] == q - (qmax - (qmax >> 1))
+    lam = _lam_after(h, [0.3], oracle.OracleParams(msg=oracle.INT8, fx_int=x, fx_frac=y), [0], 1)
+    assert lam[0] == q + (qmax - (qmax >> 1))
+
+
+def test_fixed_point_rejects_unsupported_formats():
+    h = sp.csr_matrix(np.array([[1, 1]], dtype=np.uint8))
+    syn = sample.pack_bits(np.asarray([[1]], np.uint8))
+    for x, y in [(4, 4), (0, 0 + 8), (-1, 3)]:
+        with pytest.raises(ValueError):
+            oracle.decode(h, 0.1, oracle.OracleParams(msg=oracle.INT8, fx_int=x, fx_frac=y), syn)
 
 
 # -------------------------------------------------------------- exactness on trees
@@ -154,14 +200,19 @@ def test_min_sum_is_exact_max_product_on_trees(seed):
 
 
 @pytest.mark.parametrize("seed", range(6))
-def test_int34_min_sum_is_exact_on_trees(seed):
+@pytest.mark.parametrize("fx", [(3, 4), (3, 3), (2, 4)])
+def test_int34_min_sum_is_exact_on_trees(seed, fx):
+    """Integer min-sum on a tree is max-product exactly, in every Int x.y format
+    (priors small enough that no sum saturates)."""
+    x, y = fx
     rng = np.random.default_rng(200 + seed)
     h = _random_tree(rng, int(rng.integers(4, 9)))
     m, n = h.shape
     p = rng.uniform(0.36, 0.45, n)                              # priors 3..9 in Int3.4: no saturation
-    muq = np.array([oracle.prior_int8(x) for x in p], dtype=np.int64)
+    muq = np.array([oracle.prior_fixed(v, x, y) for v in p], dtype=np.int64)
     s = rng.integers(0, 2, m)
-    lam = _lam_after(h, p, oracle.OracleParams(msg=oracle.INT8, scale_mode=1, scale=1.0), s, 2 * (n + m))
+    lam = _lam_after(h, p, oracle.OracleParams(msg=oracle.INT8, scale_mode=1, scale=1.0, fx_int=x, fx_frac=y), s,
+                     2 * (n + m))
     assert (lam == _max_marginals(h, muq, s)).all()
 
 
