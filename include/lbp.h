@@ -47,6 +47,13 @@ typedef struct lbp_server_s *lbp_server;   /* continuous-batching serving loop (
  * messages (and the prior) rounded to nearest even, saturating at the largest
  * finite value, and accumulate in fp32. */
 typedef enum { LBP_MSG_FP32 = 0, LBP_MSG_FP16 = 1, LBP_MSG_INT8 = 2 } lbp_msg;
+/* Fixed point Int x.y for the quantization study (Sec. VII-A, Fig. 15): a sign
+ * bit, x integer and y fraction bits (1 <= x + y <= 7), i.e. integers in units
+ * of 2^-y saturated symmetrically to +-(2^(x+y) - 1).  The prior is 2^y mu
+ * rounded to nearest even, then saturated; a degree-1 check sends the largest
+ * magnitude.  LBP_MSG_FIXED(3, 4) is LBP_MSG_INT8.  Other formats (x + y > 7,
+ * bits above 0x1FF) are rejected with LBP_EINVAL. */
+#define LBP_MSG_FIXED(x, y) (0x100 | ((x) << 4) | (y))
 
 /* Check-node scale (Algorithm 1, CN update).  PAPER: sigma_i = 1 - 2^-(i+1),
  * evaluated in fp32 (exactly 1.0 from i = 24); Int3.4 applies it as

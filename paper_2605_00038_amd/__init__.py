@@ -6,7 +6,7 @@ The decoding runs in hand-written HIP kernels for gfx950 behind the C ABI of
 from ._lib import (  # noqa: F401
     LbpError, load, MSG_FP32, MSG_FP16, MSG_INT8, SCALE_PAPER, SCALE_CONST, FLIP_MSG, FLIP_LLR,
     OSD_NONE, OSD_0, OSD_CS, FLAG_CONVERGED, FLAG_OSD, FLAG_OSD_INCONSISTENT,
-    CN_RANDOM, CN_WORST, VN_PROPOSED, VN_Q_FIRST, VN_UNRELIABLE, VN_RANDOM, lottery_rule,
+    CN_RANDOM, CN_WORST, VN_PROPOSED, VN_Q_FIRST, VN_UNRELIABLE, VN_RANDOM, lottery_rule, msg_fixed,
 )
 from .decoder import Code, Decoder, DecoderParams  # noqa: F401
 from .server import Server  # noqa: F401

@@ -13,6 +13,11 @@ LIB_PATH = os.path.join(_HERE, "liblbp.so")
 
 LBP_OK, LBP_EINVAL, LBP_ENOMEM, LBP_EDEVICE, LBP_EBUSY, LBP_ENOTREADY, LBP_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 MSG_FP32, MSG_FP16, MSG_INT8 = 0, 1, 2
+
+
+def msg_fixed(x: int, y: int) -> int:
+    """lbp_params.msg for fixed point Int x.y (LBP_MSG_FIXED): sign, x integer and y fraction bits."""
+    return 0x100 | (x << 4) | y
 SCALE_PAPER, SCALE_CONST = 0, 1
 FLIP_MSG, FLIP_LLR = 0, 1
 OSD_NONE, OSD_0, OSD_CS = 0, 1, 2

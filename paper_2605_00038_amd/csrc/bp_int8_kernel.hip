@@ -26,8 +26,9 @@
 // sign-extend.  Each check's slots are paired (1,3), (0,2), (5,7), (4,6).
 //
 // Padding slots point at pad columns (after column n-1) whose current half is
-// reset to 254 each iteration: alpha >= +127 there, a key that never wins a
-// minimum.  Pads are spread over PAD_COLS columns so that their sums cannot
+// reset to 254 each iteration: alpha >= +127 there, saturated to the format's
+// maximum, a key that never wins a minimum (and the magnitude a degree-1 check
+// sends).  Pads are spread over PAD_COLS columns so that their sums cannot
 // leave a 16-bit half either.
 //
 // The lottery (Algorithm 3) runs after the column pass with U from the
@@ -213,7 +214,7 @@ constexpr uint32_t SEL_PACK = 0x06020400u;  // src0 = (b1, b3), src1 = (b0, b2) 
 template <int PAR, bool FLIP, bool LLR_FLIP>
 __device__ __forceinline__ void check_update(const uint4 cw, uint32_t &bw0, uint32_t &bw1, uint32_t syn_bit,
                                              unsigned char *Lb, uint32_t base, int sh, int scale_mode, int scale_k,
-                                             uint32_t fo) {
+                                             uint32_t fo, uint32_t qm2) {
     const uint32_t T[4] = {cw.x, cw.y, cw.z, cw.w};  // (off1,off3) (off0,off2) (off5,off7) (off4,off6)
     // ---- gather lambda^(i-1) of the eight columns into four pairs
     uint32_t lam[4];
@@ -249,13 +250,13 @@ __device__ __forceinline__ void check_update(const uint4 cw, uint32_t &bw0, uint
 #pragma unroll
         for (int p = 0; p < 4; ++p) x[p] = l[p] - as_i16(b[p]);
     }
-    // |alpha| saturated at 127 (the sign of alpha is the sign of its saturated value)
+    // |alpha| saturated at qmax, both halves of qm2 (the sign of alpha is the sign of its saturated value)
 #pragma unroll
     for (int p = 0; p < 4; ++p) mg[p] = (v2i16){0, 0} - x[p];
 #pragma unroll
     for (int p = 0; p < 4; ++p) mg[p] = __builtin_elementwise_max(x[p], mg[p]);
 #pragma unroll
-    for (int p = 0; p < 4; ++p) mg[p] = __builtin_elementwise_min(mg[p], (v2i16){127, 127});
+    for (int p = 0; p < 4; ++p) mg[p] = __builtin_elementwise_min(mg[p], as_i16(qm2));
 #pragma unroll
     for (int p = 0; p < 4; ++p) key[p] = (as_u16(as_u32(mg[p])) << (v2u16){3, 3}) | kslot[p];  // |alpha| << 3 | slot
     const uint32_t px = as_u32(x[0]) ^ as_u32(x[1]) ^ as_u32(x[2]) ^ as_u32(x[3]);
@@ -321,15 +322,15 @@ __device__ __forceinline__ void check_update(const uint4 cw, uint32_t &bw0, uint
 template <int SLOTS, int PAR, bool LLR_FLIP>
 __device__ __forceinline__ void check_pass(const uint4 *cidx4, uint32_t (&bq)[SLOTS][2], uint32_t srow,
                                            unsigned char *Lb, uint32_t base, int lane, int sh, int scale_mode,
-                                           int scale_k, uint32_t flipslots, uint32_t fo) {
+                                           int scale_k, uint32_t flipslots, uint32_t fo, uint32_t qm2) {
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
         const uint4 cw = cidx4[s * 64 + lane];
         const uint32_t sb = (srow >> s) & 1u;
         if (flipslots & (1u << s))
-            check_update<PAR, true, LLR_FLIP>(cw, bq[s][0], bq[s][1], sb, Lb, base, sh, scale_mode, scale_k, fo);
+            check_update<PAR, true, LLR_FLIP>(cw, bq[s][0], bq[s][1], sb, Lb, base, sh, scale_mode, scale_k, fo, qm2);
         else
-            check_update<PAR, false, LLR_FLIP>(cw, bq[s][0], bq[s][1], sb, Lb, base, sh, scale_mode, scale_k, fo);
+            check_update<PAR, false, LLR_FLIP>(cw, bq[s][0], bq[s][1], sb, Lb, base, sh, scale_mode, scale_k, fo, qm2);
         // opaque to the optimiser: otherwise it forwards unpacked values to the next
         // iteration and keeps several registers per check
         asm volatile("" : "+v"(bq[s][0]), "+v"(bq[s][1]));
@@ -376,6 +377,7 @@ __global__ __launch_bounds__(1024) void bp_int8_kernel(BpArgs a) {
     const int nvs = (n + 63) >> 6;
     const bool mu_uniform = C.mu_q_uniform != INT32_MIN;
     const uint32_t pad_b = (uint32_t)(PAD_LAMBDA + BIAS);
+    const uint32_t qm2 = (uint32_t)P.qmax | ((uint32_t)P.qmax << 16);  // Int x.y saturation, both halves
 
     for (;;) {
         int64_t item = 0;
@@ -431,10 +433,10 @@ __global__ __launch_bounds__(1024) void bp_int8_kernel(BpArgs a) {
             // ---- check-node pass: alpha from lambda^(i-1), beta^(i), lambda^(i) += beta^(i)
             if (par == 0)
                 check_pass<SLOTS, 0, LLR_FLIP>(cidx4, bq, srow, Lb, base, lane, sh, P.scale_mode, P.scale_k,
-                                               flipslots, fo);
+                                               flipslots, fo, qm2);
             else
                 check_pass<SLOTS, 1, LLR_FLIP>(cidx4, bq, srow, Lb, base, lane, sh, P.scale_mode, P.scale_k,
-                                               flipslots, fo);
+                                               flipslots, fo, qm2);
             for (int w = lane; w < C.mw; w += 64) SHc[w] = 0u;
             wave_sync();
             // ---- column pass: hard decision, corrections, syndrome estimate, reset

@@ -251,6 +251,9 @@ __device__ void cn_half(const DevCode &C, const BpParams &P, int i, typename Fmt
                 else if (mag < m2) m2 = mag;
                 par ^= (x < 0);
             }
+            // padding slots hold 127: a degree-1 check sends the format's maximum
+            m1 = m1 < P.qmax ? m1 : P.qmax;
+            m2 = m2 < P.qmax ? m2 : P.qmax;
             const int s1 = scale_int8(P, i, m1), s2 = scale_int8(P, i, m2);
 #pragma unroll
             for (int k = 0; k < DEG; ++k) {
@@ -452,7 +455,7 @@ __device__ void vn_half(const DevCode &C, const BpParams &P, int fv, bool last, 
                 uint32_t p = (uint32_t)(tab >> (16 * j)) & 0xFFFFu;
                 if (p != NOPOS) {
                     int a = l2 - b[j];  // == mu + sum of the other C2V messages
-                    a = a > 127 ? 127 : (a < -127 ? -127 : a);
+                    a = a > P.qmax ? P.qmax : (a < -P.qmax ? -P.qmax : a);
                     if (P.flip == FLIP_MSG && flipv) a = -a;
                     E[p] = (int8_t)a;
                 }

@@ -40,6 +40,7 @@ struct BpParams {
     int32_t scale_k;     // constant k of k/8 (Int3.4)
     int32_t lottery, skip, flip, osd;
     int32_t rule;        // lottery selection rule: CN rule | VN rule << 4
+    int32_t qmax;        // fixed point: messages saturate at +-qmax (127 for Int3.4)
     uint64_t seed;
 };
 

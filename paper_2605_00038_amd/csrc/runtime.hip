@@ -61,6 +61,7 @@ void lbp::set_error(const char *msg) { g_err = msg ? msg : ""; }
 struct lbp_code_s {
     int m = 0, n = 0, nnz = 0, device = 0;
     bool uniform = true;
+    std::vector<double> mu;  // prior LLRs (fp64, host): fixed-point decoders quantize their own copy
     void *dmem = nullptr;
     DevCode dc{};
     std::atomic<int> refs{1};  // the creator's reference plus one per decoder using the code
@@ -69,6 +70,9 @@ struct lbp_code_s {
 struct lbp_decoder_s {
     lbp_code code = nullptr;
     lbp_params prm{};
+    int msgk = 0;       // message storage the kernels run: MSG_FP32 / MSG_FP16 / MSG_INT8 (any Int x.y)
+    DevCode dc{};       // the code's tables, with this decoder's fixed-point prior
+    int32_t *d_muq = nullptr;
     int64_t max_batch = 0;
     BpParams bp{};
     int wpb = 1, bp_blocks = 1, wave_bytes = 0, int8_slots = 0, table_bytes = 0;
@@ -125,14 +129,14 @@ lbp_status lbp::serve_launch_bp(lbp_decoder d, const ServeRing *ring_dev, uint32
                                 hipStream_t s) {
     HIPCHK(launch_reset(exiting, 1, s));  // the previous grid has drained: stream order
     BpArgs a{};
-    a.code = d->code->dc;
+    a.code = d->dc;
     a.prm = d->bp;
     a.ring = ring_dev;
     a.stage = d->d_stage;
     a.wave_bytes = d->wave_bytes;
     blocks = std::max(1, std::min(blocks, d->bp_blocks));  // d_stage holds bp_blocks * wpb waves
     HIPCHK(d->int8_slots ? launch_bp_int8(d->int8_slots, a, blocks, d->wpb, s)
-                         : launch_bp(d->prm.msg, a, blocks, d->wpb, s));
+                         : launch_bp(d->msgk, a, blocks, d->wpb, s));
     return LBP_OK;
 }
 
@@ -158,7 +162,7 @@ lbp_status lbp::serve_launch_osd(lbp_decoder d, const ServeRing &ring, const int
     o.gscratch = d->d_gscratch;
     o.sort_p = d->sort_p;
     o.g_in_lds = d->osd_variant == 0;
-    o.has_lo = d->prm.msg == LBP_MSG_FP32;
+    o.has_lo = d->msgk == LBP_MSG_FP32;
     o.llr_by_shot = 1;
     blocks = std::max(1, std::min(blocks, d->osd_blocks));  // d_gscratch holds osd_blocks blocks
     HIPCHK(launch_osd(o, d->osd_variant, blocks, d->osd_threads, d->osd_lds, s));
@@ -241,6 +245,8 @@ lbp_status lbp_code_create(int32_t m, int32_t n, const int32_t *row_ptr, const i
     code->n = n;
     code->nnz = nnz;
     code->uniform = uniform;
+    code->mu.resize(n);
+    for (int v = 0; v < n; ++v) code->mu[v] = std::log((1.0 - p[v]) / p[v]);
     hipGetDevice(&code->device);
     size_t o_cols = 0, o_deg = align256(o_cols + cols.size() * 2), o_tab = align256(o_deg + (size_t)m),
            o_m32 = align256(o_tab + (size_t)n * 8), o_m16 = align256(o_m32 + (size_t)n * 4),
@@ -316,6 +322,7 @@ static void free_decoder(lbp_decoder d) {
     hipFree(d->bl_shat);
     hipFree(d->bl_flipv);
     hipFree(d->bl_active);
+    hipFree(d->d_muq);
     if (d->code) code_release(d->code);
     d->code = nullptr;
 }
@@ -326,7 +333,17 @@ lbp_status lbp_decoder_create(lbp_code code, const lbp_params *prm, int64_t max_
     *out = nullptr;
     if (max_batch < 1 || max_batch > (int64_t)1 << 31) return fail(LBP_EINVAL, "lbp_decoder_create: 1 <= max_batch <= 2^31");
     if (prm->max_iter < 1) return fail(LBP_EINVAL, "lbp_decoder_create: max_iter must be >= 1");
-    if (prm->msg < 0 || prm->msg > 2) return fail(LBP_EINVAL, "lbp_decoder_create: unknown message format");
+    // message storage: FP32, FP16, or fixed point Int x.y (LBP_MSG_INT8 = Int3.4)
+    int fx = 3, fy = 4;
+    if (prm->msg & 0x100) {
+        fx = (prm->msg >> 4) & 15;
+        fy = prm->msg & 15;
+        if ((prm->msg & ~0x1FF) != 0 || fx + fy < 1 || fx + fy > 7)
+            return fail(LBP_EINVAL, "lbp_decoder_create: fixed point Int x.y needs 1 <= x + y <= 7");
+    } else if (prm->msg < 0 || prm->msg > 2) {
+        return fail(LBP_EINVAL, "lbp_decoder_create: unknown message format");
+    }
+    const int msgk = (prm->msg & 0x100) ? LBP_MSG_INT8 : prm->msg;
     if (prm->scale_mode != 0 && prm->scale_mode != 1) return fail(LBP_EINVAL, "lbp_decoder_create: unknown scale mode");
     if (prm->flip != 0 && prm->flip != 1) return fail(LBP_EINVAL, "lbp_decoder_create: unknown flip mode");
     if (prm->osd < 0 || prm->osd > 2) return fail(LBP_EINVAL, "lbp_decoder_create: unknown OSD mode");
@@ -337,7 +354,7 @@ lbp_status lbp_decoder_create(lbp_code code, const lbp_params *prm, int64_t max_
     int k = 0;
     if (prm->scale_mode == 1) {
         if (!(prm->scale > 0.0f && prm->scale <= 1.0f)) return fail(LBP_EINVAL, "lbp_decoder_create: constant scale must be in (0,1]");
-        if (prm->msg == LBP_MSG_INT8) {
+        if (msgk == LBP_MSG_INT8) {
             double kk = (double)prm->scale * 8.0;
             k = (int)std::lround(kk);
             if (std::fabs(kk - k) > 1e-6) return fail(LBP_EINVAL, "lbp_decoder_create: Int3.4 constant scale must be k/8");
@@ -350,8 +367,11 @@ lbp_status lbp_decoder_create(lbp_code code, const lbp_params *prm, int64_t max_
     d->code = code;
     code->refs.fetch_add(1, std::memory_order_relaxed);
     d->prm = *prm;
+    d->msgk = msgk;
+    d->dc = code->dc;
     d->max_batch = max_batch;
     BpParams &bp = d->bp;
+    bp.qmax = (1 << (fx + fy)) - 1;
     bp.max_iter = prm->max_iter;
     bp.scale_mode = prm->scale_mode;
     bp.scale_f = prm->scale;
@@ -373,8 +393,8 @@ lbp_status lbp_decoder_create(lbp_code code, const lbp_params *prm, int64_t max_
         hipDeviceGetAttribute(&lds_block, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
         return cleanup_fail(LBP_EDEVICE, "lbp_decoder_create: device query failed");
     // ---- BP launch shape: the waves-per-block choice with the most resident waves per CU
-    d->int8_slots = prm->msg == LBP_MSG_INT8 ? bp_int8_slots(code->m, code->n) : 0;
-    d->wave_bytes = d->int8_slots ? bp_int8_wave_bytes(code->m, code->n) : bp_wave_bytes(prm->msg, code->m, code->n);
+    d->int8_slots = msgk == LBP_MSG_INT8 ? bp_int8_slots(code->m, code->n) : 0;
+    d->wave_bytes = d->int8_slots ? bp_int8_wave_bytes(code->m, code->n) : bp_wave_bytes(msgk, code->m, code->n);
     d->table_bytes = d->int8_slots ? bp_int8_table_bytes(d->int8_slots) : 0;
     if (d->table_bytes + d->wave_bytes > lds_block)
         return cleanup_fail(LBP_EUNSUPPORTED, "lbp_decoder_create: per-shot state exceeds LDS");
@@ -384,7 +404,7 @@ lbp_status lbp_decoder_create(lbp_code code, const lbp_params *prm, int64_t max_
         if (lds + 64 > lds_block) continue;  // plus the kernels' static LDS
         int bpc = 0;
         hipError_t oe = d->int8_slots ? bp_int8_max_blocks_per_cu(d->int8_slots, wpb, lds, &bpc)
-                                      : bp_max_blocks_per_cu(prm->msg, wpb, lds, &bpc);
+                                      : bp_max_blocks_per_cu(msgk, wpb, lds, &bpc);
         if (oe != hipSuccess) continue;
         if (bpc * wpb > best_waves) {
             best_waves = bpc * wpb;
@@ -413,6 +433,21 @@ lbp_status lbp_decoder_create(lbp_code code, const lbp_params *prm, int64_t max_
                                                                  hipGetErrorString(e));                        \
     } while (0)
     ALLOC(d->d_counters, 64);
+    if (msgk == LBP_MSG_INT8 && !(fx == 3 && fy == 4)) {
+        // this format's prior: 2^y mu rounded to nearest even, saturated to +-qmax
+        std::vector<int32_t> muq(code->n);
+        bool uni = true;
+        for (int v = 0; v < code->n; ++v) {
+            double q = std::nearbyint(std::ldexp(code->mu[v], fy));
+            muq[v] = (int32_t)(q > bp.qmax ? bp.qmax : (q < -bp.qmax ? -bp.qmax : q));
+            uni = uni && muq[v] == muq[0];
+        }
+        ALLOC(d->d_muq, (size_t)code->n * 4);
+        e = hipMemcpy(d->d_muq, muq.data(), (size_t)code->n * 4, hipMemcpyHostToDevice);
+        if (e != hipSuccess) return cleanup_fail(LBP_EDEVICE, "lbp_decoder_create: hipMemcpy of the prior failed");
+        d->dc.mu_q = d->d_muq;
+        d->dc.mu_q_uniform = uni ? muq[0] : INT32_MIN;
+    }
     ALLOC(d->d_stage, (size_t)d->bp_blocks * d->wpb * code->n * 8);
     if (prm->osd) {
         ALLOC(d->d_fail_list, (size_t)max_batch * 4);
@@ -449,7 +484,7 @@ static lbp_status run_pass(lbp_decoder d, int64_t n_work, const int32_t *work_li
     lbp_code C = d->code;
     HIPCHK(launch_reset(d->d_counters, 16, s));
     BpArgs a{};
-    a.code = C->dc;
+    a.code = d->dc;
     a.prm = d->bp;
     a.n_work = n_work;
     a.first_shot_id = first_shot_id;
@@ -471,7 +506,7 @@ static lbp_status run_pass(lbp_decoder d, int64_t n_work, const int32_t *work_li
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (d->timing && (e0 = take_event(d)) && (e1 = take_event(d))) HIPCHK(hipEventRecord(e0, s));
     HIPCHK(d->int8_slots ? launch_bp_int8(d->int8_slots, a, blocks, d->wpb, s)
-                         : launch_bp(d->prm.msg, a, blocks, d->wpb, s));
+                         : launch_bp(d->msgk, a, blocks, d->wpb, s));
     if (e1) {
         HIPCHK(hipEventRecord(e1, s));
         d->recs.push_back({e0, e1, 0});
@@ -496,7 +531,7 @@ static lbp_status run_pass(lbp_decoder d, int64_t n_work, const int32_t *work_li
         o.gscratch = d->d_gscratch;
         o.sort_p = d->sort_p;
         o.g_in_lds = d->osd_variant == 0;
-        o.has_lo = d->prm.msg == LBP_MSG_FP32;
+        o.has_lo = d->msgk == LBP_MSG_FP32;
         hipEvent_t f0 = nullptr, f1 = nullptr;
         if (d->timing && (f0 = take_event(d)) && (f1 = take_event(d))) HIPCHK(hipEventRecord(f0, s));
         HIPCHK(launch_osd(o, d->osd_variant, d->osd_blocks, d->osd_threads, d->osd_lds, s));
@@ -581,7 +616,7 @@ lbp_status lbp_decode_baseline(lbp_decoder d, int64_t n_shots, uint64_t first_sh
     g_err.clear();
     if (!d) return fail(LBP_EINVAL, "lbp_decode_baseline: NULL decoder");
     if (n_shots < 0 || n_shots > d->max_batch) return fail(LBP_EINVAL, "lbp_decode_baseline: 0 <= n_shots <= max_batch");
-    if (d->prm.msg == LBP_MSG_INT8)
+    if (d->msgk == LBP_MSG_INT8)
         return fail(LBP_EUNSUPPORTED, "lbp_decode_baseline: FP32 or FP16 message storage only");
     if (n_shots == 0) return LBP_OK;
     if (!syndromes || !corrections || !flags) return fail(LBP_EINVAL, "lbp_decode_baseline: NULL buffer");
@@ -607,9 +642,9 @@ lbp_status lbp_decode_baseline(lbp_decoder d, int64_t n_shots, uint64_t first_sh
         d->bl_cap = n_shots;
     }
     BlArgs a{};
-    a.code = C->dc;
+    a.code = d->dc;
     a.prm = d->bp;
-    a.msg = d->prm.msg;
+    a.msg = d->msgk;
     a.shots = n_shots;
     a.first_shot_id = first_shot_id;
     a.synd = syndromes;

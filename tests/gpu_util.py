@@ -25,10 +25,12 @@ def gpu_decode(h, prior, prm, syn, first_shot_id=0, want_llr=False, max_batch=No
 
 
 def oracle_params(prm, **kw):
+    fixed = prm.msg & 0x100
     o = oracle.OracleParams(max_iter=prm.max_iter, scale_mode=prm.scale_mode, scale=prm.scale,
-                            msg=MSG_TO_ORACLE[prm.msg], lottery=prm.lottery, lottery_skip=prm.lottery_skip,
-                            flip=prm.flip, osd=prm.osd, osd_order=prm.osd_order, policy=prm.lottery_rule,
-                            seed=prm.seed)
+                            msg=oracle.INT8 if fixed else MSG_TO_ORACLE[prm.msg], lottery=prm.lottery,
+                            lottery_skip=prm.lottery_skip, flip=prm.flip, osd=prm.osd, osd_order=prm.osd_order,
+                            policy=prm.lottery_rule, fx_int=(prm.msg >> 4) & 15 if fixed else 3,
+                            fx_frac=prm.msg & 15 if fixed else 4, seed=prm.seed)
     for k, v in kw.items():
         setattr(o, k, v)
     return o
