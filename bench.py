@@ -338,6 +338,15 @@ def run_experiment(args):
                 for o, om in osd_modes.items():
                     grid.append((name, p, f"plain_bp/{o}", prm(lottery=False, osd=om)))
                     grid.append((name, p, f"lottery_bp/{o}", prm(osd=om)))
+    elif args.experiment == "quant":       # Fig. 15: message formats, surface d = 9
+        from paper_2605_00038_amd import msg_fixed
+        fmts = [("int2.4", msg_fixed(2, 4)), ("int3.3", msg_fixed(3, 3)), ("int4.2", msg_fixed(4, 2)),
+                ("int2.5", msg_fixed(2, 5)), ("int3.4", msg_fixed(3, 4)), ("int4.3", msg_fixed(4, 3)),
+                ("fp16", MSG_CODES["fp16"]), ("fp32", MSG_CODES["fp32"])]
+        for p in ps or [1e-3, 2e-3, 4e-3]:
+            for o, om in osd_modes.items():
+                for label, code in fmts:
+                    grid.append((sd9, p, f"{label}/{o}", prm(msg=code, osd=om)))
     elif args.experiment == "flip":        # what the lottery negates: next messages or lambda itself
         for name in (sd9, args.exp_bb):
             for p in ps or [1e-3, 3e-3]:
@@ -363,7 +372,7 @@ def run_experiment(args):
         r = decode_point(torch, h, checker, p, err, syn, pr)
         r.update(workload=name, p=p, label=label, max_iter=pr.max_iter, lottery=bool(pr.lottery),
                  lottery_skip=pr.lottery_skip, lottery_rule=pr.lottery_rule, flip=pr.flip, osd=pr.osd,
-                 msg=args.msg)
+                 msg=pr.msg)
         points.append(r)
         log(f"[{args.experiment}] {name} p={p} {label}: LER {r['ler']:.3e} "
             f"[{r['ler_ci95'][0]:.2e},{r['ler_ci95'][1]:.2e}] not-conv {r['not_converged']:.3e} "
@@ -398,7 +407,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-ler", action="store_true")
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
-    ap.add_argument("--experiment", choices=["policies", "skip", "iters", "ler", "flip"],
+    ap.add_argument("--experiment", choices=["policies", "skip", "iters", "ler", "flip", "quant"],
                     help="run one of the paper's ablations instead of the benchmark (prints a JSON table)")
     ap.add_argument("--exp-shots", type=int, default=1 << 20, help="shots per experiment point")
     ap.add_argument("--exp-p", default="", help="comma-separated physical error rates (default: per experiment)")
