@@ -270,6 +270,8 @@ def decode_point(torch, h, checker, p, err, syn, prm, batch: int = 1 << 18):
     corr = np.empty((shots, dec.nw), np.uint32)
     flags = np.empty(shots, np.uint8)
     iters = np.empty(shots, np.int32)
+    dec.kernel_times()
+    dec.set_timing(True)
     t0 = t_say = time.perf_counter()
     for lo in range(0, shots, batch):
         hi = min(shots, lo + batch)
@@ -282,6 +284,8 @@ def decode_point(torch, h, checker, p, err, syn, prm, batch: int = 1 << 18):
             t_say = time.perf_counter()
             log(f"    {hi}/{shots} shots decoded, {t_say - t0:.0f} s")
     gpu_s = time.perf_counter() - t0
+    bp_ms, bp_n, osd_ms, osd_n = dec.kernel_times()
+    dec.set_timing(False)
     del dec
     sf, lf = failures_packed(checker, err, corr, h.shape[1])
     k = int((sf | lf).sum())
@@ -291,7 +295,10 @@ def decode_point(torch, h, checker, p, err, syn, prm, batch: int = 1 << 18):
                 synd_fail=int(sf.sum()), logical_fail=int(lf.sum()),
                 not_converged=float((~conv).mean()), osd_invoke_rate=float(((flags & 2) != 0).mean()),
                 mean_iters=float(iters.mean()), max_iter_hits=int((~conv).sum()),
-                iter_hist={int(i): int(c) for i, c in enumerate(hist) if c}, decode_s=gpu_s)
+                iter_hist={int(i): int(c) for i, c in enumerate(hist) if c}, decode_s=gpu_s,
+                bp_kernel_ms=bp_ms, osd_kernel_ms=osd_ms,
+                kernel_syndromes_per_s=shots / max(1e-9, (bp_ms + osd_ms) / 1e3),
+                osd_us_per_osd_shot=1e3 * osd_ms / max(1, int(((flags & 2) != 0).sum())))
 
 
 def run_experiment(args):
@@ -347,6 +354,11 @@ def run_experiment(args):
             for o, om in osd_modes.items():
                 for label, code in fmts:
                     grid.append((sd9, p, f"{label}/{o}", prm(msg=code, osd=om)))
+    elif args.experiment == "osdheavy":    # where OSD dominates: high invoke rate, large m
+        for name, p in [("bb144_cc", 0.06), ("bb144_cc", 0.08), ("bb288_phen", 0.003), ("surface17_phen", 0.003)]:
+            for lot in (False, True):
+                grid.append((name, p, ("lottery_bp" if lot else "plain_bp") + "/osd_cs10",
+                             prm(lottery=lot, osd=2, max_iter=args.exp_max_iter)))
     elif args.experiment == "flip":        # what the lottery negates: next messages or lambda itself
         for name in (sd9, args.exp_bb):
             for p in ps or [1e-3, 3e-3]:
@@ -376,7 +388,8 @@ def run_experiment(args):
         points.append(r)
         log(f"[{args.experiment}] {name} p={p} {label}: LER {r['ler']:.3e} "
             f"[{r['ler_ci95'][0]:.2e},{r['ler_ci95'][1]:.2e}] not-conv {r['not_converged']:.3e} "
-            f"mean-iter {r['mean_iters']:.2f} ({r['decode_s']:.1f} s)")
+            f"mean-iter {r['mean_iters']:.2f} BP {r['bp_kernel_ms']:.1f} ms OSD {r['osd_kernel_ms']:.1f} ms "
+            f"({r['decode_s']:.1f} s)")
         torch.cuda.empty_cache()
     out = dict(experiment=args.experiment, shots_per_point=shots, data_seed=DATA_SEED, lottery_seed=LOTTERY_SEED,
                data="synthetic: i.i.d. Bernoulli(p) flips on every column of H_st, seeded (PCG64, chunked)",
@@ -407,7 +420,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-ler", action="store_true")
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
-    ap.add_argument("--experiment", choices=["policies", "skip", "iters", "ler", "flip", "quant"],
+    ap.add_argument("--experiment", choices=["policies", "skip", "iters", "ler", "flip", "quant", "osdheavy"],
                     help="run one of the paper's ablations instead of the benchmark (prints a JSON table)")
     ap.add_argument("--exp-shots", type=int, default=1 << 20, help="shots per experiment point")
     ap.add_argument("--exp-p", default="", help="comma-separated physical error rates (default: per experiment)")

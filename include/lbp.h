@@ -184,10 +184,15 @@ lbp_status lbp_decode_host(lbp_decoder dec, int64_t n_shots, uint64_t first_shot
 int64_t lbp_decoder_device_bytes(lbp_decoder dec);
 int64_t lbp_decoder_max_batch(lbp_decoder dec);
 
-/* Number of failed shots whose lambda one OSD pass can stage; failures beyond
- * it are re-decoded (BP is deterministic) and handled in further passes. */
+/* Number of failed shots whose lambda one OSD pass can stage (n*8 bytes each;
+ * initially 256 MiB worth).  Failures beyond it are re-decoded (BP is
+ * deterministic) and handled in a further pass; when the overflow exceeds the
+ * capacity, lbp_decode first grows the staging to the overflow, bounded by
+ * max_batch and a quarter of the free device memory, so a high OSD invoke rate
+ * costs one extra BP pass once, not one per capacity's worth of failures. */
 int64_t lbp_decoder_osd_capacity(lbp_decoder dec);
-/* Testing aid: lower the staging capacity (>= 1) to exercise the overflow path. */
+/* Testing aid: lower the staging capacity (>= 1) to exercise the overflow path;
+ * a lowered capacity is never grown again. */
 lbp_status lbp_decoder_set_osd_capacity(lbp_decoder dec, int64_t cap);
 
 /* Kernel timing (tracing aid).  While enabled, lbp_decode records a pair of HIP

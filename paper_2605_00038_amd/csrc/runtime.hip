@@ -78,6 +78,7 @@ struct lbp_decoder_s {
     int wpb = 1, bp_blocks = 1, wave_bytes = 0, int8_slots = 0, table_bytes = 0;
     int osd_blocks = 0, osd_lds = 0, osd_variant = 0, osd_threads = 1024, mws = 1, sort_p = 1;
     int64_t fail_cap = 0;
+    bool fail_cap_pinned = false;  // set by lbp_decoder_set_osd_capacity: never grown
     int64_t dev_bytes = 0;  // device workspace held by the decoder
     uint32_t *d_counters = nullptr;
     int32_t *d_fail_list = nullptr;
@@ -475,6 +476,7 @@ lbp_status lbp_decoder_set_osd_capacity(lbp_decoder d, int64_t cap) {
     if (!d) return fail(LBP_EINVAL, "lbp_decoder_set_osd_capacity: NULL decoder");
     if (cap < 1 || cap > d->fail_cap) return fail(LBP_EINVAL, "lbp_decoder_set_osd_capacity: 1 <= cap <= current capacity");
     d->fail_cap = cap;
+    d->fail_cap_pinned = true;
     return LBP_OK;
 }
 
@@ -572,6 +574,27 @@ lbp_status lbp_decoder_kernel_times(lbp_decoder d, double *bp_ms, int64_t *bp_la
     return LBP_OK;
 }
 
+// Enlarge the OSD staging of failed shots' lambda to `want` shots, bounded by
+// max_batch and a quarter of the free device memory; on any failure the old
+// buffer stays (the caller then needs more passes, never wrong results).  The
+// stream is idle here (the caller has synchronized it).
+static void grow_fail_cap(lbp_decoder d, int64_t want) {
+    const int64_t per = (int64_t)d->code->n * 8;
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return;
+    const int64_t cap = std::min<int64_t>(std::min<int64_t>(want, d->max_batch), (int64_t)(free_b / 4) / per);
+    if (cap <= d->fail_cap) return;
+    float *nb = nullptr;
+    if (hipMalloc((void **)&nb, (size_t)cap * per) != hipSuccess) {
+        (void)hipGetLastError();
+        return;
+    }
+    hipFree(d->d_fail_llr);
+    d->d_fail_llr = nb;
+    d->dev_bytes += (int64_t)align256((size_t)cap * per) - (int64_t)align256((size_t)d->fail_cap * per);
+    d->fail_cap = cap;
+}
+
 static lbp_status decode_impl(const char *who, lbp_decoder d, int64_t n_shots, uint64_t first_shot_id,
                               const uint64_t *keys, const uint32_t *syndromes, uint32_t *corrections, uint8_t *flags,
                               int32_t *iters, float *llr_out, void *stream) {
@@ -589,10 +612,15 @@ static lbp_status decode_impl(const char *who, lbp_decoder d, int64_t n_shots, u
     for (;;) {
         HIPCHK(hipMemcpyAsync(d->h_count, d->d_counters + 1, 4, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
-        int64_t total = d->h_count[0];
+        const int64_t total = d->h_count[0];
         if (total <= d->fail_cap) return LBP_OK;
-        int64_t rest = total - d->fail_cap;
-        HIPCHK(launch_gather_list(d->d_counters, d->d_fail_list, d->fail_cap, d->d_list2, rest, s));
+        // entries [0, staged) of the failure list went through OSD in the pass that just ran
+        const int64_t staged = d->fail_cap;
+        const int64_t rest = total - staged;
+        // grow the staging (once) so that the overflow takes one more pass, not
+        // rest / capacity passes that each re-decode everything still pending
+        if (!d->fail_cap_pinned && rest > d->fail_cap) grow_fail_cap(d, rest);
+        HIPCHK(launch_gather_list(d->d_counters, d->d_fail_list, staged, d->d_list2, rest, s));
         st = run_pass(d, rest, d->d_list2, first_shot_id, keys, syndromes, corrections, flags, iters, llr_out, s);
         if (st != LBP_OK) return st;
     }

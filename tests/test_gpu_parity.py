@@ -180,10 +180,11 @@ def test_full_size_sampled_bb144():
     _say("  failed-BP shots", int((g["flags"] & 2).sum()), "of 65536")
 
 
-@pytest.mark.parametrize("name", ["surface13_phen", "surface17_phen"])
+@pytest.mark.parametrize("name", ["surface13_phen", "surface17_phen", "bb288_phen"])
 def test_osd_large_codes(name):
     """Codes with m > 1024 run OSD with G in LDS (d=13, 1092 checks) or in global
-    memory (d=17, 2448 checks); few BP iterations force many shots into OSD."""
+    memory (d=17, 2448 checks; BB[[288,12,18]] r=18, 2592 checks); few BP
+    iterations force many shots into OSD."""
     h, e, syn = batch(name, 0.01, 24, 1010)
     for osd_mode in (1, 2):
         prm = _params(msg=2, max_iter=3, lottery=False, osd=osd_mode, osd_order=6)
@@ -215,3 +216,30 @@ def test_code_released_before_decoder():
     assert hip.hipPeekAtLastError() == 0
     t = torch.empty(64 << 20, dtype=torch.uint8, device="cuda")  # a fresh segment from the allocator
     del t
+
+
+def test_osd_staging_grows_for_high_invoke_rate():
+    """When more shots fail BP than the OSD staging holds, the decoder grows the
+    staging once instead of re-decoding the overflow pass after pass; results equal
+    the pinned-capacity path and the oracle."""
+    import torch
+    from paper_2605_00038_amd import Code, Decoder
+    h, e, syn = batch("surface17_phen", 0.01, 12000, 1011)
+    prm = _params(msg=2, max_iter=3, lottery=False, osd=1)
+    code = Code.from_scipy(h, 0.01)
+    s = torch.from_numpy(np.ascontiguousarray(syn).view(np.int32)).cuda()
+    grow = Decoder(code, prm, syn.shape[0])
+    cap0 = grow.osd_capacity
+    c1, f1, i1, _ = grow.decode(s)
+    torch.cuda.synchronize()
+    assert int(((f1.cpu().numpy() & 2) != 0).sum()) > 2 * cap0       # the overflow path ran
+    assert grow.osd_capacity > cap0                                   # and the staging grew
+    pinned = Decoder(code, prm, syn.shape[0])
+    pinned.set_osd_capacity(cap0)
+    c2, f2, i2, _ = pinned.decode(s)
+    torch.cuda.synchronize()
+    assert (c1.cpu().numpy() == c2.cpu().numpy()).all() and (f1.cpu().numpy() == f2.cpu().numpy()).all()
+    idx = np.random.default_rng(5).choice(syn.shape[0], 300, replace=False)
+    o = oracle.decode(h, 0.01, oracle_params(prm), syn[idx], n_threads=8)
+    assert (c1.cpu().numpy().view(np.uint32)[idx] == o["corr"]).all()
+    assert (f1.cpu().numpy()[idx] == o["flags"]).all()
