@@ -210,6 +210,8 @@ struct OsdArgs {
     int32_t g_in_lds;
     int32_t has_lo;             // lambda carries a non-zero low part (fp32 messages)
     int32_t llr_by_shot;        // fail_llr indexed by the shot (ring slot) instead of the list position
+    int32_t cols_global;        // G-in-global variant: the per-column arrays live in the block's scratch too
+    int64_t scratch_words;      // per-block stride of gscratch in 32-bit words
 };
 
 // Global-memory comparison path (one launch per half-iteration).
@@ -244,11 +246,12 @@ void set_error(const char *msg);
 // LDS bytes the BP kernel needs per wave for a code.
 int bp_wave_bytes(int msg, int m, int n);
 // OSD kernel choice for a code: variant > 0 keeps G in registers (NW words per
-// row, m <= 1024), 0 keeps G in LDS, -1 in global memory.  Returns LDS bytes
-// per block; *threads is the block size.
+// row, m <= 1024), 0 keeps G in LDS, -1 in global memory, -2 also keeps the
+// per-column arrays (sort keys, order, non-basis list) in global memory (large
+// n).  Returns LDS bytes per block; *threads is the block size.
 int osd_block_bytes(int m, int n, int lds_limit, int *variant, int *mws, int *sort_p, int *threads);
 // Per-block global scratch of the OSD kernel.
-size_t osd_scratch_bytes(int variant, int m, int mws);
+size_t osd_scratch_bytes(int variant, int m, int n, int mws, int sort_p);
 hipError_t osd_max_blocks_per_cu(int variant, int threads, int lds, int *out);
 
 // Int3.4 check-centric kernel (codes with <= 1024 checks): slots per lane

@@ -192,14 +192,28 @@ __global__ __launch_bounds__(OSD_THREADS) void osd_lds_kernel(OsdArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int m = a.m, n = a.n, tid = threadIdx.x, lane = tid & 63;
     const int P = a.sort_p;
-    size_t gbytes = a.g_in_lds ? (size_t)m * a.mws * 4 : 0;
-    size_t rbytes = gbytes > (size_t)P * 8 ? gbytes : (size_t)P * 8;
-    rbytes = (rbytes + 15) & ~(size_t)15;
-    unsigned char *q0 = smem + rbytes;
-    float *lo_s = (float *)q0;                       q0 += ((size_t)n * 4 + 15) & ~(size_t)15;
-    uint16_t *perm = (uint16_t *)q0;                 q0 += ((size_t)n * 2 + 15) & ~(size_t)15;
-    uint16_t *tl = (uint16_t *)q0;                   q0 += ((size_t)n * 2 + 15) & ~(size_t)15;
-    uint8_t *isb = q0;                               q0 += ((size_t)n + 15) & ~(size_t)15;
+    unsigned char *gblk = (unsigned char *)(a.gscratch + (size_t)blockIdx.x * a.scratch_words);
+    unsigned char *q0, *c0;  // next free byte of LDS, and of the per-column arrays
+    unsigned long long *keys;
+    if (a.cols_global) {
+        // large n: sort keys and per-column arrays after G in the block's scratch
+        c0 = gblk + (((size_t)m * a.mws * 4 + 255) & ~(size_t)255);
+        keys = (unsigned long long *)c0;
+        c0 += ((size_t)P * 8 + 255) & ~(size_t)255;
+        q0 = smem;
+    } else {
+        size_t gbytes = a.g_in_lds ? (size_t)m * a.mws * 4 : 0;
+        size_t rbytes = gbytes > (size_t)P * 8 ? gbytes : (size_t)P * 8;
+        rbytes = (rbytes + 15) & ~(size_t)15;
+        keys = (unsigned long long *)smem;
+        c0 = smem + rbytes;
+        q0 = nullptr;
+    }
+    float *lo_s = (float *)c0;                       c0 += ((size_t)n * 4 + 15) & ~(size_t)15;
+    uint16_t *perm = (uint16_t *)c0;                 c0 += ((size_t)n * 2 + 15) & ~(size_t)15;
+    uint16_t *tl = (uint16_t *)c0;                   c0 += ((size_t)n * 2 + 15) & ~(size_t)15;
+    uint8_t *isb = c0;                               c0 += ((size_t)n + 15) & ~(size_t)15;
+    if (!a.cols_global) q0 = c0;
     uint16_t *pcol = (uint16_t *)q0;                 q0 += ((size_t)m * 2 + 15) & ~(size_t)15;
     uint8_t *piv = q0;                               q0 += ((size_t)m + 15) & ~(size_t)15;
     uint8_t *sp = q0;                                q0 += ((size_t)m + 15) & ~(size_t)15;
@@ -209,7 +223,7 @@ __global__ __launch_bounds__(OSD_THREADS) void osd_lds_kernel(OsdArgs a) {
     unsigned long long *best64 = (unsigned long long *)q0;
 
     GView G;
-    G.g = a.g_in_lds ? (uint32_t *)smem : a.gscratch + (size_t)blockIdx.x * m * a.mws;
+    G.g = a.g_in_lds ? (uint32_t *)smem : (uint32_t *)gblk;
     G.m = m;
     G.mws = a.mws;
     G.in_lds = a.g_in_lds;
@@ -222,7 +236,7 @@ __global__ __launch_bounds__(OSD_THREADS) void osd_lds_kernel(OsdArgs a) {
         const float *lam = a.fail_llr + (size_t)(a.llr_by_shot ? shot : (int64_t)q) * 2 * n;  // hi[n] then lo[n]
 
         // ---- 1. sort (lambda, column) ascending
-        sort_columns(lam, n, P, a.has_lo, (unsigned long long *)smem, lo_s, perm);
+        sort_columns(lam, n, P, a.has_lo, keys, lo_s, perm);
 
         // ---- 2. G = I, s' = s
         const int mw = a.mw;
@@ -616,6 +630,7 @@ int osd_block_bytes(int m, int n, int lds_limit, int *variant, int *mws, int *so
         return (int)(al((size_t)P * 8) + common + al(32 * vb) + 32 * 4 + 16 * 8);
     }
     *threads = OSD_THREADS;
+    size_t rows = al((size_t)m * 2) + al((size_t)m) * 2 + al((size_t)((n + 31) / 32) * 4) + 16 * 4 + 32 * 4 + 16;
     size_t rest = common + al((size_t)m * 2) + al((size_t)m) * 2;
     size_t gb = (size_t)m * s * 4;
     size_t with_g = al(gb > (size_t)P * 8 ? gb : (size_t)P * 8) + rest;
@@ -624,14 +639,23 @@ int osd_block_bytes(int m, int n, int lds_limit, int *variant, int *mws, int *so
         *mws = s;
         return (int)with_g;
     }
-    *variant = -1;     // G in global memory
     *mws = mw;
-    return (int)(al((size_t)P * 8) + rest);
+    if ((int64_t)(al((size_t)P * 8) + rest) <= lds_limit) {
+        *variant = -1;  // G in global memory
+        return (int)(al((size_t)P * 8) + rest);
+    }
+    *variant = -2;      // G and the per-column arrays in global memory
+    return (int)rows;
 }
 
-size_t osd_scratch_bytes(int variant, int m, int mws) {
+size_t osd_scratch_bytes(int variant, int m, int n, int mws, int sort_p) {
+    auto a256 = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    auto al = [](size_t x) { return (x + 15) & ~(size_t)15; };
     if (variant > 0) return (size_t)16 * m * 8;       // per-wave column ballots
-    if (variant < 0) return (size_t)m * mws * 4;      // G
+    if (variant == -1) return a256((size_t)m * mws * 4);  // G
+    if (variant == -2)                                 // G, sort keys, lambda lo, order, non-basis list, flags
+        return a256(a256((size_t)m * mws * 4) + a256((size_t)sort_p * 8) + al((size_t)n * 4) + 2 * al((size_t)n * 2) +
+                    al((size_t)n));
     return 0;
 }
 

@@ -243,3 +243,19 @@ def test_osd_staging_grows_for_high_invoke_rate():
     o = oracle.decode(h, 0.01, oracle_params(prm), syn[idx], n_threads=8)
     assert (c1.cpu().numpy().view(np.uint32)[idx] == o["corr"]).all()
     assert (f1.cpu().numpy()[idx] == o["flags"]).all()
+
+
+@pytest.mark.parametrize("name,p,shots", [("surface21_phenpf", 0.002, 64), ("surface25_phenpf", 0.0015, 48)])
+def test_large_surface_codes(name, p, shots):
+    """The paper's scale on the general kernel: surface d=21 (4840 x 13881) and d=25
+    (8112 x 23425) over d rounds with the final read-out, Int3.4 bit-exact against
+    the oracle, OSD-0 with G in global memory."""
+    h, e, syn = batch(name, p, shots, 1301)
+    prm = _params(msg=2, max_iter=100, lottery=True, osd=1, seed=5)
+    g = gpu_decode(h, p, prm, syn, want_llr=True)
+    o = oracle.decode(h, p, oracle_params(prm), syn, want_llr=True, n_threads=8)
+    assert (g["flags"] & 2).sum() >= 8
+    assert (g["flags"] == o["flags"]).all()
+    assert (g["iters"] == o["iters"]).all()
+    assert (g["llr"] == o["llr"]).all()
+    assert (g["corr"] == o["corr"]).all()
