@@ -121,7 +121,15 @@ void lbp_params_default(lbp_params *p);
  * arrays on return.  The prior LLR mu_v = ln((1-p_v)/p_v) is evaluated in
  * fp64 on the host (Algorithm 1, prior).
  * Limits (LBP_EUNSUPPORTED otherwise): 1 <= row weight <= 8, column weight
- * <= 4, m <= 8191, n <= 65535.  Empty rows and malformed CSR: LBP_EINVAL.
+ * <= 4, m <= 32767, n <= 65535.  Empty rows and malformed CSR: LBP_EINVAL.
+ * Whether a decoder fits the device is decided by lbp_decoder_create (the
+ * per-shot messages of the chosen format must fit one CU's LDS: for
+ * space-time surface codes Int x.y reaches about 18000 checks, FP16 about
+ * 9500, FP32 about 4900).
+ * The column table keeps each edge's slot position (8 check + slot) in 16
+ * bits when m <= 8191 and in 32 bits above; the environment variable
+ * LBP_WIDE_COLUMN_TABLE=1, read here, selects the 32-bit layout for any code
+ * (it changes no result; it exists to test that layout on small codes).
  * The code lives on the device that is current when it is created. */
 lbp_status lbp_code_create(int32_t m, int32_t n, const int32_t *row_ptr, const int32_t *col_idx,
                            const double *p, lbp_code *out);

@@ -136,21 +136,21 @@ __global__ void bl_col(BlArgs a) {
     uint32_t pos[CDEG];
     double lam = 0.0, mu = 0.0;
     if (valid) {
-        const uint64_t tab = C.vn_tab[v];
+        const u32x4 tab = col_positions(C, v);
         mu = mu_of(C, a.msg, v);
         lam = mu;
         for (int j = 0; j < CDEG; ++j) {
-            pos[j] = (uint32_t)(tab >> (16 * j)) & 0xFFFFu;
-            b[j] = pos[j] != NOPOS ? (double)a.beta[shot * C.m * DEG + pos[j]] : 0.0;
+            pos[j] = tab[j];
+            b[j] = pos[j] != NOPOS32 ? (double)a.beta[shot * C.m * DEG + pos[j]] : 0.0;
             lam += b[j];
         }
         a.lam[shot * C.n + v] = lam;
         if (a.prm.flip == FLIP_MSG) {
             for (int j = 0; j < CDEG; ++j) {
-                if (pos[j] == NOPOS) continue;
+                if (pos[j] == NOPOS32) continue;
                 double x = mu;
                 for (int t = 0; t < CDEG; ++t)
-                    if (t != j && pos[t] != NOPOS) x += b[t];
+                    if (t != j && pos[t] != NOPOS32) x += b[t];
                 a.alpha[shot * C.m * DEG + pos[j]] = store_msg(a.msg, x);
             }
         }
@@ -258,11 +258,11 @@ __global__ void bl_check(BlArgs a, int i) {
                 long long best_q = 0;
                 for (int e = 0; e < C.cn_deg[cstar]; ++e) {
                     const int v = C.cn_cols[cstar * DEG + e];
-                    const uint64_t tab = C.vn_tab[v];
+                    const u32x4 tab = col_positions(C, v);
                     int cnt = 0;
                     for (int j = 0; j < CDEG; ++j) {
-                        const uint32_t p = (uint32_t)(tab >> (16 * j)) & 0xFFFFu;
-                        if (p == NOPOS) continue;
+                        const uint32_t p = tab[j];
+                        if (p == NOPOS32) continue;
                         const int c = (int)(p / DEG);
                         const uint32_t s = (S[c >> 5] >> (c & 31)) & 1u;
                         cnt += (int)(((SHp[c >> 5] >> (c & 31)) & 1u) ^ s);

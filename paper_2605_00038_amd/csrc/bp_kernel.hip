@@ -183,17 +183,17 @@ __device__ __forceinline__ Lam<typename Fmt<MSG>::A> sum_terms(typename Fmt<MSG>
 }
 
 // Loads the column's C2V messages; returns the slot mask and lambda = mu + sum.
-template <int MSG>
-__device__ __forceinline__ Lam<typename Fmt<MSG>::A> column_lambda(const DevCode &C, int v, uint64_t tab,
+template <int MSG, class TB>
+__device__ __forceinline__ Lam<typename Fmt<MSG>::A> column_lambda(const DevCode &C, int v, typename TB::T tab,
                                                                    const typename Fmt<MSG>::T *E,
                                                                    typename Fmt<MSG>::A b[CDEG], uint32_t &mask) {
     using F = Fmt<MSG>;
     mask = 0;
 #pragma unroll
     for (int j = 0; j < CDEG; ++j) {
-        uint32_t p = (uint32_t)(tab >> (16 * j)) & 0xFFFFu;
-        b[j] = p != NOPOS ? F::load(E[p]) : (typename F::A)0;
-        if (p != NOPOS) mask |= 1u << j;
+        uint32_t p = TB::pos(tab, j);
+        b[j] = p != TB::NONE ? F::load(E[p]) : (typename F::A)0;
+        if (p != TB::NONE) mask |= 1u << j;
     }
     return sum_terms<MSG>(F::mu(C, v), b, mask);
 }
@@ -291,7 +291,7 @@ __device__ void cn_half(const DevCode &C, const BpParams &P, int i, typename Fmt
 
 // Worst check of U (Sec. III-B): the most neighbours whose hard decision on
 // lambda^(i) (rebuilt from E) is 1, the smallest index among equals.
-template <int MSG>
+template <int MSG, class TB>
 __device__ int worst_check(const DevCode &C, const typename Fmt<MSG>::T *E, const uint32_t *S, const uint32_t *SHp,
                            int lane) {
     unsigned long long best = 0;
@@ -304,7 +304,7 @@ __device__ int worst_check(const DevCode &C, const typename Fmt<MSG>::T *E, cons
                 const int v = C.cn_cols[c * DEG + k];
                 typename Fmt<MSG>::A b[CDEG];
                 uint32_t mask;
-                cnt += hard_decision<MSG>(column_lambda<MSG>(C, v, C.vn_tab[v], E, b, mask)) ? 1 : 0;
+                cnt += hard_decision<MSG>(column_lambda<MSG, TB>(C, v, TB::load(C, v), E, b, mask)) ? 1 : 0;
             }
             const unsigned long long key = ((unsigned long long)(cnt + 1) << 32) | (0xFFFFFFFFu - (uint32_t)c);
             best = key > best ? key : best;
@@ -324,7 +324,7 @@ __device__ int worst_check(const DevCode &C, const typename Fmt<MSG>::T *E, cons
 // P.rule picks the design-space variant (Sec. III-B): random or worst check;
 // proposed key (count, Q, column), Q-first, unreliable (Q, column) or a
 // random neighbour drawn from word 1 of the same Philox block.
-template <int MSG>
+template <int MSG, class TB>
 __device__ int lottery_select(const DevCode &C, const BpParams &P, uint64_t seed, uint64_t shot_id, int i,
                               const typename Fmt<MSG>::T *E, const uint32_t *S, const uint32_t *SHp, int lane) {
     using F = Fmt<MSG>;
@@ -340,7 +340,7 @@ __device__ int lottery_select(const DevCode &C, const BpParams &P, uint64_t seed
     const uint64_t x = philox_word01(seed, shot_id, (uint64_t)i, x1);
     int cstar = -1;
     if (cn_rule == LOT_CN_WORST) {
-        cstar = __builtin_amdgcn_readfirstlane(worst_check<MSG>(C, E, S, SHp, lane));
+        cstar = __builtin_amdgcn_readfirstlane(worst_check<MSG, TB>(C, E, S, SHp, lane));
     } else {
         uint32_t k = (uint32_t)(((x >> 32) * (uint64_t)N) >> 32);  // floor(r * N)
         for (int w0 = 0; w0 < C.mw; w0 += 64) {
@@ -376,15 +376,15 @@ __device__ int lottery_select(const DevCode &C, const BpParams &P, uint64_t seed
         uint32_t vv = C.cn_cols[cstar * DEG + lane];
         if (vv != NOPOS) {
             v = (int)vv;
-            uint64_t tab = C.vn_tab[v];
+            const typename TB::T tab = TB::load(C, v);
             typename F::A b[CDEG];
             uint32_t mask;
-            Lam<typename F::A> lam = column_lambda<MSG>(C, v, tab, E, b, mask);
+            Lam<typename F::A> lam = column_lambda<MSG, TB>(C, v, tab, E, b, mask);
             cnt = 0;
 #pragma unroll
             for (int j = 0; j < CDEG; ++j) {
-                uint32_t p = (uint32_t)(tab >> (16 * j)) & 0xFFFFu;
-                if (p != NOPOS) {
+                uint32_t p = TB::pos(tab, j);
+                if (p != TB::NONE) {
                     uint32_t c = p / DEG;
                     cnt += ((SHp[c >> 5] ^ S[c >> 5]) >> (c & 31)) & 1u;
                 }
@@ -410,7 +410,7 @@ __device__ int lottery_select(const DevCode &C, const BpParams &P, uint64_t seed
 
 // ------------------------------------------------------------ variable-node half
 
-template <int MSG>
+template <int MSG, class TB>
 __device__ void vn_half(const DevCode &C, const BpParams &P, int fv, bool last, typename Fmt<MSG>::T *E,
                         uint32_t *SH, uint32_t *EH, int lane, float *llr_row, float *stage) {
     using F = Fmt<MSG>;
@@ -419,11 +419,11 @@ __device__ void vn_half(const DevCode &C, const BpParams &P, int fv, bool last, 
     for (int vs = 0; vs < nvs; ++vs) {
         const int v = vs * 64 + lane;
         const bool valid = v < C.n;
-        const uint64_t tab = valid ? C.vn_tab[v] : ~0ull;
+        const typename TB::T tab = valid ? TB::load(C, v) : TB::empty();
         A b[CDEG];
         uint32_t mask = 0;
         Lam<A> lam{(A)1, 0.f};
-        if (valid) lam = column_lambda<MSG>(C, v, tab, E, b, mask);
+        if (valid) lam = column_lambda<MSG, TB>(C, v, tab, E, b, mask);
         const bool e = valid && hard_decision<MSG>(lam);
         const uint64_t bal = __ballot(e);
         if (lane == 0) {
@@ -433,8 +433,8 @@ __device__ void vn_half(const DevCode &C, const BpParams &P, int fv, bool last, 
         if (e) {
 #pragma unroll
             for (int j = 0; j < CDEG; ++j) {
-                uint32_t p = (uint32_t)(tab >> (16 * j)) & 0xFFFFu;
-                if (p != NOPOS) {
+                uint32_t p = TB::pos(tab, j);
+                if (p != TB::NONE) {
                     uint32_t c = p / DEG;
                     atomicXor(&SH[c >> 5], 1u << (c & 31));
                 }
@@ -452,8 +452,8 @@ __device__ void vn_half(const DevCode &C, const BpParams &P, int fv, bool last, 
             const int l2 = (P.flip == FLIP_LLR && flipv) ? -lam.hi : lam.hi;
 #pragma unroll
             for (int j = 0; j < CDEG; ++j) {
-                uint32_t p = (uint32_t)(tab >> (16 * j)) & 0xFFFFu;
-                if (p != NOPOS) {
+                uint32_t p = TB::pos(tab, j);
+                if (p != TB::NONE) {
                     int a = l2 - b[j];  // == mu + sum of the other C2V messages
                     a = a > P.qmax ? P.qmax : (a < -P.qmax ? -P.qmax : a);
                     if (P.flip == FLIP_MSG && flipv) a = -a;
@@ -464,8 +464,8 @@ __device__ void vn_half(const DevCode &C, const BpParams &P, int fv, bool last, 
             const A mu = F::mu(C, v);
 #pragma unroll
             for (int j = 0; j < CDEG; ++j) {
-                uint32_t p = (uint32_t)(tab >> (16 * j)) & 0xFFFFu;
-                if (p != NOPOS) {
+                uint32_t p = TB::pos(tab, j);
+                if (p != TB::NONE) {
                     // extrinsic sum in ascending check order, rounded once to the format
                     A a = sum_terms<MSG>(mu, b, mask & ~(1u << j)).hi;
                     E[p] = F::sat(flipv ? -a : a);
@@ -475,8 +475,8 @@ __device__ void vn_half(const DevCode &C, const BpParams &P, int fv, bool last, 
             const float sg = flipv ? -1.f : 1.f;
 #pragma unroll
             for (int j = 0; j < CDEG; ++j) {
-                uint32_t p = (uint32_t)(tab >> (16 * j)) & 0xFFFFu;
-                if (p != NOPOS) {
+                uint32_t p = TB::pos(tab, j);
+                if (p != TB::NONE) {
                     // (+-lambda) - beta_j from the exact pair, rounded once
                     float s1, e1, s2, e2;
                     two_sum(sg * (float)lam.hi, -(float)b[j], s1, e1);
@@ -490,7 +490,7 @@ __device__ void vn_half(const DevCode &C, const BpParams &P, int fv, bool last, 
 
 // ------------------------------------------------------------------ kernel
 
-template <int MSG>
+template <int MSG, class TB>
 __global__ __launch_bounds__(1024) void bp_kernel(BpArgs a) {
     using F = Fmt<MSG>;
     using T = typename F::T;
@@ -548,12 +548,12 @@ __global__ __launch_bounds__(1024) void bp_kernel(BpArgs a) {
                 if (k >= deg) E[c * DEG + k] = F::pad();
         }
         for (int v = lane; v < C.n; v += 64) {
-            const uint64_t tab = C.vn_tab[v];
+            const typename TB::T tab = TB::load(C, v);
             const T mu = F::sat(F::mu(C, v));
 #pragma unroll
             for (int j = 0; j < CDEG; ++j) {
-                uint32_t p = (uint32_t)(tab >> (16 * j)) & 0xFFFFu;
-                if (p != NOPOS) E[p] = mu;
+                uint32_t p = TB::pos(tab, j);
+                if (p != TB::NONE) E[p] = mu;
             }
         }
         wave_sync();
@@ -566,11 +566,11 @@ __global__ __launch_bounds__(1024) void bp_kernel(BpArgs a) {
             cn_half<MSG>(C, P, i, E, S, lane);
             wave_sync();
             int fv = -1;
-            if (P.lottery && i >= P.skip && i <= P.max_iter - 2) fv = lottery_select<MSG>(C, P, seed, shot_id, i, E, S, SHp, lane);
+            if (P.lottery && i >= P.skip && i <= P.max_iter - 2) fv = lottery_select<MSG, TB>(C, P, seed, shot_id, i, E, S, SHp, lane);
             for (int w = lane; w < C.mw; w += 64) SHc[w] = 0u;
             wave_sync();
             const bool last = i == P.max_iter - 1;
-            vn_half<MSG>(C, P, fv, last, E, SHc, EH, lane, llr_row, stage);
+            vn_half<MSG, TB>(C, P, fv, last, E, SHc, EH, lane, llr_row, stage);
             wave_sync();
             bool mism = false;
             for (int w = lane; w < C.mw; w += 64) mism |= SHc[w] != S[w];
@@ -654,37 +654,48 @@ hipError_t launch_gather_list(const uint32_t *counters, const int32_t *fail_list
     return hipGetLastError();
 }
 
-template <int MSG>
+template <int MSG, class TB>
 static hipError_t launch_t(const BpArgs &a, int blocks, int wpb, hipStream_t s) {
     size_t lds = (size_t)a.wave_bytes * wpb;
-    hipError_t e = hipFuncSetAttribute((const void *)bp_kernel<MSG>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    hipError_t e = hipFuncSetAttribute((const void *)bp_kernel<MSG, TB>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(bp_kernel<MSG>, dim3(blocks), dim3(64 * wpb), lds, s, a);
+    hipLaunchKernelGGL((bp_kernel<MSG, TB>), dim3(blocks), dim3(64 * wpb), lds, s, a);
     return hipGetLastError();
 }
 
+template <class TB>
+static hipError_t launch_tb(int msg, const BpArgs &a, int blocks, int wpb, hipStream_t s) {
+    switch (msg) {
+    case MSG_INT8: return launch_t<MSG_INT8, TB>(a, blocks, wpb, s);
+    case MSG_FP16: return launch_t<MSG_FP16, TB>(a, blocks, wpb, s);
+    default: return launch_t<MSG_FP32, TB>(a, blocks, wpb, s);
+    }
+}
+
 hipError_t launch_bp(int msg, const BpArgs &a, int blocks, int wpb, hipStream_t s) {
-    switch (msg) {
-    case MSG_INT8: return launch_t<MSG_INT8>(a, blocks, wpb, s);
-    case MSG_FP16: return launch_t<MSG_FP16>(a, blocks, wpb, s);
-    default: return launch_t<MSG_FP32>(a, blocks, wpb, s);
-    }
+    return a.code.vn_tab4 ? launch_tb<ColTab32>(msg, a, blocks, wpb, s) : launch_tb<ColTab16>(msg, a, blocks, wpb, s);
 }
 
-template <int MSG>
+template <int MSG, class TB>
 static hipError_t occ_t(int wpb, int lds, int *out) {
-    hipError_t e = hipFuncSetAttribute((const void *)bp_kernel<MSG>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    hipError_t e =
+        hipFuncSetAttribute((const void *)bp_kernel<MSG, TB>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     if (e != hipSuccess) return e;
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(out, bp_kernel<MSG>, 64 * wpb, (size_t)lds);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(out, bp_kernel<MSG, TB>, 64 * wpb, (size_t)lds);
 }
 
-hipError_t bp_max_blocks_per_cu(int msg, int wpb, int lds, int *out) {
+template <class TB>
+static hipError_t occ_tb(int msg, int wpb, int lds, int *out) {
     switch (msg) {
-    case MSG_INT8: return occ_t<MSG_INT8>(wpb, lds, out);
-    case MSG_FP16: return occ_t<MSG_FP16>(wpb, lds, out);
-    default: return occ_t<MSG_FP32>(wpb, lds, out);
+    case MSG_INT8: return occ_t<MSG_INT8, TB>(wpb, lds, out);
+    case MSG_FP16: return occ_t<MSG_FP16, TB>(wpb, lds, out);
+    default: return occ_t<MSG_FP32, TB>(wpb, lds, out);
     }
+}
+
+hipError_t bp_max_blocks_per_cu(int msg, bool wide, int wpb, int lds, int *out) {
+    return wide ? occ_tb<ColTab32>(msg, wpb, lds, out) : occ_tb<ColTab16>(msg, wpb, lds, out);
 }
 
 }  // namespace lbp

@@ -12,6 +12,11 @@ constexpr int DEG = 8;
 // Column table: up to CDEG edge slots per column packed as u16 into one u64.
 constexpr int CDEG = 4;
 constexpr uint32_t NOPOS = 0xFFFFu;
+// Codes whose slot positions c*DEG+k do not fit 16 bits (m > 8191) keep them as
+// four u32 per column instead (all-ones for an unused entry).
+constexpr int MAX_M_NARROW = 8191;
+constexpr uint32_t NOPOS32 = 0xFFFFFFFFu;
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 // Magnitude sent by a degree-1 check (empty minimum) in float modes.
 constexpr float CAP_FLOAT = 1024.0f;
 // Hard-decision threshold in float modes: e = [lambda <= TAU].
@@ -27,11 +32,44 @@ struct DevCode {
     const uint16_t *cn_cols;  // [m*DEG]   column of each slot, NOPOS for padding
     const uint8_t *cn_deg;    // [m]       row weight
     const uint64_t *vn_tab;   // [n]       CDEG x u16 slot positions, ascending check, NOPOS-filled
+    const u32x4 *vn_tab4;     // [n]       the same as u32 (NOPOS32-filled) when the code is wide, else null
     const float *mu_f32;      // [n]       prior LLR rounded to fp32
     const float *mu_f16;      // [n]       prior LLR rounded to fp16 (held as float)
     const int32_t *mu_q;      // [n]       Int3.4 prior
     int32_t mu_q_uniform;     // the Int3.4 prior when every column has the same one, else INT32_MIN
 };
+
+// Access to a column's slot positions in either table layout: load(C, v)
+// returns the column's entry, pos(t, j) its j-th position (j < CDEG, ascending
+// check), NONE marks an unused entry.
+struct ColTab16 {
+    using T = uint64_t;
+    static constexpr uint32_t NONE = NOPOS;
+    __device__ static T load(const DevCode &C, int v) { return C.vn_tab[v]; }
+    __device__ static T empty() { return ~0ull; }
+    __device__ static uint32_t pos(T t, int j) { return (uint32_t)(t >> (16 * j)) & 0xFFFFu; }
+};
+struct ColTab32 {
+    using T = u32x4;
+    static constexpr uint32_t NONE = NOPOS32;
+    __device__ static T load(const DevCode &C, int v) { return C.vn_tab4[v]; }
+    __device__ static T empty() { return T{NOPOS32, NOPOS32, NOPOS32, NOPOS32}; }
+    __device__ static uint32_t pos(T t, int j) { return t[j]; }
+};
+
+// Slot positions of column v in either layout, NOPOS32 for an unused entry
+// (for paths where the layout test per column costs nothing that matters).
+__device__ inline u32x4 col_positions(const DevCode &C, int v) {
+    if (C.vn_tab4) return C.vn_tab4[v];
+    const uint64_t t = C.vn_tab[v];
+    u32x4 r;
+#pragma unroll
+    for (int j = 0; j < CDEG; ++j) {
+        const uint32_t p = (uint32_t)(t >> (16 * j)) & 0xFFFFu;
+        r[j] = p == NOPOS ? NOPOS32 : p;
+    }
+    return r;
+}
 
 struct BpParams {
     int32_t max_iter;
@@ -197,6 +235,7 @@ __device__ inline int64_t uniform64(int64_t x) {
 struct OsdArgs {
     int32_t m, n, mw, nw, mws;  // mws: G row stride in words (odd)
     const uint64_t *vn_tab;
+    const u32x4 *vn_tab4;       // wide codes (m > 8191): u32 slot positions, else null
     int32_t mode, order;
     const uint32_t *synd;
     uint32_t *corr;
@@ -264,7 +303,7 @@ hipError_t bp_int8_max_blocks_per_cu(int slots, int waves_per_block, int lds_byt
 
 hipError_t launch_reset(uint32_t *counters, int count, hipStream_t s);
 hipError_t launch_bp(int msg, const BpArgs &a, int blocks, int waves_per_block, hipStream_t s);
-hipError_t bp_max_blocks_per_cu(int msg, int waves_per_block, int lds_bytes, int *out);
+hipError_t bp_max_blocks_per_cu(int msg, bool wide, int waves_per_block, int lds_bytes, int *out);
 hipError_t launch_osd(const OsdArgs &a, int variant, int blocks, int threads, int lds_bytes, hipStream_t s);
 hipError_t launch_gather_list(const uint32_t *counters, const int32_t *fail_list, int64_t from, int32_t *out,
                               int64_t count, hipStream_t s);

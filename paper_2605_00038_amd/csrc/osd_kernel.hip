@@ -32,7 +32,6 @@ namespace {
 
 constexpr int OSD_THREADS = 1024;
 constexpr int OSD_WAVES = OSD_THREADS / 64;
-constexpr int MAX_ROWS_PER_THREAD = 8;  // m <= 8191
 
 __device__ __forceinline__ uint32_t orderable(float f) {
     uint32_t u = __float_as_uint(f);
@@ -88,9 +87,16 @@ __device__ __forceinline__ uint32_t xbit(const GView &G, int r, const int *rows,
     return x;
 }
 
-__device__ __forceinline__ int col_rows(const uint64_t *vn_tab, int col, int *rows) {
-    uint64_t tab = vn_tab[col];
+__device__ __forceinline__ int col_rows(const OsdArgs &a, int col, int *rows) {
     int nr = 0;
+    if (a.vn_tab4) {
+        const u32x4 tab = a.vn_tab4[col];
+#pragma unroll
+        for (int j = 0; j < CDEG; ++j)
+            if (tab[j] != NOPOS32) rows[nr++] = (int)(tab[j] / DEG);
+        return nr;
+    }
+    const uint64_t tab = a.vn_tab[col];
 #pragma unroll
     for (int j = 0; j < CDEG; ++j) {
         uint32_t p = (uint32_t)(tab >> (16 * j)) & 0xFFFFu;
@@ -258,7 +264,7 @@ __global__ __launch_bounds__(OSD_THREADS) void osd_lds_kernel(OsdArgs a) {
         for (int j = 0; j < n && rank < m; ++j) {
             const int col = perm[j];
             int rows[CDEG];
-            const int nr = col_rows(a.vn_tab, col, rows);
+            const int nr = col_rows(a, col, rows);
             const int slot = step % 3;
             if (tid == 0) red[(step + 1) % 3] = 0xFFFFFFFFu;
             uint32_t xm = 0, cand = 0xFFFFFFFFu;
@@ -318,7 +324,7 @@ __global__ __launch_bounds__(OSD_THREADS) void osd_lds_kernel(OsdArgs a) {
             unsigned long long best = (unsigned long long)scr[21] << 32;
             for (int ai = tid; ai < nt; ai += OSD_THREADS) {
                 int rows[CDEG];
-                int nr = col_rows(a.vn_tab, tl[ai], rows);
+                int nr = col_rows(a, tl[ai], rows);
                 unsigned long long cost = 1;
                 for (int r = 0; r < m; ++r) cost += sp[r] ^ xbit(G, r, rows, nr);
                 unsigned long long key = (cost << 32) | (unsigned long long)(1 + ai);
@@ -330,7 +336,7 @@ __global__ __launch_bounds__(OSD_THREADS) void osd_lds_kernel(OsdArgs a) {
                 int aa, bb;
                 pair_of(pi, w, aa, bb);
                 int ra[CDEG], rb[CDEG];
-                int na = col_rows(a.vn_tab, tl[aa], ra), nb = col_rows(a.vn_tab, tl[bb], rb);
+                int na = col_rows(a, tl[aa], ra), nb = col_rows(a, tl[bb], rb);
                 unsigned long long cost = 2;
                 for (int r = 0; r < m; ++r) cost += sp[r] ^ xbit(G, r, ra, na) ^ xbit(G, r, rb, nb);
                 unsigned long long key = (cost << 32) | (unsigned long long)(1 + nt + pi);
@@ -354,8 +360,8 @@ __global__ __launch_bounds__(OSD_THREADS) void osd_lds_kernel(OsdArgs a) {
         for (int ww = tid; ww < a.nw; ww += OSD_THREADS) cw[ww] = 0u;
         __syncthreads();
         int r0[CDEG], r1[CDEG], n0 = 0, n1 = 0;
-        if (t0 >= 0) n0 = col_rows(a.vn_tab, t0, r0);
-        if (t1 >= 0) n1 = col_rows(a.vn_tab, t1, r1);
+        if (t0 >= 0) n0 = col_rows(a, t0, r0);
+        if (t1 >= 0) n1 = col_rows(a, t1, r1);
         for (int r = tid; r < m; r += OSD_THREADS) {
             if (!piv[r]) continue;
             uint32_t e = sp[r];

@@ -5,6 +5,7 @@
 #include <climits>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -151,6 +152,7 @@ lbp_status lbp::serve_launch_osd(lbp_decoder d, const ServeRing &ring, const int
     o.nw = C->dc.nw;
     o.mws = d->mws;
     o.vn_tab = C->dc.vn_tab;
+    o.vn_tab4 = C->dc.vn_tab4;
     o.mode = d->prm.osd;
     o.order = d->prm.osd_order;
     o.synd = ring.syn;
@@ -199,7 +201,7 @@ lbp_status lbp_code_create(int32_t m, int32_t n, const int32_t *row_ptr, const i
     if (!out || !row_ptr || !col_idx || !p) return fail(LBP_EINVAL, "lbp_code_create: NULL argument");
     *out = nullptr;
     if (m < 1 || n < 1) return fail(LBP_EINVAL, "lbp_code_create: m and n must be >= 1");
-    if (m > 8191 || n > 65535) return fail(LBP_EUNSUPPORTED, "lbp_code_create: m <= 8191 and n <= 65535 supported");
+    if (m > 32767 || n > 65535) return fail(LBP_EUNSUPPORTED, "lbp_code_create: m <= 32767 and n <= 65535 supported");
     if (row_ptr[0] != 0) return fail(LBP_EINVAL, "lbp_code_create: row_ptr[0] must be 0");
     for (int c = 0; c < m; ++c) {
         int w = row_ptr[c + 1] - row_ptr[c];
@@ -218,6 +220,10 @@ lbp_status lbp_code_create(int32_t m, int32_t n, const int32_t *row_ptr, const i
     // column tables: slot positions c*DEG + k in ascending check order
     std::vector<int> cw(n, 0);
     std::vector<uint64_t> tab(n, ~0ull);
+    // wide layout (u32 positions) when c*DEG+k can exceed 16 bits, or on request
+    const char *force_wide = std::getenv("LBP_WIDE_COLUMN_TABLE");
+    const bool wide = m > MAX_M_NARROW || (force_wide && force_wide[0] == '1');
+    std::vector<uint32_t> tab4(wide ? (size_t)n * CDEG : 0, NOPOS32);
     std::vector<uint16_t> cols((size_t)m * DEG, (uint16_t)NOPOS);
     std::vector<uint8_t> deg(m);
     for (int c = 0; c < m; ++c) {
@@ -226,9 +232,12 @@ lbp_status lbp_code_create(int32_t m, int32_t n, const int32_t *row_ptr, const i
             int v = col_idx[e], k = e - row_ptr[c];
             cols[(size_t)c * DEG + k] = (uint16_t)v;
             if (cw[v] >= CDEG) return fail(LBP_EUNSUPPORTED, "lbp_code_create: column weight > 4 at column " + std::to_string(v));
-            uint64_t pos = (uint64_t)(c * DEG + k);
-            tab[v] &= ~(0xFFFFull << (16 * cw[v]));
-            tab[v] |= pos << (16 * cw[v]);
+            const uint32_t pos = (uint32_t)(c * DEG + k);
+            if (wide) tab4[(size_t)v * CDEG + cw[v]] = pos;
+            if (m <= MAX_M_NARROW) {  // the narrow table serves the kernels limited to m <= 1024 in any case
+                tab[v] &= ~(0xFFFFull << (16 * cw[v]));
+                tab[v] |= (uint64_t)pos << (16 * cw[v]);
+            }
             cw[v]++;
         }
     }
@@ -253,7 +262,8 @@ lbp_status lbp_code_create(int32_t m, int32_t n, const int32_t *row_ptr, const i
     hipGetDevice(&code->device);
     size_t o_cols = 0, o_deg = align256(o_cols + cols.size() * 2), o_tab = align256(o_deg + (size_t)m),
            o_m32 = align256(o_tab + (size_t)n * 8), o_m16 = align256(o_m32 + (size_t)n * 4),
-           o_mq = align256(o_m16 + (size_t)n * 4), total = align256(o_mq + (size_t)n * 4);
+           o_mq = align256(o_m16 + (size_t)n * 4), o_t4 = align256(o_mq + (size_t)n * 4),
+           total = align256(o_t4 + tab4.size() * 4);
     hipError_t e = hipMalloc(&code->dmem, total);
     if (e != hipSuccess) {
         delete code;
@@ -267,6 +277,7 @@ lbp_status lbp_code_create(int32_t m, int32_t n, const int32_t *row_ptr, const i
     std::memcpy(host.data() + o_m32, mu32.data(), (size_t)n * 4);
     std::memcpy(host.data() + o_m16, mu16.data(), (size_t)n * 4);
     std::memcpy(host.data() + o_mq, muq.data(), (size_t)n * 4);
+    if (wide) std::memcpy(host.data() + o_t4, tab4.data(), tab4.size() * 4);
     e = hipMemcpy(code->dmem, host.data(), total, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         hipFree(code->dmem);
@@ -281,6 +292,7 @@ lbp_status lbp_code_create(int32_t m, int32_t n, const int32_t *row_ptr, const i
     dc.cn_cols = (const uint16_t *)(b + o_cols);
     dc.cn_deg = (const uint8_t *)(b + o_deg);
     dc.vn_tab = (const uint64_t *)(b + o_tab);
+    dc.vn_tab4 = wide ? (const u32x4 *)(b + o_t4) : nullptr;
     dc.mu_f32 = (const float *)(b + o_m32);
     dc.mu_f16 = (const float *)(b + o_m16);
     dc.mu_q = (const int32_t *)(b + o_mq);
@@ -407,7 +419,7 @@ lbp_status lbp_decoder_create(lbp_code code, const lbp_params *prm, int64_t max_
         if (lds + 64 > lds_block) continue;  // plus the kernels' static LDS
         int bpc = 0;
         hipError_t oe = d->int8_slots ? bp_int8_max_blocks_per_cu(d->int8_slots, wpb, lds, &bpc)
-                                      : bp_max_blocks_per_cu(msgk, wpb, lds, &bpc);
+                                      : bp_max_blocks_per_cu(msgk, code->dc.vn_tab4 != nullptr, wpb, lds, &bpc);
         if (oe != hipSuccess) continue;
         if (bpc * wpb > best_waves) {
             best_waves = bpc * wpb;
@@ -523,6 +535,7 @@ static lbp_status run_pass(lbp_decoder d, int64_t n_work, const int32_t *work_li
         o.nw = C->dc.nw;
         o.mws = d->mws;
         o.vn_tab = C->dc.vn_tab;
+        o.vn_tab4 = C->dc.vn_tab4;
         o.mode = d->prm.osd;
         o.order = d->prm.osd_order;
         o.synd = syn;
@@ -718,6 +731,7 @@ lbp_status lbp_decode_baseline(lbp_decoder d, int64_t n_shots, uint64_t first_sh
         o.nw = C->dc.nw;
         o.mws = d->mws;
         o.vn_tab = C->dc.vn_tab;
+        o.vn_tab4 = C->dc.vn_tab4;
         o.mode = d->prm.osd;
         o.order = d->prm.osd_order;
         o.synd = syndromes;
