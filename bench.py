@@ -359,6 +359,12 @@ def run_experiment(args):
             for lot in (False, True):
                 grid.append((name, p, ("lottery_bp" if lot else "plain_bp") + "/osd_cs10",
                              prm(lottery=lot, osd=2, max_iter=args.exp_max_iter)))
+    elif args.experiment == "scale":       # the paper's code sizes: surface d up to 27 with the final read-out
+        for d in [int(x) for x in args.exp_distances.split(",")]:
+            for p in ps or [1e-3]:
+                for lot in (False, True):
+                    grid.append((f"surface{d}_phenpf", p, ("lottery_bp" if lot else "plain_bp") + "/osd0",
+                                 prm(lottery=lot, osd=1)))
     elif args.experiment == "flip":        # what the lottery negates: next messages or lambda itself
         for name in (sd9, args.exp_bb):
             for p in ps or [1e-3, 3e-3]:
@@ -381,7 +387,8 @@ def run_experiment(args):
             inputs[key] = (h, checker, err, syn)
             log(f"[{args.experiment}] sampled {name} p={p} shots={shots} in {time.perf_counter() - t0:.1f} s")
         h, checker, err, syn = inputs[key]
-        r = decode_point(torch, h, checker, p, err, syn, pr)
+        # device batches of at most ~2^28 columns keep OSD staging bounded and progress visible
+        r = decode_point(torch, h, checker, p, err, syn, pr, batch=max(4096, min(1 << 18, (1 << 28) // h.shape[1])))
         r.update(workload=name, p=p, label=label, max_iter=pr.max_iter, lottery=bool(pr.lottery),
                  lottery_skip=pr.lottery_skip, lottery_rule=pr.lottery_rule, flip=pr.flip, osd=pr.osd,
                  msg=pr.msg)
@@ -420,7 +427,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-ler", action="store_true")
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
-    ap.add_argument("--experiment", choices=["policies", "skip", "iters", "ler", "flip", "quant", "osdheavy"],
+    ap.add_argument("--experiment", choices=["policies", "skip", "iters", "ler", "flip", "quant", "osdheavy", "scale"],
                     help="run one of the paper's ablations instead of the benchmark (prints a JSON table)")
     ap.add_argument("--exp-shots", type=int, default=1 << 20, help="shots per experiment point")
     ap.add_argument("--exp-p", default="", help="comma-separated physical error rates (default: per experiment)")
@@ -429,6 +436,8 @@ def main():
                     help="workloads of the ler experiment")
     ap.add_argument("--exp-surface", default="surface9_phenpf", help="surface-code workload of the ablations")
     ap.add_argument("--exp-bb", default="bb144_phenpf", help="BB-code workload of the ablations")
+    ap.add_argument("--exp-distances", default="13,17,21,25,27",
+                    help="surface-code distances of the scale experiment (d rounds, final read-out)")
     ap.add_argument("--exp-out", default="", help="also write the experiment's JSON to this file")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (HBM counter calibration)")

@@ -223,6 +223,8 @@ __global__ __launch_bounds__(OSD_THREADS) void osd_lds_kernel(OsdArgs a) {
     uint16_t *pcol = (uint16_t *)q0;                 q0 += ((size_t)m * 2 + 15) & ~(size_t)15;
     uint8_t *piv = q0;                               q0 += ((size_t)m + 15) & ~(size_t)15;
     uint8_t *sp = q0;                                q0 += ((size_t)m + 15) & ~(size_t)15;
+    uint32_t *pl_w = (uint32_t *)q0;                 q0 += ((size_t)a.mw * 4 + 15) & ~(size_t)15;
+    uint32_t *pl_v = (uint32_t *)q0;                 q0 += ((size_t)a.mw * 4 + 15) & ~(size_t)15;
     uint32_t *cw = (uint32_t *)q0;                   q0 += ((size_t)a.nw * 4 + 15) & ~(size_t)15;
     uint32_t *red = (uint32_t *)q0;                  q0 += 16 * 4;
     int *scr = (int *)q0;                            q0 += 32 * 4;
@@ -257,9 +259,12 @@ __global__ __launch_bounds__(OSD_THREADS) void osd_lds_kernel(OsdArgs a) {
         }
         for (int j = tid; j < n; j += OSD_THREADS) isb[j] = 0;
         if (tid < 3) red[tid] = 0xFFFFFFFFu;
+        if (tid == 3) red[4] = red[5] = 0u;
         __syncthreads();
 
-        // ---- 3. Gauss-Jordan in sorted column order
+        // ---- 3. Gauss-Jordan in sorted column order.  G stays sparse (a row combines
+        // few checks), so a pivot step first lists the pivot row's non-zero words and
+        // every updated row touches only those.
         int rank = 0, step = 0;
         for (int j = 0; j < n && rank < m; ++j) {
             const int col = perm[j];
@@ -280,6 +285,18 @@ __global__ __launch_bounds__(OSD_THREADS) void osd_lds_kernel(OsdArgs a) {
             const uint32_t pv = red[slot];
             ++step;
             if (pv == 0xFFFFFFFFu) continue;
+            uint32_t *cnt = &red[4 + (rank & 1)];  // the other counter is reset for the next pivot step
+            for (int w = tid; w < mw; w += OSD_THREADS) {
+                const uint32_t v = G.at((int)pv, w);
+                if (v) {
+                    const uint32_t i = atomicAdd(cnt, 1u);
+                    pl_w[i] = (uint32_t)w;
+                    pl_v[i] = v;
+                }
+            }
+            if (tid == 0) red[4 + ((rank + 1) & 1)] = 0u;
+            __syncthreads();
+            const int nl = (int)*cnt;
             k = 0;
             const uint8_t spv = sp[pv];
             for (int r = tid; r < m; r += OSD_THREADS, ++k) {
@@ -287,7 +304,7 @@ __global__ __launch_bounds__(OSD_THREADS) void osd_lds_kernel(OsdArgs a) {
                     piv[r] = 1;
                     pcol[r] = (uint16_t)col;
                 } else if ((xm >> k) & 1u) {
-                    for (int w = 0; w < mw; ++w) G.at(r, w) ^= G.at((int)pv, w);
+                    for (int i = 0; i < nl; ++i) G.at(r, (int)pl_w[i]) ^= pl_v[i];
                     sp[r] ^= spv;
                 }
             }
@@ -636,8 +653,9 @@ int osd_block_bytes(int m, int n, int lds_limit, int *variant, int *mws, int *so
         return (int)(al((size_t)P * 8) + common + al(32 * vb) + 32 * 4 + 16 * 8);
     }
     *threads = OSD_THREADS;
-    size_t rows = al((size_t)m * 2) + al((size_t)m) * 2 + al((size_t)((n + 31) / 32) * 4) + 16 * 4 + 32 * 4 + 16;
-    size_t rest = common + al((size_t)m * 2) + al((size_t)m) * 2;
+    const size_t plist = 2 * al((size_t)mw * 4);  // the pivot row's non-zero words
+    size_t rows = al((size_t)m * 2) + al((size_t)m) * 2 + plist + al((size_t)((n + 31) / 32) * 4) + 16 * 4 + 32 * 4 + 16;
+    size_t rest = common + al((size_t)m * 2) + al((size_t)m) * 2 + plist;
     size_t gb = (size_t)m * s * 4;
     size_t with_g = al(gb > (size_t)P * 8 ? gb : (size_t)P * 8) + rest;
     if ((int64_t)with_g <= lds_limit) {
