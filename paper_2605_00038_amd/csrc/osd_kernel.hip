@@ -225,6 +225,7 @@ __global__ __launch_bounds__(OSD_THREADS) void osd_lds_kernel(OsdArgs a) {
     uint8_t *sp = q0;                                q0 += ((size_t)m + 15) & ~(size_t)15;
     uint32_t *pl_w = (uint32_t *)q0;                 q0 += ((size_t)a.mw * 4 + 15) & ~(size_t)15;
     uint32_t *pl_v = (uint32_t *)q0;                 q0 += ((size_t)a.mw * 4 + 15) & ~(size_t)15;
+    unsigned long long *Yq = (unsigned long long *)q0; q0 += ((size_t)((m + 63) >> 6) * 8 + 15) & ~(size_t)15;
     uint32_t *cw = (uint32_t *)q0;                   q0 += ((size_t)a.nw * 4 + 15) & ~(size_t)15;
     uint32_t *red = (uint32_t *)q0;                  q0 += 16 * 4;
     int *scr = (int *)q0;                            q0 += 32 * 4;
@@ -323,27 +324,44 @@ __global__ __launch_bounds__(OSD_THREADS) void osd_lds_kernel(OsdArgs a) {
             continue;
         }
 
-        // ---- 4. OSD-CS candidate sweep
+        // ---- 4. OSD-CS candidate sweep on 64-row ballots of G's columns:
+        // Bq[q*m + c] holds column c of G over rows 64q..64q+63, Yq[q] those rows of s',
+        // so a candidate's cost is a popcount per 64 rows.
         int t0 = -1, t1 = -1;
         if (a.mode == OSD_CS) {
             const int nt = list_nonbasis(isb, perm, n, tl, scr);
-            int w0 = 0;
-            for (int r = tid; r < m; r += OSD_THREADS) w0 += sp[r];
-            w0 = wave_sum(w0);
-            if (tid == 0) {
-                *best64 = ~0ull;
-                scr[21] = 0;
+            const int nq = (m + 63) >> 6, krows = (m + OSD_THREADS - 1) / OSD_THREADS;
+            unsigned long long *Bq = (unsigned long long *)(a.gscratch + (size_t)blockIdx.x * a.scratch_words +
+                                                            a.cs_offset_words);
+            for (int k = 0; k < krows; ++k) {
+                const int r = k * OSD_THREADS + tid, q = r >> 6;  // q is wave-uniform
+                const uint64_t yb = __ballot(r < m && sp[r]);
+                if (lane == 0 && q < nq) Yq[q] = yb;
+                for (int w = 0; w < mw; ++w) {
+                    const uint32_t v = r < m ? G.at(r, w) : 0u;
+                    unsigned long long mine = 0;
+                    for (int b = 0; b < 32; ++b) {
+                        const unsigned long long bal = __ballot((v >> b) & 1u);
+                        mine = lane == b ? bal : mine;
+                    }
+                    if (q < nq && lane < 32 && 32 * w + lane < m) Bq[(size_t)q * m + 32 * w + lane] = mine;
+                }
             }
+            if (tid == 0) *best64 = ~0ull;
             __syncthreads();
-            if (lane == 0) atomicAdd(&scr[21], w0);
-            __syncthreads();
+            uint32_t cost0 = 0;
+            for (int q = 0; q < nq; ++q) cost0 += __popcll(Yq[q]);
             // OSD-0 candidate: cost |s'|, enumeration index 0
-            unsigned long long best = (unsigned long long)scr[21] << 32;
+            unsigned long long best = (unsigned long long)cost0 << 32;
             for (int ai = tid; ai < nt; ai += OSD_THREADS) {
                 int rows[CDEG];
-                int nr = col_rows(a, tl[ai], rows);
+                const int nr = col_rows(a, tl[ai], rows);
                 unsigned long long cost = 1;
-                for (int r = 0; r < m; ++r) cost += sp[r] ^ xbit(G, r, rows, nr);
+                for (int q = 0; q < nq; ++q) {
+                    unsigned long long x = Yq[q];
+                    for (int t = 0; t < nr; ++t) x ^= Bq[(size_t)q * m + rows[t]];
+                    cost += __popcll(x);
+                }
                 unsigned long long key = (cost << 32) | (unsigned long long)(1 + ai);
                 best = key < best ? key : best;
             }
@@ -353,9 +371,14 @@ __global__ __launch_bounds__(OSD_THREADS) void osd_lds_kernel(OsdArgs a) {
                 int aa, bb;
                 pair_of(pi, w, aa, bb);
                 int ra[CDEG], rb[CDEG];
-                int na = col_rows(a, tl[aa], ra), nb = col_rows(a, tl[bb], rb);
+                const int na = col_rows(a, tl[aa], ra), nb = col_rows(a, tl[bb], rb);
                 unsigned long long cost = 2;
-                for (int r = 0; r < m; ++r) cost += sp[r] ^ xbit(G, r, ra, na) ^ xbit(G, r, rb, nb);
+                for (int q = 0; q < nq; ++q) {
+                    unsigned long long x = Yq[q];
+                    for (int t = 0; t < na; ++t) x ^= Bq[(size_t)q * m + ra[t]];
+                    for (int t = 0; t < nb; ++t) x ^= Bq[(size_t)q * m + rb[t]];
+                    cost += __popcll(x);
+                }
                 unsigned long long key = (cost << 32) | (unsigned long long)(1 + nt + pi);
                 best = key < best ? key : best;
             }
@@ -653,7 +676,7 @@ int osd_block_bytes(int m, int n, int lds_limit, int *variant, int *mws, int *so
         return (int)(al((size_t)P * 8) + common + al(32 * vb) + 32 * 4 + 16 * 8);
     }
     *threads = OSD_THREADS;
-    const size_t plist = 2 * al((size_t)mw * 4);  // the pivot row's non-zero words
+    const size_t plist = 2 * al((size_t)mw * 4) + al((size_t)((m + 63) / 64) * 8);  // pivot row words, s' ballots
     size_t rows = al((size_t)m * 2) + al((size_t)m) * 2 + plist + al((size_t)((n + 31) / 32) * 4) + 16 * 4 + 32 * 4 + 16;
     size_t rest = common + al((size_t)m * 2) + al((size_t)m) * 2 + plist;
     size_t gb = (size_t)m * s * 4;
@@ -672,15 +695,17 @@ int osd_block_bytes(int m, int n, int lds_limit, int *variant, int *mws, int *so
     return (int)rows;
 }
 
-size_t osd_scratch_bytes(int variant, int m, int n, int mws, int sort_p) {
+size_t osd_scratch_bytes(int variant, int m, int n, int mws, int sort_p, int cs) {
     auto a256 = [](size_t x) { return (x + 255) & ~(size_t)255; };
     auto al = [](size_t x) { return (x + 15) & ~(size_t)15; };
     if (variant > 0) return (size_t)16 * m * 8;       // per-wave column ballots
-    if (variant == -1) return a256((size_t)m * mws * 4);  // G
+    size_t b = 0;
+    if (variant == -1) b = a256((size_t)m * mws * 4);  // G
     if (variant == -2)                                 // G, sort keys, lambda lo, order, non-basis list, flags
-        return a256(a256((size_t)m * mws * 4) + a256((size_t)sort_p * 8) + al((size_t)n * 4) + 2 * al((size_t)n * 2) +
-                    al((size_t)n));
-    return 0;
+        b = a256(a256((size_t)m * mws * 4) + a256((size_t)sort_p * 8) + al((size_t)n * 4) + 2 * al((size_t)n * 2) +
+                 al((size_t)n));
+    if (cs) b += a256((size_t)((m + 63) / 64) * m * 8);  // OSD-CS: 64-row ballots of G's columns
+    return b;
 }
 
 template <class K>

@@ -245,13 +245,14 @@ def test_osd_staging_grows_for_high_invoke_rate():
     assert (f1.cpu().numpy()[idx] == o["flags"]).all()
 
 
-@pytest.mark.parametrize("name,p,shots", [("surface21_phenpf", 0.002, 64), ("surface25_phenpf", 0.0015, 48)])
-def test_large_surface_codes(name, p, shots):
+@pytest.mark.parametrize("name,p,shots,osd", [("surface21_phenpf", 0.002, 64, 1), ("surface25_phenpf", 0.0015, 48, 1),
+                                               ("surface21_phenpf", 0.002, 32, 2)])
+def test_large_surface_codes(name, p, shots, osd):
     """The paper's scale on the general kernel: surface d=21 (4840 x 13881) and d=25
     (8112 x 23425) over d rounds with the final read-out, Int3.4 bit-exact against
-    the oracle, OSD-0 with G in global memory."""
+    the oracle, OSD-0 or OSD-CS(10) with G in global memory."""
     h, e, syn = batch(name, p, shots, 1301)
-    prm = _params(msg=2, max_iter=100, lottery=True, osd=1, seed=5)
+    prm = _params(msg=2, max_iter=100, lottery=True, osd=osd, osd_order=10, seed=5)
     g = gpu_decode(h, p, prm, syn, want_llr=True)
     o = oracle.decode(h, p, oracle_params(prm), syn, want_llr=True, n_threads=8)
     assert ((g["flags"] & 2) != 0).sum() >= 8
