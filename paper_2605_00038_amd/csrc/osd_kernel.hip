@@ -194,7 +194,7 @@ __device__ __forceinline__ void pair_of(int pi, int w, int &aa, int &bb) {
     bb = aa + 1 + rem;
 }
 
-__global__ __launch_bounds__(OSD_THREADS) void osd_lds_kernel(OsdArgs a) {
+__global__ __launch_bounds__(OSD_THREADS, 8) void osd_lds_kernel(OsdArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int m = a.m, n = a.n, tid = threadIdx.x, lane = tid & 63;
     const int P = a.sort_p;
