@@ -387,8 +387,9 @@ def run_experiment(args):
             inputs[key] = (h, checker, err, syn)
             log(f"[{args.experiment}] sampled {name} p={p} shots={shots} in {time.perf_counter() - t0:.1f} s")
         h, checker, err, syn = inputs[key]
-        # device batches of at most ~2^28 columns keep OSD staging bounded and progress visible
-        r = decode_point(torch, h, checker, p, err, syn, pr, batch=max(4096, min(1 << 18, (1 << 28) // h.shape[1])))
+        # above 16K columns (surface d >= 25), batches of ~2^28 columns keep OSD staging bounded and progress visible
+        nb = 1 << 18 if h.shape[1] <= 16384 else max(4096, (1 << 28) // h.shape[1])
+        r = decode_point(torch, h, checker, p, err, syn, pr, batch=nb)
         r.update(workload=name, p=p, label=label, max_iter=pr.max_iter, lottery=bool(pr.lottery),
                  lottery_skip=pr.lottery_skip, lottery_rule=pr.lottery_rule, flip=pr.flip, osd=pr.osd,
                  msg=pr.msg)

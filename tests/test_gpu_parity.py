@@ -38,6 +38,9 @@ INT8_CASES = [
     # H_st with the noiseless final read-out: weight-1 rows, every measurement column of weight 2
     ("surface9_phenpf", 0.003, 2000, 1007, dict(max_iter=100, lottery=True, osd=2, osd_order=10, seed=12)),
     ("bb144_phenpf", 0.004, 1000, 1008, dict(max_iter=100, lottery=True, osd=1, seed=13)),
+    # unrotated (planar) surface code, the layout of Table II: 720 x 1953 (d=9), 4896 x 13889 (d=17)
+    ("usurface9_phenpf", 0.004, 2000, 1009, dict(max_iter=100, lottery=True, osd=2, osd_order=10, seed=14)),
+    ("usurface17_phenpf", 0.002, 96, 1011, dict(max_iter=100, lottery=True, osd=1, seed=15)),
 ]
 
 

@@ -116,3 +116,25 @@ def test_pack_roundtrip_and_chunk_independence():
     e_all = sample.sample_errors(25, 0.1, 70000, seed=5)
     e_part = sample.sample_errors(25, 0.1, 1000, seed=5, first_shot=65000)
     assert (e_all[65000:66000] != e_part).nnz == 0
+
+
+def test_unrotated_surface_code():
+    """Planar (unrotated) surface code: checks commute, one logical qubit, weights
+    <= 4 / <= 2, d = 3 is the paper's Fig. 4 matrix, and its distance is 3 by
+    enumeration of every Z-type vector."""
+    for d in (3, 5, 7, 9):
+        hx, hz = codes.unrotated_surface_x(d), codes.unrotated_surface_z(d)
+        n = d * d + (d - 1) ** 2
+        assert hx.shape == (d * (d - 1), n) and hz.shape == (d * (d - 1), n)
+        assert not ((hx @ hz.T).toarray() % 2).any()
+        assert n - codes.gf2_rank(hx) - codes.gf2_rank(hz) == 1
+        assert hx.sum(axis=1).max() == 4 and hx.sum(axis=0).max() == 2
+    assert (codes.unrotated_surface_x(3) != codes.worked_example_h()).nnz == 0
+    hx, hz = codes.unrotated_surface_x(3), codes.unrotated_surface_z(3)
+    xs = ((np.arange(1 << 13)[:, None] >> np.arange(13)) & 1).astype(np.int64)
+    in_ker = ~((xs @ hx.toarray().T.astype(np.int64)) % 2).any(axis=1)
+    rank_z = codes.gf2_rank(hz)
+    logical = [x for x in xs[in_ker] if x.any() and codes.gf2_rank(np.vstack([hz.toarray(), x])) > rank_z]
+    assert min(int(x.sum()) for x in logical) == 3
+    h, hc, r = codes.workload_matrices("usurface9_phenpf")
+    assert h.shape == (10 * 72, 9 * (145 + 72)) and r == 9 and hc.shape == (72, 145)

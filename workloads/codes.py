@@ -145,6 +145,25 @@ def unrotated_surface_x(d: int) -> sp.csr_matrix:
     return _csr(rows, n)
 
 
+def unrotated_surface_z(d: int) -> sp.csr_matrix:
+    """Z-check matrix of the same unrotated surface code, (d-1)d x (d^2 + (d-1)^2):
+    one check per face between vertex rows y and y+1 and vertex columns x and x+1
+    (two horizontal edges, and the vertical edges that are not on the left or
+    right boundary)."""
+    nh = d * d
+    n = nh + (d - 1) * (d - 1)
+    rows = []
+    for y in range(d - 1):
+        for x in range(d):
+            qs = [y * d + x, (y + 1) * d + x]
+            if x >= 1:
+                qs.append(nh + y * (d - 1) + (x - 1))
+            if x <= d - 2:
+                qs.append(nh + y * (d - 1) + x)
+            rows.append(sorted(qs))
+    return _csr(rows, n)
+
+
 def worked_example_h() -> sp.csr_matrix:
     """The 6 x 13 X-check matrix of the paper's Fig. 4 ([[13,1,3]] surface code).
 
@@ -229,6 +248,11 @@ def workload_matrices(name: str) -> tuple[sp.csr_matrix, sp.csr_matrix, int]:
         d = int(name[len("surface"):-len("_phenpf")])
         hx, hz = rotated_surface(d)
         return spacetime(hz, d, final_round=True), hx, d
+    if name.startswith("usurface") and (name.endswith("_phen") or name.endswith("_phenpf")):
+        # unrotated (planar) surface code, X checks decoded, d rounds
+        final = name.endswith("_phenpf")
+        d = int(name[len("usurface"):name.index("_")])
+        return spacetime(unrotated_surface_x(d), d, final_round=final), unrotated_surface_z(d), d
     if name == "bb144_cc":
         hx, hz = bb144()
         return hx, hz, 1
