@@ -1,4 +1,6 @@
-// Batched Lottery BP on gfx950: one wavefront decodes one shot at a time.
+// Batched Lottery BP on gfx950: one wavefront decodes one shot at a time, or,
+// for codes whose per-shot state leaves room for few shots per CU, one
+// workgroup decodes one shot (the GRP variant of bp_kernel).
 //
 // Normalized min-sum BP (Algorithm 1) with the lottery policy (Algorithm 3)
 // and the delayed-syndrome trick of Sec. IV-B: the unsatisfied set of
@@ -11,7 +13,7 @@
 // outputs.  A wave never waits for another wave, so early-terminating shots do
 // not idle the SIMD behind a slow one.
 //
-// Per-wave LDS (the shot's whole state):
+// Per-wave (per-workgroup in GRP) LDS, the shot's whole state:
 //   E  [m][DEG] messages, in place: alpha (V2C) before the check-node half,
 //               beta (C2V) after it; padding slots hold a sentinel that never
 //               wins a minimum and is never read by a column.
@@ -230,10 +232,10 @@ __device__ __forceinline__ uint64_t quantized_abs(const Lam<typename Fmt<MSG>::A
 
 template <int MSG>
 __device__ void cn_half(const DevCode &C, const BpParams &P, int i, typename Fmt<MSG>::T *E,
-                        const uint32_t *S, int lane) {
+                        const uint32_t *S, int t0, int tn) {
     using F = Fmt<MSG>;
     using T = typename F::T;
-    for (int c = lane; c < C.m; c += 64) {
+    for (int c = t0; c < C.m; c += tn) {
         T a[DEG];
         T *row = E + c * DEG;
 #pragma unroll
@@ -412,11 +414,11 @@ __device__ int lottery_select(const DevCode &C, const BpParams &P, uint64_t seed
 
 template <int MSG, class TB>
 __device__ void vn_half(const DevCode &C, const BpParams &P, int fv, bool last, typename Fmt<MSG>::T *E,
-                        uint32_t *SH, uint32_t *EH, int lane, float *llr_row, float *stage) {
+                        uint32_t *SH, uint32_t *EH, int lane, int w0, int wn, float *llr_row, float *stage) {
     using F = Fmt<MSG>;
     using A = typename F::A;
     const int nvs = (C.n + 63) >> 6;
-    for (int vs = 0; vs < nvs; ++vs) {
+    for (int vs = w0; vs < nvs; vs += wn) {
         const int v = vs * 64 + lane;
         const bool valid = v < C.n;
         const typename TB::T tab = valid ? TB::load(C, v) : TB::empty();
@@ -490,31 +492,62 @@ __device__ void vn_half(const DevCode &C, const BpParams &P, int fv, bool last, 
 
 // ------------------------------------------------------------------ kernel
 
-template <int MSG, class TB>
+// GRP = false: each wave of the block decodes its own shot (per-wave LDS state).
+// GRP = true: the whole block decodes one shot.  The check-node half splits the
+// checks over the block's threads, the variable-node half the 64-column groups
+// over its waves, block barriers separate the halves, and wave 0 runs the
+// lottery and takes work items.  This is for large codes, whose per-shot state
+// leaves room for only a few shots per CU: one wave per shot would leave the CU
+// with too few waves to hide LDS and memory latency.
+template <int MSG, class TB, bool GRP>
 __global__ __launch_bounds__(1024) void bp_kernel(BpArgs a) {
     using F = Fmt<MSG>;
     using T = typename F::T;
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ uint32_t claim_lock;  // serving: the wave of this block that polls the ring
+    __shared__ uint32_t claim_lock;  // serving, a shot per wave: the wave of this block that polls the ring
+    __shared__ int64_t grp_item;     // GRP: the block's current work item, -1 when there is none
+    __shared__ int32_t grp_fv;       // GRP: the lottery's column of this iteration
+    __shared__ uint32_t grp_q;       // GRP: the shot's failure-list position
     const DevCode &C = a.code;
     const BpParams &P = a.prm;
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
+    const int nwv = (int)(blockDim.x >> 6);
+    // work split: thread t0 of tn over checks and words, wave w0 of wn over 64-column groups
+    const int t0 = GRP ? (int)threadIdx.x : lane, tn = GRP ? (int)blockDim.x : 64;
+    const int w0 = GRP ? wv : 0, wn = GRP ? nwv : 1;
+    auto sync = [] {
+        if constexpr (GRP) __syncthreads();
+        else wave_sync();
+    };
     if (threadIdx.x == 0) claim_lock = 0u;
     __syncthreads();
-    unsigned char *base = smem + (size_t)wv * a.wave_bytes;
+    unsigned char *base = smem + (GRP ? (size_t)0 : (size_t)wv * a.wave_bytes);
     T *E = (T *)base;
     size_t off = ((size_t)C.m * DEG * sizeof(T) + 15) & ~(size_t)15;
     uint32_t *S = (uint32_t *)(base + off);
     uint32_t *SH0 = S + C.mw;
     uint32_t *SH1 = SH0 + C.mw;
     uint32_t *EH = SH1 + C.mw;
-    const int gwave = blockIdx.x * (blockDim.x >> 6) + wv;
-    float *stage = a.stage + (size_t)gwave * 2 * C.n;
+    const int slot = GRP ? (int)blockIdx.x : (int)blockIdx.x * nwv + wv;  // shot slot: its staging row
+    float *stage = a.stage + (size_t)slot * 2 * C.n;
 
     for (;;) {
         int64_t item = 0;
-        if (a.ring) {
+        if constexpr (GRP) {
+            if (threadIdx.x == 0) {
+                if (a.ring) {
+                    grp_item = serve_claim(*a.ring);
+                } else {
+                    const uint32_t it0 = atomicAdd(&a.counters[0], 1u);
+                    grp_item = (int64_t)it0 < a.n_work ? (int64_t)it0 : -1;
+                }
+            }
+            __syncthreads();
+            item = grp_item;
+            if (item < 0) break;
+            if (a.ring) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");  // the host's writes of this ring slot
+        } else if (a.ring) {
             item = serve_claim_block(*a.ring, &claim_lock, lane);
             if (item < 0) break;
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");  // the host's writes of this ring slot
@@ -536,18 +569,18 @@ __global__ __launch_bounds__(1024) void bp_kernel(BpArgs a) {
 
         // padding bits of the last word are ignored (they could otherwise name checks >= m)
         const uint32_t last_mask = (C.m & 31) ? ((1u << (C.m & 31)) - 1u) : ~0u;
-        for (int w = lane; w < C.mw; w += 64) {
+        for (int w = t0; w < C.mw; w += tn) {
             uint32_t x = syn_row[w];
             S[w] = w == C.mw - 1 ? (x & last_mask) : x;
         }
         // alpha^(0) = mu (Algorithm 1 initialisation); padding slots get the sentinel.
-        for (int c = lane; c < C.m; c += 64) {
+        for (int c = t0; c < C.m; c += tn) {
             const int deg = C.cn_deg[c];
 #pragma unroll
             for (int k = 0; k < DEG; ++k)
                 if (k >= deg) E[c * DEG + k] = F::pad();
         }
-        for (int v = lane; v < C.n; v += 64) {
+        for (int v = t0; v < C.n; v += tn) {
             const typename TB::T tab = TB::load(C, v);
             const T mu = F::sat(F::mu(C, v));
 #pragma unroll
@@ -556,26 +589,40 @@ __global__ __launch_bounds__(1024) void bp_kernel(BpArgs a) {
                 if (p != TB::NONE) E[p] = mu;
             }
         }
-        wave_sync();
+        sync();
 
         int it = 0;
         bool converged = false;
         for (int i = 0; i < P.max_iter; ++i) {
             uint32_t *SHc = (i & 1) ? SH1 : SH0;
             uint32_t *SHp = (i & 1) ? SH0 : SH1;
-            cn_half<MSG>(C, P, i, E, S, lane);
-            wave_sync();
+            cn_half<MSG>(C, P, i, E, S, t0, tn);
+            sync();
             int fv = -1;
-            if (P.lottery && i >= P.skip && i <= P.max_iter - 2) fv = lottery_select<MSG, TB>(C, P, seed, shot_id, i, E, S, SHp, lane);
-            for (int w = lane; w < C.mw; w += 64) SHc[w] = 0u;
-            wave_sync();
+            const bool lot = P.lottery && i >= P.skip && i <= P.max_iter - 2;
+            if constexpr (GRP) {
+                if (lot && wv == 0) {
+                    const int f = lottery_select<MSG, TB>(C, P, seed, shot_id, i, E, S, SHp, lane);
+                    if (lane == 0) grp_fv = f;
+                }
+            } else if (lot) {
+                fv = lottery_select<MSG, TB>(C, P, seed, shot_id, i, E, S, SHp, lane);
+            }
+            for (int w = t0; w < C.mw; w += tn) SHc[w] = 0u;
+            sync();
+            if constexpr (GRP) {
+                if (lot) fv = grp_fv;
+            }
             const bool last = i == P.max_iter - 1;
-            vn_half<MSG, TB>(C, P, fv, last, E, SHc, EH, lane, llr_row, stage);
-            wave_sync();
+            vn_half<MSG, TB>(C, P, fv, last, E, SHc, EH, lane, w0, wn, llr_row, stage);
+            sync();
             bool mism = false;
-            for (int w = lane; w < C.mw; w += 64) mism |= SHc[w] != S[w];
+            for (int w = t0; w < C.mw; w += tn) mism |= SHc[w] != S[w];
             it = i + 1;
-            if (__ballot(mism) == 0ull) {
+            bool differs;
+            if constexpr (GRP) differs = __syncthreads_or(mism) != 0;
+            else differs = __ballot(mism) != 0ull;
+            if (!differs) {
                 converged = true;
                 break;
             }
@@ -584,37 +631,52 @@ __global__ __launch_bounds__(1024) void bp_kernel(BpArgs a) {
         if (a.ring) {
             const ServeRing &R = *a.ring;
             uint32_t *corr_row = R.corr + shot * C.nw;
-            for (int w = lane; w < C.nw; w += 64) corr_row[w] = EH[w];
+            for (int w = t0; w < C.nw; w += tn) corr_row[w] = EH[w];
             const bool osd = !converged && P.osd != OSD_NONE;
             if (osd) {
                 float *dst = R.llr + shot * 2 * C.n;
-                for (int v = lane; v < 2 * C.n; v += 64) dst[v] = stage[v];
+                for (int v = t0; v < 2 * C.n; v += tn) dst[v] = stage[v];
             }
-            if (lane == 0) {
+            if (t0 == 0) {
                 R.flags[shot] = converged ? (uint8_t)FLAG_CONVERGED : osd ? (uint8_t)(FLAG_OSD | FLAG_OSD_PENDING) : 0;
                 R.iters[shot] = it;
             }
-            serve_publish(R, item, lane);
-            wave_sync();
+            if constexpr (GRP) {
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");  // every thread's stores, before the entry
+                __syncthreads();
+                if (wv == 0) serve_publish(R, item, lane);
+            } else {
+                serve_publish(R, item, lane);
+            }
+            sync();
             continue;
         }
-        for (int w = lane; w < C.nw; w += 64) a.corr[shot * C.nw + w] = EH[w];
+        for (int w = t0; w < C.nw; w += tn) a.corr[shot * C.nw + w] = EH[w];
         const uint8_t fl = converged ? (uint8_t)FLAG_CONVERGED : (uint8_t)(P.osd != OSD_NONE ? FLAG_OSD : 0);
-        if (lane == 0) {
+        if (t0 == 0) {
             a.flags[shot] = fl;
             if (a.iters) a.iters[shot] = it;
         }
         if (!converged && P.osd != OSD_NONE) {
             uint32_t q = 0;
-            if (lane == 0) q = atomicAdd(&a.counters[1], 1u);
-            q = __builtin_amdgcn_readfirstlane(q);
-            if (lane == 0) a.fail_list[q] = (int32_t)shot;
+            if constexpr (GRP) {
+                if (threadIdx.x == 0) {
+                    grp_q = atomicAdd(&a.counters[1], 1u);
+                    a.fail_list[grp_q] = (int32_t)shot;
+                }
+                __syncthreads();
+                q = grp_q;
+            } else {
+                if (lane == 0) q = atomicAdd(&a.counters[1], 1u);
+                q = __builtin_amdgcn_readfirstlane(q);
+                if (lane == 0) a.fail_list[q] = (int32_t)shot;
+            }
             if ((int64_t)q < a.fail_cap) {
                 float *dst = a.fail_llr + (size_t)q * 2 * C.n;
-                for (int v = lane; v < 2 * C.n; v += 64) dst[v] = stage[v];
+                for (int v = t0; v < 2 * C.n; v += tn) dst[v] = stage[v];
             }
         }
-        wave_sync();
+        sync();
     }
 }
 
@@ -654,48 +716,53 @@ hipError_t launch_gather_list(const uint32_t *counters, const int32_t *fail_list
     return hipGetLastError();
 }
 
-template <int MSG, class TB>
+template <int MSG, class TB, bool GRP>
 static hipError_t launch_t(const BpArgs &a, int blocks, int wpb, hipStream_t s) {
-    size_t lds = (size_t)a.wave_bytes * wpb;
-    hipError_t e = hipFuncSetAttribute((const void *)bp_kernel<MSG, TB>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)lds);
+    size_t lds = GRP ? (size_t)a.wave_bytes : (size_t)a.wave_bytes * wpb;
+    hipError_t e = hipFuncSetAttribute((const void *)bp_kernel<MSG, TB, GRP>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((bp_kernel<MSG, TB>), dim3(blocks), dim3(64 * wpb), lds, s, a);
+    hipLaunchKernelGGL((bp_kernel<MSG, TB, GRP>), dim3(blocks), dim3(64 * wpb), lds, s, a);
     return hipGetLastError();
 }
 
-template <class TB>
+template <class TB, bool GRP>
 static hipError_t launch_tb(int msg, const BpArgs &a, int blocks, int wpb, hipStream_t s) {
     switch (msg) {
-    case MSG_INT8: return launch_t<MSG_INT8, TB>(a, blocks, wpb, s);
-    case MSG_FP16: return launch_t<MSG_FP16, TB>(a, blocks, wpb, s);
-    default: return launch_t<MSG_FP32, TB>(a, blocks, wpb, s);
+    case MSG_INT8: return launch_t<MSG_INT8, TB, GRP>(a, blocks, wpb, s);
+    case MSG_FP16: return launch_t<MSG_FP16, TB, GRP>(a, blocks, wpb, s);
+    default: return launch_t<MSG_FP32, TB, GRP>(a, blocks, wpb, s);
     }
 }
 
 hipError_t launch_bp(int msg, const BpArgs &a, int blocks, int wpb, hipStream_t s) {
-    return a.code.vn_tab4 ? launch_tb<ColTab32>(msg, a, blocks, wpb, s) : launch_tb<ColTab16>(msg, a, blocks, wpb, s);
+    if (a.group)
+        return a.code.vn_tab4 ? launch_tb<ColTab32, true>(msg, a, blocks, wpb, s)
+                              : launch_tb<ColTab16, true>(msg, a, blocks, wpb, s);
+    return a.code.vn_tab4 ? launch_tb<ColTab32, false>(msg, a, blocks, wpb, s)
+                          : launch_tb<ColTab16, false>(msg, a, blocks, wpb, s);
 }
 
-template <int MSG, class TB>
+template <int MSG, class TB, bool GRP>
 static hipError_t occ_t(int wpb, int lds, int *out) {
     hipError_t e =
-        hipFuncSetAttribute((const void *)bp_kernel<MSG, TB>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+        hipFuncSetAttribute((const void *)bp_kernel<MSG, TB, GRP>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     if (e != hipSuccess) return e;
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(out, bp_kernel<MSG, TB>, 64 * wpb, (size_t)lds);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(out, bp_kernel<MSG, TB, GRP>, 64 * wpb, (size_t)lds);
 }
 
-template <class TB>
+template <class TB, bool GRP>
 static hipError_t occ_tb(int msg, int wpb, int lds, int *out) {
     switch (msg) {
-    case MSG_INT8: return occ_t<MSG_INT8, TB>(wpb, lds, out);
-    case MSG_FP16: return occ_t<MSG_FP16, TB>(wpb, lds, out);
-    default: return occ_t<MSG_FP32, TB>(wpb, lds, out);
+    case MSG_INT8: return occ_t<MSG_INT8, TB, GRP>(wpb, lds, out);
+    case MSG_FP16: return occ_t<MSG_FP16, TB, GRP>(wpb, lds, out);
+    default: return occ_t<MSG_FP32, TB, GRP>(wpb, lds, out);
     }
 }
 
-hipError_t bp_max_blocks_per_cu(int msg, bool wide, int wpb, int lds, int *out) {
-    return wide ? occ_tb<ColTab32>(msg, wpb, lds, out) : occ_tb<ColTab16>(msg, wpb, lds, out);
+hipError_t bp_max_blocks_per_cu(int msg, bool wide, bool group, int wpb, int lds, int *out) {
+    if (group) return wide ? occ_tb<ColTab32, true>(msg, wpb, lds, out) : occ_tb<ColTab16, true>(msg, wpb, lds, out);
+    return wide ? occ_tb<ColTab32, false>(msg, wpb, lds, out) : occ_tb<ColTab16, false>(msg, wpb, lds, out);
 }
 
 }  // namespace lbp

@@ -138,7 +138,8 @@ struct BpArgs {
     float *fail_llr;            // [fail_cap][2n]: lambda as hi[n], lo[n] (value = hi + lo)
     int64_t fail_cap;
     float *stage;               // [grid waves][2n]
-    int32_t wave_bytes;         // LDS bytes per wave
+    int32_t wave_bytes;         // LDS bytes of one shot's state
+    int32_t group;              // nonzero: a block decodes one shot (bp_kernel), else each wave its own
     const ServeRing *ring;      // device copy; non-null: take items from the ring, not the batch arrays
 };
 
@@ -304,7 +305,7 @@ hipError_t bp_int8_max_blocks_per_cu(int slots, int waves_per_block, int lds_byt
 
 hipError_t launch_reset(uint32_t *counters, int count, hipStream_t s);
 hipError_t launch_bp(int msg, const BpArgs &a, int blocks, int waves_per_block, hipStream_t s);
-hipError_t bp_max_blocks_per_cu(int msg, bool wide, int waves_per_block, int lds_bytes, int *out);
+hipError_t bp_max_blocks_per_cu(int msg, bool wide, bool group, int waves_per_block, int lds_bytes, int *out);
 hipError_t launch_osd(const OsdArgs &a, int variant, int blocks, int threads, int lds_bytes, hipStream_t s);
 hipError_t launch_gather_list(const uint32_t *counters, const int32_t *fail_list, int64_t from, int32_t *out,
                               int64_t count, hipStream_t s);

@@ -76,7 +76,7 @@ struct lbp_decoder_s {
     int32_t *d_muq = nullptr;
     int64_t max_batch = 0;
     BpParams bp{};
-    int wpb = 1, bp_blocks = 1, wave_bytes = 0, int8_slots = 0, table_bytes = 0;
+    int wpb = 1, bp_blocks = 1, wave_bytes = 0, int8_slots = 0, table_bytes = 0, group = 0;
     int osd_blocks = 0, osd_lds = 0, osd_variant = 0, osd_threads = 1024, mws = 1, sort_p = 1;
     int64_t fail_cap = 0;
     bool fail_cap_pinned = false;  // set by lbp_decoder_set_osd_capacity: never grown
@@ -136,6 +136,7 @@ lbp_status lbp::serve_launch_bp(lbp_decoder d, const ServeRing *ring_dev, uint32
     a.ring = ring_dev;
     a.stage = d->d_stage;
     a.wave_bytes = d->wave_bytes;
+    a.group = d->group;
     blocks = std::max(1, std::min(blocks, d->bp_blocks));  // d_stage holds bp_blocks * wpb waves
     HIPCHK(d->int8_slots ? launch_bp_int8(d->int8_slots, a, blocks, d->wpb, s)
                          : launch_bp(d->msgk, a, blocks, d->wpb, s));
@@ -414,18 +415,44 @@ lbp_status lbp_decoder_create(lbp_code code, const lbp_params *prm, int64_t max_
     d->table_bytes = d->int8_slots ? bp_int8_table_bytes(d->int8_slots) : 0;
     if (d->table_bytes + d->wave_bytes > lds_block)
         return cleanup_fail(LBP_EUNSUPPORTED, "lbp_decoder_create: per-shot state exceeds LDS");
+    // A workgroup per shot when a shot per wave would leave a CU with fewer than 8
+    // waves (large codes): the smallest group of 2..16 waves that brings the CU
+    // to 16.  LBP_BP_GROUP=g (read here) forces groups of g waves, for tests.
+    const bool wide = code->dc.vn_tab4 != nullptr;
+    int group = 1;
+    if (!d->int8_slots) {
+        const int per_cu = (lds_block - 64) / d->wave_bytes;
+        const char *force = std::getenv("LBP_BP_GROUP");
+        const int fg = force ? std::atoi(force) : 0;
+        if (fg > 0) {
+            group = fg >= 16 ? 16 : fg >= 8 ? 8 : fg >= 4 ? 4 : fg >= 2 ? 2 : 1;
+        } else if (per_cu < 8) {
+            group = 2;
+            while (group < 16 && per_cu * group < 16) group *= 2;
+        }
+    }
+    d->group = group > 1;
     int best_waves = 0;
-    for (int wpb : {16, 12, 8, 4, 2, 1}) {
-        int lds = d->table_bytes + d->wave_bytes * wpb;
-        if (lds + 64 > lds_block) continue;  // plus the kernels' static LDS
+    if (d->group) {
         int bpc = 0;
-        hipError_t oe = d->int8_slots ? bp_int8_max_blocks_per_cu(d->int8_slots, wpb, lds, &bpc)
-                                      : bp_max_blocks_per_cu(msgk, code->dc.vn_tab4 != nullptr, wpb, lds, &bpc);
-        if (oe != hipSuccess) continue;
-        if (bpc * wpb > best_waves) {
-            best_waves = bpc * wpb;
-            d->wpb = wpb;
+        if (bp_max_blocks_per_cu(msgk, wide, true, group, d->wave_bytes, &bpc) == hipSuccess && bpc > 0) {
+            best_waves = bpc * group;
+            d->wpb = group;
             d->bp_blocks = bpc * ncu;
+        }
+    } else {
+        for (int wpb : {16, 12, 8, 4, 2, 1}) {
+            int lds = d->table_bytes + d->wave_bytes * wpb;
+            if (lds + 64 > lds_block) continue;  // plus the kernels' static LDS
+            int bpc = 0;
+            hipError_t oe = d->int8_slots ? bp_int8_max_blocks_per_cu(d->int8_slots, wpb, lds, &bpc)
+                                          : bp_max_blocks_per_cu(msgk, wide, false, wpb, lds, &bpc);
+            if (oe != hipSuccess) continue;
+            if (bpc * wpb > best_waves) {
+                best_waves = bpc * wpb;
+                d->wpb = wpb;
+                d->bp_blocks = bpc * ncu;
+            }
         }
     }
     if (best_waves == 0) return cleanup_fail(LBP_EDEVICE, "lbp_decoder_create: no feasible BP launch shape");
@@ -519,7 +546,9 @@ static lbp_status run_pass(lbp_decoder d, int64_t n_work, const int32_t *work_li
     a.fail_cap = d->fail_cap;
     a.stage = d->d_stage;
     a.wave_bytes = d->wave_bytes;
-    int64_t need_blocks = (n_work + d->wpb - 1) / d->wpb;
+    a.group = d->group;
+    const int shots_per_block = d->group ? 1 : d->wpb;
+    int64_t need_blocks = (n_work + shots_per_block - 1) / shots_per_block;
     int blocks = (int)std::min<int64_t>(d->bp_blocks, std::max<int64_t>(1, need_blocks));
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (d->timing && (e0 = take_event(d)) && (e1 = take_event(d))) HIPCHK(hipEventRecord(e0, s));
