@@ -194,9 +194,10 @@ __device__ __forceinline__ void pair_of(int pi, int w, int &aa, int &bb) {
     bb = aa + 1 + rem;
 }
 
-__global__ __launch_bounds__(OSD_THREADS, 8) void osd_lds_kernel(OsdArgs a) {
+__global__ __launch_bounds__(1024, 8) void osd_lds_kernel(OsdArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int m = a.m, n = a.n, tid = threadIdx.x, lane = tid & 63;
+    const int nth = (int)blockDim.x;  // 512 or 1024; a thread's rows fit one 32-bit mask (m <= 32 nth)
     const int P = a.sort_p;
     unsigned char *gblk = (unsigned char *)(a.gscratch + (size_t)blockIdx.x * a.scratch_words);
     unsigned char *q0, *c0;  // next free byte of LDS, and of the per-column arrays
@@ -231,6 +232,12 @@ __global__ __launch_bounds__(OSD_THREADS, 8) void osd_lds_kernel(OsdArgs a) {
     int *scr = (int *)q0;                            q0 += 32 * 4;
     unsigned long long *best64 = (unsigned long long *)q0;
 
+    // G in global memory: bit b of occ[w * mw + t] is set when word w of row 32t+b
+    // may be non-zero (a superset, never cleared), so the column test loads only
+    // G's words that can be non-zero; G stays sparse on the codes that need this.
+    uint32_t *occ = a.g_in_lds ? nullptr : (uint32_t *)(gblk + a.occ_offset_words * 4);
+    const int krows = (m + nth - 1) / nth;
+
     GView G;
     G.g = a.g_in_lds ? (uint32_t *)smem : (uint32_t *)gblk;
     G.m = m;
@@ -249,16 +256,22 @@ __global__ __launch_bounds__(OSD_THREADS, 8) void osd_lds_kernel(OsdArgs a) {
 
         // ---- 2. G = I, s' = s
         const int mw = a.mw;
-        for (size_t idx = tid; idx < (size_t)m * mw; idx += OSD_THREADS) {
+        for (size_t idx = tid; idx < (size_t)m * mw; idx += nth) {
             int r = (int)(idx / mw), w = (int)(idx % mw);
             G.at(r, w) = (w == (r >> 5)) ? (1u << (r & 31)) : 0u;
         }
+        if (occ)
+            for (int idx = tid; idx < mw * mw; idx += nth) {
+                const int w = idx / mw, t = idx % mw;
+                const int valid = m - 32 * t;  // rows of word t that exist
+                occ[idx] = w != t ? 0u : valid >= 32 ? ~0u : (1u << valid) - 1u;
+            }
         const uint32_t *sw = a.synd + shot * a.mw;
-        for (int r = tid; r < m; r += OSD_THREADS) {
+        for (int r = tid; r < m; r += nth) {
             sp[r] = (uint8_t)((sw[r >> 5] >> (r & 31)) & 1u);
             piv[r] = 0;
         }
-        for (int j = tid; j < n; j += OSD_THREADS) isb[j] = 0;
+        for (int j = tid; j < n; j += nth) isb[j] = 0;
         if (tid < 3) red[tid] = 0xFFFFFFFFu;
         if (tid == 3) red[4] = red[5] = 0u;
         __syncthreads();
@@ -275,8 +288,17 @@ __global__ __launch_bounds__(OSD_THREADS, 8) void osd_lds_kernel(OsdArgs a) {
             if (tid == 0) red[(step + 1) % 3] = 0xFFFFFFFFu;
             uint32_t xm = 0, cand = 0xFFFFFFFFu;
             int k = 0;
-            for (int r = tid; r < m; r += OSD_THREADS, ++k) {
-                uint32_t x = xbit(G, r, rows, nr);
+            for (int r = tid; r < m; r += nth, ++k) {
+                uint32_t x = 0;
+                if (occ) {
+                    for (int q = 0; q < nr; ++q) {
+                        const int c = rows[q];
+                        if ((occ[(size_t)(c >> 5) * mw + (r >> 5)] >> (r & 31)) & 1u)
+                            x ^= (G.at(r, c >> 5) >> (c & 31)) & 1u;
+                    }
+                } else {
+                    x = xbit(G, r, rows, nr);
+                }
                 xm |= x << k;
                 if (x && !piv[r] && (uint32_t)r < cand) cand = (uint32_t)r;
             }
@@ -287,7 +309,7 @@ __global__ __launch_bounds__(OSD_THREADS, 8) void osd_lds_kernel(OsdArgs a) {
             ++step;
             if (pv == 0xFFFFFFFFu) continue;
             uint32_t *cnt = &red[4 + (rank & 1)];  // the other counter is reset for the next pivot step
-            for (int w = tid; w < mw; w += OSD_THREADS) {
+            for (int w = tid; w < mw; w += nth) {
                 const uint32_t v = G.at((int)pv, w);
                 if (v) {
                     const uint32_t i = atomicAdd(cnt, 1u);
@@ -298,15 +320,28 @@ __global__ __launch_bounds__(OSD_THREADS, 8) void osd_lds_kernel(OsdArgs a) {
             if (tid == 0) red[4 + ((rank + 1) & 1)] = 0u;
             __syncthreads();
             const int nl = (int)*cnt;
-            k = 0;
             const uint8_t spv = sp[pv];
-            for (int r = tid; r < m; r += OSD_THREADS, ++k) {
-                if ((uint32_t)r == pv) {
+            for (k = 0; k < krows; ++k) {  // uniform trip count: the occupancy update ballots
+                const int r = k * nth + tid;
+                const bool upd = r < m && (uint32_t)r != pv && ((xm >> k) & 1u);
+                if (r < m && (uint32_t)r == pv) {
                     piv[r] = 1;
                     pcol[r] = (uint16_t)col;
-                } else if ((xm >> k) & 1u) {
+                } else if (upd) {
                     for (int i = 0; i < nl; ++i) G.at(r, (int)pl_w[i]) ^= pl_v[i];
                     sp[r] ^= spv;
+                }
+                if (occ) {
+                    // this wave's 64 rows are row words t0, t0+1: one lane per (pivot word, half)
+                    const uint64_t um = __ballot(upd);
+                    if (um) {
+                        const int t0 = (r - lane) >> 5;
+                        for (int i = lane; i < 2 * nl; i += 64) {
+                            const uint32_t msk = (uint32_t)(um >> (32 * (i & 1)));
+                            const int t = t0 + (i & 1);
+                            if (msk && t < mw) occ[(size_t)pl_w[i >> 1] * mw + t] |= msk;
+                        }
+                    }
                 }
             }
             if (tid == 0) isb[j] = 1;
@@ -316,7 +351,7 @@ __global__ __launch_bounds__(OSD_THREADS, 8) void osd_lds_kernel(OsdArgs a) {
 
         // ---- consistency: a row with no pivot reduced to 0 = s'_r
         int bad = 0;
-        for (int r = tid; r < m; r += OSD_THREADS) bad |= (!piv[r] && sp[r]);
+        for (int r = tid; r < m; r += nth) bad |= (!piv[r] && sp[r]);
         bad = __syncthreads_or(bad);
         if (bad) {
             if (tid == 0) a.flags[shot] = (uint8_t)(FLAG_OSD | FLAG_OSD_INCONSISTENT);
@@ -330,11 +365,11 @@ __global__ __launch_bounds__(OSD_THREADS, 8) void osd_lds_kernel(OsdArgs a) {
         int t0 = -1, t1 = -1;
         if (a.mode == OSD_CS) {
             const int nt = list_nonbasis(isb, perm, n, tl, scr);
-            const int nq = (m + 63) >> 6, krows = (m + OSD_THREADS - 1) / OSD_THREADS;
+            const int nq = (m + 63) >> 6, krows = (m + nth - 1) / nth;
             unsigned long long *Bq = (unsigned long long *)(a.gscratch + (size_t)blockIdx.x * a.scratch_words +
                                                             a.cs_offset_words);
             for (int k = 0; k < krows; ++k) {
-                const int r = k * OSD_THREADS + tid, q = r >> 6;  // q is wave-uniform
+                const int r = k * nth + tid, q = r >> 6;  // q is wave-uniform
                 const uint64_t yb = __ballot(r < m && sp[r]);
                 if (lane == 0 && q < nq) Yq[q] = yb;
                 for (int w = 0; w < mw; ++w) {
@@ -353,7 +388,7 @@ __global__ __launch_bounds__(OSD_THREADS, 8) void osd_lds_kernel(OsdArgs a) {
             for (int q = 0; q < nq; ++q) cost0 += __popcll(Yq[q]);
             // OSD-0 candidate: cost |s'|, enumeration index 0
             unsigned long long best = (unsigned long long)cost0 << 32;
-            for (int ai = tid; ai < nt; ai += OSD_THREADS) {
+            for (int ai = tid; ai < nt; ai += nth) {
                 int rows[CDEG];
                 const int nr = col_rows(a, tl[ai], rows);
                 unsigned long long cost = 1;
@@ -367,7 +402,7 @@ __global__ __launch_bounds__(OSD_THREADS, 8) void osd_lds_kernel(OsdArgs a) {
             }
             const int w = a.order < nt ? a.order : nt;
             const int npairs = w * (w - 1) / 2;
-            for (int pi = tid; pi < npairs; pi += OSD_THREADS) {
+            for (int pi = tid; pi < npairs; pi += nth) {
                 int aa, bb;
                 pair_of(pi, w, aa, bb);
                 int ra[CDEG], rb[CDEG];
@@ -397,12 +432,12 @@ __global__ __launch_bounds__(OSD_THREADS, 8) void osd_lds_kernel(OsdArgs a) {
         }
 
         // ---- 5. e_S = s' + G H_T t on the basis, t on the rest; scatter to columns
-        for (int ww = tid; ww < a.nw; ww += OSD_THREADS) cw[ww] = 0u;
+        for (int ww = tid; ww < a.nw; ww += nth) cw[ww] = 0u;
         __syncthreads();
         int r0[CDEG], r1[CDEG], n0 = 0, n1 = 0;
         if (t0 >= 0) n0 = col_rows(a, t0, r0);
         if (t1 >= 0) n1 = col_rows(a, t1, r1);
-        for (int r = tid; r < m; r += OSD_THREADS) {
+        for (int r = tid; r < m; r += nth) {
             if (!piv[r]) continue;
             uint32_t e = sp[r];
             if (t0 >= 0) e ^= xbit(G, r, r0, n0);
@@ -417,7 +452,7 @@ __global__ __launch_bounds__(OSD_THREADS, 8) void osd_lds_kernel(OsdArgs a) {
             if (t1 >= 0) atomicOr(&cw[t1 >> 5], 1u << (t1 & 31));
         }
         __syncthreads();
-        for (int ww = tid; ww < a.nw; ww += OSD_THREADS) a.corr[shot * a.nw + ww] = cw[ww];
+        for (int ww = tid; ww < a.nw; ww += nth) a.corr[shot * a.nw + ww] = cw[ww];
         if (tid == 0) a.flags[shot] = (uint8_t)FLAG_OSD;  // clears a serving ring's pending bit
         __syncthreads();
     }
@@ -692,20 +727,32 @@ int osd_block_bytes(int m, int n, int lds_limit, int *variant, int *mws, int *so
         return (int)(al((size_t)P * 8) + rest);
     }
     *variant = -2;      // G and the per-column arrays in global memory
+    // latency-bound steps: half-size blocks put more shots in flight per CU (LDS permitting)
+    if (m <= 8 * OSD_THREADS) *threads = OSD_THREADS / 2;
     return (int)rows;
 }
 
-size_t osd_scratch_bytes(int variant, int m, int n, int mws, int sort_p, int cs) {
+size_t osd_scratch_layout(int variant, int m, int n, int mws, int sort_p, int cs, size_t *occ_off, size_t *cs_off) {
     auto a256 = [](size_t x) { return (x + 255) & ~(size_t)255; };
     auto al = [](size_t x) { return (x + 15) & ~(size_t)15; };
+    const size_t mw = (size_t)(m + 31) / 32;
+    *occ_off = *cs_off = 0;
     if (variant > 0) return (size_t)16 * m * 8;       // per-wave column ballots
     size_t b = 0;
     if (variant == -1) b = a256((size_t)m * mws * 4);  // G
     if (variant == -2)                                 // G, sort keys, lambda lo, order, non-basis list, flags
         b = a256(a256((size_t)m * mws * 4) + a256((size_t)sort_p * 8) + al((size_t)n * 4) + 2 * al((size_t)n * 2) +
                  al((size_t)n));
+    *occ_off = b;
+    if (variant < 0) b += a256(mw * mw * 4);           // occupancy of G's words
+    *cs_off = b;
     if (cs) b += a256((size_t)((m + 63) / 64) * m * 8);  // OSD-CS: 64-row ballots of G's columns
     return b;
+}
+
+size_t osd_scratch_bytes(int variant, int m, int n, int mws, int sort_p, int cs) {
+    size_t o, c;
+    return osd_scratch_layout(variant, m, n, mws, sort_p, cs, &o, &c);
 }
 
 template <class K>

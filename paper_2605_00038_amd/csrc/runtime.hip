@@ -167,8 +167,13 @@ lbp_status lbp::serve_launch_osd(lbp_decoder d, const ServeRing &ring, const int
     o.sort_p = d->sort_p;
     o.g_in_lds = d->osd_variant == 0;
     o.cols_global = d->osd_variant == -2;
-    o.scratch_words = (int64_t)(osd_scratch_bytes(d->osd_variant, C->m, C->n, d->mws, d->sort_p, d->prm.osd == LBP_OSD_CS) / 4);
-    o.cs_offset_words = (int64_t)(osd_scratch_bytes(d->osd_variant, C->m, C->n, d->mws, d->sort_p, 0) / 4);
+    {
+        size_t occ_off = 0, cs_off = 0;
+        o.scratch_words = (int64_t)(osd_scratch_layout(d->osd_variant, C->m, C->n, d->mws, d->sort_p,
+                                                       d->prm.osd == LBP_OSD_CS, &occ_off, &cs_off) / 4);
+        o.occ_offset_words = (int64_t)(occ_off / 4);
+        o.cs_offset_words = (int64_t)(cs_off / 4);
+    }
     o.has_lo = d->msgk == LBP_MSG_FP32;
     o.llr_by_shot = 1;
     blocks = std::max(1, std::min(blocks, d->osd_blocks));  // d_gscratch holds osd_blocks blocks
@@ -580,8 +585,13 @@ static lbp_status run_pass(lbp_decoder d, int64_t n_work, const int32_t *work_li
         o.sort_p = d->sort_p;
         o.g_in_lds = d->osd_variant == 0;
         o.cols_global = d->osd_variant == -2;
-        o.scratch_words = (int64_t)(osd_scratch_bytes(d->osd_variant, C->m, C->n, d->mws, d->sort_p, d->prm.osd == LBP_OSD_CS) / 4);
-    o.cs_offset_words = (int64_t)(osd_scratch_bytes(d->osd_variant, C->m, C->n, d->mws, d->sort_p, 0) / 4);
+        {
+        size_t occ_off = 0, cs_off = 0;
+        o.scratch_words = (int64_t)(osd_scratch_layout(d->osd_variant, C->m, C->n, d->mws, d->sort_p,
+                                                       d->prm.osd == LBP_OSD_CS, &occ_off, &cs_off) / 4);
+        o.occ_offset_words = (int64_t)(occ_off / 4);
+        o.cs_offset_words = (int64_t)(cs_off / 4);
+    }
         o.has_lo = d->msgk == LBP_MSG_FP32;
         hipEvent_t f0 = nullptr, f1 = nullptr;
         if (d->timing && (f0 = take_event(d)) && (f1 = take_event(d))) HIPCHK(hipEventRecord(f0, s));
@@ -777,8 +787,13 @@ lbp_status lbp_decode_baseline(lbp_decoder d, int64_t n_shots, uint64_t first_sh
         o.sort_p = d->sort_p;
         o.g_in_lds = d->osd_variant == 0;
         o.cols_global = d->osd_variant == -2;
-        o.scratch_words = (int64_t)(osd_scratch_bytes(d->osd_variant, C->m, C->n, d->mws, d->sort_p, d->prm.osd == LBP_OSD_CS) / 4);
-    o.cs_offset_words = (int64_t)(osd_scratch_bytes(d->osd_variant, C->m, C->n, d->mws, d->sort_p, 0) / 4);
+        {
+        size_t occ_off = 0, cs_off = 0;
+        o.scratch_words = (int64_t)(osd_scratch_layout(d->osd_variant, C->m, C->n, d->mws, d->sort_p,
+                                                       d->prm.osd == LBP_OSD_CS, &occ_off, &cs_off) / 4);
+        o.occ_offset_words = (int64_t)(occ_off / 4);
+        o.cs_offset_words = (int64_t)(cs_off / 4);
+    }
         o.has_lo = 1;
         HIPCHK(launch_osd(o, d->osd_variant, d->osd_blocks, d->osd_threads, d->osd_lds, s));
     }
