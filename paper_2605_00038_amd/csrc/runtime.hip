@@ -420,9 +420,11 @@ lbp_status lbp_decoder_create(lbp_code code, const lbp_params *prm, int64_t max_
     d->table_bytes = d->int8_slots ? bp_int8_table_bytes(d->int8_slots) : 0;
     if (d->table_bytes + d->wave_bytes > lds_block)
         return cleanup_fail(LBP_EUNSUPPORTED, "lbp_decoder_create: per-shot state exceeds LDS");
-    // A workgroup per shot when a shot per wave would leave a CU with fewer than 8
-    // waves (large codes): the smallest group of 2..16 waves that brings the CU
-    // to 16.  LBP_BP_GROUP=g (read here) forces groups of g waves, for tests.
+    // A workgroup per shot when a shot per wave would leave a CU with fewer than 32
+    // waves (the per-shot state fits fewer than 32 times in LDS): the smallest
+    // group of 2..16 waves that brings the CU to 32 (measured best or within 10 %
+    // on BB144 FP16/FP32, surface d=13..27 and BB288 in Int3.4).
+    // LBP_BP_GROUP=g (read here) forces groups of g waves, for tests.
     const bool wide = code->dc.vn_tab4 != nullptr;
     int group = 1;
     if (!d->int8_slots) {
@@ -431,9 +433,9 @@ lbp_status lbp_decoder_create(lbp_code code, const lbp_params *prm, int64_t max_
         const int fg = force ? std::atoi(force) : 0;
         if (fg > 0) {
             group = fg >= 16 ? 16 : fg >= 8 ? 8 : fg >= 4 ? 4 : fg >= 2 ? 2 : 1;
-        } else if (per_cu < 8) {
+        } else if (per_cu < 32) {
             group = 2;
-            while (group < 16 && per_cu * group < 16) group *= 2;
+            while (group < 16 && per_cu * group < 32) group *= 2;
         }
     }
     d->group = group > 1;
