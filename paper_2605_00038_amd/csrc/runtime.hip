@@ -448,7 +448,7 @@ lbp_status lbp_decoder_create(lbp_code code, const lbp_params *prm, int64_t max_
             d->bp_blocks = bpc * ncu;
         }
     } else {
-        for (int wpb : {16, 12, 8, 4, 2, 1}) {
+        for (int wpb : {16, 15, 14, 13, 12, 11, 10, 9, 8, 7, 6, 5, 4, 3, 2, 1}) {
             int lds = d->table_bytes + d->wave_bytes * wpb;
             if (lds + 64 > lds_block) continue;  // plus the kernels' static LDS
             int bpc = 0;
