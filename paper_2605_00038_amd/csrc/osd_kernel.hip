@@ -342,11 +342,18 @@ __global__ __launch_bounds__(1024, 8) void osd_lds_kernel(OsdArgs a) {
                             if (msk && t < mw) occ[(size_t)pl_w[i >> 1] * mw + t] |= msk;
                         }
                     }
+                    // the wave reads these occupancy words itself in the next column test
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
                 }
             }
             if (tid == 0) isb[j] = 1;
             ++rank;
-            __syncthreads();
+            // No barrier here: a thread only ever updates and tests its own rows, and
+            // everything shared (the pivot row, the word list, red[]) is next touched
+            // after the next step's first barrier, which every thread reaches only
+            // once its updates of this step are done.
         }
 
         // ---- consistency: a row with no pivot reduced to 0 = s'_r

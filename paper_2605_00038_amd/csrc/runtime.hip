@@ -422,9 +422,11 @@ lbp_status lbp_decoder_create(lbp_code code, const lbp_params *prm, int64_t max_
         return cleanup_fail(LBP_EUNSUPPORTED, "lbp_decoder_create: per-shot state exceeds LDS");
     // A workgroup per shot when a shot per wave would leave a CU with fewer than 32
     // waves (the per-shot state fits fewer than 32 times in LDS): the smallest
-    // group of 2..16 waves that brings the CU to 32 (measured best or within 10 %
-    // on BB144 FP16/FP32, surface d=13..27 and BB288 in Int3.4).
-    // LBP_BP_GROUP=g (read here) forces groups of g waves, for tests.
+    // group of 2..8 waves that brings the CU to 32, or 16 when only one shot fits.
+    // Measured best or within 10 % on BB144 FP16/FP32, BB288 and surface d=13..27
+    // in Int3.4; larger groups cost more in barriers than they gain in waves once
+    // they leave fewer shots per CU.  LBP_BP_GROUP=g (read here) forces groups of
+    // g waves, for tests.
     const bool wide = code->dc.vn_tab4 != nullptr;
     int group = 1;
     if (!d->int8_slots) {
@@ -435,7 +437,8 @@ lbp_status lbp_decoder_create(lbp_code code, const lbp_params *prm, int64_t max_
             group = fg >= 16 ? 16 : fg >= 8 ? 8 : fg >= 4 ? 4 : fg >= 2 ? 2 : 1;
         } else if (per_cu < 32) {
             group = 2;
-            while (group < 16 && per_cu * group < 32) group *= 2;
+            while (group < 8 && per_cu * group < 32) group *= 2;
+            if (per_cu <= 1) group = 16;
         }
     }
     d->group = group > 1;
