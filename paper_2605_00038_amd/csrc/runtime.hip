@@ -458,7 +458,11 @@ lbp_status lbp_decoder_create(lbp_code code, const lbp_params *prm, int64_t max_
             hipError_t oe = d->int8_slots ? bp_int8_max_blocks_per_cu(d->int8_slots, wpb, lds, &bpc)
                                           : bp_max_blocks_per_cu(msgk, wide, false, wpb, lds, &bpc);
             if (oe != hipSuccess) continue;
-            if (bpc * wpb > best_waves) {
+            // most resident waves; among equals a multiple of 4 waves per block, whose
+            // waves spread evenly over the CU's four SIMDs (10-wave blocks of a 20-wave
+            // shape ran 15-25 % slower than 4-wave ones on BB144 code capacity)
+            const bool even = wpb % 4 == 0, best_even = d->wpb % 4 == 0;
+            if (bpc * wpb > best_waves || (bpc * wpb == best_waves && even && !best_even)) {
                 best_waves = bpc * wpb;
                 d->wpb = wpb;
                 d->bp_blocks = bpc * ncu;
