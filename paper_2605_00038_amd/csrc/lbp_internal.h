@@ -253,7 +253,7 @@ struct OsdArgs {
     int32_t cols_global;        // G-in-global variant: the per-column arrays live in the block's scratch too
     int64_t scratch_words;      // per-block stride of gscratch in 32-bit words
     int64_t cs_offset_words;    // OSD-CS column ballots in the block's scratch (kernels for m > 1024)
-    int64_t occ_offset_words;   // occupancy words of G in the block's scratch (G in global memory)
+    int64_t occ_offset_words;   // occupancy words of G in the block's scratch (G in global memory), -1: none
 };
 
 // Global-memory comparison path (one launch per half-iteration).

@@ -32,6 +32,7 @@ namespace {
 
 constexpr int OSD_THREADS = 1024;
 constexpr int OSD_WAVES = OSD_THREADS / 64;
+constexpr int OSD_OCC_MIN_M = 4096;  // smallest m whose global-G OSD keeps an occupancy mask
 
 __device__ __forceinline__ uint32_t orderable(float f) {
     uint32_t u = __float_as_uint(f);
@@ -235,7 +236,7 @@ __global__ __launch_bounds__(1024, 8) void osd_lds_kernel(OsdArgs a) {
     // G in global memory: bit b of occ[w * mw + t] is set when word w of row 32t+b
     // may be non-zero (a superset, never cleared), so the column test loads only
     // G's words that can be non-zero; G stays sparse on the codes that need this.
-    uint32_t *occ = a.g_in_lds ? nullptr : (uint32_t *)(gblk + a.occ_offset_words * 4);
+    uint32_t *occ = a.g_in_lds || a.occ_offset_words < 0 ? nullptr : (uint32_t *)(gblk + a.occ_offset_words * 4);
     const int krows = (m + nth - 1) / nth;
 
     GView G;
@@ -750,8 +751,13 @@ size_t osd_scratch_layout(int variant, int m, int n, int mws, int sort_p, int cs
     if (variant == -2)                                 // G, sort keys, lambda lo, order, non-basis list, flags
         b = a256(a256((size_t)m * mws * 4) + a256((size_t)sort_p * 8) + al((size_t)n * 4) + 2 * al((size_t)n * 2) +
                  al((size_t)n));
-    *occ_off = b;
-    if (variant < 0) b += a256(mw * mw * 4);           // occupancy of G's words
+    // occupancy of G's words: it pays from ~4096 checks on (surface d=21: 9 % faster
+    // OSD, d=25-27: 1.5x) and costs ~8 % at d=17, where G's columns are short
+    *occ_off = (size_t)-1;
+    if (variant < 0 && m >= OSD_OCC_MIN_M) {
+        *occ_off = b;
+        b += a256(mw * mw * 4);
+    }
     *cs_off = b;
     if (cs) b += a256((size_t)((m + 63) / 64) * m * 8);  // OSD-CS: 64-row ballots of G's columns
     return b;

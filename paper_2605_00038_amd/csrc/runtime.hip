@@ -171,7 +171,7 @@ lbp_status lbp::serve_launch_osd(lbp_decoder d, const ServeRing &ring, const int
         size_t occ_off = 0, cs_off = 0;
         o.scratch_words = (int64_t)(osd_scratch_layout(d->osd_variant, C->m, C->n, d->mws, d->sort_p,
                                                        d->prm.osd == LBP_OSD_CS, &occ_off, &cs_off) / 4);
-        o.occ_offset_words = (int64_t)(occ_off / 4);
+        o.occ_offset_words = occ_off == (size_t)-1 ? -1 : (int64_t)(occ_off / 4);
         o.cs_offset_words = (int64_t)(cs_off / 4);
     }
     o.has_lo = d->msgk == LBP_MSG_FP32;
@@ -598,7 +598,7 @@ static lbp_status run_pass(lbp_decoder d, int64_t n_work, const int32_t *work_li
         size_t occ_off = 0, cs_off = 0;
         o.scratch_words = (int64_t)(osd_scratch_layout(d->osd_variant, C->m, C->n, d->mws, d->sort_p,
                                                        d->prm.osd == LBP_OSD_CS, &occ_off, &cs_off) / 4);
-        o.occ_offset_words = (int64_t)(occ_off / 4);
+        o.occ_offset_words = occ_off == (size_t)-1 ? -1 : (int64_t)(occ_off / 4);
         o.cs_offset_words = (int64_t)(cs_off / 4);
     }
         o.has_lo = d->msgk == LBP_MSG_FP32;
@@ -800,7 +800,7 @@ lbp_status lbp_decode_baseline(lbp_decoder d, int64_t n_shots, uint64_t first_sh
         size_t occ_off = 0, cs_off = 0;
         o.scratch_words = (int64_t)(osd_scratch_layout(d->osd_variant, C->m, C->n, d->mws, d->sort_p,
                                                        d->prm.osd == LBP_OSD_CS, &occ_off, &cs_off) / 4);
-        o.occ_offset_words = (int64_t)(occ_off / 4);
+        o.occ_offset_words = occ_off == (size_t)-1 ? -1 : (int64_t)(occ_off / 4);
         o.cs_offset_words = (int64_t)(cs_off / 4);
     }
         o.has_lo = 1;
