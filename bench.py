@@ -235,7 +235,7 @@ def traffic_from_profiles(msg: str):
 # ---------------------------------------------------------------- experiments
 # The paper's ablations and accuracy studies on synthetic phenomenological
 # inputs: lottery rules (Sec. III-B, Table I), the skip-K sweep, iteration
-# histograms, LER and OSD invoke rate vs p (Sec. VI), LLR vs message flip.
+# histograms, LER and OSD invoke rate vs p (Sec. VII-A), LLR vs message flip.
 # Each prints one JSON object with every point; progress goes to stderr.
 
 def _sample_job(args):
