@@ -536,10 +536,14 @@ __device__ __forceinline__ uint64_t ballot_cost_mask(const unsigned long long *B
     return x;
 }
 
+// Compiled for 8 waves per SIMD (<= 64 VGPRs): two 14-wave blocks then share a CU
+// (their waves land 8/8/6/6 on the SIMDs), which hides the step's barrier and LDS
+// latency behind the other shot; some registers of the non-elimination phases spill.
 template <int NW>
-__global__ __launch_bounds__(1024) void osd_reg_kernel(OsdArgs a) {
+__global__ __launch_bounds__(1024, 8) void osd_reg_kernel(OsdArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
-    const int m = a.m, n = a.n, tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int m = a.m, n = a.n, tid = threadIdx.x, lane = tid & 63;
+    const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int nth = blockDim.x, nwv = nth >> 6;
     const int P = a.sort_p;
     const bool valid = tid < m;
@@ -580,14 +584,17 @@ __global__ __launch_bounds__(1024) void osd_reg_kernel(OsdArgs a) {
         bool piv = false;
         int pcol = 0;
         for (int j = tid; j < n; j += nth) isb[j] = 0;
-        if (tid < 3) red[tid] = 0xFFFFFFFFu;
+        if (tid < 3) red[tid] = 0u;
         __syncthreads();
 
         // ---- 3. Gauss-Jordan in sorted column order, one block barrier per column:
         // each wave publishes its first candidate row before the barrier, so the
-        // winner's row is already in LDS when the pivot is known.
+        // winner's row is already in LDS when the pivot is known.  The candidates
+        // meet in red[] by atomicMax of (j + 1) << 16 | (0xFFFF - row): the column's
+        // tag outranks every older entry, so the three rotating slots never need a
+        // reset, and a slot whose tag is not this column's had no candidate.
         int rank = 0;
-        int slot = 0, nslot = 1, buf = 0;  // reduction slot rotates over 3, row buffers over 2
+        int slot = 0, buf = 0;  // reduction slot rotates over 3, row buffers over 2
         uint64_t tab = n > 0 ? ptab[0] : ~0ull;
         for (int j = 0; j < n && rank < m; ++j) {
             const uint64_t tu = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(tab >> 32)) << 32) |
@@ -595,27 +602,27 @@ __global__ __launch_bounds__(1024) void osd_reg_kernel(OsdArgs a) {
             if (j + 1 < n) tab = ptab[j + 1];  // prefetch the next column's rows
             const uint32_t x = reduced_bit<NW>(g, tu);
             const uint64_t bal = __ballot(valid && x && !piv);
-            if (tid == 0) red[nslot] = 0xFFFFFFFFu;
+            const uint32_t tag = (uint32_t)(j + 1) << 16;
             if (bal) {
                 const int first = __ffsll((unsigned long long)bal) - 1;
                 if (lane == first) {
                     crow[buf * 16 + wid] = g;
                     csp[buf * 16 + wid] = sp;
                 }
-                if (lane == 0) atomicMin(&red[slot], (uint32_t)(wid * 64 + first));
+                if (lane == 0) atomicMax(&red[slot], tag | (0xFFFFu - (uint32_t)(wid * 64 + first)));
             }
             __syncthreads();
-            const int pv = (int)red[slot];
+            const uint32_t rv = red[slot];
             const int pb = buf;
-            slot = nslot;
-            nslot = nslot == 2 ? 0 : nslot + 1;
+            slot = slot == 2 ? 0 : slot + 1;
             buf ^= 1;
-            if (pv == (int)0xFFFFFFFFu) continue;
+            if ((rv & 0xFFFF0000u) != tag) continue;  // no row of this column is free
+            const int pv = (int)(0xFFFFu - (rv & 0xFFFFu));
             if (tid == pv) {
                 piv = true;
                 pcol = perm[j];
+                isb[j] = 1;
             }
-            if (tid == 0) isb[j] = 1;
             // reduced columns are sparse early on: waves with no row to update skip the row read
             if (__ballot(x && tid != pv)) {
                 const vrow<NW> pr = crow[pb * 16 + (pv >> 6)];
