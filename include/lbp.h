@@ -143,7 +143,12 @@ int32_t lbp_code_cols(lbp_code code);
  * device).  OSD-CS requires a uniform prior (LBP_EUNSUPPORTED otherwise): its
  * candidate cost is the Hamming weight.  The decoder holds a reference to the
  * code: lbp_code_destroy may come before lbp_decoder_destroy (in any order);
- * the code's device memory is released with its last user. */
+ * the code's device memory is released with its last user.
+ * The launch shape is chosen here from the per-shot state and the device: a
+ * wavefront per shot, or a workgroup of 2-16 waves per shot when fewer than 32
+ * one-wave shots fit a CU.  The environment variable LBP_BP_GROUP=g, read
+ * here, forces workgroups of g waves (it changes no result; it exists to test
+ * that variant on small codes). */
 lbp_status lbp_decoder_create(lbp_code code, const lbp_params *prm, int64_t max_batch, lbp_decoder *out);
 void lbp_decoder_destroy(lbp_decoder dec);
 
