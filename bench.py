@@ -301,6 +301,58 @@ def decode_point(torch, h, checker, p, err, syn, prm, batch: int = 1 << 18):
                 osd_us_per_osd_shot=1e3 * osd_ms / max(1, int(((flags & 2) != 0).sum())))
 
 
+# The serving mix: single-syndrome requests drawn uniformly over seven codes
+# (surface d = 5..21 over d rounds, BB144 over 12 and BB288 over 18 rounds),
+# p = 0.003, Int3.4 lottery BP + OSD-0, Poisson arrivals at fractions of the
+# mix's flood rate; latency from the scheduled arrival to the poll-visible result.
+SERVE_MIX = [("surface5_phen", 100), ("surface9_phen", 100), ("surface13_phen", 100), ("surface17_phen", 100),
+             ("surface21_phen", 100), ("bb144_phen", 200), ("bb288_phen", 200)]
+
+
+def run_servemix(args):
+    import torch
+    assert torch.cuda.is_available(), "experiments need a GPU"
+    from paper_2605_00038_amd import Code, DecoderParams, Server
+    t_start = time.perf_counter()
+    srv = Server(device_mem_budget=64 << 30, max_slots=len(SERVE_MIX))  # seven rings, 64 GiB of 288
+    slots, pools, names = [], [], []
+    for j, (name, iters) in enumerate(SERVE_MIX):
+        h, _, _ = codes.workload_matrices(name)
+        _, syn = sample.make_batch(h, P_ERR, 4096, 5000 + j)
+        prm = DecoderParams(max_iter=iters, msg=2, lottery=True, lottery_skip=6, osd=1, seed=5000 + j)
+        slots.append(srv.add_code(Code.from_scipy(h, P_ERR), prm))
+        pools.append(syn)
+        names.append(name)
+        log(f"[servemix] {name} {h.shape[0]}x{h.shape[1]}: slot {slots[-1]} {srv.slot_info(slots[-1])}")
+
+    def stats(lat):
+        return dict(requests=int(lat.size), p50_us=float(np.percentile(lat, 50)), p99_us=float(np.percentile(lat, 99)),
+                    p999_us=float(np.percentile(lat, 99.9)))
+
+    def run(rate, n, seed):
+        lat, code, el = srv.run_load(slots, pools, n, 1, rate, seed)
+        r = dict(offered_requests_per_s=rate, achieved_requests_per_s=n / el, overall=stats(lat),
+                 per_code={names[k]: stats(lat[code == k]) for k in range(len(names)) if (code == k).any()})
+        log(f"[servemix] offered {rate:.0f}/s achieved {n / el:.0f}/s overall p50 {r['overall']['p50_us']:.0f} "
+            f"p99 {r['overall']['p99_us']:.0f} p99.9 {r['overall']['p999_us']:.0f} us")
+        return r
+
+    n = args.exp_shots
+    run(0.0, min(n, 5000), LOTTERY_SEED)  # warm-up
+    flood = run(0.0, n, LOTTERY_SEED)
+    points = [run(frac * flood["achieved_requests_per_s"], n, LOTTERY_SEED + 1 + k)
+              for k, frac in enumerate((0.1, 0.3, 0.5, 0.7))]
+    srv.close()
+    out = dict(experiment="servemix", codes=[dict(workload=nm, max_iter=it) for nm, it in SERVE_MIX], p=P_ERR,
+               data="synthetic: i.i.d. Bernoulli(p) flips on every column of H_st, 4096-shot pool per code",
+               flood=flood, points=points, seconds=time.perf_counter() - t_start)
+    text = json.dumps(out)
+    if args.exp_out:
+        with open(args.exp_out, "w") as f:
+            f.write(text + "\n")
+    print(text, flush=True)
+
+
 def run_experiment(args):
     import torch
     assert torch.cuda.is_available(), "experiments need a GPU"
@@ -428,7 +480,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-ler", action="store_true")
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
-    ap.add_argument("--experiment", choices=["policies", "skip", "iters", "ler", "flip", "quant", "osdheavy", "scale"],
+    ap.add_argument("--experiment", choices=["policies", "skip", "iters", "ler", "flip", "quant", "osdheavy", "scale",
+                                             "servemix"],
                     help="run one of the paper's ablations instead of the benchmark (prints a JSON table)")
     ap.add_argument("--exp-shots", type=int, default=1 << 20, help="shots per experiment point")
     ap.add_argument("--exp-p", default="", help="comma-separated physical error rates (default: per experiment)")
@@ -461,7 +514,10 @@ def main():
               "range of shots with no exchange; only --gpus 1 is supported here.", file=sys.stderr)
         sys.exit(2)
     if args.experiment:
-        run_experiment(args)
+        if args.experiment == "servemix":
+            run_servemix(args)
+        else:
+            run_experiment(args)
         return
 
     h, hc, rounds = codes.workload_matrices(WORKLOAD)

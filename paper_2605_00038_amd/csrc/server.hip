@@ -40,6 +40,11 @@ constexpr int64_t kMinRing = 1024;
 constexpr int64_t kQueueFactor = 16;       // admission: queued shots per slot <= kQueueFactor * R
 constexpr int64_t kOsdList = 4096;         // failed shots per OSD launch
 constexpr uint64_t kIdleTicks = 200000;    // the BP grid exits after 2 ms without a claim (100 MHz clock)
+// With several code slots the grids share the GPU's few hardware queues: a grid
+// that waits out 2 ms of idleness holds its queue, and every launch of another
+// slot's stream behind it on that queue, so grids of a shared server exit after
+// 20 us without a claim and the worker relaunches them when items arrive.
+constexpr uint64_t kIdleTicksShared = 2000;
 constexpr double kOsdFraction = 0.375;     // CUs left to OSD launches
 constexpr int64_t kDefaultBudget = (int64_t)16 << 30;
 constexpr auto kQueryGap = std::chrono::microseconds(20);
@@ -160,6 +165,21 @@ void free_slot(Slot &sl) {
     if (sl.s_osd) (void)hipStreamDestroy(sl.s_osd);
 }
 
+// CU masks of a slot's streams: OSD launches get 12 of every 32 CUs (the OSD
+// fraction), BP grids the other 20, so a long OSD launch (large codes) never
+// holds the CUs a BP grid needs.  The pattern is taken modulo 32, so every XCD
+// keeps CUs of both kinds whether the mask bits run along or across XCDs.
+void cu_masks(int ncu, std::vector<uint32_t> &bp, std::vector<uint32_t> &osd) {
+    const int words = (ncu + 31) / 32;
+    bp.assign((size_t)words, 0u);
+    osd.assign((size_t)words, 0u);
+    const int osd_per32 = (int)(32 * kOsdFraction + 0.5);
+    for (int i = 0; i < ncu; ++i) {
+        if (i % 32 < osd_per32) osd[(size_t)(i / 32)] |= 1u << (i % 32);
+        else bp[(size_t)(i / 32)] |= 1u << (i % 32);
+    }
+}
+
 // Allocate the rings and device state of a slot with R items.
 lbp_status setup_slot(Slot &sl, int64_t R) {
     sl.R = R;
@@ -183,8 +203,18 @@ lbp_status setup_slot(Slot &sl, int64_t R) {
     chk(hipMalloc((void **)&sl.d_llr, (size_t)R * 2 * sl.n * 4));
     chk(hipMalloc((void **)&sl.d_list, (size_t)kOsdList * 4));
     chk(hipMalloc((void **)&sl.d_ocount, 64));
-    chk(hipStreamCreateWithFlags(&sl.s_bp, hipStreamNonBlocking));
-    chk(hipStreamCreateWithFlags(&sl.s_osd, hipStreamNonBlocking));
+    int ncu = 0, dev = 0;
+    chk(hipGetDevice(&dev));
+    chk(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    if (e == hipSuccess && ncu >= 32) {
+        std::vector<uint32_t> mbp, mosd;
+        cu_masks(ncu, mbp, mosd);
+        chk(hipExtStreamCreateWithCUMask(&sl.s_bp, (uint32_t)mbp.size(), mbp.data()));
+        chk(hipExtStreamCreateWithCUMask(&sl.s_osd, (uint32_t)mosd.size(), mosd.data()));
+    } else {
+        chk(hipStreamCreateWithFlags(&sl.s_bp, hipStreamNonBlocking));
+        chk(hipStreamCreateWithFlags(&sl.s_osd, hipStreamNonBlocking));
+    }
     chk(hipEventCreateWithFlags(&sl.e_bp, hipEventDisableTiming));
     chk(hipEventCreateWithFlags(&sl.e_osd, hipEventDisableTiming));
     if (e != hipSuccess)
@@ -350,7 +380,12 @@ bool service(lbp_server srv, Slot &sl, bool &busy) {
     if (query && sl.bp_running && hipEventQuery(sl.e_bp) == hipSuccess) sl.bp_running = false;
     const bool bp_waiting = sl.bp_done < sl.published;
     if (!sl.bp_running && bp_waiting && srv->dead.load() == LBP_OK) {
-        lbp_status st = lbp::serve_launch_bp(sl.dec, sl.d_ring, sl.ring.exiting, sl.shape.bp_blocks, sl.s_bp);
+        // Persistent grids of several code slots share the BP CUs: a grid sized for
+        // all of them would keep the other slots' grids from becoming resident
+        // while its ring stays busy, and their requests would wait for it to idle out.
+        const int nslots = (int)srv->slots.size();
+        const int blocks = std::max(1, sl.shape.bp_blocks / std::max(1, nslots));
+        lbp_status st = lbp::serve_launch_bp(sl.dec, sl.d_ring, sl.ring.exiting, blocks, sl.s_bp);
         if (st == LBP_OK && hipEventRecord(sl.e_bp, sl.s_bp) == hipSuccess) {
             sl.bp_running = true;
             sl.bp_launches += 1;
@@ -526,6 +561,22 @@ lbp_status lbp_server_add_code(lbp_server srv, lbp_code code, const lbp_params *
     inf.queued.store(0);
     sl->info = &inf;
     srv->slots.push_back(std::move(sl));
+    if (srv->slots.size() > 1) {
+        // the next grid of each slot reads the new idle time: the copy is ordered
+        // on the slot's BP stream (a running grid keeps the one it started with)
+        int prev_dev = -1;
+        (void)hipGetDevice(&prev_dev);
+        (void)hipSetDevice(srv->device);
+        for (auto &sp : srv->slots) {
+            if (sp->ring.idle_ticks == kIdleTicksShared) continue;
+            sp->ring.idle_ticks = kIdleTicksShared;
+            if (hipMemcpyAsync(sp->d_ring, &sp->ring, sizeof(sp->ring), hipMemcpyHostToDevice, sp->s_bp) != hipSuccess) {
+                srv->dead_msg = "server: ring update failed";
+                srv->dead = LBP_EDEVICE;
+            }
+        }
+        if (prev_dev >= 0) (void)hipSetDevice(prev_dev);
+    }
     srv->n_slots.store(idx + 1, std::memory_order_release);  // submit may use the slot from here on
     *code_slot = (int32_t)idx;
     return LBP_OK;
