@@ -224,16 +224,20 @@ lbp_status lbp_decoder_kernel_times(lbp_decoder dec, double *bp_ms, int64_t *bp_
  * arrays.  lbp_server_* calls are thread-safe.
  *
  * Streaming: every code slot has a ring of R shots in pinned host memory and
- * a persistent BP grid that claims published shots one per wavefront, so each
- * shot's result is visible as soon as that shot is done (no batch
- * boundaries).  Shots whose BP run fails are handed to OSD launches on the
- * CUs the BP grid leaves free (3/8 of them).  The worker publishes queued
- * shots first come first served, splitting large requests, with at most R
- * shots in flight per slot; a request completes when all of its shots have.
- * Each shot is decoded with the key (seed, first_shot_id + j) of its request,
- * so results equal a lone lbp_decode of the request with that seed, whatever
- * else is in flight.  The BP grid exits after 2 ms without work and is
- * relaunched when shots arrive. */
+ * a persistent BP grid that claims published shots one per wavefront (or
+ * workgroup, for large codes), so each shot's result is visible as soon as
+ * that shot is done (no batch boundaries).  Shots whose BP run fails are
+ * handed to OSD launches.  A slot's BP and OSD streams are CU-masked to 20 and
+ * 12 of every 32 CUs, so OSD never holds the CUs BP needs; with several slots
+ * their BP grids split the BP CUs.  The worker publishes queued shots first
+ * come first served, splitting large requests, with at most R shots in flight
+ * per slot; a request completes when all of its shots have.  Each shot is
+ * decoded with the key (seed, first_shot_id + j) of its request, so results
+ * equal a lone lbp_decode of the request with that seed, whatever else is in
+ * flight.  The BP grid exits after 2 ms without work (20 us when the server
+ * holds several slots) and is relaunched when shots arrive.  CU-masked
+ * streams synchronize with the legacy default stream: work the caller
+ * enqueues there waits for a running grid to exit. */
 
 /* device_mem_budget_bytes: cap on the device memory all slots may hold (0 =
  * 16 GiB); max_slots: number of codes (1..64). */
