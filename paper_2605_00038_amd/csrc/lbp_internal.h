@@ -253,7 +253,6 @@ struct OsdArgs {
     int32_t cols_global;        // G-in-global variant: the per-column arrays live in the block's scratch too
     int64_t scratch_words;      // per-block stride of gscratch in 32-bit words
     int64_t cs_offset_words;    // OSD-CS column ballots in the block's scratch (kernels for m > 1024)
-    int64_t occ_offset_words;   // occupancy words of G in the block's scratch (G in global memory), -1: none
 };
 
 // Global-memory comparison path (one launch per half-iteration).
@@ -294,7 +293,7 @@ int bp_wave_bytes(int msg, int m, int n);
 int osd_block_bytes(int m, int n, int lds_limit, int *variant, int *mws, int *sort_p, int *threads);
 // Per-block global scratch of the OSD kernel.
 size_t osd_scratch_bytes(int variant, int m, int n, int mws, int sort_p, int cs);
-size_t osd_scratch_layout(int variant, int m, int n, int mws, int sort_p, int cs, size_t *occ_off, size_t *cs_off);
+size_t osd_scratch_layout(int variant, int m, int n, int mws, int sort_p, int cs, size_t *cs_off);
 hipError_t osd_max_blocks_per_cu(int variant, int threads, int lds, int *out);
 
 // Int3.4 check-centric kernel (codes with <= 1024 checks): slots per lane

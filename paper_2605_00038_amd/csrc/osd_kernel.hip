@@ -32,7 +32,17 @@ namespace {
 
 constexpr int OSD_THREADS = 1024;
 constexpr int OSD_WAVES = OSD_THREADS / 64;
-constexpr int OSD_OCC_MIN_M = 4096;  // smallest m whose global-G OSD keeps an occupancy mask
+// Smallest m whose global-G OSD keeps an occupancy mask of G: it pays from ~4096
+// checks on (surface d=21 and up) and cost a few percent at d=17, where G's
+// columns are short.
+constexpr int OSD_OCC_MIN_M = 4096;
+
+// Words of that mask: bit t of word (w * ceil(mw/32) + t/32) is set when some row
+// of the 32-row group t may have a non-zero word w of G.
+__host__ __device__ inline int osd_occ_words(int m) {
+    const int mw = (m + 31) / 32;
+    return mw * ((mw + 31) / 32);
+}
 
 __device__ __forceinline__ uint32_t orderable(float f) {
     uint32_t u = __float_as_uint(f);
@@ -228,15 +238,19 @@ __global__ __launch_bounds__(1024, 8) void osd_lds_kernel(OsdArgs a) {
     uint32_t *pl_w = (uint32_t *)q0;                 q0 += ((size_t)a.mw * 4 + 15) & ~(size_t)15;
     uint32_t *pl_v = (uint32_t *)q0;                 q0 += ((size_t)a.mw * 4 + 15) & ~(size_t)15;
     unsigned long long *Yq = (unsigned long long *)q0; q0 += ((size_t)((m + 63) >> 6) * 8 + 15) & ~(size_t)15;
+    // G in global memory (large m): the occupancy mask of its words lives in LDS
+    const bool use_occ = !a.g_in_lds && m >= OSD_OCC_MIN_M;
+    uint32_t *occ = use_occ ? (uint32_t *)q0 : nullptr;
+    if (use_occ) q0 += ((size_t)osd_occ_words(m) * 4 + 15) & ~(size_t)15;
     uint32_t *cw = (uint32_t *)q0;                   q0 += ((size_t)a.nw * 4 + 15) & ~(size_t)15;
     uint32_t *red = (uint32_t *)q0;                  q0 += 16 * 4;
     int *scr = (int *)q0;                            q0 += 32 * 4;
     unsigned long long *best64 = (unsigned long long *)q0;
 
-    // G in global memory: bit b of occ[w * mw + t] is set when word w of row 32t+b
-    // may be non-zero (a superset, never cleared), so the column test loads only
-    // G's words that can be non-zero; G stays sparse on the codes that need this.
-    uint32_t *occ = a.g_in_lds || a.occ_offset_words < 0 ? nullptr : (uint32_t *)(gblk + a.occ_offset_words * 4);
+    // occ: a set bit (w, t) says rows 32t..32t+31 may hold a non-zero word w of G
+    // (a superset, never cleared), so the column test loads only G's words that
+    // can be non-zero; G stays sparse on the codes that need this.
+    const int mwt = (a.mw + 31) / 32;  // mask words per G word
     const int krows = (m + nth - 1) / nth;
 
     GView G;
@@ -262,10 +276,9 @@ __global__ __launch_bounds__(1024, 8) void osd_lds_kernel(OsdArgs a) {
             G.at(r, w) = (w == (r >> 5)) ? (1u << (r & 31)) : 0u;
         }
         if (occ)
-            for (int idx = tid; idx < mw * mw; idx += nth) {
-                const int w = idx / mw, t = idx % mw;
-                const int valid = m - 32 * t;  // rows of word t that exist
-                occ[idx] = w != t ? 0u : valid >= 32 ? ~0u : (1u << valid) - 1u;
+            for (int idx = tid; idx < mw * mwt; idx += nth) {
+                const int w = idx / mwt, j = idx % mwt;  // G = I: group w holds word w
+                occ[idx] = (w >> 5) == j ? 1u << (w & 31) : 0u;
             }
         const uint32_t *sw = a.synd + shot * a.mw;
         for (int r = tid; r < m; r += nth) {
@@ -292,9 +305,10 @@ __global__ __launch_bounds__(1024, 8) void osd_lds_kernel(OsdArgs a) {
             for (int r = tid; r < m; r += nth, ++k) {
                 uint32_t x = 0;
                 if (occ) {
+                    const int t = r >> 5;
                     for (int q = 0; q < nr; ++q) {
                         const int c = rows[q];
-                        if ((occ[(size_t)(c >> 5) * mw + (r >> 5)] >> (r & 31)) & 1u)
+                        if ((occ[(c >> 5) * mwt + (t >> 5)] >> (t & 31)) & 1u)
                             x ^= (G.at(r, c >> 5) >> (c & 31)) & 1u;
                     }
                 } else {
@@ -322,7 +336,7 @@ __global__ __launch_bounds__(1024, 8) void osd_lds_kernel(OsdArgs a) {
             __syncthreads();
             const int nl = (int)*cnt;
             const uint8_t spv = sp[pv];
-            for (k = 0; k < krows; ++k) {  // uniform trip count: the occupancy update ballots
+            for (k = 0; k < krows; ++k) {
                 const int r = k * nth + tid;
                 const bool upd = r < m && (uint32_t)r != pv && ((xm >> k) & 1u);
                 if (r < m && (uint32_t)r == pv) {
@@ -331,22 +345,12 @@ __global__ __launch_bounds__(1024, 8) void osd_lds_kernel(OsdArgs a) {
                 } else if (upd) {
                     for (int i = 0; i < nl; ++i) G.at(r, (int)pl_w[i]) ^= pl_v[i];
                     sp[r] ^= spv;
-                }
-                if (occ) {
-                    // this wave's 64 rows are row words t0, t0+1: one lane per (pivot word, half)
-                    const uint64_t um = __ballot(upd);
-                    if (um) {
-                        const int t0 = (r - lane) >> 5;
-                        for (int i = lane; i < 2 * nl; i += 64) {
-                            const uint32_t msk = (uint32_t)(um >> (32 * (i & 1)));
-                            const int t = t0 + (i & 1);
-                            if (msk && t < mw) occ[(size_t)pl_w[i >> 1] * mw + t] |= msk;
-                        }
+                    // the bit of this row's group is only ever read by this wave (its 64
+                    // rows span two groups), and LDS operations of a wave stay in order
+                    if (occ) {
+                        const int t = r >> 5;
+                        for (int i = 0; i < nl; ++i) atomicOr(&occ[(int)pl_w[i] * mwt + (t >> 5)], 1u << (t & 31));
                     }
-                    // the wave reads these occupancy words itself in the next column test
-                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                    __builtin_amdgcn_wave_barrier();
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
                 }
             }
             if (tid == 0) isb[j] = 1;
@@ -726,8 +730,11 @@ int osd_block_bytes(int m, int n, int lds_limit, int *variant, int *mws, int *so
         return (int)(al((size_t)P * 8) + common + al(32 * vb) + 32 * 4 + 16 * 8);
     }
     *threads = OSD_THREADS;
-    const size_t plist = 2 * al((size_t)mw * 4) + al((size_t)((m + 63) / 64) * 8);  // pivot row words, s' ballots
-    size_t rows = al((size_t)m * 2) + al((size_t)m) * 2 + plist + al((size_t)((n + 31) / 32) * 4) + 16 * 4 + 32 * 4 + 16;
+    // pivot row words, s' ballots, and for G in global memory at large m its occupancy mask
+    const size_t plist = 2 * al((size_t)mw * 4) + al((size_t)((m + 63) / 64) * 8);
+    const size_t occb = m >= OSD_OCC_MIN_M ? al((size_t)osd_occ_words(m) * 4) : 0;
+    size_t rows = al((size_t)m * 2) + al((size_t)m) * 2 + plist + occb + al((size_t)((n + 31) / 32) * 4) + 16 * 4 +
+                  32 * 4 + 16;
     size_t rest = common + al((size_t)m * 2) + al((size_t)m) * 2 + plist;
     size_t gb = (size_t)m * s * 4;
     size_t with_g = al(gb > (size_t)P * 8 ? gb : (size_t)P * 8) + rest;
@@ -737,9 +744,9 @@ int osd_block_bytes(int m, int n, int lds_limit, int *variant, int *mws, int *so
         return (int)with_g;
     }
     *mws = mw;
-    if ((int64_t)(al((size_t)P * 8) + rest) <= lds_limit) {
+    if ((int64_t)(al((size_t)P * 8) + rest + occb) <= lds_limit) {
         *variant = -1;  // G in global memory
-        return (int)(al((size_t)P * 8) + rest);
+        return (int)(al((size_t)P * 8) + rest + occb);
     }
     *variant = -2;      // G and the per-column arrays in global memory
     // latency-bound steps: half-size blocks put more shots in flight per CU (LDS permitting)
@@ -747,32 +754,24 @@ int osd_block_bytes(int m, int n, int lds_limit, int *variant, int *mws, int *so
     return (int)rows;
 }
 
-size_t osd_scratch_layout(int variant, int m, int n, int mws, int sort_p, int cs, size_t *occ_off, size_t *cs_off) {
+size_t osd_scratch_layout(int variant, int m, int n, int mws, int sort_p, int cs, size_t *cs_off) {
     auto a256 = [](size_t x) { return (x + 255) & ~(size_t)255; };
     auto al = [](size_t x) { return (x + 15) & ~(size_t)15; };
-    const size_t mw = (size_t)(m + 31) / 32;
-    *occ_off = *cs_off = 0;
+    *cs_off = 0;
     if (variant > 0) return (size_t)16 * m * 8;       // per-wave column ballots
     size_t b = 0;
     if (variant == -1) b = a256((size_t)m * mws * 4);  // G
     if (variant == -2)                                 // G, sort keys, lambda lo, order, non-basis list, flags
         b = a256(a256((size_t)m * mws * 4) + a256((size_t)sort_p * 8) + al((size_t)n * 4) + 2 * al((size_t)n * 2) +
                  al((size_t)n));
-    // occupancy of G's words: it pays from ~4096 checks on (surface d=21: 9 % faster
-    // OSD, d=25-27: 1.5x) and costs ~8 % at d=17, where G's columns are short
-    *occ_off = (size_t)-1;
-    if (variant < 0 && m >= OSD_OCC_MIN_M) {
-        *occ_off = b;
-        b += a256(mw * mw * 4);
-    }
     *cs_off = b;
     if (cs) b += a256((size_t)((m + 63) / 64) * m * 8);  // OSD-CS: 64-row ballots of G's columns
     return b;
 }
 
 size_t osd_scratch_bytes(int variant, int m, int n, int mws, int sort_p, int cs) {
-    size_t o, c;
-    return osd_scratch_layout(variant, m, n, mws, sort_p, cs, &o, &c);
+    size_t c;
+    return osd_scratch_layout(variant, m, n, mws, sort_p, cs, &c);
 }
 
 template <class K>

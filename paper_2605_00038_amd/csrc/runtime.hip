@@ -168,10 +168,9 @@ lbp_status lbp::serve_launch_osd(lbp_decoder d, const ServeRing &ring, const int
     o.g_in_lds = d->osd_variant == 0;
     o.cols_global = d->osd_variant == -2;
     {
-        size_t occ_off = 0, cs_off = 0;
+        size_t cs_off = 0;
         o.scratch_words = (int64_t)(osd_scratch_layout(d->osd_variant, C->m, C->n, d->mws, d->sort_p,
-                                                       d->prm.osd == LBP_OSD_CS, &occ_off, &cs_off) / 4);
-        o.occ_offset_words = occ_off == (size_t)-1 ? -1 : (int64_t)(occ_off / 4);
+                                                       d->prm.osd == LBP_OSD_CS, &cs_off) / 4);
         o.cs_offset_words = (int64_t)(cs_off / 4);
     }
     o.has_lo = d->msgk == LBP_MSG_FP32;
@@ -595,10 +594,9 @@ static lbp_status run_pass(lbp_decoder d, int64_t n_work, const int32_t *work_li
         o.g_in_lds = d->osd_variant == 0;
         o.cols_global = d->osd_variant == -2;
         {
-        size_t occ_off = 0, cs_off = 0;
+        size_t cs_off = 0;
         o.scratch_words = (int64_t)(osd_scratch_layout(d->osd_variant, C->m, C->n, d->mws, d->sort_p,
-                                                       d->prm.osd == LBP_OSD_CS, &occ_off, &cs_off) / 4);
-        o.occ_offset_words = occ_off == (size_t)-1 ? -1 : (int64_t)(occ_off / 4);
+                                                       d->prm.osd == LBP_OSD_CS, &cs_off) / 4);
         o.cs_offset_words = (int64_t)(cs_off / 4);
     }
         o.has_lo = d->msgk == LBP_MSG_FP32;
@@ -797,10 +795,9 @@ lbp_status lbp_decode_baseline(lbp_decoder d, int64_t n_shots, uint64_t first_sh
         o.g_in_lds = d->osd_variant == 0;
         o.cols_global = d->osd_variant == -2;
         {
-        size_t occ_off = 0, cs_off = 0;
+        size_t cs_off = 0;
         o.scratch_words = (int64_t)(osd_scratch_layout(d->osd_variant, C->m, C->n, d->mws, d->sort_p,
-                                                       d->prm.osd == LBP_OSD_CS, &occ_off, &cs_off) / 4);
-        o.occ_offset_words = occ_off == (size_t)-1 ? -1 : (int64_t)(occ_off / 4);
+                                                       d->prm.osd == LBP_OSD_CS, &cs_off) / 4);
         o.cs_offset_words = (int64_t)(cs_off / 4);
     }
         o.has_lo = 1;
