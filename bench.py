@@ -89,7 +89,15 @@ def time_format(torch, h, syn_dev, msg: str, steps: int, warmup: int, shots: int
     t1 = time.perf_counter()
     dec.set_timing(False)
     bp_ms, bp_n, osd_ms, osd_n = dec.kernel_times()
-    res = dict(seconds=t1 - t0, bp_ms=bp_ms, bp_launches=bp_n, osd_ms=osd_ms, osd_launches=osd_n,
+    # after the timed region: five steps each bracketed by its own synchronisation (their median)
+    runs = []
+    for _ in range(5):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        dec.decode(syn_dev, out=out)
+        torch.cuda.synchronize()
+        runs.append((time.perf_counter() - t) * 1e3)
+    res = dict(seconds=t1 - t0, bp_ms=bp_ms, bp_launches=bp_n, osd_ms=osd_ms, osd_launches=osd_n, step_ms_runs=runs,
                corr=corr.cpu().numpy().view(np.uint32), flags=flags.cpu().numpy(), iters=iters.cpu().numpy())
     return dec, res
 
@@ -546,7 +554,8 @@ def main():
                      bp_ms_per_launch=r["bp_ms"] / max(1, r["bp_launches"]),
                      osd_ms_per_launch=r["osd_ms"] / max(1, r["osd_launches"]),
                      mean_iters=float(r["iters"].mean()), osd_invoke_rate=float(((r["flags"] & 2) != 0).mean()),
-                     edge_updates_per_step=edges, steps=steps)
+                     edge_updates_per_step=edges, steps=steps,
+                     step_ms_median_of_5=float(np.median(r["step_ms_runs"])))
         if not args.no_ler:
             sf, lf = failures_packed(checker, err_p, r["corr"], n)
             k = int((sf | lf).sum())
