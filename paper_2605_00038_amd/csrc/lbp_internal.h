@@ -286,11 +286,13 @@ void set_error(const char *msg);
 
 // LDS bytes the BP kernel needs per wave for a code.
 int bp_wave_bytes(int msg, int m, int n);
-// OSD kernel choice for a code: variant > 0 keeps G in registers (NW words per
-// row, m <= 1024), 0 keeps G in LDS, -1 in global memory, -2 also keeps the
-// per-column arrays (sort keys, order, non-basis list) in global memory (large
-// n).  Returns LDS bytes per block; *threads is the block size.
-int osd_block_bytes(int m, int n, int lds_limit, int *variant, int *mws, int *sort_p, int *threads);
+// OSD kernel choice for a code: variant > 0 keeps G in registers (m < 1024;
+// variant = 100 * rows per lane + NW words per row; rows_per_lane 1, else 2),
+// 0 keeps G in LDS, -1 in global memory, -2 also keeps the per-column arrays
+// (sort keys, order, non-basis list) in global memory (large n).  Returns LDS
+// bytes per block; *threads is the block size.
+int osd_block_bytes(int m, int n, int lds_limit, int rows_per_lane, int *variant, int *mws, int *sort_p,
+                    int *threads);
 // Per-block global scratch of the OSD kernel.
 size_t osd_scratch_bytes(int variant, int m, int n, int mws, int sort_p, int cs);
 size_t osd_scratch_layout(int variant, int m, int n, int mws, int sort_p, int cs, size_t *cs_off);

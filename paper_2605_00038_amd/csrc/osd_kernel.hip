@@ -472,13 +472,13 @@ __global__ __launch_bounds__(1024, 8) void osd_lds_kernel(OsdArgs a) {
 
 
 // ---------------------------------------------------------------------------
-// Register-resident variant for m <= 32*NW <= 1024: thread r owns row r of G as
-// an NW-word vector register, so the Gauss-Jordan XOR of a pivot row is NW
-// VALU ops against a broadcast LDS copy, and the bit of the reduced column is
-// read with a wave-uniform word index (indexed register move, no LDS).  Two
-// block barriers per pivot step, one per dependent column.  For OSD-CS each
-// wave turns every column c of G into a 64-bit ballot of its rows; the cost of
-// a candidate is then a popcount per wave.
+// Register-resident variant for m < 32*NW <= 1024: a lane owns rows of G as
+// NW-word vector registers, so the Gauss-Jordan XOR of a pivot row is NW VALU
+// ops against a broadcast LDS copy, and the bit of the reduced column is read
+// with a wave-uniform word index (indexed register move, no LDS).  One block
+// barrier per column.  For OSD-CS each wave turns every column c of G into
+// 64-bit ballots of its rows; the cost of a candidate is then a popcount per
+// ballot.
 template <int NW>
 using vrow = uint32_t __attribute__((ext_vector_type(NW)));
 
@@ -490,15 +490,19 @@ __device__ __forceinline__ uint32_t row_bit(const vrow<NW> &g, int c) {
     return (g[c >> 5] >> (c & 31)) & 1u;  // c is wave-uniform
 }
 
-template <int NW>
-__device__ __forceinline__ uint32_t reduced_bit(const vrow<NW> &g, uint64_t tab) {
-    uint32_t x = 0;
+// Bit of each of the lane's R rows of the reduced column whose CDEG check indices
+// are packed as u16 in chk (wave-uniform).  An absent slot names check m, a bit
+// that is zero in every row of G (its support is [0, m), and m < 32 NW).
+template <int NW, int R>
+__device__ __forceinline__ void reduced_bits(const vrow<NW> (&g)[R], uint64_t chk, uint32_t (&x)[R]) {
+#pragma unroll
+    for (int k = 0; k < R; ++k) x[k] = 0;
 #pragma unroll
     for (int j = 0; j < CDEG; ++j) {
-        uint32_t p = (uint32_t)(tab >> (16 * j)) & 0xFFFFu;
-        if (p != NOPOS) x ^= row_bit<NW>(g, __builtin_amdgcn_readfirstlane((int)(p / DEG)));
+        const int c = (int)((chk >> (16 * j)) & 0xFFFFu);
+#pragma unroll
+        for (int k = 0; k < R; ++k) x[k] ^= row_bit<NW>(g[k], c);
     }
-    return x;
 }
 
 __device__ __forceinline__ uint64_t uniform_tab(const uint64_t *vn_tab, int col) {
@@ -540,17 +544,28 @@ __device__ __forceinline__ uint64_t ballot_cost_mask(const unsigned long long *B
     return x;
 }
 
-// Compiled for 8 waves per SIMD (<= 64 VGPRs): two 14-wave blocks then share a CU
-// (their waves land 8/8/6/6 on the SIMDs), which hides the step's barrier and LDS
-// latency behind the other shot; some registers of the non-elimination phases spill.
-template <int NW>
-__global__ __launch_bounds__(1024, 8) void osd_reg_kernel(OsdArgs a) {
+// Each lane holds R rows of G (rows tid and nth + tid), NW words per row.  A
+// column step's wave-uniform work (slot parse, loop control, candidate
+// publication) is paid once per wave, so R = 2 halves it per shot against R = 1;
+// the per-row VALU work is the same.  R = 1 is compiled for 8 waves per SIMD
+// (<= 64 VGPRs, some registers of the non-elimination phases spill), R = 2 for 4
+// (<= 128 VGPRs); either way two blocks share a CU, which hides one shot's step
+// barrier and LDS latency behind the other's.
+template <int NW, int R>
+__global__ __launch_bounds__(1024 / R, 8 / R) void osd_reg_kernel(OsdArgs a) {
+    static_assert(R == 1 || R == 2, "one or two rows per lane");
     extern __shared__ __align__(16) unsigned char smem[];
     const int m = a.m, n = a.n, tid = threadIdx.x, lane = tid & 63;
     const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int nth = blockDim.x, nwv = nth >> 6;
     const int P = a.sort_p;
-    const bool valid = tid < m;
+    int row[R];
+    bool valid[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        row[k] = k * nth + tid;
+        valid[k] = row[k] < m;
+    }
     unsigned char *q0 = smem + (((size_t)P * 8 + 15) & ~(size_t)15);
     float *lo_s = (float *)q0;                       q0 += ((size_t)n * 4 + 15) & ~(size_t)15;
     uint16_t *perm = (uint16_t *)q0;                 q0 += ((size_t)n * 2 + 15) & ~(size_t)15;
@@ -563,7 +578,9 @@ __global__ __launch_bounds__(1024, 8) void osd_reg_kernel(OsdArgs a) {
     int *scr = (int *)q0;                            q0 += 32 * 4;
     unsigned long long *Y = (unsigned long long *)q0; q0 += 16 * 8;
     unsigned long long *best64 = (unsigned long long *)q0;
+    // 64-row ballots of G's columns: group k * nwv + w holds rows k * nth + 64 w + lane (R * nwv <= 16)
     unsigned long long *B = (unsigned long long *)a.gscratch + (size_t)blockIdx.x * 16 * m;
+    const int ngr = R * nwv;
 
     uint32_t nfail = a.counters[1];
     if ((int64_t)nfail > a.fail_cap) nfail = (uint32_t)a.fail_cap;
@@ -575,18 +592,33 @@ __global__ __launch_bounds__(1024, 8) void osd_reg_kernel(OsdArgs a) {
         // ---- 1. sort (lambda, column) ascending
         sort_columns(lam, n, P, a.has_lo, (unsigned long long *)smem, lo_s, perm);
 
-        // sorted column tables, staged over the dead sort keys: ptab[j] = vn_tab[perm[j]]
+        // check indices of the sorted columns, staged over the dead sort keys
         uint64_t *ptab = (uint64_t *)smem;
-        for (int j = tid; j < n; j += nth) ptab[j] = a.vn_tab[perm[j]];
-
-        // ---- 2. G = I (row tid), s' = s
-        vrow<NW> g;
+        for (int j = tid; j < n; j += nth) {
+            const uint64_t t = a.vn_tab[perm[j]];
+            uint64_t c = 0;
 #pragma unroll
-        for (int k = 0; k < NW; ++k) g[k] = (valid && k == (tid >> 5)) ? (1u << (tid & 31)) : 0u;
+            for (int k = 0; k < CDEG; ++k) {
+                const uint32_t p = (uint32_t)(t >> (16 * k)) & 0xFFFFu;
+                c |= (uint64_t)(p == NOPOS ? (uint32_t)m : p / DEG) << (16 * k);
+            }
+            ptab[j] = c;
+        }
+
+        // ---- 2. G = I, s' = s
+        vrow<NW> g[R];
+        uint32_t sp[R];
+        int pcol[R];
+        uint64_t freem[R];  // wave-uniform: lanes whose row k is valid and not yet a pivot
         const uint32_t *sw = a.synd + shot * a.mw;
-        uint32_t sp = valid ? (sw[tid >> 5] >> (tid & 31)) & 1u : 0u;
-        bool piv = false;
-        int pcol = 0;
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+#pragma unroll
+            for (int w = 0; w < NW; ++w) g[k][w] = (valid[k] && w == (row[k] >> 5)) ? (1u << (row[k] & 31)) : 0u;
+            sp[k] = valid[k] ? (sw[row[k] >> 5] >> (row[k] & 31)) & 1u : 0u;
+            pcol[k] = 0;
+            freem[k] = __ballot(valid[k]);
+        }
         for (int j = tid; j < n; j += nth) isb[j] = 0;
         if (tid < 3) red[tid] = 0u;
         __syncthreads();
@@ -599,71 +631,115 @@ __global__ __launch_bounds__(1024, 8) void osd_reg_kernel(OsdArgs a) {
         // reset, and a slot whose tag is not this column's had no candidate.
         int rank = 0;
         int slot = 0, buf = 0;  // reduction slot rotates over 3, row buffers over 2
-        uint64_t tab = n > 0 ? ptab[0] : ~0ull;
+        uint64_t tab = n > 0 ? ptab[0] : 0ull;
         for (int j = 0; j < n && rank < m; ++j) {
             const uint64_t tu = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(tab >> 32)) << 32) |
                                 __builtin_amdgcn_readfirstlane((uint32_t)tab);
-            if (j + 1 < n) tab = ptab[j + 1];  // prefetch the next column's rows
-            const uint32_t x = reduced_bit<NW>(g, tu);
-            const uint64_t bal = __ballot(valid && x && !piv);
-            const uint32_t tag = (uint32_t)(j + 1) << 16;
-            if (bal) {
-                const int first = __ffsll((unsigned long long)bal) - 1;
-                if (lane == first) {
-                    crow[buf * 16 + wid] = g;
-                    csp[buf * 16 + wid] = sp;
+            if (j + 1 < n) tab = ptab[j + 1];  // prefetch the next column's checks
+            uint32_t x[R];
+            reduced_bits<NW, R>(g, tu, x);
+            uint64_t xm[R];
+#pragma unroll
+            for (int k = 0; k < R; ++k) xm[k] = __ballot(x[k]);
+            // every slot k publishes its lowest free row with a 1 (row buffer k * nwv + wave);
+            // the wave's candidate is the lowest of them (its rows tid precede its rows nth + tid)
+            uint32_t key = 0;
+#pragma unroll
+            for (int k = R - 1; k >= 0; --k) {
+                const uint64_t cm = xm[k] & freem[k];
+                if (cm) {
+                    const int first = __ffsll((unsigned long long)cm) - 1;
+                    if (lane == first) {
+                        crow[buf * 16 + k * nwv + wid] = g[k];
+                        csp[buf * 16 + k * nwv + wid] = sp[k];
+                    }
+                    key = 0xFFFFu - (uint32_t)(k * nth + wid * 64 + first);
                 }
-                if (lane == 0) atomicMax(&red[slot], tag | (0xFFFFu - (uint32_t)(wid * 64 + first)));
             }
+            const uint32_t tag = (uint32_t)(j + 1) << 16;
+            if (key && lane == 0) atomicMax(&red[slot], tag | key);
             __syncthreads();
-            const uint32_t rv = red[slot];
+            const uint32_t rv = __builtin_amdgcn_readfirstlane(red[slot]);
             const int pb = buf;
             slot = slot == 2 ? 0 : slot + 1;
             buf ^= 1;
             if ((rv & 0xFFFF0000u) != tag) continue;  // no row of this column is free
             const int pv = (int)(0xFFFFu - (rv & 0xFFFFu));
-            if (tid == pv) {
-                piv = true;
-                pcol = perm[j];
-                isb[j] = 1;
+            const int pk = (R == 2 && pv >= nth) ? 1 : 0;
+            const int pt = pv - pk * nth;  // the pivot row's thread, in wave pw
+            const int pw = pt >> 6;
+            uint64_t um[R];  // rows to update: every row with a 1 but the pivot row
+#pragma unroll
+            for (int k = 0; k < R; ++k) um[k] = xm[k];
+            if (wid == pw) {
+                const uint64_t bit = 1ull << (pt & 63);
+#pragma unroll
+                for (int k = 0; k < R; ++k)
+                    if (k == pk) {
+                        freem[k] &= ~bit;
+                        um[k] &= ~bit;
+                    }
+                if (lane == (pt & 63)) {
+                    if (pk == 0)
+                        pcol[0] = perm[j];
+                    else
+                        pcol[R - 1] = perm[j];
+                    isb[j] = 1;
+                }
             }
             // reduced columns are sparse early on: waves with no row to update skip the row read
-            if (__ballot(x && tid != pv)) {
-                const vrow<NW> pr = crow[pb * 16 + (pv >> 6)];
-                const uint32_t ps = csp[pb * 16 + (pv >> 6)];
-                if (x && tid != pv) {
-                    g ^= pr;
-                    sp ^= ps;
-                }
+            if (um[0] | um[R - 1]) {
+                const vrow<NW> pr = crow[pb * 16 + pk * nwv + pw];
+                const uint32_t ps = csp[pb * 16 + pk * nwv + pw];
+#pragma unroll
+                for (int k = 0; k < R; ++k)
+                    if ((um[k] >> lane) & 1ull) {
+                        g[k] ^= pr;
+                        sp[k] ^= ps;
+                    }
             }
             ++rank;
         }
+        bool piv[R];
+#pragma unroll
+        for (int k = 0; k < R; ++k) piv[k] = valid[k] && !((freem[k] >> lane) & 1ull);
 
         // ---- consistency: a row with no pivot reduced to 0 = s'_r
-        if (__syncthreads_or(valid && !piv && sp)) {
+        bool bad = false;
+#pragma unroll
+        for (int k = 0; k < R; ++k) bad = bad || (valid[k] && !piv[k] && sp[k]);
+        if (__syncthreads_or(bad)) {
             if (tid == 0) a.flags[shot] = (uint8_t)(FLAG_OSD | FLAG_OSD_INCONSISTENT);
             __syncthreads();
             continue;
         }
 
-        // ---- 4. OSD-CS candidate sweep on per-wave column ballots of G (G is dead afterwards)
+        // ---- 4. OSD-CS candidate sweep on 64-row column ballots of G (G is dead afterwards)
         int t0 = -1, t1 = -1;
-        uint32_t e = sp;
+        uint32_t e[R];
+#pragma unroll
+        for (int k = 0; k < R; ++k) e[k] = sp[k];
         if (a.mode == OSD_CS) {
             const int nt = list_nonbasis(isb, perm, n, tl, scr);
             for (int c = 0; c < m; ++c) {
-                const uint64_t b = __ballot(valid && row_bit<NW>(g, c));
-                if (lane == 0) B[(size_t)wid * m + c] = b;
+#pragma unroll
+                for (int k = 0; k < R; ++k) {
+                    const uint64_t b = __ballot(valid[k] && row_bit<NW>(g[k], c));
+                    if (lane == 0) B[(size_t)(k * nwv + wid) * m + c] = b;
+                }
             }
-            const uint64_t yb = __ballot(valid && sp);
-            if (lane == 0) Y[wid] = yb;
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+                const uint64_t yb = __ballot(valid[k] && sp[k]);
+                if (lane == 0) Y[k * nwv + wid] = yb;
+            }
             if (tid == 0) *best64 = ~0ull;
             __syncthreads();
             uint32_t cost0 = 0;
-            for (int w = 0; w < nwv; ++w) cost0 += __popcll(Y[w]);
+            for (int w = 0; w < ngr; ++w) cost0 += __popcll(Y[w]);
             unsigned long long best = (unsigned long long)cost0 << 32;
             for (int ai = tid; ai < nt; ai += nth) {
-                unsigned long long cost = 1 + ballot_cost(B, Y, m, nwv, a.vn_tab[tl[ai]], ~0ull);
+                unsigned long long cost = 1 + ballot_cost(B, Y, m, ngr, a.vn_tab[tl[ai]], ~0ull);
                 unsigned long long key = (cost << 32) | (unsigned long long)(1 + ai);
                 best = key < best ? key : best;
             }
@@ -672,7 +748,7 @@ __global__ __launch_bounds__(1024, 8) void osd_reg_kernel(OsdArgs a) {
             for (int pi = tid; pi < npairs; pi += nth) {
                 int aa, bb;
                 pair_of(pi, w, aa, bb);
-                unsigned long long cost = 2 + ballot_cost(B, Y, m, nwv, a.vn_tab[tl[aa]], a.vn_tab[tl[bb]]);
+                unsigned long long cost = 2 + ballot_cost(B, Y, m, ngr, a.vn_tab[tl[aa]], a.vn_tab[tl[bb]]);
                 unsigned long long key = (cost << 32) | (unsigned long long)(1 + nt + pi);
                 best = key < best ? key : best;
             }
@@ -688,16 +764,21 @@ __global__ __launch_bounds__(1024, 8) void osd_reg_kernel(OsdArgs a) {
                 t0 = tl[aa];
                 t1 = tl[bb];
             }
-            // this row's bit of the chosen candidate's reduced columns, from the ballots
+            // each row's bit of the chosen candidate's reduced columns, from the ballots
             const uint64_t tab0 = t0 >= 0 ? a.vn_tab[t0] : ~0ull, tab1 = t1 >= 0 ? a.vn_tab[t1] : ~0ull;
-            const uint64_t xb = ballot_cost_mask(B, m, wid, tab0, tab1);
-            e ^= (uint32_t)(xb >> lane) & 1u;
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+                const uint64_t xb = ballot_cost_mask(B, m, k * nwv + wid, tab0, tab1);
+                e[k] ^= (uint32_t)(xb >> lane) & 1u;
+            }
         }
 
         // ---- 5. e_S = s' + G H_T t on the basis, t on the rest; scatter to columns
         for (int ww = tid; ww < a.nw; ww += nth) cw[ww] = 0u;
         __syncthreads();
-        if (valid && piv && e) atomicOr(&cw[pcol >> 5], 1u << (pcol & 31));
+#pragma unroll
+        for (int k = 0; k < R; ++k)
+            if (valid[k] && piv[k] && e[k]) atomicOr(&cw[pcol[k] >> 5], 1u << (pcol[k] & 31));
         if (tid == 0) {
             if (t0 >= 0) atomicOr(&cw[t0 >> 5], 1u << (t0 & 31));
             if (t1 >= 0) atomicOr(&cw[t1 >> 5], 1u << (t1 & 31));
@@ -711,7 +792,8 @@ __global__ __launch_bounds__(1024, 8) void osd_reg_kernel(OsdArgs a) {
 
 }  // namespace
 
-int osd_block_bytes(int m, int n, int lds_limit, int *variant, int *mws, int *sort_p, int *threads) {
+int osd_block_bytes(int m, int n, int lds_limit, int rows_per_lane, int *variant, int *mws, int *sort_p,
+                    int *threads) {
     int P = 1;
     while (P < n) P <<= 1;
     int mw = (m + 31) / 32;
@@ -720,11 +802,12 @@ int osd_block_bytes(int m, int n, int lds_limit, int *variant, int *mws, int *so
     *sort_p = P;
     size_t common = al((size_t)n * 4) + al((size_t)n * 2) * 2 + al((size_t)n) + al((size_t)((n + 31) / 32) * 4) +
                     16 * 4 + 32 * 4 + 16;
-    if (m <= 1024) {
-        int nw = m <= 256 ? 8 : (m <= 512 ? 16 : (m <= 896 ? 28 : 32));
-        *variant = nw;
+    if (m < 1024) {  // m < 32 NW: bit m of every row is a zero bit
+        int nw = m < 256 ? 8 : (m < 512 ? 16 : (m < 896 ? 28 : 32));
+        const int r = rows_per_lane == 1 ? 1 : 2;
+        *variant = 100 * r + nw;
         *mws = mw;
-        *threads = 64 * ((m + 63) / 64);
+        *threads = 64 * ((m + 64 * r - 1) / (64 * r));
         size_t vb = 4;  // a vector of nw words occupies the next power of two bytes
         while (vb < (size_t)nw * 4) vb <<= 1;
         return (int)(al((size_t)P * 8) + common + al(32 * vb) + 32 * 4 + 16 * 8);
@@ -784,11 +867,16 @@ static hipError_t launch_k(K kern, const OsdArgs &a, int blocks, int threads, in
 
 hipError_t launch_osd(const OsdArgs &a, int variant, int blocks, int threads, int lds, hipStream_t s) {
     switch (variant) {
-    case 8: return launch_k(osd_reg_kernel<8>, a, blocks, threads, lds, s);
-    case 16: return launch_k(osd_reg_kernel<16>, a, blocks, threads, lds, s);
-    case 28: return launch_k(osd_reg_kernel<28>, a, blocks, threads, lds, s);
-    case 32: return launch_k(osd_reg_kernel<32>, a, blocks, threads, lds, s);
-    default: return launch_k(osd_lds_kernel, a, blocks, threads, lds, s);
+    case 108: return launch_k(osd_reg_kernel<8, 1>, a, blocks, threads, lds, s);
+    case 116: return launch_k(osd_reg_kernel<16, 1>, a, blocks, threads, lds, s);
+    case 128: return launch_k(osd_reg_kernel<28, 1>, a, blocks, threads, lds, s);
+    case 132: return launch_k(osd_reg_kernel<32, 1>, a, blocks, threads, lds, s);
+    case 208: return launch_k(osd_reg_kernel<8, 2>, a, blocks, threads, lds, s);
+    case 216: return launch_k(osd_reg_kernel<16, 2>, a, blocks, threads, lds, s);
+    case 228: return launch_k(osd_reg_kernel<28, 2>, a, blocks, threads, lds, s);
+    case 232: return launch_k(osd_reg_kernel<32, 2>, a, blocks, threads, lds, s);
+    case 0: case -1: case -2: return launch_k(osd_lds_kernel, a, blocks, threads, lds, s);
+    default: return hipErrorInvalidValue;
     }
 }
 
@@ -801,11 +889,16 @@ static hipError_t occ_k(K kern, int threads, int lds, int *out) {
 
 hipError_t osd_max_blocks_per_cu(int variant, int threads, int lds, int *out) {
     switch (variant) {
-    case 8: return occ_k(osd_reg_kernel<8>, threads, lds, out);
-    case 16: return occ_k(osd_reg_kernel<16>, threads, lds, out);
-    case 28: return occ_k(osd_reg_kernel<28>, threads, lds, out);
-    case 32: return occ_k(osd_reg_kernel<32>, threads, lds, out);
-    default: return occ_k(osd_lds_kernel, threads, lds, out);
+    case 108: return occ_k(osd_reg_kernel<8, 1>, threads, lds, out);
+    case 116: return occ_k(osd_reg_kernel<16, 1>, threads, lds, out);
+    case 128: return occ_k(osd_reg_kernel<28, 1>, threads, lds, out);
+    case 132: return occ_k(osd_reg_kernel<32, 1>, threads, lds, out);
+    case 208: return occ_k(osd_reg_kernel<8, 2>, threads, lds, out);
+    case 216: return occ_k(osd_reg_kernel<16, 2>, threads, lds, out);
+    case 228: return occ_k(osd_reg_kernel<28, 2>, threads, lds, out);
+    case 232: return occ_k(osd_reg_kernel<32, 2>, threads, lds, out);
+    case 0: case -1: case -2: return occ_k(osd_lds_kernel, threads, lds, out);
+    default: return hipErrorInvalidValue;
     }
 }
 

@@ -472,8 +472,12 @@ lbp_status lbp_decoder_create(lbp_code code, const lbp_params *prm, int64_t max_
     // ---- OSD workspace
     d->fail_cap = prm->osd ? std::min<int64_t>(max_batch, std::max<int64_t>(1024, ((int64_t)256 << 20) / ((int64_t)code->n * 8)))
                            : 0;
-    // the OSD kernel also holds a little static LDS (block-wide reductions)
-    d->osd_lds = osd_block_bytes(code->m, code->n, lds_block - 1024, &d->osd_variant, &d->mws, &d->sort_p,
+    // the OSD kernel also holds a little static LDS (block-wide reductions).  Codes
+    // with < 1024 checks keep G in registers, two rows per lane unless
+    // LBP_OSD_ROWS_PER_LANE=1 (read here) asks for one, for tests.
+    const char *rpl_env = std::getenv("LBP_OSD_ROWS_PER_LANE");
+    const int rpl = rpl_env && std::atoi(rpl_env) == 1 ? 1 : 2;
+    d->osd_lds = osd_block_bytes(code->m, code->n, lds_block - 1024, rpl, &d->osd_variant, &d->mws, &d->sort_p,
                                  &d->osd_threads);
     if (d->osd_lds > lds_block - 1024) return cleanup_fail(LBP_EUNSUPPORTED, "lbp_decoder_create: OSD sort does not fit LDS");
     int obpc = 0;
