@@ -148,7 +148,9 @@ int32_t lbp_code_cols(lbp_code code);
  * wavefront per shot, or a workgroup of 2-16 waves per shot when fewer than 32
  * one-wave shots fit a CU.  The environment variable LBP_BP_GROUP=g, read
  * here, forces workgroups of g waves (it changes no result; it exists to test
- * that variant on small codes). */
+ * that variant on small codes).  OSD keeps G in registers for codes with
+ * fewer than 1024 checks, two rows per lane; LBP_OSD_ROWS_PER_LANE=1, read
+ * here, selects one row per lane (same results; for tests). */
 lbp_status lbp_decoder_create(lbp_code code, const lbp_params *prm, int64_t max_batch, lbp_decoder *out);
 void lbp_decoder_destroy(lbp_decoder dec);
 

@@ -136,16 +136,23 @@ __device__ int block_excl_scan(int x, int *scr, int *total) {
 }
 
 // Step 1 (LLR sorting): perm[j] = j-th column in ascending (lambda, column)
-// order, lambda = hi + lo.  Bitonic sort of (orderable(hi) << 32 | column) in
-// `keys` (P entries), then each run of equal hi is ordered by lo with a stable
-// insertion sort (runs only exist with a non-zero lo, i.e. fp32 messages).
-__device__ void sort_columns(const float *lam, int n, int P, int has_lo, unsigned long long *keys, float *lo_s,
+// order, lambda = hi + lo.  Bitonic sort of P u64 keys: without a lo part the
+// key is orderable(hi) << 32 | column; with one (fp32 messages) it is
+// orderable(hi) << 32 | orderable(lo), and the column rides along in `cols`
+// (P u16; P < 2n, so they fit the space of n floats) as the tie-break.
+__device__ void sort_columns(const float *lam, int n, int P, int has_lo, unsigned long long *keys, uint16_t *cols,
                              uint16_t *perm) {
     const int tid = threadIdx.x, nth = blockDim.x;
-    for (int j = tid; j < P; j += nth)
-        keys[j] = j < n ? (((unsigned long long)orderable(lam[j]) << 32) | (unsigned)j) : ~0ull;
-    if (has_lo)
-        for (int j = tid; j < n; j += nth) lo_s[j] = lam[n + j];
+    for (int j = tid; j < P; j += nth) {
+        if (j < n) {
+            const unsigned long long h = (unsigned long long)orderable(lam[j]) << 32;
+            keys[j] = h | (has_lo ? orderable(lam[n + j]) : (unsigned)j);
+            if (has_lo) cols[j] = (uint16_t)j;
+        } else {
+            keys[j] = ~0ull;
+            if (has_lo) cols[j] = 0xFFFFu;
+        }
+    }
     __syncthreads();
     for (int k = 2; k <= P; k <<= 1) {
         for (int jj = k >> 1; jj > 0; jj >>= 1) {
@@ -154,31 +161,20 @@ __device__ void sort_columns(const float *lam, int n, int P, int has_lo, unsigne
                 int l = i + jj;
                 bool asc = (i & k) == 0;
                 unsigned long long x = keys[i], y = keys[l];
-                if ((x > y) == asc) { keys[i] = y; keys[l] = x; }
+                if (has_lo) {
+                    const uint16_t cx = cols[i], cy = cols[l];
+                    if ((x > y || (x == y && cx > cy)) == asc) {
+                        keys[i] = y; keys[l] = x;
+                        cols[i] = cy; cols[l] = cx;
+                    }
+                } else if ((x > y) == asc) {
+                    keys[i] = y; keys[l] = x;
+                }
             }
             __syncthreads();
         }
     }
-    if (has_lo) {
-        for (int j = tid; j < n; j += nth) {
-            const uint32_t h = (uint32_t)(keys[j] >> 32);
-            if (j > 0 && (uint32_t)(keys[j - 1] >> 32) == h) continue;  // not the start of a run
-            int e = j + 1;
-            while (e < n && (uint32_t)(keys[e] >> 32) == h) ++e;
-            for (int x = j + 1; x < e; ++x) {
-                unsigned long long kx = keys[x];
-                uint32_t ox = orderable(lo_s[kx & 0xFFFFu]);
-                int y = x - 1;
-                while (y >= j && orderable(lo_s[keys[y] & 0xFFFFu]) > ox) {
-                    keys[y + 1] = keys[y];
-                    --y;
-                }
-                keys[y + 1] = kx;
-            }
-        }
-        __syncthreads();
-    }
-    for (int j = tid; j < n; j += nth) perm[j] = (uint16_t)(keys[j] & 0xFFFFu);
+    for (int j = tid; j < n; j += nth) perm[j] = has_lo ? cols[j] : (uint16_t)(keys[j] & 0xFFFFu);
     __syncthreads();
 }
 
@@ -227,7 +223,7 @@ __global__ __launch_bounds__(1024, 8) void osd_lds_kernel(OsdArgs a) {
         c0 = smem + rbytes;
         q0 = nullptr;
     }
-    float *lo_s = (float *)c0;                       c0 += ((size_t)n * 4 + 15) & ~(size_t)15;
+    uint16_t *scol = (uint16_t *)c0;                 c0 += ((size_t)n * 4 + 15) & ~(size_t)15;
     uint16_t *perm = (uint16_t *)c0;                 c0 += ((size_t)n * 2 + 15) & ~(size_t)15;
     uint16_t *tl = (uint16_t *)c0;                   c0 += ((size_t)n * 2 + 15) & ~(size_t)15;
     uint8_t *isb = c0;                               c0 += ((size_t)n + 15) & ~(size_t)15;
@@ -267,7 +263,7 @@ __global__ __launch_bounds__(1024, 8) void osd_lds_kernel(OsdArgs a) {
         const float *lam = a.fail_llr + (size_t)(a.llr_by_shot ? shot : (int64_t)q) * 2 * n;  // hi[n] then lo[n]
 
         // ---- 1. sort (lambda, column) ascending
-        sort_columns(lam, n, P, a.has_lo, keys, lo_s, perm);
+        sort_columns(lam, n, P, a.has_lo, keys, scol, perm);
 
         // ---- 2. G = I, s' = s
         const int mw = a.mw;
@@ -567,7 +563,7 @@ __global__ __launch_bounds__(1024 / R, 8 / R) void osd_reg_kernel(OsdArgs a) {
         valid[k] = row[k] < m;
     }
     unsigned char *q0 = smem + (((size_t)P * 8 + 15) & ~(size_t)15);
-    float *lo_s = (float *)q0;                       q0 += ((size_t)n * 4 + 15) & ~(size_t)15;
+    uint16_t *scol = (uint16_t *)q0;                 q0 += ((size_t)n * 4 + 15) & ~(size_t)15;
     uint16_t *perm = (uint16_t *)q0;                 q0 += ((size_t)n * 2 + 15) & ~(size_t)15;
     uint16_t *tl = (uint16_t *)q0;                   q0 += ((size_t)n * 2 + 15) & ~(size_t)15;
     uint8_t *isb = q0;                               q0 += ((size_t)n + 15) & ~(size_t)15;
@@ -590,7 +586,7 @@ __global__ __launch_bounds__(1024 / R, 8 / R) void osd_reg_kernel(OsdArgs a) {
         const float *lam = a.fail_llr + (size_t)(a.llr_by_shot ? shot : (int64_t)q) * 2 * n;
 
         // ---- 1. sort (lambda, column) ascending
-        sort_columns(lam, n, P, a.has_lo, (unsigned long long *)smem, lo_s, perm);
+        sort_columns(lam, n, P, a.has_lo, (unsigned long long *)smem, scol, perm);
 
         // check indices of the sorted columns, staged over the dead sort keys
         uint64_t *ptab = (uint64_t *)smem;
@@ -844,7 +840,7 @@ size_t osd_scratch_layout(int variant, int m, int n, int mws, int sort_p, int cs
     if (variant > 0) return (size_t)16 * m * 8;       // per-wave column ballots
     size_t b = 0;
     if (variant == -1) b = a256((size_t)m * mws * 4);  // G
-    if (variant == -2)                                 // G, sort keys, lambda lo, order, non-basis list, flags
+    if (variant == -2)                                 // G, sort keys, sort columns, order, non-basis list, flags
         b = a256(a256((size_t)m * mws * 4) + a256((size_t)sort_p * 8) + al((size_t)n * 4) + 2 * al((size_t)n * 2) +
                  al((size_t)n));
     *cs_off = b;
