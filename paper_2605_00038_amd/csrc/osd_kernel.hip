@@ -570,7 +570,7 @@ __global__ __launch_bounds__(1024 / R, 8 / R) void osd_reg_kernel(OsdArgs a) {
     vrow<NW> *crow = (vrow<NW> *)q0;                 q0 += (32 * sizeof(vrow<NW>) + 15) & ~(size_t)15;
     uint32_t *csp = (uint32_t *)q0;                  q0 += 32 * 4;
     uint32_t *cw = (uint32_t *)q0;                   q0 += ((size_t)a.nw * 4 + 15) & ~(size_t)15;
-    uint32_t *red = (uint32_t *)q0;                  q0 += 16 * 4;
+    uint32_t *wkey = (uint32_t *)q0;                 q0 += 32 * 4;  // per wave and row buffer: candidate key
     int *scr = (int *)q0;                            q0 += 32 * 4;
     unsigned long long *Y = (unsigned long long *)q0; q0 += 16 * 8;
     unsigned long long *best64 = (unsigned long long *)q0;
@@ -616,17 +616,16 @@ __global__ __launch_bounds__(1024 / R, 8 / R) void osd_reg_kernel(OsdArgs a) {
             freem[k] = __ballot(valid[k]);
         }
         for (int j = tid; j < n; j += nth) isb[j] = 0;
-        if (tid < 3) red[tid] = 0u;
+        if (tid < 32) wkey[tid] = 0u;  // slots of waves that do not exist stay 0
         __syncthreads();
 
         // ---- 3. Gauss-Jordan in sorted column order, one block barrier per column:
         // each wave publishes its first candidate row before the barrier, so the
-        // winner's row is already in LDS when the pivot is known.  The candidates
-        // meet in red[] by atomicMax of (j + 1) << 16 | (0xFFFF - row): the column's
-        // tag outranks every older entry, so the three rotating slots never need a
-        // reset, and a slot whose tag is not this column's had no candidate.
+        // winner's row is already in LDS when the pivot is known.  Each wave also
+        // writes its key 0xFFFF - row (0: no candidate) to its slot, every step;
+        // after the barrier every wave takes the maximum over the slots.
         int rank = 0;
-        int slot = 0, buf = 0;  // reduction slot rotates over 3, row buffers over 2
+        int buf = 0;  // row buffers and key slots alternate over 2
         uint64_t tab = n > 0 ? ptab[0] : 0ull;
         for (int j = 0; j < n && rank < m; ++j) {
             const uint64_t tu = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(tab >> 32)) << 32) |
@@ -652,15 +651,24 @@ __global__ __launch_bounds__(1024 / R, 8 / R) void osd_reg_kernel(OsdArgs a) {
                     key = 0xFFFFu - (uint32_t)(k * nth + wid * 64 + first);
                 }
             }
-            const uint32_t tag = (uint32_t)(j + 1) << 16;
-            if (key && lane == 0) atomicMax(&red[slot], tag | key);
+            if (lane == 0) wkey[buf * 16 + wid] = key;
             __syncthreads();
-            const uint32_t rv = __builtin_amdgcn_readfirstlane(red[slot]);
+            uint32_t kmax = 0;
+            {
+                const uint4 *kv = (const uint4 *)(wkey + buf * 16);
+#pragma unroll
+                for (int q4 = 0; q4 < 4; ++q4) {
+                    const uint4 v = kv[q4];
+                    const uint32_t a01 = v.x > v.y ? v.x : v.y, a23 = v.z > v.w ? v.z : v.w;
+                    const uint32_t a = a01 > a23 ? a01 : a23;
+                    kmax = a > kmax ? a : kmax;
+                }
+            }
+            const uint32_t rv = __builtin_amdgcn_readfirstlane(kmax);
             const int pb = buf;
-            slot = slot == 2 ? 0 : slot + 1;
             buf ^= 1;
-            if ((rv & 0xFFFF0000u) != tag) continue;  // no row of this column is free
-            const int pv = (int)(0xFFFFu - (rv & 0xFFFFu));
+            if (rv == 0) continue;  // no row of this column is free
+            const int pv = (int)(0xFFFFu - rv);
             const int pk = (R == 2 && pv >= nth) ? 1 : 0;
             const int pt = pv - pk * nth;  // the pivot row's thread, in wave pw
             const int pw = pt >> 6;
@@ -806,7 +814,7 @@ int osd_block_bytes(int m, int n, int lds_limit, int rows_per_lane, int *variant
         *threads = 64 * ((m + 64 * r - 1) / (64 * r));
         size_t vb = 4;  // a vector of nw words occupies the next power of two bytes
         while (vb < (size_t)nw * 4) vb <<= 1;
-        return (int)(al((size_t)P * 8) + common + al(32 * vb) + 32 * 4 + 16 * 8);
+        return (int)(al((size_t)P * 8) + common + al(32 * vb) + 32 * 4 + 16 * 8 + 16 * 4);  // key slots: 32 words
     }
     *threads = OSD_THREADS;
     // pivot row words, s' ballots, and for G in global memory at large m its occupancy mask
