@@ -1,6 +1,8 @@
 // OSD-0 (Algorithm 2) and OSD-CS for the shots whose BP run did not converge.
 //
-// One 1024-thread workgroup per failed shot (persistent over the failure list).
+// One workgroup per failed shot (persistent over the failure list): 1024 or 512
+// threads with G in LDS or global memory, one or two rows of G per lane with G
+// in registers (m < 1024).
 //  1. LLR sorting: bitonic sort of (orderable(lambda) << 32 | column) keys in
 //     LDS, i.e. ascending lambda with ties broken by column (stable order).
 //  2. Basis selection + LU/forward substitution as one Gauss-Jordan sweep in
