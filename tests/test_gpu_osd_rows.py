@@ -58,3 +58,38 @@ def test_two_rows_match_one_row_and_oracle(case, monkeypatch):
         o = oracle.decode(h, p, oracle_params(prm), syn, first_shot_id=5, want_llr=True, n_threads=8)
         for k in ("corr", "flags", "iters", "llr"):
             assert (two[k] == o[k]).all(), k
+
+
+def _random_code(m, n, cdeg, seed):
+    """Random code with column degree <= cdeg and row degree <= n * cdeg / m
+    (configuration model, repeated edges dropped; n * cdeg divisible by m)."""
+    import numpy as np
+    import scipy.sparse as sps
+    rng = np.random.default_rng(seed)
+    cols = np.repeat(np.arange(n), cdeg)
+    assert len(cols) % m == 0
+    rows = rng.permutation(np.repeat(np.arange(m), len(cols) // m))
+    h = sps.csr_matrix((np.ones(len(cols), dtype=np.uint8), (rows, cols)), shape=(m, n))
+    h.data[:] = 1  # repeated (row, column) pairs were summed: keep one edge
+    h.eliminate_zeros()
+    return h
+
+
+@pytest.mark.parametrize("m", [1023, 1024], ids=["m1023-registers", "m1024-lds"])
+@pytest.mark.parametrize("osd", [1, 2], ids=["osd0", "osdcs"])
+def test_register_kernel_boundary(m, osd):
+    """The last size with G in registers (m = 1023: rows 512..1022 in the second
+    slot of 511 lanes) and the first with G in LDS, on random codes whose rows
+    reach the 8-slot limit; Int3.4 bit-exact against the oracle."""
+    from workloads import sample
+    h = _random_code(m, 2 * m, 4, 1700 + m)
+    assert h.shape == (m, 2 * m) and h.getnnz(axis=1).max() <= 8 and h.getnnz(axis=0).max() <= 4
+    p = 0.07
+    e, syn = sample.make_batch(h, p, 60, 1710 + m)
+    prm = _params(msg=2, max_iter=8, lottery=False, osd=osd, osd_order=10)
+    _say("osd boundary", m, osd)
+    g = gpu_decode(h, p, prm, syn, want_llr=True)
+    o = oracle.decode(h, p, oracle_params(prm), syn, want_llr=True, n_threads=8)
+    assert ((g["flags"] & 2) != 0).sum() >= 20
+    for k in ("corr", "flags", "iters", "llr"):
+        assert (g[k] == o[k]).all(), k
