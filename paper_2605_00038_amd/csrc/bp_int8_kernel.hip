@@ -401,9 +401,12 @@ __global__ __launch_bounds__(1024) void bp_int8_kernel(BpArgs a) {
         float *llr_row = a.llr_out ? a.llr_out + shot * n : nullptr;
         const uint32_t *syn_row = (a.ring ? a.ring->syn : a.synd) + shot * C.mw;
 
+        // SH1 is the estimate "before iteration 0" that the lottery of iteration 0
+        // reads when K = 0: the hard decision of the prior, H * 0 = 0
         for (int w = lane; w < C.mw; w += 64) {
             uint32_t x = syn_row[w];
             S[w] = w == C.mw - 1 ? (x & last_mask) : x;
+            SH1[w] = 0u;
         }
         // lambda^(-1) = mu in both halves (Algorithm 1 initialisation: alpha^(0) = mu)
         for (int v = lane; v < nl; v += 64) {

@@ -569,9 +569,12 @@ __global__ __launch_bounds__(1024) void bp_kernel(BpArgs a) {
 
         // padding bits of the last word are ignored (they could otherwise name checks >= m)
         const uint32_t last_mask = (C.m & 31) ? ((1u << (C.m & 31)) - 1u) : ~0u;
+        // SH1 is the estimate "before iteration 0" that the lottery of iteration 0
+        // reads when K = 0: the hard decision of the prior, H * 0 = 0
         for (int w = t0; w < C.mw; w += tn) {
             uint32_t x = syn_row[w];
             S[w] = w == C.mw - 1 ? (x & last_mask) : x;
+            SH1[w] = 0u;
         }
         // alpha^(0) = mu (Algorithm 1 initialisation); padding slots get the sentinel.
         for (int c = t0; c < C.m; c += tn) {

@@ -41,6 +41,11 @@ INT8_CASES = [
     # unrotated (planar) surface code, the layout of Table II: 720 x 1953 (d=9), 4896 x 13889 (d=17)
     ("usurface9_phenpf", 0.004, 2000, 1009, dict(max_iter=100, lottery=True, osd=2, osd_order=10, seed=14)),
     ("usurface17_phenpf", 0.002, 96, 1011, dict(max_iter=100, lottery=True, osd=1, seed=15)),
+    # K = 0: the first lottery reads the estimate before iteration 0 (all zero); 20000
+    # shots of a small code give every wave many shots, so a stale estimate would show
+    ("surface5_phen", 0.02, 20000, 1014, dict(max_iter=60, lottery=True, lottery_skip=0, osd=1, seed=18)),
+    ("bb144_phen", 0.006, 4000, 1015, dict(max_iter=100, lottery=True, lottery_skip=0, osd=1, seed=19)),
+    ("surface13_phen", 0.003, 300, 1016, dict(max_iter=100, lottery=True, lottery_skip=0, osd=1, seed=20)),
 ]
 
 
@@ -79,6 +84,7 @@ FLOAT_CASES = [
     ("bb144_cc", 0.04, 3000, 1032, dict(max_iter=100, lottery=True, osd=1, seed=2032)),
     ("surface5_cc", 0.05, 3000, 1001, dict(max_iter=50, scale_mode=1, scale=0.625, lottery=False, osd=1)),
     ("surface9_phenpf", 0.003, 3000, 1007, dict(max_iter=100, lottery=True, osd=2, seed=12)),
+    ("surface5_phen", 0.02, 20000, 1014, dict(max_iter=60, lottery=True, lottery_skip=0, osd=1, seed=18)),
 ]
 
 
