@@ -199,8 +199,9 @@ lbp_status lbp_decode_host(lbp_decoder dec, int64_t n_shots, uint64_t first_shot
 int64_t lbp_decoder_device_bytes(lbp_decoder dec);
 int64_t lbp_decoder_max_batch(lbp_decoder dec);
 
-/* Number of failed shots whose lambda one OSD pass can stage (n*8 bytes each;
- * initially 256 MiB worth).  Failures beyond it are re-decoded (BP is
+/* Number of failed shots whose lambda one OSD pass can stage (2n bytes each as
+ * int16 for Int x.y codes of at most 1024 checks, else 8n bytes as an fp32
+ * (hi, lo) pair; initially 256 MiB worth).  Failures beyond it are re-decoded (BP is
  * deterministic) and handled in a further pass; when the overflow exceeds the
  * capacity, lbp_decode first grows the staging to the overflow, bounded by
  * max_batch and a quarter of the free device memory, so a high OSD invoke rate
@@ -246,7 +247,8 @@ lbp_status lbp_decoder_kernel_times(lbp_decoder dec, double *bp_ms, int64_t *bp_
 lbp_status lbp_server_create(int64_t device_mem_budget_bytes, int32_t max_slots, lbp_server *out);
 /* Register a code with its decoding parameters (params.seed is ignored: each
  * request brings its own).  Picks the largest ring (power of two, 1024 ..
- * 65536 shots; 8n bytes of device memory per shot) that fits the remaining
+ * 65536 shots; per shot 2n bytes of device memory for Int x.y codes of at most
+ * 1024 checks, else 8n, for the lambda of shots left to OSD) that fits the remaining
  * budget: LBP_ENOMEM if none does, LBP_EBUSY if all slots are taken.  The
  * slot holds a reference to the code (as a decoder does). */
 lbp_status lbp_server_add_code(lbp_server srv, lbp_code code, const lbp_params *prm, int32_t *code_slot);

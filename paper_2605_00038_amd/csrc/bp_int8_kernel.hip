@@ -97,9 +97,11 @@ __device__ __forceinline__ int lambda_next(const uint32_t *L, int v, int nxt_hi)
     return (int)(nxt_hi ? (w >> 16) : (w & 0xFFFFu)) - BIAS;
 }
 
-// Worst check of U (Sec. III-B): the most neighbours in the hard decision EH,
-// the smallest index among equals.  One check per lane, wave-wide maximum.
-__device__ int worst_check(const DevCode &C, const uint32_t *S, const uint32_t *SHp, const uint32_t *EH, int lane) {
+// Worst check of U (Sec. III-B): the most neighbours in the current hard
+// decision (lambda^(i) <= 0, read from the half nxt_hi), the smallest index
+// among equals.  One check per lane, wave-wide maximum.
+__device__ int worst_check(const DevCode &C, const uint32_t *S, const uint32_t *SHp, const uint32_t *L, int nxt_hi,
+                           int lane) {
     unsigned long long best = 0;
     for (int c0 = 0; c0 < C.m; c0 += 64) {
         const int c = c0 + lane;
@@ -108,7 +110,7 @@ __device__ int worst_check(const DevCode &C, const uint32_t *S, const uint32_t *
             const int deg = C.cn_deg[c];
             for (int k = 0; k < deg; ++k) {
                 const uint32_t v = C.cn_cols[c * DEG + k];
-                cnt += (EH[v >> 5] >> (v & 31)) & 1u;
+                cnt += lambda_next(L, (int)v, nxt_hi) <= 0;
             }
             const unsigned long long key = ((unsigned long long)(cnt + 1) << 32) | (0xFFFFFFFFu - (uint32_t)c);
             best = key > best ? key : best;
@@ -127,7 +129,7 @@ __device__ int worst_check(const DevCode &C, const uint32_t *S, const uint32_t *
 // random or worst check; proposed key (count, Q, column), Q-first (Q, count,
 // column), unreliable (Q, column) or a random neighbour.  Q = |lambda|.
 __device__ int lottery_pick_q(const DevCode &C, int rule, uint64_t seed, uint64_t shot_id, int i, const uint32_t *L,
-                              int nxt_hi, const uint32_t *S, const uint32_t *SHp, const uint32_t *EH, int lane) {
+                              int nxt_hi, const uint32_t *S, const uint32_t *SHp, int lane) {
     int N = 0;
     for (int w0 = 0; w0 < C.mw; w0 += 64) {
         int w = w0 + lane;
@@ -139,7 +141,7 @@ __device__ int lottery_pick_q(const DevCode &C, int rule, uint64_t seed, uint64_
     const uint64_t x = philox_w01(seed, shot_id, (uint64_t)i, x1);
     int cstar = 0;
     if (cn_rule == LOT_CN_WORST) {
-        cstar = __builtin_amdgcn_readfirstlane(worst_check(C, S, SHp, EH, lane));
+        cstar = __builtin_amdgcn_readfirstlane(worst_check(C, S, SHp, L, nxt_hi, lane));
     } else {
         uint32_t k = (uint32_t)(((x >> 32) * (uint64_t)N) >> 32);
         for (int w0 = 0; w0 < C.mw; w0 += 64) {
@@ -213,8 +215,8 @@ constexpr uint32_t SEL_PACK = 0x06020400u;  // src0 = (b1, b3), src1 = (b0, b2) 
 // other half.  FLIP: the wave-uniform flip path (fo = v*'s offset in both halves).
 template <int PAR, bool FLIP, bool LLR_FLIP>
 __device__ __forceinline__ void check_update(const uint4 cw, uint32_t &bw0, uint32_t &bw1, uint32_t syn_bit,
-                                             unsigned char *Lb, uint32_t base, int sh, int scale_mode, int scale_k,
-                                             uint32_t fo, uint32_t qm2) {
+                                             unsigned char *Lb, uint32_t base, v2u16 kmul, v2u16 shv, uint32_t fo,
+                                             uint32_t qm2) {
     const uint32_t T[4] = {cw.x, cw.y, cw.z, cw.w};  // (off1,off3) (off0,off2) (off5,off7) (off4,off6)
     // ---- gather lambda^(i-1) of the eight columns into four pairs
     uint32_t lam[4];
@@ -273,18 +275,15 @@ __device__ __forceinline__ void check_update(const uint4 cw, uint32_t &bw0, uint
     const uint32_t m2m = m2a < m2c ? m2a : m2c;
     const uint32_t k2 = hi1 < m2m ? hi1 : m2m;
     const uint32_t par = (((px ^ (px >> 16)) >> 15) & 1u) ^ syn_bit;
-    const int g1 = (int)(k1 >> 3), g2 = (int)(k2 >> 3);
-    int s1, s2;
-    if (scale_mode == 1) {
-        s1 = (scale_k * g1) >> 3;
-        s2 = (scale_k * g2) >> 3;
-    } else {
-        s1 = g1 - (g1 >> sh);
-        s2 = g2 - (g2 >> sh);
-    }
+    // the scale on both magnitudes g = key >> 3 at once: s = ((K g) >> 3) - (g >> SH), with
+    // (K, SH) = (8, min(i+1, 15)) for sigma_i (g - (g >> (i+1)); g < 2^7, so SH = 15 covers
+    // every i >= 14) and (k, 15) for a constant k/8 ((k g) >> 3)
+    const v2u16 gg = (v2u16){(unsigned short)k1, (unsigned short)k2} >> (v2u16){3, 3};
+    const v2u16 ss = ((gg * kmul) >> (v2u16){3, 3}) - (gg >> shv);
+    const v2u16 s11 = __builtin_shufflevector(ss, ss, 0, 0), s22 = __builtin_shufflevector(ss, ss, 1, 1);
     const v2u16 k1p = {(unsigned short)(k1 + 1), (unsigned short)(k1 + 1)};
-    const uint32_t s1p = (uint32_t)s1 | ((uint32_t)s1 << 16);
-    const uint32_t dxp = (uint32_t)(s1 ^ s2) | ((uint32_t)(s1 ^ s2) << 16);
+    const uint32_t s1p = as_u32(s11);
+    const uint32_t dxp = as_u32(s11 ^ s22);
     const uint32_t pp = par ? 0x80008000u : 0u;
     uint32_t nb[4];
     v2i16 eq[4], sm[4];
@@ -318,22 +317,65 @@ __device__ __forceinline__ void check_update(const uint4 cw, uint32_t &bw0, uint
     bw1 = __builtin_amdgcn_perm(nb[2], nb[3], SEL_PACK);
 }
 
-// The check pass of one iteration over all of the lane's checks.
+// The check pass of one iteration over all of the lane's checks.  flipslots (bit s:
+// slot s holds a check of v*) is wave-uniform, so the flip variant is a scalar branch.
 template <int SLOTS, int PAR, bool LLR_FLIP>
 __device__ __forceinline__ void check_pass(const uint4 *cidx4, uint32_t (&bq)[SLOTS][2], uint32_t srow,
-                                           unsigned char *Lb, uint32_t base, int lane, int sh, int scale_mode,
-                                           int scale_k, uint32_t flipslots, uint32_t fo, uint32_t qm2) {
+                                           unsigned char *Lb, uint32_t base, int lane, v2u16 kmul, v2u16 shv,
+                                           uint32_t flipslots, uint32_t fo, uint32_t qm2) {
+    const uint32_t fs = __builtin_amdgcn_readfirstlane(flipslots);
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
         const uint4 cw = cidx4[s * 64 + lane];
         const uint32_t sb = (srow >> s) & 1u;
-        if (flipslots & (1u << s))
-            check_update<PAR, true, LLR_FLIP>(cw, bq[s][0], bq[s][1], sb, Lb, base, sh, scale_mode, scale_k, fo, qm2);
+        if (fs & (1u << s))
+            check_update<PAR, true, LLR_FLIP>(cw, bq[s][0], bq[s][1], sb, Lb, base, kmul, shv, fo, qm2);
         else
-            check_update<PAR, false, LLR_FLIP>(cw, bq[s][0], bq[s][1], sb, Lb, base, sh, scale_mode, scale_k, fo, qm2);
+            check_update<PAR, false, LLR_FLIP>(cw, bq[s][0], bq[s][1], sb, Lb, base, kmul, shv, fo, qm2);
         // opaque to the optimiser: otherwise it forwards unpacked values to the next
         // iteration and keeps several registers per check
         asm volatile("" : "+v"(bq[s][0]), "+v"(bq[s][1]));
+    }
+}
+
+// Syndrome estimate contribution of a column whose hard decision is 1: flip the
+// bit of each of its checks (order-independent LDS atomics).
+__device__ __forceinline__ void xor_checks(const DevCode &C, int v, uint32_t *SHc) {
+    const uint64_t tab = C.vn_tab[v];
+#pragma unroll
+    for (int j = 0; j < CDEG; ++j) {
+        const uint32_t p = (uint32_t)(tab >> (16 * j)) & 0xFFFFu;
+        if (p != NOPOS) {
+            const uint32_t c = p / DEG;
+            atomicXor(&SHc[c >> 5], 1u << (c & 31));
+        }
+    }
+}
+
+// Column pass of an iteration whose sums went to half 1 - PAR: hard decision of
+// lambda^(i) (e = [lambda <= 0], i.e. biased half <= BIAS), syndrome estimate by
+// LDS atomic XOR of the columns with e = 1, and reset of the consumed half PAR to
+// mu (the accumulation base of iteration i+1).  Corrections and lambda leave the
+// wave once per shot, after the last iteration.
+template <int PAR, bool MU_UNIFORM>
+__device__ __forceinline__ void column_pass(const DevCode &C, uint32_t *L, uint32_t *SHc, int n, int lane,
+                                            uint32_t mu_b) {
+    uint16_t *Lh = (uint16_t *)L;
+    const int nfull = n >> 6;
+#pragma unroll 2
+    for (int vs = 0; vs < nfull; ++vs) {
+        const int v = vs * 64 + lane;
+        const uint32_t w = L[v];
+        const uint32_t h = PAR == 0 ? (w >> 16) : (w & 0xFFFFu);
+        if (h <= (uint32_t)BIAS) xor_checks(C, v, SHc);
+        Lh[2 * v + PAR] = (uint16_t)(MU_UNIFORM ? mu_b : (uint32_t)(C.mu_q[v] + BIAS));
+    }
+    const int v = nfull * 64 + lane;
+    if (v < n) {
+        const uint32_t w = L[v];
+        const uint32_t h = PAR == 0 ? (w >> 16) : (w & 0xFFFFu);
+        if (h <= (uint32_t)BIAS) xor_checks(C, v, SHc);
+        Lh[2 * v + PAR] = (uint16_t)(MU_UNIFORM ? mu_b : (uint32_t)(C.mu_q[v] + BIAS));
     }
 }
 
@@ -370,14 +412,16 @@ __global__ __launch_bounds__(1024) void bp_int8_kernel(BpArgs a) {
     const uint32_t base = (uint32_t)(base_p - smem);
     const int nl = n + PAD_COLS;
     uint32_t *S = (uint32_t *)(base_p + (((size_t)nl * 4 + 15) & ~(size_t)15));
-    uint32_t *SH0 = S + C.mw, *SH1 = SH0 + C.mw, *EH = SH1 + C.mw;
-    const int gwave = blockIdx.x * (blockDim.x >> 6) + wv;
-    float *stage = a.stage + (size_t)gwave * 2 * n;
+    uint32_t *SH0 = S + C.mw, *SH1 = SH0 + C.mw;
     const uint32_t last_mask = (m & 31) ? ((1u << (m & 31)) - 1u) : ~0u;
     const int nvs = (n + 63) >> 6;
     const bool mu_uniform = C.mu_q_uniform != INT32_MIN;
+    const uint32_t mu_b = (uint32_t)((mu_uniform ? C.mu_q_uniform : 0) + BIAS);
     const uint32_t pad_b = (uint32_t)(PAD_LAMBDA + BIAS);
     const uint32_t qm2 = (uint32_t)P.qmax | ((uint32_t)P.qmax << 16);  // Int x.y saturation, both halves
+    // check-node scale: (K, SH) of check_update, both halves
+    const unsigned short kscale = P.scale_mode == 1 ? (unsigned short)P.scale_k : (unsigned short)8;
+    const v2u16 kmul = {kscale, kscale};
 
     for (;;) {
         int64_t item = 0;
@@ -398,7 +442,6 @@ __global__ __launch_bounds__(1024) void bp_int8_kernel(BpArgs a) {
         const uint64_t seed = (uint64_t)uniform64((int64_t)(keys ? keys[2 * shot] : P.seed));
         const uint64_t shot_id =
             (uint64_t)uniform64((int64_t)(keys ? keys[2 * shot + 1] : a.first_shot_id + (uint64_t)shot));
-        float *llr_row = a.llr_out ? a.llr_out + shot * n : nullptr;
         const uint32_t *syn_row = (a.ring ? a.ring->syn : a.synd) + shot * C.mw;
 
         // SH1 is the estimate "before iteration 0" that the lottery of iteration 0
@@ -410,7 +453,7 @@ __global__ __launch_bounds__(1024) void bp_int8_kernel(BpArgs a) {
         }
         // lambda^(-1) = mu in both halves (Algorithm 1 initialisation: alpha^(0) = mu)
         for (int v = lane; v < nl; v += 64) {
-            const uint32_t mb = v < n ? (uint32_t)((mu_uniform ? C.mu_q_uniform : C.mu_q[v]) + BIAS) : pad_b;
+            const uint32_t mb = v < n ? (mu_uniform ? mu_b : (uint32_t)(C.mu_q[v] + BIAS)) : pad_b;
             L[v] = mb | (mb << 16);
         }
         wave_sync();
@@ -432,54 +475,26 @@ __global__ __launch_bounds__(1024) void bp_int8_kernel(BpArgs a) {
             uint32_t *SHc = (i & 1) ? SH1 : SH0;
             uint32_t *SHp = (i & 1) ? SH0 : SH1;
             const int par = i & 1;  // half holding lambda^(i-1)
-            const int sh = i + 1 > 30 ? 30 : i + 1;
+            const unsigned short sh = P.scale_mode == 1 ? (unsigned short)15 : (unsigned short)(i + 1 > 15 ? 15 : i + 1);
+            const v2u16 shv = {sh, sh};
             // ---- check-node pass: alpha from lambda^(i-1), beta^(i), lambda^(i) += beta^(i)
             if (par == 0)
-                check_pass<SLOTS, 0, LLR_FLIP>(cidx4, bq, srow, Lb, base, lane, sh, P.scale_mode, P.scale_k,
-                                               flipslots, fo, qm2);
+                check_pass<SLOTS, 0, LLR_FLIP>(cidx4, bq, srow, Lb, base, lane, kmul, shv, flipslots, fo, qm2);
             else
-                check_pass<SLOTS, 1, LLR_FLIP>(cidx4, bq, srow, Lb, base, lane, sh, P.scale_mode, P.scale_k,
-                                               flipslots, fo, qm2);
+                check_pass<SLOTS, 1, LLR_FLIP>(cidx4, bq, srow, Lb, base, lane, kmul, shv, flipslots, fo, qm2);
             for (int w = lane; w < C.mw; w += 64) SHc[w] = 0u;
             wave_sync();
-            // ---- column pass: hard decision, corrections, syndrome estimate, reset
-            const bool last = i == P.max_iter - 1;
-            const int nxt_hi = par == 0;
-            uint16_t *Lh = (uint16_t *)L;
-            for (int vs = 0; vs < nvs; ++vs) {
-                const int v = vs * 64 + lane;
-                const bool valid = v < n;
-                const int l = valid ? lambda_next(L, v, nxt_hi) : 1;
-                const bool e = valid && l <= 0;
-                const uint64_t bal = __ballot(e);
-                if (lane == 0) {
-                    EH[2 * vs] = (uint32_t)bal;
-                    EH[2 * vs + 1] = (uint32_t)(bal >> 32);
-                }
-                if (e) {
-                    const uint64_t tab = C.vn_tab[v];
-#pragma unroll
-                    for (int j = 0; j < CDEG; ++j) {
-                        uint32_t p = (uint32_t)(tab >> (16 * j)) & 0xFFFFu;
-                        if (p != NOPOS) {
-                            uint32_t c = p / DEG;
-                            atomicXor(&SHc[c >> 5], 1u << (c & 31));
-                        }
-                    }
-                }
-                if (valid) {
-                    // the consumed half becomes the accumulation base of iteration i+1
-                    Lh[2 * v + par] = (uint16_t)((mu_uniform ? C.mu_q_uniform : C.mu_q[v]) + BIAS);
-                    if (llr_row) llr_row[v] = (float)l;
-                    if (last) {
-                        stage[v] = (float)l;
-                        stage[n + v] = 0.f;
-                    }
-                }
+            // ---- column pass: hard decision, syndrome estimate, reset of the consumed half
+            if (mu_uniform) {
+                if (par == 0) column_pass<0, true>(C, L, SHc, n, lane, mu_b);
+                else column_pass<1, true>(C, L, SHc, n, lane, mu_b);
+            } else {
+                if (par == 0) column_pass<0, false>(C, L, SHc, n, lane, mu_b);
+                else column_pass<1, false>(C, L, SHc, n, lane, mu_b);
             }
             // pads: re-arm the half that just collected this iteration's pad sums (it is
             // read next iteration); the other half collects the next sums from 254
-            if (lane < PAD_COLS) Lh[2 * (n + lane) + (par ^ 1)] = (uint16_t)pad_b;
+            if (lane < PAD_COLS) ((uint16_t *)L)[2 * (n + lane) + (par ^ 1)] = (uint16_t)pad_b;
             wave_sync();
             bool mism = false;
             for (int w = lane; w < C.mw; w += 64) mism |= SHc[w] != S[w];
@@ -490,7 +505,8 @@ __global__ __launch_bounds__(1024) void bp_int8_kernel(BpArgs a) {
             }
             flipslots = 0;
             if (P.lottery && i >= P.skip && i <= P.max_iter - 2) {
-                const int fv = lottery_pick_q(C, P.rule, seed, shot_id, i, L, nxt_hi, S, SHp, EH, lane);
+                const int nxt_hi = par == 0;
+                const int fv = lottery_pick_q(C, P.rule, seed, shot_id, i, L, nxt_hi, S, SHp, lane);
                 if (fv >= 0) {
                     // slots holding a check of v*: its column table names them
                     const uint64_t tab = C.vn_tab[__builtin_amdgcn_readfirstlane(fv)];
@@ -507,15 +523,39 @@ __global__ __launch_bounds__(1024) void bp_int8_kernel(BpArgs a) {
             wave_sync();
         }
 
+        // ---- once per shot: corrections (hard decision of the last lambda), the
+        // lambda outputs, and for a failed shot its lambda for OSD as int16
+        const int fin_hi = ((it - 1) & 1) == 0;  // half holding lambda of the last iteration
+        const bool osd = !converged && P.osd != OSD_NONE;
+        uint32_t *corr_row;
+        int16_t *lam_dst = nullptr;
+        if (a.ring) {
+            corr_row = a.ring->corr + shot * C.nw;
+            if (osd) lam_dst = a.ring->llr16 + shot * n;
+        } else {
+            corr_row = a.corr + shot * C.nw;
+            if (osd) {
+                uint32_t q = 0;
+                if (lane == 0) q = atomicAdd(&a.counters[1], 1u);
+                q = __builtin_amdgcn_readfirstlane(q);
+                if (lane == 0) a.fail_list[q] = (int32_t)shot;
+                if ((int64_t)q < a.fail_cap) lam_dst = a.fail_q + (size_t)q * n;
+            }
+        }
+        float *llr_row = a.llr_out ? a.llr_out + shot * n : nullptr;
+        for (int vs = 0; vs < nvs; ++vs) {
+            const int v = vs * 64 + lane;
+            const bool valid = v < n;
+            const int l = valid ? lambda_next(L, v, fin_hi) : 1;
+            const uint64_t bal = __ballot(l <= 0);
+            if (lane < 2 && 2 * vs + lane < C.nw) corr_row[2 * vs + lane] = lane ? (uint32_t)(bal >> 32) : (uint32_t)bal;
+            if (valid) {
+                if (llr_row) llr_row[v] = (float)l;
+                if (lam_dst) lam_dst[v] = (int16_t)l;
+            }
+        }
         if (a.ring) {
             const ServeRing &R = *a.ring;
-            uint32_t *corr_row = R.corr + shot * C.nw;
-            for (int w = lane; w < C.nw; w += 64) corr_row[w] = EH[w];
-            const bool osd = !converged && P.osd != OSD_NONE;
-            if (osd) {
-                float *dst = R.llr + shot * 2 * n;
-                for (int v = lane; v < 2 * n; v += 64) dst[v] = stage[v];
-            }
             if (lane == 0) {
                 R.flags[shot] = converged ? (uint8_t)FLAG_CONVERGED : osd ? (uint8_t)(FLAG_OSD | FLAG_OSD_PENDING) : 0;
                 R.iters[shot] = it;
@@ -524,21 +564,10 @@ __global__ __launch_bounds__(1024) void bp_int8_kernel(BpArgs a) {
             wave_sync();
             continue;
         }
-        for (int w = lane; w < C.nw; w += 64) a.corr[shot * C.nw + w] = EH[w];
         const uint8_t fl = converged ? (uint8_t)FLAG_CONVERGED : (uint8_t)(P.osd != OSD_NONE ? FLAG_OSD : 0);
         if (lane == 0) {
             a.flags[shot] = fl;
             if (a.iters) a.iters[shot] = it;
-        }
-        if (!converged && P.osd != OSD_NONE) {
-            uint32_t q = 0;
-            if (lane == 0) q = atomicAdd(&a.counters[1], 1u);
-            q = __builtin_amdgcn_readfirstlane(q);
-            if (lane == 0) a.fail_list[q] = (int32_t)shot;
-            if ((int64_t)q < a.fail_cap) {
-                float *dst = a.fail_llr + (size_t)q * 2 * n;
-                for (int v = lane; v < 2 * n; v += 64) dst[v] = stage[v];
-            }
         }
         wave_sync();
     }
@@ -558,8 +587,7 @@ int bp_int8_table_bytes(int slots) { return slots * 64 * 16; }
 
 int bp_int8_wave_bytes(int m, int n) {
     size_t mw = (size_t)(m + 31) / 32;
-    size_t eh = 2 * (size_t)((n + 63) / 64);
-    size_t tot = (((size_t)(n + PAD_COLS) * 4 + 15) & ~(size_t)15) + 4 * (3 * mw + eh);
+    size_t tot = (((size_t)(n + PAD_COLS) * 4 + 15) & ~(size_t)15) + 4 * (3 * mw);  // L, then S, SH0, SH1
     return (int)((tot + 15) & ~(size_t)15);
 }
 

@@ -114,7 +114,8 @@ struct ServeRing {
     uint32_t *token;                // device: 1 while a wave polls host memory
     unsigned long long *last_claim; // device: clock of the latest claim by any wave
     uint32_t *exiting;              // device: set by the first wave that finds the ring idle; every wave then exits
-    float *llr;                     // device [R][2n]: lambda (hi, lo) of items left to OSD
+    float *llr;                     // device [R][2n]: lambda (hi, lo) of items left to OSD (float kernels)
+    int16_t *llr16;                 // device [R][n]: the same buffer as int16 lambda (Int x.y check-centric kernel)
     int64_t mask;                   // R - 1 (R a power of two)
     uint64_t idle_ticks;            // the grid exits after this long without a claim (100 MHz ticks)
 };
@@ -135,9 +136,10 @@ struct BpArgs {
     float *llr_out;             // [shots][n] or null
     uint32_t *counters;         // [0] next work item, [1] failed shots
     int32_t *fail_list;         // [n_work]
-    float *fail_llr;            // [fail_cap][2n]: lambda as hi[n], lo[n] (value = hi + lo)
+    float *fail_llr;            // [fail_cap][2n]: lambda as hi[n], lo[n] (value = hi + lo) (float kernels)
+    int16_t *fail_q;            // [fail_cap][n]: the same buffer as int16 lambda (Int x.y check-centric kernel)
     int64_t fail_cap;
-    float *stage;               // [grid waves][2n]
+    float *stage;               // [grid waves][2n] (float kernels)
     int32_t wave_bytes;         // LDS bytes of one shot's state
     int32_t group;              // nonzero: a block decodes one shot (bp_kernel), else each wave its own
     const ServeRing *ring;      // device copy; non-null: take items from the ring, not the batch arrays
@@ -243,8 +245,9 @@ struct OsdArgs {
     uint8_t *flags;
     const uint32_t *counters;   // [1] failed shots
     const int32_t *fail_list;
-    const float *fail_llr;      // [fail_cap][2n]
+    const float *fail_llr;      // [fail_cap][2n]: lambda hi[n], lo[n]; or, with llr_i16, int16 lambda [fail_cap][n]
     int64_t fail_cap;
+    int32_t llr_i16;            // fail_llr holds int16 lambda (the Int x.y check-centric kernel)
     uint32_t *gscratch;         // per-block scratch: G in global memory, or column ballots
     int32_t sort_p;             // power of two >= n
     int32_t g_in_lds;

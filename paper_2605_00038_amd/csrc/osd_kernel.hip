@@ -141,13 +141,17 @@ __device__ int block_excl_scan(int x, int *scr, int *total) {
 // order, lambda = hi + lo.  Bitonic sort of P u64 keys: without a lo part the
 // key is orderable(hi) << 32 | column; with one (fp32 messages) it is
 // orderable(hi) << 32 | orderable(lo), and the column rides along in `cols`
-// (P u16; P < 2n, so they fit the space of n floats) as the tie-break.
-__device__ void sort_columns(const float *lam, int n, int P, int has_lo, unsigned long long *keys, uint16_t *cols,
-                             uint16_t *perm) {
+// (P u16; P < 2n, so they fit the space of n floats) as the tie-break.  With
+// i16 set, lambda is int16 (the Int x.y kernel's integers) and its key
+// lambda + 2^15 keeps the same order.
+__device__ void sort_columns(const float *lam, int n, int P, int has_lo, int i16, unsigned long long *keys,
+                             uint16_t *cols, uint16_t *perm) {
     const int tid = threadIdx.x, nth = blockDim.x;
+    const int16_t *lq = (const int16_t *)lam;
     for (int j = tid; j < P; j += nth) {
         if (j < n) {
-            const unsigned long long h = (unsigned long long)orderable(lam[j]) << 32;
+            const uint32_t hk = i16 ? (uint32_t)((int32_t)lq[j] + 32768) : orderable(lam[j]);
+            const unsigned long long h = (unsigned long long)hk << 32;
             keys[j] = h | (has_lo ? orderable(lam[n + j]) : (unsigned)j);
             if (has_lo) cols[j] = (uint16_t)j;
         } else {
@@ -262,10 +266,12 @@ __global__ __launch_bounds__(1024, 8) void osd_lds_kernel(OsdArgs a) {
 
     for (uint32_t q = blockIdx.x; q < nfail; q += gridDim.x) {
         const int64_t shot = a.fail_list[q];
-        const float *lam = a.fail_llr + (size_t)(a.llr_by_shot ? shot : (int64_t)q) * 2 * n;  // hi[n] then lo[n]
+        // hi[n] then lo[n], or int16 [n]
+        const size_t lrow = (size_t)(a.llr_by_shot ? shot : (int64_t)q);
+        const float *lam = a.llr_i16 ? (const float *)((const int16_t *)a.fail_llr + lrow * n) : a.fail_llr + lrow * 2 * n;
 
         // ---- 1. sort (lambda, column) ascending
-        sort_columns(lam, n, P, a.has_lo, keys, scol, perm);
+        sort_columns(lam, n, P, a.has_lo, a.llr_i16, keys, scol, perm);
 
         // ---- 2. G = I, s' = s
         const int mw = a.mw;
@@ -585,10 +591,11 @@ __global__ __launch_bounds__(1024 / R, 8 / R) void osd_reg_kernel(OsdArgs a) {
 
     for (uint32_t q = blockIdx.x; q < nfail; q += gridDim.x) {
         const int64_t shot = a.fail_list[q];
-        const float *lam = a.fail_llr + (size_t)(a.llr_by_shot ? shot : (int64_t)q) * 2 * n;
+        const size_t lrow = (size_t)(a.llr_by_shot ? shot : (int64_t)q);
+        const float *lam = a.llr_i16 ? (const float *)((const int16_t *)a.fail_llr + lrow * n) : a.fail_llr + lrow * 2 * n;
 
         // ---- 1. sort (lambda, column) ascending
-        sort_columns(lam, n, P, a.has_lo, (unsigned long long *)smem, scol, perm);
+        sort_columns(lam, n, P, a.has_lo, a.llr_i16, (unsigned long long *)smem, scol, perm);
 
         // check indices of the sorted columns, staged over the dead sort keys
         uint64_t *ptab = (uint64_t *)smem;

@@ -79,6 +79,7 @@ struct lbp_decoder_s {
     int wpb = 1, bp_blocks = 1, wave_bytes = 0, int8_slots = 0, table_bytes = 0, group = 0;
     int osd_blocks = 0, osd_lds = 0, osd_variant = 0, osd_threads = 1024, mws = 1, sort_p = 1;
     int64_t fail_cap = 0;
+    int64_t llr_bytes = 0;         // staged lambda per failed shot: 2n (int16, Int x.y kernel) or 8n (hi, lo floats)
     bool fail_cap_pinned = false;  // set by lbp_decoder_set_osd_capacity: never grown
     int64_t dev_bytes = 0;  // device workspace held by the decoder
     uint32_t *d_counters = nullptr;
@@ -127,6 +128,8 @@ lbp_status lbp::serve_shape(lbp_decoder d, double osd_fraction, ServeShape *out)
     return LBP_OK;
 }
 
+int64_t lbp::serve_llr_bytes(lbp_decoder d) { return (int64_t)d->code->n * (d->int8_slots ? 2 : 8); }
+
 lbp_status lbp::serve_launch_bp(lbp_decoder d, const ServeRing *ring_dev, uint32_t *exiting, int blocks,
                                 hipStream_t s) {
     HIPCHK(launch_reset(exiting, 1, s));  // the previous grid has drained: stream order
@@ -174,6 +177,8 @@ lbp_status lbp::serve_launch_osd(lbp_decoder d, const ServeRing &ring, const int
         o.cs_offset_words = (int64_t)(cs_off / 4);
     }
     o.has_lo = d->msgk == LBP_MSG_FP32;
+    o.llr_i16 = d->int8_slots != 0;
+    if (o.llr_i16) o.fail_llr = (const float *)ring.llr16;
     o.llr_by_shot = 1;
     blocks = std::max(1, std::min(blocks, d->osd_blocks));  // d_gscratch holds osd_blocks blocks
     HIPCHK(launch_osd(o, d->osd_variant, blocks, d->osd_threads, d->osd_lds, s));
@@ -470,7 +475,8 @@ lbp_status lbp_decoder_create(lbp_code code, const lbp_params *prm, int64_t max_
     }
     if (best_waves == 0) return cleanup_fail(LBP_EDEVICE, "lbp_decoder_create: no feasible BP launch shape");
     // ---- OSD workspace
-    d->fail_cap = prm->osd ? std::min<int64_t>(max_batch, std::max<int64_t>(1024, ((int64_t)256 << 20) / ((int64_t)code->n * 8)))
+    d->llr_bytes = (int64_t)code->n * (d->int8_slots ? 2 : 8);
+    d->fail_cap = prm->osd ? std::min<int64_t>(max_batch, std::max<int64_t>(1024, ((int64_t)256 << 20) / d->llr_bytes))
                            : 0;
     // the OSD kernel also holds a little static LDS (block-wide reductions).  Codes
     // with < 1024 checks keep G in registers, two rows per lane unless
@@ -508,11 +514,13 @@ lbp_status lbp_decoder_create(lbp_code code, const lbp_params *prm, int64_t max_
         d->dc.mu_q = d->d_muq;
         d->dc.mu_q_uniform = uni ? muq[0] : INT32_MIN;
     }
-    ALLOC(d->d_stage, (size_t)d->bp_blocks * d->wpb * code->n * 8);
+    // the float kernels stage lambda of the last iteration per wave; the Int x.y
+    // check-centric kernel reads it from LDS once the shot is done
+    if (!d->int8_slots) ALLOC(d->d_stage, (size_t)d->bp_blocks * d->wpb * code->n * 8);
     if (prm->osd) {
         ALLOC(d->d_fail_list, (size_t)max_batch * 4);
         ALLOC(d->d_list2, (size_t)max_batch * 4);
-        ALLOC(d->d_fail_llr, (size_t)d->fail_cap * code->n * 8);
+        ALLOC(d->d_fail_llr, (size_t)d->fail_cap * d->llr_bytes);
         ALLOC(d->d_gscratch, (size_t)d->osd_blocks * osd_scratch_bytes(d->osd_variant, code->m, code->n, d->mws, d->sort_p,
                                                                        prm->osd == LBP_OSD_CS));
     }
@@ -560,6 +568,7 @@ static lbp_status run_pass(lbp_decoder d, int64_t n_work, const int32_t *work_li
     a.counters = d->d_counters;
     a.fail_list = d->d_fail_list;
     a.fail_llr = d->d_fail_llr;
+    a.fail_q = (int16_t *)d->d_fail_llr;
     a.fail_cap = d->fail_cap;
     a.stage = d->d_stage;
     a.wave_bytes = d->wave_bytes;
@@ -604,6 +613,7 @@ static lbp_status run_pass(lbp_decoder d, int64_t n_work, const int32_t *work_li
         o.cs_offset_words = (int64_t)(cs_off / 4);
     }
         o.has_lo = d->msgk == LBP_MSG_FP32;
+        o.llr_i16 = d->int8_slots != 0;
         hipEvent_t f0 = nullptr, f1 = nullptr;
         if (d->timing && (f0 = take_event(d)) && (f1 = take_event(d))) HIPCHK(hipEventRecord(f0, s));
         HIPCHK(launch_osd(o, d->osd_variant, d->osd_blocks, d->osd_threads, d->osd_lds, s));
@@ -649,7 +659,7 @@ lbp_status lbp_decoder_kernel_times(lbp_decoder d, double *bp_ms, int64_t *bp_la
 // buffer stays (the caller then needs more passes, never wrong results).  The
 // stream is idle here (the caller has synchronized it).
 static void grow_fail_cap(lbp_decoder d, int64_t want) {
-    const int64_t per = (int64_t)d->code->n * 8;
+    const int64_t per = d->llr_bytes;
     size_t free_b = 0, total_b = 0;
     if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return;
     const int64_t cap = std::min<int64_t>(std::min<int64_t>(want, d->max_batch), (int64_t)(free_b / 4) / per);

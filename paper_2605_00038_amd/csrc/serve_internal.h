@@ -14,6 +14,9 @@ struct ServeShape {
 // Split the device between the persistent BP grid and OSD launches:
 // osd_fraction of the CUs are left to OSD.
 lbp_status serve_shape(lbp_decoder d, double osd_fraction, ServeShape *out);
+// Device bytes of one ring item's staged lambda (for OSD): 2n for the Int x.y
+// check-centric kernel (int16), 8n for the others (hi, lo floats).
+int64_t serve_llr_bytes(lbp_decoder d);
 // Persistent BP kernel over the ring described by ring_dev (device copy).
 // Clears `exiting` (stream-ordered) and launches the persistent BP grid.
 lbp_status serve_launch_bp(lbp_decoder d, const ServeRing *ring_dev, uint32_t *exiting, int blocks, hipStream_t s);

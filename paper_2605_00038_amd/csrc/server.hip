@@ -98,7 +98,8 @@ struct Slot {
     lbp::ServeRing ring{};
     lbp::ServeRing *d_ring = nullptr;
     unsigned long long *d_ctl = nullptr;  // head, tail, token, last claim, completion-queue tail, exiting
-    float *d_llr = nullptr;
+    float *d_llr = nullptr;      // staged lambda of OSD-pending items: llr_bytes per ring item
+    int64_t llr_bytes = 0;
     int32_t *d_list = nullptr;
     uint32_t *d_ocount = nullptr;
     hipStream_t s_bp = nullptr, s_osd = nullptr;
@@ -200,7 +201,7 @@ lbp_status setup_slot(Slot &sl, int64_t R) {
     chk(hipHostMalloc((void **)&sl.h_ocount, 64, hipHostMallocDefault));
     chk(hipMalloc((void **)&sl.d_ring, sizeof(lbp::ServeRing)));
     chk(hipMalloc((void **)&sl.d_ctl, 64));
-    chk(hipMalloc((void **)&sl.d_llr, (size_t)R * 2 * sl.n * 4));
+    chk(hipMalloc((void **)&sl.d_llr, (size_t)R * sl.llr_bytes));
     chk(hipMalloc((void **)&sl.d_list, (size_t)kOsdList * 4));
     chk(hipMalloc((void **)&sl.d_ocount, 64));
     int ncu = 0, dev = 0;
@@ -243,6 +244,7 @@ lbp_status setup_slot(Slot &sl, int64_t R) {
     r.last_claim = sl.d_ctl + 3;
     r.exiting = (uint32_t *)(sl.d_ctl + 5);
     r.llr = sl.d_llr;
+    r.llr16 = (int16_t *)sl.d_llr;
     r.mask = R - 1;
     r.idle_ticks = kIdleTicks;
     chk(hipMemcpy(sl.d_ring, &r, sizeof(r), hipMemcpyHostToDevice));
@@ -250,7 +252,7 @@ lbp_status setup_slot(Slot &sl, int64_t R) {
     sl.ref_req.assign((size_t)R, ReqPtr());
     sl.ref_off.assign((size_t)R, 0);
     sl.state.assign((size_t)R, S_FREE);
-    sl.dev_bytes = (int64_t)R * 2 * sl.n * 4 + lbp_decoder_device_bytes(sl.dec) + 4096;
+    sl.dev_bytes = (int64_t)R * sl.llr_bytes + lbp_decoder_device_bytes(sl.dec) + 4096;
     return LBP_OK;
 }
 
@@ -531,11 +533,13 @@ lbp_status lbp_server_add_code(lbp_server srv, lbp_code code, const lbp_params *
         (void)hipSetDevice(prev);
         return sfail(st, msg);
     }
-    // the largest ring whose lambda staging (R * 8n bytes) fits the budget left
+    // the largest ring whose lambda staging (R items of llr_bytes: 2n for Int x.y
+    // codes of at most 1024 checks, else 8n) fits the budget left
+    sl->llr_bytes = lbp::serve_llr_bytes(sl->dec);
     const int64_t fixed = lbp_decoder_device_bytes(sl->dec) + 4096;
     int64_t R = kMaxRing;
-    while (R > kMinRing && fixed + R * 8 * (int64_t)sl->n > left) R /= 2;
-    if (fixed + R * 8 * (int64_t)sl->n > left) {
+    while (R > kMinRing && fixed + R * sl->llr_bytes > left) R /= 2;
+    if (fixed + R * sl->llr_bytes > left) {
         free_slot(*sl);
         (void)hipSetDevice(prev);
         return sfail(LBP_ENOMEM, "lbp_server_add_code: the code's buffers do not fit the device memory budget");

@@ -150,7 +150,8 @@ def test_server_memory_budget_limits_ring_size():
     name, p, kw = CODES[0]
     h, e, syn = batch(name, p, 64, 901)
     big = Server(device_mem_budget=16 << 30, max_slots=1)
-    small = Server(device_mem_budget=400 << 20, max_slots=1)
+    # Int3.4 stages 2n bytes of lambda per ring item: 65536 items of BB144 r=12 take 340 MB
+    small = Server(device_mem_budget=200 << 20, max_slots=1)
     s1 = big.add_code(_code(h, p), _params(**kw))
     s2 = small.add_code(_code(h, p), _params(**kw))
     t1, t2 = big.slot_info(s1)["ring_items"], small.slot_info(s2)["ring_items"]
