@@ -177,6 +177,28 @@ lbp_status lbp_decode(lbp_decoder dec, int64_t n_shots, uint64_t first_shot_id, 
 lbp_status lbp_decode_keyed(lbp_decoder dec, int64_t n_shots, const uint64_t *shot_keys, const uint32_t *syndromes,
                             uint32_t *corrections, uint8_t *flags, int32_t *iters, float *llr_out, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): lbp_decode with the
+ * same arguments, kernels and results, that allocates nothing and never
+ * synchronizes.  Every buffer besides the caller's inputs and outputs (work
+ * and failure counters, the failure list, the staged lambda of failed shots,
+ * the float kernels' per-wave staging, the OSD blocks' scratch) is carved from
+ * one static device array of LBP_NOALLOC_SCRATCH_BYTES that the library holds
+ * on each GPU it runs on until the process ends; its address is looked up once
+ * per device (at lbp_decoder_create).  The counters are cleared by a kernel at
+ * the start of each call.  Staging is reserved for every shot, so n_shots is
+ * bounded by that array: a larger n_shots returns LBP_EINVAL and the message
+ * names the largest batch of this decoder that fits (e.g. about 14000 shots of
+ * BB[[144,12,12]] over 12 rounds with Int3.4 and OSD-CS).  n_shots is not
+ * bounded by the decoder's max_batch, and the decoder's own workspace is not
+ * used.  All calls on one GPU share the array, which keeps the last call's
+ * contents: calls that overlap on one GPU (other streams, other threads) race
+ * and must be serialized by the caller.  Timing (lbp_decoder_set_timing) does
+ * not record these calls. */
+#define LBP_NOALLOC_SCRATCH_BYTES ((uint64_t)128 << 20)
+lbp_status lbp_decode_noalloc(lbp_decoder dec, int64_t n_shots, uint64_t first_shot_id, const uint32_t *syndromes,
+                              uint32_t *corrections, uint8_t *flags, int32_t *iters, float *llr_out, void *stream);
+
 /* Comparison path: the same decoding as lbp_decode (FP32 or FP16 message
  * storage; LBP_EUNSUPPORTED for INT8) written the plain way, with every
  * message in global memory, one thread per check or per column and a kernel

@@ -29,6 +29,7 @@ def lottery_rule(cn: int = CN_RANDOM, vn: int = VN_PROPOSED) -> int:
     """lbp_params.lottery_rule for a check rule and a neighbour rule (LBP_LOTTERY_RULE)."""
     return cn | (vn << 4)
 FLAG_CONVERGED, FLAG_OSD, FLAG_OSD_INCONSISTENT = 1, 2, 4
+NOALLOC_SCRATCH_BYTES = 128 << 20   # LBP_NOALLOC_SCRATCH_BYTES
 
 _STATUS = {0: "LBP_OK", -1: "LBP_EINVAL", -2: "LBP_ENOMEM", -3: "LBP_EDEVICE", -4: "LBP_EBUSY",
            -5: "LBP_ENOTREADY", -6: "LBP_EUNSUPPORTED"}
@@ -74,6 +75,7 @@ SIGNATURES = {
     "lbp_decoder_kernel_times": (_I32, [_VP, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I64),
                                         ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I64)]),
     "lbp_decode_keyed": (_I32, [_VP, _I64, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
+    "lbp_decode_noalloc": (_I32, [_VP, _I64, _U64, _VP, _VP, _VP, _VP, _VP, _VP]),
     "lbp_decode_baseline": (_I32, [_VP, _I64, _U64, _VP, _VP, _VP, _VP, _VP]),
     "lbp_decoder_device_bytes": (_I64, [_VP]),
     "lbp_decoder_max_batch": (_I64, [_VP]),

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -58,6 +59,39 @@ float to_fp16_value(double x) {
 }  // namespace
 
 void lbp::set_error(const char *msg) { g_err = msg ? msg : ""; }
+
+// Scratch of lbp_decode_noalloc: a static device array that the library holds on
+// every GPU it runs on until the process ends (LBP_NOALLOC_SCRATCH_BYTES).  In
+// host code `scratch` names a host-side stand-in, never the device memory: its
+// device address is looked up once per device with hipGetSymbolAddress (each GPU
+// has its own copy at its own address) and only that pointer is used.
+static __device__ __align__(256) unsigned char scratch[LBP_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_dev[kMaxDevices];
+
+// Device address of `scratch` on device `dev`, which must be current; nullptr
+// with the error message set when the lookup fails.
+void *scratch_on(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) {
+        g_err = "lbp_decode_noalloc: device index out of range";
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            g_err = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+            return nullptr;
+        }
+        g_scratch_dev[dev] = ptr;
+    }
+    return g_scratch_dev[dev];
+}
+}  // namespace
 
 struct lbp_code_s {
     int m = 0, n = 0, nnz = 0, device = 0;
@@ -146,8 +180,8 @@ lbp_status lbp::serve_launch_bp(lbp_decoder d, const ServeRing *ring_dev, uint32
     return LBP_OK;
 }
 
-lbp_status lbp::serve_launch_osd(lbp_decoder d, const ServeRing &ring, const int32_t *d_list,
-                                 const uint32_t *d_counters, int blocks, hipStream_t s) {
+// OSD arguments that depend only on the decoder (code tables, variant, formats).
+static OsdArgs osd_args(lbp_decoder d) {
     lbp_code C = d->code;
     OsdArgs o{};
     o.m = C->m;
@@ -159,26 +193,29 @@ lbp_status lbp::serve_launch_osd(lbp_decoder d, const ServeRing &ring, const int
     o.vn_tab4 = C->dc.vn_tab4;
     o.mode = d->prm.osd;
     o.order = d->prm.osd_order;
+    o.sort_p = d->sort_p;
+    o.g_in_lds = d->osd_variant == 0;
+    o.cols_global = d->osd_variant == -2;
+    size_t cs_off = 0;
+    o.scratch_words = (int64_t)(osd_scratch_layout(d->osd_variant, C->m, C->n, d->mws, d->sort_p,
+                                                   d->prm.osd == LBP_OSD_CS, &cs_off) / 4);
+    o.cs_offset_words = (int64_t)(cs_off / 4);
+    o.has_lo = d->msgk == LBP_MSG_FP32;
+    o.llr_i16 = d->int8_slots != 0;
+    return o;
+}
+
+lbp_status lbp::serve_launch_osd(lbp_decoder d, const ServeRing &ring, const int32_t *d_list,
+                                 const uint32_t *d_counters, int blocks, hipStream_t s) {
+    OsdArgs o = osd_args(d);
     o.synd = ring.syn;
     o.corr = ring.corr;
     o.flags = ring.flags;
     o.counters = d_counters;
     o.fail_list = d_list;
-    o.fail_llr = ring.llr;
+    o.fail_llr = o.llr_i16 ? (const float *)ring.llr16 : ring.llr;
     o.fail_cap = (int64_t)1 << 40;
     o.gscratch = d->d_gscratch;
-    o.sort_p = d->sort_p;
-    o.g_in_lds = d->osd_variant == 0;
-    o.cols_global = d->osd_variant == -2;
-    {
-        size_t cs_off = 0;
-        o.scratch_words = (int64_t)(osd_scratch_layout(d->osd_variant, C->m, C->n, d->mws, d->sort_p,
-                                                       d->prm.osd == LBP_OSD_CS, &cs_off) / 4);
-        o.cs_offset_words = (int64_t)(cs_off / 4);
-    }
-    o.has_lo = d->msgk == LBP_MSG_FP32;
-    o.llr_i16 = d->int8_slots != 0;
-    if (o.llr_i16) o.fail_llr = (const float *)ring.llr16;
     o.llr_by_shot = 1;
     blocks = std::max(1, std::min(blocks, d->osd_blocks));  // d_gscratch holds osd_blocks blocks
     HIPCHK(launch_osd(o, d->osd_variant, blocks, d->osd_threads, d->osd_lds, s));
@@ -527,6 +564,8 @@ lbp_status lbp_decoder_create(lbp_code code, const lbp_params *prm, int64_t max_
 #undef ALLOC
     e = hipHostMalloc((void **)&d->h_count, 64, hipHostMallocDefault);
     if (e != hipSuccess) return cleanup_fail(LBP_ENOMEM, "lbp_decoder_create: hipHostMalloc failed");
+    // set-up of lbp_decode_noalloc on this device (its scratch address), while the device is current
+    if (!scratch_on(dev)) return cleanup_fail(LBP_EDEVICE, "lbp_decoder_create: " + g_err);
     *out = d;
     return LBP_OK;
 }
@@ -548,11 +587,29 @@ lbp_status lbp_decoder_set_osd_capacity(lbp_decoder d, int64_t cap) {
     return LBP_OK;
 }
 
-static lbp_status run_pass(lbp_decoder d, int64_t n_work, const int32_t *work_list, uint64_t first_shot_id,
-                           const uint64_t *keys, const uint32_t *syn, uint32_t *corr, uint8_t *flags, int32_t *iters,
-                           float *llr, hipStream_t s) {
-    lbp_code C = d->code;
-    HIPCHK(launch_reset(d->d_counters, 16, s));
+// Device buffers one decode pass works in: the decoder's own workspace, or the
+// library's static scratch (lbp_decode_noalloc).
+struct PassBufs {
+    uint32_t *counters;     // [16]: next work item, failed shots, ...
+    int32_t *fail_list;     // [n_work]
+    float *fail_llr;        // [fail_cap] staged lambda, llr_bytes each
+    int64_t fail_cap;
+    float *stage;           // float kernels: [launched BP waves or blocks][2n]
+    int max_bp_blocks;      // BP blocks the stage rows cover
+    uint32_t *gscratch;     // [osd_blocks] OSD per-block scratch
+    int osd_blocks;
+    bool timing;            // record the decoder's timing events (they may be created here)
+};
+
+static PassBufs own_bufs(lbp_decoder d) {
+    return PassBufs{d->d_counters, d->d_fail_list, d->d_fail_llr, d->fail_cap, d->d_stage, d->bp_blocks,
+                    d->d_gscratch, d->osd_blocks, d->timing};
+}
+
+static lbp_status run_pass(lbp_decoder d, const PassBufs &w, int64_t n_work, const int32_t *work_list,
+                           uint64_t first_shot_id, const uint64_t *keys, const uint32_t *syn, uint32_t *corr,
+                           uint8_t *flags, int32_t *iters, float *llr, hipStream_t s) {
+    HIPCHK(launch_reset(w.counters, 16, s));
     BpArgs a{};
     a.code = d->dc;
     a.prm = d->bp;
@@ -565,19 +622,19 @@ static lbp_status run_pass(lbp_decoder d, int64_t n_work, const int32_t *work_li
     a.flags = flags;
     a.iters = iters;
     a.llr_out = llr;
-    a.counters = d->d_counters;
-    a.fail_list = d->d_fail_list;
-    a.fail_llr = d->d_fail_llr;
-    a.fail_q = (int16_t *)d->d_fail_llr;
-    a.fail_cap = d->fail_cap;
-    a.stage = d->d_stage;
+    a.counters = w.counters;
+    a.fail_list = w.fail_list;
+    a.fail_llr = w.fail_llr;
+    a.fail_q = (int16_t *)w.fail_llr;
+    a.fail_cap = w.fail_cap;
+    a.stage = w.stage;
     a.wave_bytes = d->wave_bytes;
     a.group = d->group;
     const int shots_per_block = d->group ? 1 : d->wpb;
     int64_t need_blocks = (n_work + shots_per_block - 1) / shots_per_block;
-    int blocks = (int)std::min<int64_t>(d->bp_blocks, std::max<int64_t>(1, need_blocks));
+    int blocks = (int)std::min<int64_t>(std::min(d->bp_blocks, w.max_bp_blocks), std::max<int64_t>(1, need_blocks));
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (d->timing && (e0 = take_event(d)) && (e1 = take_event(d))) HIPCHK(hipEventRecord(e0, s));
+    if (w.timing && (e0 = take_event(d)) && (e1 = take_event(d))) HIPCHK(hipEventRecord(e0, s));
     HIPCHK(d->int8_slots ? launch_bp_int8(d->int8_slots, a, blocks, d->wpb, s)
                          : launch_bp(d->msgk, a, blocks, d->wpb, s));
     if (e1) {
@@ -585,38 +642,18 @@ static lbp_status run_pass(lbp_decoder d, int64_t n_work, const int32_t *work_li
         d->recs.push_back({e0, e1, 0});
     }
     if (d->prm.osd) {
-        OsdArgs o{};
-        o.m = C->m;
-        o.n = C->n;
-        o.mw = C->dc.mw;
-        o.nw = C->dc.nw;
-        o.mws = d->mws;
-        o.vn_tab = C->dc.vn_tab;
-        o.vn_tab4 = C->dc.vn_tab4;
-        o.mode = d->prm.osd;
-        o.order = d->prm.osd_order;
+        OsdArgs o = osd_args(d);
         o.synd = syn;
         o.corr = corr;
         o.flags = flags;
-        o.counters = d->d_counters;
-        o.fail_list = d->d_fail_list;
-        o.fail_llr = d->d_fail_llr;
-        o.fail_cap = d->fail_cap;
-        o.gscratch = d->d_gscratch;
-        o.sort_p = d->sort_p;
-        o.g_in_lds = d->osd_variant == 0;
-        o.cols_global = d->osd_variant == -2;
-        {
-        size_t cs_off = 0;
-        o.scratch_words = (int64_t)(osd_scratch_layout(d->osd_variant, C->m, C->n, d->mws, d->sort_p,
-                                                       d->prm.osd == LBP_OSD_CS, &cs_off) / 4);
-        o.cs_offset_words = (int64_t)(cs_off / 4);
-    }
-        o.has_lo = d->msgk == LBP_MSG_FP32;
-        o.llr_i16 = d->int8_slots != 0;
+        o.counters = w.counters;
+        o.fail_list = w.fail_list;
+        o.fail_llr = w.fail_llr;
+        o.fail_cap = w.fail_cap;
+        o.gscratch = w.gscratch;
         hipEvent_t f0 = nullptr, f1 = nullptr;
-        if (d->timing && (f0 = take_event(d)) && (f1 = take_event(d))) HIPCHK(hipEventRecord(f0, s));
-        HIPCHK(launch_osd(o, d->osd_variant, d->osd_blocks, d->osd_threads, d->osd_lds, s));
+        if (w.timing && (f0 = take_event(d)) && (f1 = take_event(d))) HIPCHK(hipEventRecord(f0, s));
+        HIPCHK(launch_osd(o, d->osd_variant, w.osd_blocks, d->osd_threads, d->osd_lds, s));
         if (f1) {
             HIPCHK(hipEventRecord(f1, s));
             d->recs.push_back({f0, f1, 1});
@@ -685,7 +722,8 @@ static lbp_status decode_impl(const char *who, lbp_decoder d, int64_t n_shots, u
     if (!syndromes || !corrections || !flags) return fail(LBP_EINVAL, std::string(who) + ": NULL buffer");
     DeviceGuard g(d->code->device);
     hipStream_t s = (hipStream_t)stream;
-    lbp_status st = run_pass(d, n_shots, nullptr, first_shot_id, keys, syndromes, corrections, flags, iters, llr_out, s);
+    lbp_status st = run_pass(d, own_bufs(d), n_shots, nullptr, first_shot_id, keys, syndromes, corrections, flags,
+                             iters, llr_out, s);
     if (st != LBP_OK || !d->prm.osd || n_shots <= d->fail_cap) return st;
     // More shots may have failed BP than one OSD pass can stage: re-decode the
     // overflow (BP is deterministic per shot) and run OSD on it, until done.
@@ -701,7 +739,8 @@ static lbp_status decode_impl(const char *who, lbp_decoder d, int64_t n_shots, u
         // rest / capacity passes that each re-decode everything still pending
         if (!d->fail_cap_pinned && rest > d->fail_cap) grow_fail_cap(d, rest);
         HIPCHK(launch_gather_list(d->d_counters, d->d_fail_list, staged, d->d_list2, rest, s));
-        st = run_pass(d, rest, d->d_list2, first_shot_id, keys, syndromes, corrections, flags, iters, llr_out, s);
+        st = run_pass(d, own_bufs(d), rest, d->d_list2, first_shot_id, keys, syndromes, corrections, flags, iters,
+                      llr_out, s);
         if (st != LBP_OK) return st;
     }
 }
@@ -717,6 +756,78 @@ lbp_status lbp_decode_keyed(lbp_decoder d, int64_t n_shots, const uint64_t *shot
     if (n_shots > 0 && !shot_keys) return fail(LBP_EINVAL, "lbp_decode_keyed: NULL shot_keys");
     return decode_impl("lbp_decode_keyed", d, n_shots, 0, shot_keys, syndromes, corrections, flags, iters, llr_out,
                        stream);
+}
+
+// Scratch layout of a no-allocation decode of n shots, in bytes from the start
+// of the array (0 when it does not fit).  Every shot gets failure staging, so a
+// pass never overflows and needs no second pass or host synchronisation.
+static size_t noalloc_layout(lbp_decoder d, int64_t n, PassBufs *w, unsigned char *base) {
+    lbp_code C = d->code;
+    const size_t cap = LBP_NOALLOC_SCRATCH_BYTES;
+    size_t off = 0;
+    const size_t o_cnt = off;
+    off += 256;
+    const size_t o_list = off;
+    off += align256((size_t)n * 4);
+    const size_t o_llr = off;
+    if (d->prm.osd) off += align256((size_t)n * (size_t)d->llr_bytes);
+    // BP blocks the launch uses; the float kernels stage lambda per wave (or per block in groups)
+    const int64_t per_block_shots = d->group ? 1 : d->wpb;
+    int blocks = (int)std::min<int64_t>(d->bp_blocks, std::max<int64_t>(1, (n + per_block_shots - 1) / per_block_shots));
+    const size_t stage_row = (size_t)C->n * 8 * (d->group ? 1 : d->wpb);
+    const size_t o_stage = off;
+    if (!d->int8_slots) {
+        if (off > cap) return 0;
+        blocks = (int)std::min<size_t>((size_t)blocks, (cap - off) / stage_row);
+        if (blocks < 1) return 0;
+        off += align256((size_t)blocks * stage_row);
+    }
+    const size_t o_g = off;
+    int ob = 0;
+    if (d->prm.osd) {
+        const size_t per = align256(osd_scratch_bytes(d->osd_variant, C->m, C->n, d->mws, d->sort_p,
+                                                      d->prm.osd == LBP_OSD_CS));
+        if (off > cap) return 0;
+        ob = (int)std::min<int64_t>(std::min<int64_t>(d->osd_blocks, std::max<int64_t>(1, n)),
+                                    (int64_t)((cap - off) / per));
+        if (ob < 1) return 0;
+        off += (size_t)ob * per;
+    }
+    if (off > cap) return 0;
+    if (w) {
+        *w = PassBufs{(uint32_t *)(base + o_cnt), (int32_t *)(base + o_list), (float *)(base + o_llr), n,
+                      d->int8_slots ? nullptr : (float *)(base + o_stage), blocks, (uint32_t *)(base + o_g), ob,
+                      false};
+    }
+    return off;
+}
+
+lbp_status lbp_decode_noalloc(lbp_decoder d, int64_t n_shots, uint64_t first_shot_id, const uint32_t *syndromes,
+                              uint32_t *corrections, uint8_t *flags, int32_t *iters, float *llr_out, void *stream) {
+    g_err.clear();
+    if (!d) return fail(LBP_EINVAL, "lbp_decode_noalloc: NULL decoder");
+    if (n_shots < 0) return fail(LBP_EINVAL, "lbp_decode_noalloc: n_shots < 0");
+    if (n_shots == 0) return LBP_OK;
+    if (!syndromes || !corrections || !flags) return fail(LBP_EINVAL, "lbp_decode_noalloc: NULL buffer");
+    if (n_shots > (int64_t)1 << 31) return fail(LBP_EINVAL, "lbp_decode_noalloc: n_shots > 2^31");
+    if (!noalloc_layout(d, n_shots, nullptr, nullptr)) {
+        int64_t lo = 0, hi = n_shots;  // largest batch that fits, for the message
+        while (lo + 1 < hi) {
+            const int64_t mid = lo + (hi - lo) / 2;
+            (noalloc_layout(d, mid, nullptr, nullptr) ? lo : hi) = mid;
+        }
+        return fail(LBP_EINVAL, "lbp_decode_noalloc: " + std::to_string(n_shots) + " shots exceed the " +
+                                    std::to_string(LBP_NOALLOC_SCRATCH_BYTES >> 20) +
+                                    " MiB static scratch; at most " + std::to_string(lo) +
+                                    " shots of this code and format fit one call");
+    }
+    DeviceGuard g(d->code->device);
+    unsigned char *base = (unsigned char *)scratch_on(d->code->device);
+    if (!base) return fail(LBP_EDEVICE, "lbp_decode_noalloc: " + g_err);
+    PassBufs w{};
+    noalloc_layout(d, n_shots, &w, base);
+    return run_pass(d, w, n_shots, nullptr, first_shot_id, nullptr, syndromes, corrections, flags, iters, llr_out,
+                    (hipStream_t)stream);
 }
 
 lbp_status lbp_decode_baseline(lbp_decoder d, int64_t n_shots, uint64_t first_shot_id, const uint32_t *syndromes,
@@ -787,16 +898,7 @@ lbp_status lbp_decode_baseline(lbp_decoder d, int64_t n_shots, uint64_t first_sh
         const int64_t cnt = std::min<int64_t>(d->fail_cap, total - from);
         uint32_t *oc = d->d_counters + 8;
         HIPCHK(baseline_stage(a, from, cnt, d->d_fail_llr, oc, s));
-        OsdArgs o{};
-        o.m = C->m;
-        o.n = C->n;
-        o.mw = C->dc.mw;
-        o.nw = C->dc.nw;
-        o.mws = d->mws;
-        o.vn_tab = C->dc.vn_tab;
-        o.vn_tab4 = C->dc.vn_tab4;
-        o.mode = d->prm.osd;
-        o.order = d->prm.osd_order;
+        OsdArgs o = osd_args(d);
         o.synd = syndromes;
         o.corr = corrections;
         o.flags = flags;
@@ -805,16 +907,8 @@ lbp_status lbp_decode_baseline(lbp_decoder d, int64_t n_shots, uint64_t first_sh
         o.fail_llr = d->d_fail_llr;
         o.fail_cap = d->fail_cap;
         o.gscratch = d->d_gscratch;
-        o.sort_p = d->sort_p;
-        o.g_in_lds = d->osd_variant == 0;
-        o.cols_global = d->osd_variant == -2;
-        {
-        size_t cs_off = 0;
-        o.scratch_words = (int64_t)(osd_scratch_layout(d->osd_variant, C->m, C->n, d->mws, d->sort_p,
-                                                       d->prm.osd == LBP_OSD_CS, &cs_off) / 4);
-        o.cs_offset_words = (int64_t)(cs_off / 4);
-    }
-        o.has_lo = 1;
+        o.has_lo = 1;     // the comparison path stages lambda as an fp32 (hi, lo) pair
+        o.llr_i16 = 0;
         HIPCHK(launch_osd(o, d->osd_variant, d->osd_blocks, d->osd_threads, d->osd_lds, s));
     }
     return LBP_OK;

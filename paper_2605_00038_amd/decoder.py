@@ -120,6 +120,20 @@ class Decoder:
                                 llr.data_ptr() if llr is not None else None, s.cuda_stream))
         return corr, flags, iters, llr
 
+    def decode_noalloc(self, syndromes, out, first_shot_id: int = 0, stream=None):
+        """lbp_decode_noalloc: lbp_decode on the library's static scratch (no allocation).
+        ``out`` = (corrections, flags, iters or None, llr or None), preallocated CUDA tensors."""
+        import torch
+        assert syndromes.is_cuda and syndromes.dim() == 2 and syndromes.shape[1] == self.mw
+        assert syndromes.dtype in (torch.int32, torch.uint32) and syndromes.is_contiguous()
+        corr, flags, iters, llr = out
+        s = stream if stream is not None else torch.cuda.current_stream(syndromes.device)
+        check(load().lbp_decode_noalloc(self._h, syndromes.shape[0], first_shot_id & 0xFFFFFFFFFFFFFFFF,
+                                        syndromes.data_ptr(), corr.data_ptr(), flags.data_ptr(),
+                                        iters.data_ptr() if iters is not None else None,
+                                        llr.data_ptr() if llr is not None else None, s.cuda_stream))
+        return corr, flags, iters, llr
+
     def decode_keyed(self, syndromes, shot_keys, out=None, stream=None):
         """lbp_decode_keyed: shot_keys is a CUDA int64/uint64 tensor [shots, 2] of (seed, shot_id)."""
         import torch
