@@ -2,71 +2,63 @@
 //
 // The same decoding as lbp_decode for FP32 / FP16 message storage, written the
 // way a straightforward GPU port is: every message lives in HBM
-// ([shots][m][DEG] alpha and beta, [shots][n] lambda), one thread per check or
-// per column, and one kernel launch per half-iteration:
+// ([shots][m][DEG] alpha and beta, [shots][2][n] lambda), one thread per check
+// or per column, and one kernel launch per half-iteration:
 //   cn    (shot, check):  alpha -> beta           (Algorithm 1, CN update)
 //   col   (shot, column): beta -> lambda, e_hat, next alpha (LLR update, hard
 //                          decision, VN update of the next iteration)
 //   check (wave per shot): syndrome estimate, termination, lottery
 //                          (Algorithm 3), failure list for OSD
-// Sums run in fp64 in ascending check order and are rounded once to the
-// storage format, so lambda and the messages carry the exact arithmetic of the
-// method's reading; nothing is kept on chip between launches.
+// All arithmetic is fp32.  Column sums run in ascending check order as exact
+// TwoSum pairs (lambda is stored as hi and lo), and each stored message is the
+// exact value rounded once to the storage format (fp16 through fp32, which
+// rounds like one step: 24 >= 2 * 11 + 2), so the messages follow the method's
+// reading without any fp64 on the device; nothing is kept on chip between
+// launches.
 #include <hip/hip_fp16.h>
 
+#include "device_util.h"
 #include "lbp_internal.h"
 
 namespace lbp {
 namespace {
 
-__device__ __forceinline__ float store_msg(int msg, double x) {
+// Round an fp32 value to the message storage format, saturating at the
+// format's largest finite value.
+__device__ __forceinline__ float store_msg(int msg, float x) {
     if (msg == MSG_FP16) {
-        // double -> float with round-to-odd, then float -> half to nearest even:
-        // the odd sticky bit makes the two steps round like one
-        float t = (float)x;
-        if ((double)t != x && (__float_as_uint(t) & 1u) == 0u) {
-            // step one ulp toward x (the neighbour on x's side has the odd last bit)
-            uint32_t u = __float_as_uint(t);
-            if (t == 0.0f) u = (x < 0 ? 0x80000000u : 0u) | 1u;
-            else if (((double)t < x) == (t > 0.0f)) u += 1u;  // away from zero
-            else u -= 1u;                                      // toward zero
-            t = __uint_as_float(u);
-        }
-        __half h = __float2half_rn(t);
-        if (__hisinf(h)) return x > 0 ? 65504.0f : -65504.0f;
+        __half h = __float2half_rn(x);
+        if (__hisinf(h)) return x > 0.f ? 65504.0f : -65504.0f;
         return __half2float(h);
     }
-    float f = (float)x;
-    if (__builtin_isinf(f)) return x > 0 ? 3.402823466e38f : -3.402823466e38f;
-    return f;
+    if (__builtin_isinf(x)) return x > 0.f ? 3.402823466e38f : -3.402823466e38f;
+    return x;
 }
 
-__device__ __forceinline__ double mu_of(const DevCode &C, int msg, int v) {
-    return msg == MSG_FP16 ? (double)C.mu_f16[v] : (double)C.mu_f32[v];
+__device__ __forceinline__ float mu_of(const DevCode &C, int msg, int v) {
+    return msg == MSG_FP16 ? C.mu_f16[v] : C.mu_f32[v];
 }
 
-__device__ __forceinline__ double sigma_of(const BpParams &P, int i) {
-    if (P.scale_mode == 1) return (double)P.scale_f;
-    return i >= 24 ? 1.0 : 1.0 - __builtin_ldexp(1.0, -(i + 1));  // fl32(1 - 2^-(i+1)), exact
-}
-
-// Philox4x64-10 (Salmon et al., SC'11): words 0 (returned) and 1 (w1) for
-// counter (c0, c1, 0, 0), key (k0, 0).
-__device__ uint64_t philox_w01(uint64_t k0, uint64_t c0, uint64_t c1, uint64_t &w1) {
-    uint64_t x0 = c0, x1 = c1, x2 = 0, x3 = 0, ka = k0, kb = 0;
-    for (int r = 0; r < 10; ++r) {
-        const uint64_t h0 = __umul64hi(0xD2E7470EE14C6C93ULL, x0), l0 = 0xD2E7470EE14C6C93ULL * x0;
-        const uint64_t h1 = __umul64hi(0xCA5A826395121157ULL, x2), l1 = 0xCA5A826395121157ULL * x2;
-        const uint64_t y0 = h1 ^ x1 ^ ka, y2 = h0 ^ x3 ^ kb;
-        x0 = y0;
-        x1 = l1;
-        x2 = y2;
-        x3 = l0;
-        ka += 0x9E3779B97F4A7C15ULL;
-        kb += 0xBB67AE8584CAA73BULL;
+// mu + sum of the terms b[j] selected by mask, in ascending check order, as an
+// exact pair (hi, lo) with hi the sum rounded once to fp32.
+__device__ __forceinline__ void exact_sum(float mu, const float (&b)[CDEG], uint32_t mask, float &hi, float &lo) {
+    hi = mu;
+    lo = 0.f;
+    for (int j = 0; j < CDEG; ++j)
+        if ((mask >> j) & 1u) {
+            float s, e;
+            two_sum(hi, b[j], s, e);
+            hi = s;
+            lo += e;
+        }
+    if (__builtin_isinf(hi)) {
+        lo = 0.f;
+        return;
     }
-    w1 = x1;
-    return x0;
+    float s, e;
+    two_sum(hi, lo, s, e);
+    hi = s;
+    lo = e;
 }
 
 // alpha^(0) = mu on every real slot, +inf (never a minimum) on padding slots.
@@ -95,18 +87,26 @@ __global__ void bl_cn(BlArgs a, int i) {
     const int deg = C.cn_deg[c];
     const int fv = a.flipv[shot];
     const bool llr = a.prm.flip == FLIP_LLR && i > 0;
+    const float *lhi = a.lam + shot * 2 * C.n, *llo = lhi + C.n;
     float x[DEG];
-    double m1 = __builtin_inf(), m2 = __builtin_inf();
+    float m1 = __builtin_inff(), m2 = __builtin_inff();
     int arg = -1, par = (a.synd[shot * C.mw + (c >> 5)] >> (c & 31)) & 1u;
     for (int k = 0; k < DEG; ++k) {
         const uint32_t v = C.cn_cols[c * DEG + k];
         if (k >= deg) break;
         float al;
-        if (llr) al = store_msg(a.msg, a.lam[shot * C.n + v] - (double)a.beta[base + k]);
-        else al = a.alpha[base + k];
+        if (llr) {
+            // lambda - beta from the exact pair, rounded once (LLR flip: lambda may be negated)
+            float s1, e1, s2, e2;
+            two_sum(lhi[v], -a.beta[base + k], s1, e1);
+            two_sum(s1, e1 + llo[v], s2, e2);
+            al = store_msg(a.msg, __builtin_isinf(s1) ? s1 : s2);
+        } else {
+            al = a.alpha[base + k];
+        }
         if (!llr && (int)v == fv) al = -al;  // message flip (Algorithm 3)
         x[k] = al;
-        const double mag = __builtin_fabs((double)al);
+        const float mag = __builtin_fabsf(al);
         if (mag < m1) {
             m2 = m1;
             m1 = mag;
@@ -117,9 +117,10 @@ __global__ void bl_cn(BlArgs a, int i) {
         par ^= al < 0.f;
     }
     if (deg == 1) m2 = CAP_FLOAT;
-    const double sig = sigma_of(a.prm, i);
+    const float s1 = scale_float(a.prm.scale_mode, a.prm.scale_f, i, m1);
+    const float s2 = scale_float(a.prm.scale_mode, a.prm.scale_f, i, m2);
     for (int k = 0; k < deg; ++k) {
-        const double b = sig * (k == arg ? m2 : m1);
+        const float b = k == arg ? s2 : s1;
         const int neg = par ^ (x[k] < 0.f);
         a.beta[base + k] = store_msg(a.msg, neg ? -b : b);
     }
@@ -132,30 +133,31 @@ __global__ void bl_col(BlArgs a) {
     const DevCode &C = a.code;
     if (!a.active[shot]) return;  // uniform per block
     const bool valid = v < C.n;
-    double b[CDEG];
+    float b[CDEG];
     uint32_t pos[CDEG];
-    double lam = 0.0, mu = 0.0;
+    uint32_t mask = 0;
+    float hi = 1.f, lo = 0.f;
     if (valid) {
         const u32x4 tab = col_positions(C, v);
-        mu = mu_of(C, a.msg, v);
-        lam = mu;
+        const float mu = mu_of(C, a.msg, v);
         for (int j = 0; j < CDEG; ++j) {
             pos[j] = tab[j];
-            b[j] = pos[j] != NOPOS32 ? (double)a.beta[shot * C.m * DEG + pos[j]] : 0.0;
-            lam += b[j];
+            b[j] = pos[j] != NOPOS32 ? a.beta[shot * C.m * DEG + pos[j]] : 0.f;
+            if (pos[j] != NOPOS32) mask |= 1u << j;
         }
-        a.lam[shot * C.n + v] = lam;
+        exact_sum(mu, b, mask, hi, lo);
+        a.lam[shot * 2 * C.n + v] = hi;
+        a.lam[shot * 2 * C.n + C.n + v] = lo;
         if (a.prm.flip == FLIP_MSG) {
             for (int j = 0; j < CDEG; ++j) {
                 if (pos[j] == NOPOS32) continue;
-                double x = mu;
-                for (int t = 0; t < CDEG; ++t)
-                    if (t != j && pos[t] != NOPOS32) x += b[t];
-                a.alpha[shot * C.m * DEG + pos[j]] = store_msg(a.msg, x);
+                float xh, xl;
+                exact_sum(mu, b, mask & ~(1u << j), xh, xl);  // extrinsic sum, rounded once
+                a.alpha[shot * C.m * DEG + pos[j]] = store_msg(a.msg, xh);
             }
         }
     }
-    const uint64_t bal = __ballot(valid && lam <= (double)TAU_FLOAT);
+    const uint64_t bal = __ballot(valid && hard_pair(hi, lo));
     if ((threadIdx.x & 63) == 0 && v < C.n) {
         const int w = v >> 5;
         a.ehat[shot * C.nw + w] = (uint32_t)bal;
@@ -222,7 +224,7 @@ __global__ void bl_check(BlArgs a, int i) {
                 const uint64_t seed = a.shot_keys ? a.shot_keys[2 * shot] : P.seed;
                 const uint64_t sid = a.shot_keys ? a.shot_keys[2 * shot + 1] : a.first_shot_id + (uint64_t)shot;
                 uint64_t x1;
-                const uint64_t x = philox_w01(seed, sid, (uint64_t)i, x1);
+                const uint64_t x = philox_word01(seed, sid, (uint64_t)i, x1);
                 const int cn_rule = P.rule & 3, vn_rule = (P.rule >> 4) & 3;
                 int cstar = -1;
                 if (cn_rule == LOT_CN_WORST) {
@@ -267,8 +269,8 @@ __global__ void bl_check(BlArgs a, int i) {
                         const uint32_t s = (S[c >> 5] >> (c & 31)) & 1u;
                         cnt += (int)(((SHp[c >> 5] >> (c & 31)) & 1u) ^ s);
                     }
-                    const double qa = __builtin_fabs(a.lam[shot * C.n + v]) * 4096.0;
-                    const long long q = qa >= 4.0e18 ? (long long)4.0e18 : (long long)__builtin_floor(qa);
+                    const long long q = (long long)quantized_abs_pair(a.lam[shot * 2 * C.n + v],
+                                                                      a.lam[shot * 2 * C.n + C.n + v]);
                     if (best_v < 0 || lottery_key_less(vn_rule, cnt, q, v, best_cnt, best_q, best_v)) {
                         best_v = v;
                         best_cnt = cnt;
@@ -282,7 +284,10 @@ __global__ void bl_check(BlArgs a, int i) {
         }
         if (lane == 0) {
             if (P.flip == FLIP_LLR) {
-                if (fv >= 0) a.lam[shot * C.n + fv] = -a.lam[shot * C.n + fv];
+                if (fv >= 0) {
+                    a.lam[shot * 2 * C.n + fv] = -a.lam[shot * 2 * C.n + fv];
+                    a.lam[shot * 2 * C.n + C.n + fv] = -a.lam[shot * 2 * C.n + C.n + fv];
+                }
                 a.flipv[shot] = -1;
             } else {
                 a.flipv[shot] = fv;
@@ -291,18 +296,15 @@ __global__ void bl_check(BlArgs a, int i) {
     }
 }
 
-// lambda of failed shots [from, from + count) into the OSD staging format.
+// lambda of failed shots [from, from + count) into the OSD staging format (hi[n], lo[n]).
 __global__ void bl_stage(BlArgs a, int64_t from, int64_t count, float *dst, uint32_t *ocounters) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int n = a.code.n;
     if (t == 0) ocounters[1] = (uint32_t)count;
-    if (t >= count * n) return;
-    const int64_t q = t / n;
-    const int v = (int)(t - q * n);
-    const double l = a.lam[(int64_t)a.fail_list[from + q] * n + v];
-    const float hi = (float)l;
-    dst[q * 2 * n + v] = hi;
-    dst[q * 2 * n + n + v] = (float)(l - (double)hi);
+    if (t >= count * 2 * n) return;
+    const int64_t q = t / (2 * n);
+    const int64_t r = t - q * 2 * n;
+    dst[q * 2 * n + r] = a.lam[(int64_t)a.fail_list[from + q] * 2 * n + r];
 }
 
 }  // namespace
@@ -323,7 +325,7 @@ hipError_t baseline_iteration(const BlArgs &a, int i, hipStream_t s) {
 
 hipError_t baseline_stage(const BlArgs &a, int64_t from, int64_t count, float *dst, uint32_t *ocounters,
                           hipStream_t s) {
-    const int64_t total = std::max<int64_t>(1, count * a.code.n);
+    const int64_t total = std::max<int64_t>(1, count * 2 * a.code.n);
     hipLaunchKernelGGL(bl_stage, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, a, from, count, dst,
                        ocounters);
     return hipGetLastError();

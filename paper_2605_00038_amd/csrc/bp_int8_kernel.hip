@@ -37,6 +37,7 @@
 // a wave-uniform branch taken only by the slots that hold a check of v*.
 #include <climits>
 
+#include "device_util.h"
 #include "lbp_internal.h"
 
 namespace lbp {
@@ -48,43 +49,6 @@ constexpr int PAD_COLS = 48;
 
 typedef short v2i16 __attribute__((ext_vector_type(2)));
 typedef unsigned short v2u16 __attribute__((ext_vector_type(2)));
-
-__device__ __forceinline__ void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-__device__ __forceinline__ int wave_sum(int x) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-    return x;
-}
-
-__device__ __forceinline__ int wave_incl_scan(int x, int lane) {
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        int y = __shfl_up(x, o, 64);
-        if (lane >= o) x += y;
-    }
-    return x;
-}
-
-// Philox4x64-10 (Salmon et al., SC'11): words 0 and 1 for counter (c0, c1, 0, 0), key (k0, 0).
-__device__ uint64_t philox_w01(uint64_t k0, uint64_t c0, uint64_t c1, uint64_t &w1) {
-    uint64_t x0 = c0, x1 = c1, x2 = 0, x3 = 0, ka = k0, kb = 0;
-#pragma unroll 1
-    for (int r = 0; r < 10; ++r) {
-        uint64_t h0 = __umul64hi(0xD2E7470EE14C6C93ULL, x0), l0 = 0xD2E7470EE14C6C93ULL * x0;
-        uint64_t h1 = __umul64hi(0xCA5A826395121157ULL, x2), l1 = 0xCA5A826395121157ULL * x2;
-        uint64_t y0 = h1 ^ x1 ^ ka, y2 = h0 ^ x3 ^ kb;
-        x0 = y0; x1 = l1; x2 = y2; x3 = l0;
-        ka += 0x9E3779B97F4A7C15ULL;
-        kb += 0xBB67AE8584CAA73BULL;
-    }
-    w1 = x1;
-    return x0;
-}
 
 __device__ __forceinline__ v2i16 as_i16(uint32_t x) { return __builtin_bit_cast(v2i16, x); }
 __device__ __forceinline__ v2u16 as_u16(uint32_t x) { return __builtin_bit_cast(v2u16, x); }
@@ -138,7 +102,7 @@ __device__ int lottery_pick_q(const DevCode &C, int rule, uint64_t seed, uint64_
     if (N == 0) return -1;
     const int cn_rule = rule & 3, vn_rule = (rule >> 4) & 3;
     uint64_t x1;
-    const uint64_t x = philox_w01(seed, shot_id, (uint64_t)i, x1);
+    const uint64_t x = philox_word01(seed, shot_id, (uint64_t)i, x1);
     int cstar = 0;
     if (cn_rule == LOT_CN_WORST) {
         cstar = __builtin_amdgcn_readfirstlane(worst_check(C, S, SHp, L, nxt_hi, lane));

@@ -30,59 +30,13 @@
 // C2V messages through the column table, forms lambda (fixed ascending-check
 // order, so float results are deterministic), the hard decision, the syndrome
 // estimate (LDS atomic XOR, order-independent) and the next V2C messages.
+#include "device_util.h"
 #include "lbp_internal.h"
 
 #include <hip/hip_fp16.h>
 
 namespace lbp {
 namespace {
-
-__device__ __forceinline__ void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-__device__ __forceinline__ int wave_sum(int x) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-    return x;
-}
-
-__device__ __forceinline__ int wave_incl_scan(int x, int lane) {
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        int y = __shfl_up(x, o, 64);
-        if (lane >= o) x += y;
-    }
-    return x;
-}
-
-__device__ __forceinline__ uint64_t wave_min_u64(uint64_t x) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        uint64_t y = __shfl_xor(x, o, 64);
-        x = y < x ? y : x;
-    }
-    return x;
-}
-
-// Philox4x64-10 (Salmon et al., SC'11): words 0 (returned) and 1 (w1) of the
-// block for counter (ctr0, ctr1, 0, 0) under key (k0, 0).
-__device__ uint64_t philox_word01(uint64_t k0, uint64_t ctr0, uint64_t ctr1, uint64_t &w1) {
-    uint64_t x0 = ctr0, x1 = ctr1, x2 = 0, x3 = 0, ka = k0, kb = 0;
-#pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        uint64_t p0hi = __umul64hi(0xD2E7470EE14C6C93ULL, x0), p0lo = 0xD2E7470EE14C6C93ULL * x0;
-        uint64_t p1hi = __umul64hi(0xCA5A826395121157ULL, x2), p1lo = 0xCA5A826395121157ULL * x2;
-        uint64_t n0 = p1hi ^ x1 ^ ka, n2 = p0hi ^ x3 ^ kb;
-        x0 = n0; x1 = p1lo; x2 = n2; x3 = p0lo;
-        ka += 0x9E3779B97F4A7C15ULL;
-        kb += 0xBB67AE8584CAA73BULL;
-    }
-    w1 = x1;
-    return x0;
-}
 
 // ---------------------------------------------------------------- formats
 
@@ -132,25 +86,11 @@ __device__ __forceinline__ int scale_int8(const BpParams &P, int i, int mag) {
     return mag - (mag >> sh);
 }
 
-__device__ __forceinline__ float scale_float(const BpParams &P, int i, float mag) {
-    if (P.scale_mode == 1) return P.scale_f * mag;
-    // sigma_i = fl32(1 - 2^-(i+1)) is exact for i <= 23 and 1.0 beyond; the fma
-    // rounds mag * sigma_i once.
-    if (i >= 24) return mag;
-    return __builtin_fmaf(-mag, __builtin_ldexpf(1.0f, -(i + 1)), mag);
-}
-
-// Error-free sum of two floats: s + e == a + b exactly (Knuth's TwoSum).
-__device__ __forceinline__ void two_sum(float a, float b, float &s, float &e) {
-    s = a + b;
-    float bb = s - a;
-    e = (a - (s - bb)) + (b - bb);
-}
-
-// A column sum carried as an unevaluated pair hi + lo.  Int3.4 and FP16 sums
-// are exact in their accumulator (lo = 0); FP32 sums use TwoSum so that the
-// pair equals the exact sum, hi is that sum rounded once to fp32, and every
-// decision taken on lambda sees the exact value.
+// A column sum carried as an unevaluated pair hi + lo.  Int x.y sums are exact
+// integers (lo = 0); FP32 and FP16 sums use TwoSum so that the pair equals the
+// exact sum (fp16 terms span about 40 binades, more than an fp32 significand
+// holds), hi is that sum rounded once to fp32, and every decision taken on
+// lambda sees the exact value.
 template <typename A> struct Lam {
     A hi;
     float lo;
@@ -161,7 +101,7 @@ template <int MSG>
 __device__ __forceinline__ Lam<typename Fmt<MSG>::A> sum_terms(typename Fmt<MSG>::A mu,
                                                                const typename Fmt<MSG>::A b[CDEG], uint32_t mask) {
     using A = typename Fmt<MSG>::A;
-    if constexpr (MSG == MSG_FP32) {
+    if constexpr (MSG != MSG_INT8) {
         float hi = mu, lo = 0.f;
 #pragma unroll
         for (int j = 0; j < CDEG; ++j)
@@ -207,25 +147,11 @@ __device__ __forceinline__ bool hard_decision(const Lam<typename Fmt<MSG>::A> &l
     else return l.hi < TAU_FLOAT || (l.hi == TAU_FLOAT && l.lo <= 0.f);
 }
 
-// Q(|lambda|): |lambda| for Int3.4, floor(|lambda| * 2^12) for float (exact),
-// capped at 4e18 (a value no real lambda reaches; the cap only keeps Q finite).
+// Q(|lambda|): |lambda| for Int x.y, floor(|lambda| * 2^12) for float (exact).
 template <int MSG>
 __device__ __forceinline__ uint64_t quantized_abs(const Lam<typename Fmt<MSG>::A> &l) {
-    if constexpr (MSG == MSG_INT8) {
-        return (uint64_t)(l.hi < 0 ? -l.hi : l.hi);
-    } else {
-        float hi = l.hi, lo = l.lo;
-        if (hi < 0.f || (hi == 0.f && lo < 0.f)) { hi = -hi; lo = -lo; }
-        float H = hi * 4096.0f, L = lo * 4096.0f;  // exact scalings
-        if (!((double)H + (double)L < 4.0e18)) return 4000000000000000000ull;
-        float fh = __builtin_floorf(H);
-        if (fh == H) {
-            // H integral: floor(H + L) = H + floor(L)
-            float fl = __builtin_floorf(L);
-            return (uint64_t)((int64_t)H + (int64_t)fl);
-        }
-        return (uint64_t)fh;  // H not integral: H + L cannot cross an integer
-    }
+    if constexpr (MSG == MSG_INT8) return (uint64_t)(l.hi < 0 ? -l.hi : l.hi);
+    else return quantized_abs_pair(l.hi, l.lo);
 }
 
 // ------------------------------------------------------------ check-node half
@@ -276,7 +202,7 @@ __device__ void cn_half(const DevCode &C, const BpParams &P, int i, typename Fmt
                 par ^= (x[k] < 0.f);
             }
             if (deg == 1) m2 = CAP_FLOAT;
-            const float s1 = scale_float(P, i, m1), s2 = scale_float(P, i, m2);
+            const float s1 = scale_float(P.scale_mode, P.scale_f, i, m1), s2 = scale_float(P.scale_mode, P.scale_f, i, m2);
 #pragma unroll
             for (int k = 0; k < DEG; ++k) {
                 float mag = k == arg ? s2 : s1;

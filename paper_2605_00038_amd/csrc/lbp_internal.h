@@ -271,7 +271,7 @@ struct BlArgs {
     uint8_t *flags;             // [shots]
     int32_t *iters;             // [shots] or null
     float *alpha, *beta;        // [shots][m*DEG]
-    double *lam;                // [shots][n]
+    float *lam;                 // [shots][2][n]: lambda as an exact pair, hi[n] then lo[n]
     uint32_t *ehat;             // [shots][nw]
     uint32_t *shat;             // [shots][2][mw]: estimate of iteration i in slot i&1
     int32_t *flipv;             // [shots] column whose messages the next CN update negates, or -1

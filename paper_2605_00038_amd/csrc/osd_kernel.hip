@@ -27,6 +27,7 @@
 // G lives in LDS (row-major, odd word stride: conflict-free column access)
 // when it fits, otherwise in a per-workgroup global buffer (word-major, so
 // that a column word of all rows is one coalesced access).
+#include "device_util.h"
 #include "lbp_internal.h"
 
 namespace lbp {
@@ -50,39 +51,6 @@ __device__ __forceinline__ uint32_t orderable(float f) {
     uint32_t u = __float_as_uint(f);
     if (u == 0x80000000u) u = 0u;  // -0 sorts with +0
     return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
-}
-
-__device__ __forceinline__ uint32_t wave_min_u32(uint32_t x) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        uint32_t y = __shfl_xor(x, o, 64);
-        x = y < x ? y : x;
-    }
-    return x;
-}
-
-__device__ __forceinline__ uint64_t wave_min_u64(uint64_t x) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        uint64_t y = __shfl_xor(x, o, 64);
-        x = y < x ? y : x;
-    }
-    return x;
-}
-
-__device__ __forceinline__ int wave_incl_scan(int x, int lane) {
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        int y = __shfl_up(x, o, 64);
-        if (lane >= o) x += y;
-    }
-    return x;
-}
-
-__device__ __forceinline__ int wave_sum(int x) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-    return x;
 }
 
 struct GView {

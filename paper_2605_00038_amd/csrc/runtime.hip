@@ -126,7 +126,7 @@ struct lbp_decoder_s {
     // global-memory comparison path, allocated on first use
     int64_t bl_cap = 0;
     float *bl_alpha = nullptr, *bl_beta = nullptr;
-    double *bl_lam = nullptr;
+    float *bl_lam = nullptr;   // [shots][2][n] exact pairs
     uint32_t *bl_ehat = nullptr, *bl_shat = nullptr;
     int32_t *bl_flipv = nullptr;
     uint8_t *bl_active = nullptr;
@@ -853,7 +853,7 @@ lbp_status lbp_decode_baseline(lbp_decoder d, int64_t n_shots, uint64_t first_sh
         const size_t S = (size_t)n_shots;
         HIPCHK(hipMalloc((void **)&d->bl_alpha, S * slots * 4));
         HIPCHK(hipMalloc((void **)&d->bl_beta, S * slots * 4));
-        HIPCHK(hipMalloc((void **)&d->bl_lam, S * C->n * 8));
+        HIPCHK(hipMalloc((void **)&d->bl_lam, S * C->n * 8));  // hi and lo floats
         HIPCHK(hipMalloc((void **)&d->bl_ehat, S * C->dc.nw * 4));
         HIPCHK(hipMalloc((void **)&d->bl_shat, S * 2 * C->dc.mw * 4));
         HIPCHK(hipMalloc((void **)&d->bl_flipv, S * 4));

@@ -1,10 +1,11 @@
 """Global-memory comparison path (lbp_decode_baseline) against the oracle.
 
-The comparison path sums in fp64 in the oracle's order and rounds once to the
-storage format, so its corrections, flags and iteration counts should agree
-with the oracle on (essentially) every shot; the bar is the float bar of the
-fused kernels, identical corrections on >= 99.9% of shots.  It must also agree
-with the fused LDS kernel of the same format at that bar.
+The comparison path computes in fp32 only: column sums are exact TwoSum pairs
+in the oracle's order, each stored message is rounded once to the storage
+format, so its corrections, flags and iteration counts should agree with the
+oracle on (essentially) every shot; the bar is the float bar of the fused
+kernels, identical corrections on >= 99.9% of shots.  It must also agree with
+the fused LDS kernel of the same format at that bar.
 """
 import sys
 
