@@ -361,6 +361,102 @@ def run_servemix(args):
     print(text, flush=True)
 
 
+# The batching configuration: BB[[144,12,12]] code capacity (72 x 144) at four
+# error rates, 10^6 shots each (I=100, lottery, OSD-0), packed into one
+# persistent launch with the rotated surface d=5 code-capacity shots (12 x 25,
+# FP32, constant scale 0.625, plain BP, I=50, OSD-0, 10^4 shots) through an
+# autotuned multi-group plan replayed from a HIP graph; the same groups decoded
+# by one lbp_decode call each are timed beside it.
+BATCH_P = [0.01, 0.02, 0.04, 0.06]
+
+
+def run_batching(args):
+    import torch
+    assert torch.cuda.is_available(), "experiments need a GPU"
+    from paper_2605_00038_amd import Code, Decoder, DecoderParams, Plan
+    t_start = time.perf_counter()
+    shots = args.exp_shots
+    h_bb, _, _ = codes.workload_matrices("bb144_cc")
+    h_s5, _, _ = codes.workload_matrices("surface5_cc")
+    out = dict(experiment="batching", data="synthetic: i.i.d. Bernoulli(p) flips on every column, seeded (PCG64, "
+               "chunked)", shots_per_p=shots, formats={})
+    inputs = []
+    for j, p in enumerate(BATCH_P):
+        err, syn = sample_workload("bb144_cc", p, shots, 1030 + j, args.workers)
+        inputs.append(("bb144_cc", h_bb, p, err, syn, 2030 + j))
+    err, syn = sample_workload("surface5_cc", 0.05, 10000, 1001, args.workers)
+    inputs.append(("surface5_cc", h_s5, 0.05, err, syn, 2001))
+    log(f"[batching] sampled {len(BATCH_P)} x {shots} BB144 code-capacity shots + 10^4 surface d=5 shots")
+    for fmt in ("int8", "fp16"):
+        groups, decs, meta = [], [], []
+        for j, (name, h, p, err, syn, seed) in enumerate(inputs):
+            if name == "surface5_cc":
+                prm = DecoderParams(max_iter=50, msg=0, scale_mode=1, scale=0.625, lottery=False, osd=1, seed=seed)
+            else:
+                prm = DecoderParams(max_iter=100, msg=MSG_CODES[fmt], lottery=True, lottery_skip=6, osd=1, seed=seed)
+            dec = Decoder(Code.from_scipy(h, p), prm, syn.shape[0])
+            s = torch.from_numpy(np.ascontiguousarray(syn).view(np.int32)).cuda()
+            groups.append((dec, s, 0))
+            decs.append(dec)
+            meta.append((name, h, p, err, syn, prm))
+        total = sum(g[1].shape[0] for g in groups)
+        t0 = time.perf_counter()
+        plan = Plan(groups, autotune=True)
+        create_s = time.perf_counter() - t0
+        wpb, blocks, cand_ms = plan.info()
+        runs = []
+        for _ in range(args.exp_reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            plan.launch()
+            torch.cuda.synchronize()
+            runs.append(time.perf_counter() - t0)
+        plan_s = float(np.median(runs))
+        # the same groups, one lbp_decode each, back to back on one stream
+        sep = []
+        outs = [(torch.empty((g[1].shape[0], d.nw), dtype=torch.int32, device="cuda"),
+                 torch.empty(g[1].shape[0], dtype=torch.uint8, device="cuda"),
+                 torch.empty(g[1].shape[0], dtype=torch.int32, device="cuda"), None) for g, d in zip(groups, decs)]
+        for rep in range(args.exp_reps + 1):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for (dec, s, first), o in zip(groups, outs):
+                dec.decode(s, first_shot_id=first, out=o)
+            torch.cuda.synchronize()
+            if rep:
+                sep.append(time.perf_counter() - t0)
+        sep_s = float(np.median(sep))
+        per_group = []
+        for g, (name, h, p, err, syn, prm) in enumerate(meta):
+            corr, flags, iters = (t.cpu().numpy() for t in plan.outputs[g])
+            same_sep = bool(np.array_equal(corr, outs[g][0].cpu().numpy()))
+            h_, hc, r = codes.workload_matrices(name)
+            sf, lf = failures_packed(LogicalChecker(h_, hc, r), err, corr.view(np.uint32), h.shape[1])
+            k = int((sf | lf).sum())
+            per_group.append(dict(workload=name, p=p, shots=int(syn.shape[0]), msg=int(prm.msg),
+                                  max_iter=prm.max_iter, lottery=bool(prm.lottery), ler=k / syn.shape[0],
+                                  ler_ci95=list(wilson(k, syn.shape[0])),
+                                  osd_invoke_rate=float(((flags & 2) != 0).mean()), mean_iters=float(iters.mean()),
+                                  equal_to_lone_decode=same_sep))
+            log(f"[batching] {fmt} {name} p={p}: LER {k / syn.shape[0]:.3e} invoke "
+                f"{per_group[-1]['osd_invoke_rate']:.3e} equal to the lone decode: {same_sep}")
+        out["formats"][fmt] = dict(
+            total_shots=total, plan_create_s=create_s, waves_per_block=wpb, blocks=blocks,
+            autotune_candidates_ms=cand_ms, plan_replay_s=plan_s, plan_syndromes_per_s=total / plan_s,
+            separate_decodes_s=sep_s, separate_syndromes_per_s=total / sep_s, groups=per_group)
+        log(f"[batching] {fmt}: plan {total / plan_s:.3e} syndromes/s ({plan_s * 1e3:.1f} ms, {wpb} waves x "
+            f"{blocks} blocks, candidates {[round(x, 2) for x in cand_ms]}), separate decodes "
+            f"{total / sep_s:.3e} syndromes/s ({sep_s * 1e3:.1f} ms)")
+        del plan, decs, groups, outs
+        torch.cuda.empty_cache()
+    out["seconds"] = time.perf_counter() - t_start
+    text = json.dumps(out)
+    if args.exp_out:
+        with open(args.exp_out, "w") as f:
+            f.write(text + "\n")
+    print(text, flush=True)
+
+
 def run_experiment(args):
     import torch
     assert torch.cuda.is_available(), "experiments need a GPU"
@@ -489,7 +585,7 @@ def main():
     ap.add_argument("--no-ler", action="store_true")
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
     ap.add_argument("--experiment", choices=["policies", "skip", "iters", "ler", "flip", "quant", "osdheavy", "scale",
-                                             "servemix"],
+                                             "servemix", "batching"],
                     help="run one of the paper's ablations instead of the benchmark (prints a JSON table)")
     ap.add_argument("--exp-shots", type=int, default=1 << 20, help="shots per experiment point")
     ap.add_argument("--exp-p", default="", help="comma-separated physical error rates (default: per experiment)")
@@ -501,6 +597,7 @@ def main():
     ap.add_argument("--exp-distances", default="13,17,21,25,27",
                     help="surface-code distances of the scale experiment (d rounds, final read-out)")
     ap.add_argument("--exp-out", default="", help="also write the experiment's JSON to this file")
+    ap.add_argument("--exp-reps", type=int, default=5, help="timed repetitions (batching experiment)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (HBM counter calibration)")
     args = ap.parse_args()
@@ -524,6 +621,8 @@ def main():
     if args.experiment:
         if args.experiment == "servemix":
             run_servemix(args)
+        elif args.experiment == "batching":
+            run_batching(args)
         else:
             run_experiment(args)
         return

@@ -242,6 +242,53 @@ lbp_status lbp_decoder_set_timing(lbp_decoder dec, int32_t enable);
 lbp_status lbp_decoder_kernel_times(lbp_decoder dec, double *bp_ms, int64_t *bp_launches, double *osd_ms,
                                     int64_t *osd_launches);
 
+/* ---- Multi-group plans: shots of several codes in one launch.  A plan decodes
+ * groups of shots whose codes, message formats and parameters differ (each
+ * group is one decoder's code and lbp_params) with one persistent BP launch:
+ * every wavefront claims the next shot of any group from a device descriptor
+ * table and decodes it with that group's code, format and parameters, in an LDS
+ * slice sized for the largest group; then each group with OSD gets its OSD
+ * launch (Algorithm 1 and 3 for BP, Algorithm 2 for OSD-0; OSD-CS as for
+ * lbp_decode).  Every shot's result equals lbp_decode of its group alone (same
+ * seed and shot ids): per-shot results never depend on what shares the launch.
+ * The groups' buffers are bound when the plan is created, and the launch
+ * sequence is captured once into a HIP graph: a caller writes new syndromes
+ * into the same buffers and replays the graph with lbp_plan_launch.  The plan
+ * reserves failure staging for every shot of every group (8n bytes per shot of
+ * a group with OSD), so a replay never needs a second pass.  Codes above 8191
+ * checks are not supported in plans (LBP_EUNSUPPORTED). */
+typedef struct lbp_plan_s *lbp_plan;
+typedef struct {
+    lbp_decoder dec;            /* code, format and parameters of the group (its workspace is not used);
+                                   it must outlive the plan */
+    int64_t n_shots;            /* >= 0 */
+    uint64_t first_shot_id;     /* lottery counter of the group's shot 0 (shot k uses first_shot_id + k) */
+    const uint32_t *syndromes;  /* DEVICE [n_shots][ceil(m/32)] */
+    uint32_t *corrections;      /* DEVICE [n_shots][ceil(n/32)] */
+    uint8_t *flags;             /* DEVICE [n_shots] */
+    int32_t *iters;             /* DEVICE [n_shots] or NULL */
+} lbp_group;
+/* Autotuning: time every feasible launch shape (waves per block, with the
+ * resident blocks the occupancy allows) on the device, on the groups' own
+ * buffers, and keep the fastest; without it the shape with the most resident
+ * waves is used. */
+enum { LBP_PLAN_AUTOTUNE = 1 };
+/* Build a plan over n_groups (1..64) groups on one device (the decoders'):
+ * allocates its descriptor table and workspace, runs the sequence eagerly
+ * (with LBP_PLAN_AUTOTUNE, three times per candidate shape), so the groups'
+ * outputs then hold the results of their current syndromes, and captures the
+ * sequence into a graph.  Synchronous. */
+lbp_status lbp_plan_create(int32_t n_groups, const lbp_group *groups, int32_t options, lbp_plan *out);
+/* Decode every group again (replay of the captured graph) on `stream`
+ * (hipStream_t, NULL = default), asynchronously.  Replays on one plan must not
+ * overlap (they share the plan's workspace). */
+lbp_status lbp_plan_launch(lbp_plan plan, void *stream);
+/* The launch shape in use and, after autotuning, the measured milliseconds of
+ * each candidate (candidate_ms: room for 8 values; any output may be NULL). */
+lbp_status lbp_plan_info(lbp_plan plan, int32_t *waves_per_block, int32_t *blocks, int32_t *n_candidates,
+                         double *candidate_ms);
+void lbp_plan_destroy(lbp_plan plan);
+
 /* ---- Serving (real-time decoding of a stream of requests, Sec. I and VI-B:
  * the decoder must keep up with syndromes as they arrive, and its tail
  * latency matters).  A server owns one worker thread on the device current

@@ -8,7 +8,7 @@ from ._lib import (  # noqa: F401
     OSD_NONE, OSD_0, OSD_CS, FLAG_CONVERGED, FLAG_OSD, FLAG_OSD_INCONSISTENT,
     CN_RANDOM, CN_WORST, VN_PROPOSED, VN_Q_FIRST, VN_UNRELIABLE, VN_RANDOM, lottery_rule, msg_fixed,
 )
-from .decoder import Code, Decoder, DecoderParams  # noqa: F401
+from .decoder import Code, Decoder, DecoderParams, Plan  # noqa: F401
 from .server import Server  # noqa: F401
 
 __version__ = "0.1.0"

@@ -41,6 +41,22 @@ class LbpError(RuntimeError):
         self.status = status
 
 
+class Group(ctypes.Structure):
+    """lbp_group: one group of shots of a multi-group plan (device pointers)."""
+    _fields_ = [
+        ("dec", ctypes.c_void_p),
+        ("n_shots", ctypes.c_int64),
+        ("first_shot_id", ctypes.c_uint64),
+        ("syndromes", ctypes.c_void_p),
+        ("corrections", ctypes.c_void_p),
+        ("flags", ctypes.c_void_p),
+        ("iters", ctypes.c_void_p),
+    ]
+
+
+PLAN_AUTOTUNE = 1
+
+
 class Params(ctypes.Structure):
     _fields_ = [
         ("max_iter", ctypes.c_int32),
@@ -79,6 +95,11 @@ SIGNATURES = {
     "lbp_decode_baseline": (_I32, [_VP, _I64, _U64, _VP, _VP, _VP, _VP, _VP]),
     "lbp_decoder_device_bytes": (_I64, [_VP]),
     "lbp_decoder_max_batch": (_I64, [_VP]),
+    "lbp_plan_create": (_I32, [_I32, _VP, _I32, ctypes.POINTER(_VP)]),
+    "lbp_plan_launch": (_I32, [_VP, _VP]),
+    "lbp_plan_info": (_I32, [_VP, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32),
+                             ctypes.POINTER(ctypes.c_double)]),
+    "lbp_plan_destroy": (None, [_VP]),
     "lbp_server_create": (_I32, [_I64, _I32, ctypes.POINTER(_VP)]),
     "lbp_server_add_code": (_I32, [_VP, _VP, ctypes.POINTER(Params), ctypes.POINTER(_I32)]),
     "lbp_server_submit": (_I32, [_VP, _I32, _I64, _U64, _U64, _VP, ctypes.POINTER(_U64)]),

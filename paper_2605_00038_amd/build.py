@@ -8,7 +8,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbp.so")
-SOURCES = ["runtime.hip", "server.hip", "bp_kernel.hip", "bp_int8_kernel.hip", "osd_kernel.hip", "baseline.hip"]
+SOURCES = ["runtime.hip", "server.hip", "plan.hip", "bp_kernel.hip", "bp_int8_kernel.hip", "osd_kernel.hip",
+           "baseline.hip"]
 ARCH = os.environ.get("LBP_OFFLOAD_ARCH", "gfx950")
 
 

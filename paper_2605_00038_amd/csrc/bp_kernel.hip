@@ -416,6 +416,124 @@ __device__ void vn_half(const DevCode &C, const BpParams &P, int fv, bool last, 
     }
 }
 
+// ------------------------------------------------------------------ one shot
+
+// Sync of the threads that decode one shot: the wave, or the block in GRP.
+template <bool GRP>
+__device__ __forceinline__ void shot_sync() {
+    if constexpr (GRP) __syncthreads();
+    else wave_sync();
+}
+
+// Decode one shot (Algorithm 1 with Algorithm 3) in the LDS state E, S, SH0,
+// SH1, EH; returns whether BP converged and sets *it to the iterations run.
+// Thread t0 of tn works on checks and words, wave w0 of wn on 64-column groups;
+// in GRP, wave 0 runs the lottery and passes v* through *grp_fv (LDS).  The
+// lambda of the last iteration is written to stage (hi[n], lo[n]) when the run
+// reaches the iteration limit, and to llr_row when it is not null.
+template <int MSG, class TB, bool GRP>
+__device__ bool decode_shot(const DevCode &C, const BpParams &P, uint64_t seed, uint64_t shot_id,
+                            const uint32_t *syn_row, typename Fmt<MSG>::T *E, uint32_t *S, uint32_t *SH0,
+                            uint32_t *SH1, uint32_t *EH, float *llr_row, float *stage, int lane, int wv, int t0,
+                            int tn, int w0, int wn, int32_t *grp_fv, int &it) {
+    using F = Fmt<MSG>;
+    using T = typename F::T;
+    // padding bits of the last word are ignored (they could otherwise name checks >= m)
+    const uint32_t last_mask = (C.m & 31) ? ((1u << (C.m & 31)) - 1u) : ~0u;
+    // SH1 is the estimate "before iteration 0" that the lottery of iteration 0
+    // reads when K = 0: the hard decision of the prior, H * 0 = 0
+    for (int w = t0; w < C.mw; w += tn) {
+        uint32_t x = syn_row[w];
+        S[w] = w == C.mw - 1 ? (x & last_mask) : x;
+        SH1[w] = 0u;
+    }
+    // alpha^(0) = mu (Algorithm 1 initialisation); padding slots get the sentinel.
+    for (int c = t0; c < C.m; c += tn) {
+        const int deg = C.cn_deg[c];
+#pragma unroll
+        for (int k = 0; k < DEG; ++k)
+            if (k >= deg) E[c * DEG + k] = F::pad();
+    }
+    for (int v = t0; v < C.n; v += tn) {
+        const typename TB::T tab = TB::load(C, v);
+        const T mu = F::sat(F::mu(C, v));
+#pragma unroll
+        for (int j = 0; j < CDEG; ++j) {
+            uint32_t p = TB::pos(tab, j);
+            if (p != TB::NONE) E[p] = mu;
+        }
+    }
+    shot_sync<GRP>();
+
+    it = 0;
+    for (int i = 0; i < P.max_iter; ++i) {
+        uint32_t *SHc = (i & 1) ? SH1 : SH0;
+        uint32_t *SHp = (i & 1) ? SH0 : SH1;
+        cn_half<MSG>(C, P, i, E, S, t0, tn);
+        shot_sync<GRP>();
+        int fv = -1;
+        const bool lot = P.lottery && i >= P.skip && i <= P.max_iter - 2;
+        if constexpr (GRP) {
+            if (lot && wv == 0) {
+                const int f = lottery_select<MSG, TB>(C, P, seed, shot_id, i, E, S, SHp, lane);
+                if (lane == 0) *grp_fv = f;
+            }
+        } else if (lot) {
+            fv = lottery_select<MSG, TB>(C, P, seed, shot_id, i, E, S, SHp, lane);
+        }
+        for (int w = t0; w < C.mw; w += tn) SHc[w] = 0u;
+        shot_sync<GRP>();
+        if constexpr (GRP) {
+            if (lot) fv = *grp_fv;
+        }
+        const bool last = i == P.max_iter - 1;
+        vn_half<MSG, TB>(C, P, fv, last, E, SHc, EH, lane, w0, wn, llr_row, stage);
+        shot_sync<GRP>();
+        bool mism = false;
+        for (int w = t0; w < C.mw; w += tn) mism |= SHc[w] != S[w];
+        it = i + 1;
+        bool differs;
+        if constexpr (GRP) differs = __syncthreads_or(mism) != 0;
+        else differs = __ballot(mism) != 0ull;
+        if (!differs) return true;
+    }
+    return false;
+}
+
+// Outputs of a batch shot: corrections, flags, iterations, and for a failed
+// shot with OSD its failure-list entry and staged lambda (when it fits).
+template <bool GRP>
+__device__ void batch_outputs(const DevCode &C, const BpParams &P, int64_t shot, bool converged, int it,
+                              const uint32_t *EH, const float *stage, uint32_t *corr, uint8_t *flags, int32_t *iters,
+                              uint32_t *counters, int32_t *fail_list, float *fail_llr, int64_t fail_cap, int lane,
+                              int t0, int tn, uint32_t *grp_q) {
+    for (int w = t0; w < C.nw; w += tn) corr[shot * C.nw + w] = EH[w];
+    const uint8_t fl = converged ? (uint8_t)FLAG_CONVERGED : (uint8_t)(P.osd != OSD_NONE ? FLAG_OSD : 0);
+    if (t0 == 0) {
+        flags[shot] = fl;
+        if (iters) iters[shot] = it;
+    }
+    if (!converged && P.osd != OSD_NONE) {
+        uint32_t q = 0;
+        if constexpr (GRP) {
+            if (threadIdx.x == 0) {
+                *grp_q = atomicAdd(&counters[1], 1u);
+                fail_list[*grp_q] = (int32_t)shot;
+            }
+            __syncthreads();
+            q = *grp_q;
+        } else {
+            if (lane == 0) q = atomicAdd(&counters[1], 1u);
+            q = __builtin_amdgcn_readfirstlane(q);
+            if (lane == 0) fail_list[q] = (int32_t)shot;
+        }
+        if ((int64_t)q < fail_cap) {
+            float *dst = fail_llr + (size_t)q * 2 * C.n;
+            for (int v = t0; v < 2 * C.n; v += tn) dst[v] = stage[v];
+        }
+    }
+}
+
 // ------------------------------------------------------------------ kernel
 
 // GRP = false: each wave of the block decodes its own shot (per-wave LDS state).
@@ -442,10 +560,6 @@ __global__ __launch_bounds__(1024) void bp_kernel(BpArgs a) {
     // work split: thread t0 of tn over checks and words, wave w0 of wn over 64-column groups
     const int t0 = GRP ? (int)threadIdx.x : lane, tn = GRP ? (int)blockDim.x : 64;
     const int w0 = GRP ? wv : 0, wn = GRP ? nwv : 1;
-    auto sync = [] {
-        if constexpr (GRP) __syncthreads();
-        else wave_sync();
-    };
     if (threadIdx.x == 0) claim_lock = 0u;
     __syncthreads();
     unsigned char *base = smem + (GRP ? (size_t)0 : (size_t)wv * a.wave_bytes);
@@ -493,69 +607,9 @@ __global__ __launch_bounds__(1024) void bp_kernel(BpArgs a) {
         float *llr_row = a.llr_out ? a.llr_out + shot * C.n : nullptr;
         const uint32_t *syn_row = (a.ring ? a.ring->syn : a.synd) + shot * C.mw;
 
-        // padding bits of the last word are ignored (they could otherwise name checks >= m)
-        const uint32_t last_mask = (C.m & 31) ? ((1u << (C.m & 31)) - 1u) : ~0u;
-        // SH1 is the estimate "before iteration 0" that the lottery of iteration 0
-        // reads when K = 0: the hard decision of the prior, H * 0 = 0
-        for (int w = t0; w < C.mw; w += tn) {
-            uint32_t x = syn_row[w];
-            S[w] = w == C.mw - 1 ? (x & last_mask) : x;
-            SH1[w] = 0u;
-        }
-        // alpha^(0) = mu (Algorithm 1 initialisation); padding slots get the sentinel.
-        for (int c = t0; c < C.m; c += tn) {
-            const int deg = C.cn_deg[c];
-#pragma unroll
-            for (int k = 0; k < DEG; ++k)
-                if (k >= deg) E[c * DEG + k] = F::pad();
-        }
-        for (int v = t0; v < C.n; v += tn) {
-            const typename TB::T tab = TB::load(C, v);
-            const T mu = F::sat(F::mu(C, v));
-#pragma unroll
-            for (int j = 0; j < CDEG; ++j) {
-                uint32_t p = TB::pos(tab, j);
-                if (p != TB::NONE) E[p] = mu;
-            }
-        }
-        sync();
-
         int it = 0;
-        bool converged = false;
-        for (int i = 0; i < P.max_iter; ++i) {
-            uint32_t *SHc = (i & 1) ? SH1 : SH0;
-            uint32_t *SHp = (i & 1) ? SH0 : SH1;
-            cn_half<MSG>(C, P, i, E, S, t0, tn);
-            sync();
-            int fv = -1;
-            const bool lot = P.lottery && i >= P.skip && i <= P.max_iter - 2;
-            if constexpr (GRP) {
-                if (lot && wv == 0) {
-                    const int f = lottery_select<MSG, TB>(C, P, seed, shot_id, i, E, S, SHp, lane);
-                    if (lane == 0) grp_fv = f;
-                }
-            } else if (lot) {
-                fv = lottery_select<MSG, TB>(C, P, seed, shot_id, i, E, S, SHp, lane);
-            }
-            for (int w = t0; w < C.mw; w += tn) SHc[w] = 0u;
-            sync();
-            if constexpr (GRP) {
-                if (lot) fv = grp_fv;
-            }
-            const bool last = i == P.max_iter - 1;
-            vn_half<MSG, TB>(C, P, fv, last, E, SHc, EH, lane, w0, wn, llr_row, stage);
-            sync();
-            bool mism = false;
-            for (int w = t0; w < C.mw; w += tn) mism |= SHc[w] != S[w];
-            it = i + 1;
-            bool differs;
-            if constexpr (GRP) differs = __syncthreads_or(mism) != 0;
-            else differs = __ballot(mism) != 0ull;
-            if (!differs) {
-                converged = true;
-                break;
-            }
-        }
+        const bool converged = decode_shot<MSG, TB, GRP>(C, P, seed, shot_id, syn_row, E, S, SH0, SH1, EH, llr_row,
+                                                         stage, lane, wv, t0, tn, w0, wn, &grp_fv, it);
 
         if (a.ring) {
             const ServeRing &R = *a.ring;
@@ -577,35 +631,56 @@ __global__ __launch_bounds__(1024) void bp_kernel(BpArgs a) {
             } else {
                 serve_publish(R, item, lane);
             }
-            sync();
+            shot_sync<GRP>();
             continue;
         }
-        for (int w = t0; w < C.nw; w += tn) a.corr[shot * C.nw + w] = EH[w];
-        const uint8_t fl = converged ? (uint8_t)FLAG_CONVERGED : (uint8_t)(P.osd != OSD_NONE ? FLAG_OSD : 0);
-        if (t0 == 0) {
-            a.flags[shot] = fl;
-            if (a.iters) a.iters[shot] = it;
+        batch_outputs<GRP>(C, P, shot, converged, it, EH, stage, a.corr, a.flags, a.iters, a.counters, a.fail_list,
+                           a.fail_llr, a.fail_cap, lane, t0, tn, &grp_q);
+        shot_sync<GRP>();
+    }
+}
+
+// One persistent launch over several groups of shots (uneven codes, formats and
+// parameters): every wave claims the next work item, finds its group in the
+// descriptor table (groups hold consecutive item ranges) and decodes that shot
+// with the group's code, format and parameters in its LDS slice, which is sized
+// for the largest group.  Results are those of lbp_decode of each group alone.
+template <int MSG, class TB>
+__device__ void multi_shot(const GroupDesc &G, int64_t shot, unsigned char *base, float *stage, int lane) {
+    using T = typename Fmt<MSG>::T;
+    const DevCode &C = G.code;
+    T *E = (T *)base;
+    uint32_t *S = (uint32_t *)(base + (((size_t)C.m * DEG * sizeof(T) + 15) & ~(size_t)15));
+    uint32_t *SH0 = S + C.mw, *SH1 = SH0 + C.mw, *EH = SH1 + C.mw;
+    int it = 0;
+    const bool conv = decode_shot<MSG, TB, false>(C, G.prm, G.prm.seed, G.first_shot_id + (uint64_t)shot,
+                                                  G.synd + shot * C.mw, E, S, SH0, SH1, EH, nullptr, stage, lane, 0,
+                                                  lane, 64, 0, 1, nullptr, it);
+    batch_outputs<false>(C, G.prm, shot, conv, it, EH, stage, G.corr, G.flags, G.iters, G.counters, G.fail_list,
+                         G.fail_llr, G.n_shots, lane, lane, 64, nullptr);
+    wave_sync();
+}
+
+template <class TB>
+__global__ __launch_bounds__(1024) void bp_multi_kernel(MultiArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    unsigned char *base = smem + (size_t)wv * a.wave_bytes;
+    float *stage = a.stage + (size_t)(blockIdx.x * (blockDim.x >> 6) + wv) * (size_t)a.stage_stride;
+    for (;;) {
+        uint32_t it0 = 0;
+        if (lane == 0) it0 = atomicAdd(a.counter, 1u);
+        const int64_t item = (int64_t)__builtin_amdgcn_readfirstlane(it0);
+        if (item >= a.n_work) break;
+        int g = 0;
+        while (g + 1 < a.n_groups && item >= a.groups[g + 1].first_item) ++g;
+        const GroupDesc &G = a.groups[g];
+        const int64_t shot = item - G.first_item;
+        switch (G.msg) {
+        case MSG_INT8: multi_shot<MSG_INT8, TB>(G, shot, base, stage, lane); break;
+        case MSG_FP16: multi_shot<MSG_FP16, TB>(G, shot, base, stage, lane); break;
+        default: multi_shot<MSG_FP32, TB>(G, shot, base, stage, lane); break;
         }
-        if (!converged && P.osd != OSD_NONE) {
-            uint32_t q = 0;
-            if constexpr (GRP) {
-                if (threadIdx.x == 0) {
-                    grp_q = atomicAdd(&a.counters[1], 1u);
-                    a.fail_list[grp_q] = (int32_t)shot;
-                }
-                __syncthreads();
-                q = grp_q;
-            } else {
-                if (lane == 0) q = atomicAdd(&a.counters[1], 1u);
-                q = __builtin_amdgcn_readfirstlane(q);
-                if (lane == 0) a.fail_list[q] = (int32_t)shot;
-            }
-            if ((int64_t)q < a.fail_cap) {
-                float *dst = a.fail_llr + (size_t)q * 2 * C.n;
-                for (int v = t0; v < 2 * C.n; v += tn) dst[v] = stage[v];
-            }
-        }
-        sync();
     }
 }
 
@@ -670,6 +745,23 @@ hipError_t launch_bp(int msg, const BpArgs &a, int blocks, int wpb, hipStream_t 
                               : launch_tb<ColTab16, true>(msg, a, blocks, wpb, s);
     return a.code.vn_tab4 ? launch_tb<ColTab32, false>(msg, a, blocks, wpb, s)
                           : launch_tb<ColTab16, false>(msg, a, blocks, wpb, s);
+}
+
+hipError_t launch_bp_multi(const MultiArgs &a, int blocks, int wpb, hipStream_t s) {
+    const size_t lds = (size_t)a.wave_bytes * wpb;
+    hipLaunchKernelGGL(bp_multi_kernel<ColTab16>, dim3(blocks), dim3(64 * wpb), lds, s, a);
+    return hipGetLastError();
+}
+
+hipError_t bp_multi_prepare(int lds_bytes) {
+    return hipFuncSetAttribute((const void *)bp_multi_kernel<ColTab16>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               lds_bytes);
+}
+
+hipError_t bp_multi_max_blocks_per_cu(int wpb, int lds, int *out) {
+    hipError_t e = bp_multi_prepare(lds);
+    if (e != hipSuccess) return e;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(out, bp_multi_kernel<ColTab16>, 64 * wpb, (size_t)lds);
 }
 
 template <int MSG, class TB, bool GRP>

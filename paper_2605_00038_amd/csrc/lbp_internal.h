@@ -258,6 +258,38 @@ struct OsdArgs {
     int64_t cs_offset_words;    // OSD-CS column ballots in the block's scratch (kernels for m > 1024)
 };
 
+// One group of a multi-group launch (lbp_plan): a code with its format and
+// parameters, and the group's own input, output and OSD buffers.
+struct GroupDesc {
+    DevCode code;               // tables and priors (Int x.y prior of the group's format)
+    BpParams prm;
+    int32_t msg;                // MSG_FP32 / MSG_FP16 / MSG_INT8 (any Int x.y)
+    int32_t pad0;
+    int64_t first_item;         // work items [first_item, first_item + n_shots) are this group's shots
+    int64_t n_shots;
+    uint64_t first_shot_id;     // lottery counter of shot 0
+    const uint32_t *synd;       // [n_shots][mw]
+    uint32_t *corr;             // [n_shots][nw]
+    uint8_t *flags;             // [n_shots]
+    int32_t *iters;             // [n_shots] or null
+    uint32_t *counters;         // [16]: [1] failed shots of the group
+    int32_t *fail_list;         // [n_shots]
+    float *fail_llr;            // [n_shots][2n]: staging for every shot (no overflow pass)
+};
+
+struct MultiArgs {
+    const GroupDesc *groups;    // device table, ascending first_item
+    int32_t n_groups;
+    int32_t wave_bytes;         // LDS per wave: the largest group's shot state
+    int64_t n_work;             // shots of all groups
+    uint32_t *counter;          // next work item
+    float *stage;               // [launched waves][stage_stride]
+    int64_t stage_stride;       // floats per wave: 2 n of the widest group
+};
+hipError_t launch_bp_multi(const MultiArgs &a, int blocks, int wpb, hipStream_t s);
+hipError_t bp_multi_prepare(int lds_bytes);
+hipError_t bp_multi_max_blocks_per_cu(int wpb, int lds, int *out);
+
 // Global-memory comparison path (one launch per half-iteration).
 struct BlArgs {
     DevCode code;

@@ -200,7 +200,7 @@ static OsdArgs osd_args(lbp_decoder d) {
     o.scratch_words = (int64_t)(osd_scratch_layout(d->osd_variant, C->m, C->n, d->mws, d->sort_p,
                                                    d->prm.osd == LBP_OSD_CS, &cs_off) / 4);
     o.cs_offset_words = (int64_t)(cs_off / 4);
-    o.has_lo = d->msgk == LBP_MSG_FP32;
+    o.has_lo = d->msgk != LBP_MSG_INT8;  // float lambda is an exact (hi, lo) pair
     o.llr_i16 = d->int8_slots != 0;
     return o;
 }
@@ -218,6 +218,38 @@ lbp_status lbp::serve_launch_osd(lbp_decoder d, const ServeRing &ring, const int
     o.gscratch = d->d_gscratch;
     o.llr_by_shot = 1;
     blocks = std::max(1, std::min(blocks, d->osd_blocks));  // d_gscratch holds osd_blocks blocks
+    HIPCHK(launch_osd(o, d->osd_variant, blocks, d->osd_threads, d->osd_lds, s));
+    return LBP_OK;
+}
+
+lbp_status lbp::decoder_view(lbp_decoder d, DecoderView *out) {
+    if (!d || !out) return fail(LBP_EINVAL, "NULL decoder");
+    lbp_code C = d->code;
+    out->dc = d->dc;
+    out->bp = d->bp;
+    out->msgk = d->msgk;
+    out->osd = d->prm.osd;
+    out->device = C->device;
+    out->osd_blocks = d->osd_blocks;
+    out->osd_scratch = d->prm.osd ? osd_scratch_bytes(d->osd_variant, C->m, C->n, d->mws, d->sort_p,
+                                                      d->prm.osd == LBP_OSD_CS)
+                                  : 0;
+    return LBP_OK;
+}
+
+lbp_status lbp::decoder_launch_osd(lbp_decoder d, const uint32_t *synd, uint32_t *corr, uint8_t *flags,
+                                   const uint32_t *counters, const int32_t *fail_list, const float *fail_llr,
+                                   int64_t fail_cap, uint32_t *gscratch, int blocks, hipStream_t s) {
+    OsdArgs o = osd_args(d);
+    o.synd = synd;
+    o.corr = corr;
+    o.flags = flags;
+    o.counters = counters;
+    o.fail_list = fail_list;
+    o.fail_llr = fail_llr;
+    o.fail_cap = fail_cap;
+    o.gscratch = gscratch;
+    o.llr_i16 = 0;  // the general kernel stages every format as fp32 pairs
     HIPCHK(launch_osd(o, d->osd_variant, blocks, d->osd_threads, d->osd_lds, s));
     return LBP_OK;
 }

@@ -190,3 +190,52 @@ class Decoder:
         if getattr(self, "_h", None) and _lib._lib is not None:
             _lib._lib.lbp_decoder_destroy(self._h)
             self._h = None
+
+
+class Plan:
+    """lbp_plan: groups of shots of several decoders in one persistent launch,
+    replayed from a captured HIP graph.
+
+    ``groups`` is a list of (decoder, syndromes CUDA tensor [shots, ceil(m/32)],
+    first_shot_id).  Outputs are allocated here (``outputs[g]`` = (corrections,
+    flags, iters)) and bound to the plan, as are the syndrome tensors: write new
+    syndromes into them in place and call ``launch``."""
+
+    def __init__(self, groups, autotune: bool = True):
+        import torch
+        lib = load()
+        self._keep = []
+        self.outputs = []
+        arr = (_lib.Group * len(groups))()
+        for g, (dec, syn, first) in enumerate(groups):
+            assert syn.is_cuda and syn.is_contiguous() and syn.dim() == 2 and syn.shape[1] == dec.mw
+            shots = syn.shape[0]
+            corr = torch.zeros((shots, dec.nw), dtype=torch.int32, device=syn.device)
+            flags = torch.zeros(shots, dtype=torch.uint8, device=syn.device)
+            iters = torch.zeros(shots, dtype=torch.int32, device=syn.device)
+            self._keep += [dec, syn, corr, flags, iters]
+            self.outputs.append((corr, flags, iters))
+            arr[g] = _lib.Group(dec._h, shots, first & 0xFFFFFFFFFFFFFFFF, syn.data_ptr(), corr.data_ptr(),
+                                flags.data_ptr(), iters.data_ptr())
+        torch.cuda.synchronize()
+        h = ctypes.c_void_p()
+        check(lib.lbp_plan_create(len(groups), ctypes.cast(arr, ctypes.c_void_p),
+                                  _lib.PLAN_AUTOTUNE if autotune else 0, ctypes.byref(h)))
+        self._h = h
+
+    def launch(self, stream=None):
+        import torch
+        s = stream if stream is not None else torch.cuda.current_stream()
+        check(load().lbp_plan_launch(self._h, s.cuda_stream))
+
+    def info(self):
+        """(waves per block, blocks, measured ms of each autotuning candidate)."""
+        w, b, k = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        ms = (ctypes.c_double * 8)()
+        check(load().lbp_plan_info(self._h, ctypes.byref(w), ctypes.byref(b), ctypes.byref(k), ms))
+        return w.value, b.value, [ms[i] for i in range(k.value)]
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib._lib is not None:
+            _lib._lib.lbp_plan_destroy(self._h)
+            self._h = None
