@@ -36,6 +36,7 @@
 // the next iteration's alpha (message flip) or on lambda_v* (LLR flip), inside
 // a wave-uniform branch taken only by the slots that hold a check of v*.
 #include <climits>
+#include <vector>
 
 #include "device_util.h"
 #include "lbp_internal.h"
@@ -46,6 +47,11 @@ namespace {
 constexpr int BIAS = 32768;
 constexpr int PAD_LAMBDA = 254;
 constexpr int PAD_COLS = 48;
+
+// LDS bytes of the column-offset table ahead of the waves' slices (see row_offsets).
+__host__ __device__ inline int bp_int8_table_bytes_t(int table, int slots, int m0) {
+    return table == 0 ? slots * 64 * 16 : table == 1 ? (2 * m0 + 1) * 32 : 0;
+}
 
 typedef short v2i16 __attribute__((ext_vector_type(2)));
 typedef unsigned short v2u16 __attribute__((ext_vector_type(2)));
@@ -281,16 +287,48 @@ __device__ __forceinline__ void check_update(const uint4 cw, uint32_t &bw0, uint
     bw1 = __builtin_amdgcn_perm(nb[2], nb[3], SEL_PACK);
 }
 
+// Where the column offsets of a check come from (template TABLE):
+//   0: a per-check table, cidx4[s*64 + lane] = the four offset pairs of check lane + 64 s;
+//   1 / 2: the space-time structure of Eq. 1, H = [I_r (x) H0 | D (x) I_m0]: check
+//      c = t m0 + s0 (t = c / m0) reads row s0 (t = 0), m0 + s0 (t >= 1) or 2 m0 (the
+//      padding checks c >= m) of a compact table whose rows hold offset pairs b and
+//      multiplier pairs k (4 n0 for data slots, 4 m0 for measurement slots, 0 for
+//      padding); the check's offsets are b + t k, two slots per packed instruction.
+//      The compact table lives in LDS (1) or is read from global memory (2).
+struct StShape {
+    uint32_t m0, r, magic;  // magic = floor(2^32 / m0) + 1: c / m0 = umulhi(c, magic) for c < 2^16
+};
+
+template <int TABLE>
+__device__ __forceinline__ uint4 row_offsets(const uint4 *tab, int s, int lane, const StShape &st) {
+    if constexpr (TABLE == 0) {
+        return tab[s * 64 + lane];
+    } else {
+        const uint32_t c = (uint32_t)(lane + 64 * s);
+        const uint32_t t = __umulhi(c, st.magic);
+        const uint32_t s0 = c - t * st.m0;
+        const uint32_t row = t == 0 ? s0 : (t < st.r ? st.m0 + s0 : 2 * st.m0);
+        const uint4 b = tab[2 * row], k = tab[2 * row + 1];
+        const v2u16 tt = {(unsigned short)t, (unsigned short)t};
+        uint4 o;
+        o.x = as_u32(as_u16(b.x) + as_u16(k.x) * tt);
+        o.y = as_u32(as_u16(b.y) + as_u16(k.y) * tt);
+        o.z = as_u32(as_u16(b.z) + as_u16(k.z) * tt);
+        o.w = as_u32(as_u16(b.w) + as_u16(k.w) * tt);
+        return o;
+    }
+}
+
 // The check pass of one iteration over all of the lane's checks.  flipslots (bit s:
 // slot s holds a check of v*) is wave-uniform, so the flip variant is a scalar branch.
-template <int SLOTS, int PAR, bool LLR_FLIP>
-__device__ __forceinline__ void check_pass(const uint4 *cidx4, uint32_t (&bq)[SLOTS][2], uint32_t srow,
-                                           unsigned char *Lb, uint32_t base, int lane, v2u16 kmul, v2u16 shv,
-                                           uint32_t flipslots, uint32_t fo, uint32_t qm2) {
+template <int SLOTS, int PAR, bool LLR_FLIP, int TABLE>
+__device__ __forceinline__ void check_pass(const uint4 *tab, const StShape &st, uint32_t (&bq)[SLOTS][2],
+                                           uint32_t srow, unsigned char *Lb, uint32_t base, int lane, v2u16 kmul,
+                                           v2u16 shv, uint32_t flipslots, uint32_t fo, uint32_t qm2) {
     const uint32_t fs = __builtin_amdgcn_readfirstlane(flipslots);
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
-        const uint4 cw = cidx4[s * 64 + lane];
+        const uint4 cw = row_offsets<TABLE>(tab, s, lane, st);
         const uint32_t sb = (srow >> s) & 1u;
         if (fs & (1u << s))
             check_update<PAR, true, LLR_FLIP>(cw, bq[s][0], bq[s][1], sb, Lb, base, kmul, shv, fo, qm2);
@@ -343,7 +381,7 @@ __device__ __forceinline__ void column_pass(const DevCode &C, uint32_t *L, uint3
     }
 }
 
-template <int SLOTS, bool LLR_FLIP>
+template <int SLOTS, bool LLR_FLIP, int TABLE>
 __global__ __launch_bounds__(1024) void bp_int8_kernel(BpArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ uint32_t claim_lock;  // serving: the wave of this block that polls the ring
@@ -352,25 +390,33 @@ __global__ __launch_bounds__(1024) void bp_int8_kernel(BpArgs a) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     if (threadIdx.x == 0) claim_lock = 0u;
     const int n = C.n, m = C.m;
-    // block-shared byte offsets (4 * column) of every padded slot, paired as
-    // cidx4[s*64 + lane] = {(o1,o3), (o0,o2), (o5,o7), (o4,o6)} of check lane + 64 s
-    uint32_t *cidx = (uint32_t *)smem;
-    for (int t = threadIdx.x; t < SLOTS * 64 * 4; t += blockDim.x) {
-        const int c = t >> 2, w = t & 3;
-        const int k0 = (w & 2) * 2 + ((w & 1) ? 0 : 1);  // slot of the low half: 1, 0, 5, 4
-        uint32_t off[2];
+    // column offsets of the checks (TABLE 0: per check; 1: compact space-time rows in
+    // LDS; 2: compact rows read from global memory), ahead of the waves' slices
+    const int table_bytes = bp_int8_table_bytes_t(TABLE, SLOTS, C.st_m0);
+    if constexpr (TABLE == 0) {
+        // byte offsets (4 * column) of every padded slot, paired as
+        // cidx4[s*64 + lane] = {(o1,o3), (o0,o2), (o5,o7), (o4,o6)} of check lane + 64 s
+        uint32_t *cidx = (uint32_t *)smem;
+        for (int t = threadIdx.x; t < SLOTS * 64 * 4; t += blockDim.x) {
+            const int c = t >> 2, w = t & 3;
+            const int k0 = (w & 2) * 2 + ((w & 1) ? 0 : 1);  // slot of the low half: 1, 0, 5, 4
+            uint32_t off[2];
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int k = k0 + 2 * h;
-            uint32_t v = c < m ? C.cn_cols[c * DEG + k] : NOPOS;
-            if (v == NOPOS) v = (uint32_t)n + (uint32_t)((c * DEG + k) % PAD_COLS);
-            off[h] = 4u * v;
+            for (int h = 0; h < 2; ++h) {
+                const int k = k0 + 2 * h;
+                uint32_t v = c < m ? C.cn_cols[c * DEG + k] : NOPOS;
+                if (v == NOPOS) v = (uint32_t)n + (uint32_t)((c * DEG + k) % PAD_COLS);
+                off[h] = 4u * v;
+            }
+            cidx[t] = off[0] | (off[1] << 16);
         }
-        cidx[t] = off[0] | (off[1] << 16);
+    } else if constexpr (TABLE == 1) {
+        for (int t = threadIdx.x; t < table_bytes / 4; t += blockDim.x) ((uint32_t *)smem)[t] = C.st_tab[t];
     }
     __syncthreads();
-    const uint4 *cidx4 = (const uint4 *)smem;
-    unsigned char *base_p = smem + (size_t)SLOTS * 64 * 16 + (size_t)wv * a.wave_bytes;
+    const uint4 *tab = TABLE == 2 ? (const uint4 *)C.st_tab : (const uint4 *)smem;
+    StShape st{(uint32_t)C.st_m0, (uint32_t)C.st_r, C.st_m0 ? (uint32_t)(0xFFFFFFFFull / (uint32_t)C.st_m0) + 1u : 0u};
+    unsigned char *base_p = smem + (size_t)table_bytes + (size_t)wv * a.wave_bytes;
     uint32_t *L = (uint32_t *)base_p;  // [n + PAD_COLS] column words
     unsigned char *Lb = smem;
     const uint32_t base = (uint32_t)(base_p - smem);
@@ -443,9 +489,9 @@ __global__ __launch_bounds__(1024) void bp_int8_kernel(BpArgs a) {
             const v2u16 shv = {sh, sh};
             // ---- check-node pass: alpha from lambda^(i-1), beta^(i), lambda^(i) += beta^(i)
             if (par == 0)
-                check_pass<SLOTS, 0, LLR_FLIP>(cidx4, bq, srow, Lb, base, lane, kmul, shv, flipslots, fo, qm2);
+                check_pass<SLOTS, 0, LLR_FLIP, TABLE>(tab, st, bq, srow, Lb, base, lane, kmul, shv, flipslots, fo, qm2);
             else
-                check_pass<SLOTS, 1, LLR_FLIP>(cidx4, bq, srow, Lb, base, lane, kmul, shv, flipslots, fo, qm2);
+                check_pass<SLOTS, 1, LLR_FLIP, TABLE>(tab, st, bq, srow, Lb, base, lane, kmul, shv, flipslots, fo, qm2);
             for (int w = lane; w < C.mw; w += 64) SHc[w] = 0u;
             wave_sync();
             // ---- column pass: hard decision, syndrome estimate, reset of the consumed half
@@ -547,7 +593,52 @@ int bp_int8_slots(int m, int n) {
     return 0;
 }
 
-int bp_int8_table_bytes(int slots) { return slots * 64 * 16; }
+int bp_int8_table_bytes(int table, int slots, int m0) { return bp_int8_table_bytes_t(table, slots, m0); }
+
+bool bp_int8_build_st_table(const uint16_t *cols, int m, int n, int r, int m0, int n0, std::vector<uint32_t> &out) {
+    const int slots = bp_int8_slots(m, n);
+    if (!slots || r < 2 || m != r * m0) return false;
+    const int rows = 2 * m0 + 1;
+    out.assign((size_t)rows * 8, 0u);
+    // slot pairs of the four offset words, as in the per-check table
+    const int pair_k[4][2] = {{1, 3}, {0, 2}, {5, 7}, {4, 6}};
+    std::vector<int> pad_load(PAD_COLS, 0);
+    for (int R = 0; R < rows; ++R) {
+        // the check whose columns the row describes: row R < 2 m0 is check R (round 0 for
+        // R < m0, round 1 after), row 2 m0 none (padding)
+        const int c = R < 2 * m0 ? R : -1;
+        const int t = R < m0 ? 0 : 1;
+        uint32_t off[DEG], mul[DEG];
+        for (int k = 0; k < DEG; ++k) {
+            const uint32_t v = c >= 0 ? cols[(size_t)c * DEG + k] : NOPOS;
+            if (v == NOPOS) {
+                off[k] = 4u * (uint32_t)(n + (R * DEG + k) % PAD_COLS);
+                mul[k] = 0;
+            } else {
+                mul[k] = 4u * (uint32_t)((int)v < r * n0 ? n0 : m0);
+                off[k] = 4u * v - (uint32_t)t * mul[k];  // the offset at t = 0 of this row's checks
+            }
+            if (off[k] > 0xFFFFu || (uint64_t)off[k] + (uint64_t)(r - 1) * mul[k] > 0xFFFFu) return false;
+        }
+        for (int w = 0; w < 4; ++w) {
+            out[(size_t)R * 8 + w] = off[pair_k[w][0]] | (off[pair_k[w][1]] << 16);
+            out[(size_t)R * 8 + 4 + w] = mul[pair_k[w][0]] | (mul[pair_k[w][1]] << 16);
+        }
+    }
+    // the padding columns' sums of one iteration must stay inside a 16-bit half:
+    // count the padded slots each receives over all 64 * slots check positions
+    for (int c = 0; c < 64 * slots; ++c) {
+        const int t = c / m0, s0 = c - t * m0;
+        const int R = t == 0 ? s0 : (t < r ? m0 + s0 : 2 * m0);
+        for (int k = 0; k < DEG; ++k) {
+            const uint32_t v = R < 2 * m0 ? cols[(size_t)R * DEG + k] : NOPOS;
+            if (v == NOPOS) ++pad_load[(R * DEG + k) % PAD_COLS];
+        }
+    }
+    for (int j = 0; j < PAD_COLS; ++j)
+        if (PAD_LAMBDA + 127 * pad_load[j] > 32767) return false;
+    return true;
+}
 
 int bp_int8_wave_bytes(int m, int n) {
     size_t mw = (size_t)(m + 31) / 32;
@@ -555,50 +646,70 @@ int bp_int8_wave_bytes(int m, int n) {
     return (int)((tot + 15) & ~(size_t)15);
 }
 
-template <int SLOTS, bool LLR_FLIP>
+template <int SLOTS, bool LLR_FLIP, int TABLE>
 static hipError_t launch_q(const BpArgs &a, int blocks, int wpb, hipStream_t s) {
-    size_t lds = (size_t)bp_int8_table_bytes(SLOTS) + (size_t)a.wave_bytes * wpb;
-    hipError_t e = hipFuncSetAttribute((const void *)bp_int8_kernel<SLOTS, LLR_FLIP>,
+    size_t lds = (size_t)bp_int8_table_bytes_t(TABLE, SLOTS, a.code.st_m0) + (size_t)a.wave_bytes * wpb;
+    hipError_t e = hipFuncSetAttribute((const void *)bp_int8_kernel<SLOTS, LLR_FLIP, TABLE>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((bp_int8_kernel<SLOTS, LLR_FLIP>), dim3(blocks), dim3(64 * wpb), lds, s, a);
+    hipLaunchKernelGGL((bp_int8_kernel<SLOTS, LLR_FLIP, TABLE>), dim3(blocks), dim3(64 * wpb), lds, s, a);
     return hipGetLastError();
 }
 
-template <int SLOTS>
+template <int SLOTS, int TABLE>
 static hipError_t launch_s(const BpArgs &a, int blocks, int wpb, hipStream_t s) {
-    return a.prm.flip == FLIP_LLR ? launch_q<SLOTS, true>(a, blocks, wpb, s) : launch_q<SLOTS, false>(a, blocks, wpb, s);
+    return a.prm.flip == FLIP_LLR ? launch_q<SLOTS, true, TABLE>(a, blocks, wpb, s)
+                                  : launch_q<SLOTS, false, TABLE>(a, blocks, wpb, s);
 }
 
-template <int SLOTS>
+template <int SLOTS, int TABLE>
 static hipError_t occ_q(int wpb, int lds, int *out) {
     // both flip variants use the same registers to within the allocation granule;
     // the message-flip variant is the one queried
-    hipError_t e = hipFuncSetAttribute((const void *)bp_int8_kernel<SLOTS, false>,
+    hipError_t e = hipFuncSetAttribute((const void *)bp_int8_kernel<SLOTS, false, TABLE>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     if (e != hipSuccess) return e;
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(out, bp_int8_kernel<SLOTS, false>, 64 * wpb, (size_t)lds);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(out, bp_int8_kernel<SLOTS, false, TABLE>, 64 * wpb,
+                                                         (size_t)lds);
 }
 
-hipError_t launch_bp_int8(int slots, const BpArgs &a, int blocks, int wpb, hipStream_t s) {
+// The compact space-time tables are built for the large slot counts only, where
+// the per-check table takes most of the LDS (8 to 16 KiB).
+hipError_t launch_bp_int8(int slots, int table, const BpArgs &a, int blocks, int wpb, hipStream_t s) {
+    if (table == 1 || table == 2) {
+        switch (slots) {
+        case 8: return table == 1 ? launch_s<8, 1>(a, blocks, wpb, s) : launch_s<8, 2>(a, blocks, wpb, s);
+        case 14: return table == 1 ? launch_s<14, 1>(a, blocks, wpb, s) : launch_s<14, 2>(a, blocks, wpb, s);
+        case 16: return table == 1 ? launch_s<16, 1>(a, blocks, wpb, s) : launch_s<16, 2>(a, blocks, wpb, s);
+        default: return hipErrorInvalidValue;
+        }
+    }
     switch (slots) {
-    case 1: return launch_s<1>(a, blocks, wpb, s);
-    case 2: return launch_s<2>(a, blocks, wpb, s);
-    case 4: return launch_s<4>(a, blocks, wpb, s);
-    case 8: return launch_s<8>(a, blocks, wpb, s);
-    case 14: return launch_s<14>(a, blocks, wpb, s);
-    default: return launch_s<16>(a, blocks, wpb, s);
+    case 1: return launch_s<1, 0>(a, blocks, wpb, s);
+    case 2: return launch_s<2, 0>(a, blocks, wpb, s);
+    case 4: return launch_s<4, 0>(a, blocks, wpb, s);
+    case 8: return launch_s<8, 0>(a, blocks, wpb, s);
+    case 14: return launch_s<14, 0>(a, blocks, wpb, s);
+    default: return launch_s<16, 0>(a, blocks, wpb, s);
     }
 }
 
-hipError_t bp_int8_max_blocks_per_cu(int slots, int wpb, int lds, int *out) {
+hipError_t bp_int8_max_blocks_per_cu(int slots, int table, int wpb, int lds, int *out) {
+    if (table == 1 || table == 2) {
+        switch (slots) {
+        case 8: return table == 1 ? occ_q<8, 1>(wpb, lds, out) : occ_q<8, 2>(wpb, lds, out);
+        case 14: return table == 1 ? occ_q<14, 1>(wpb, lds, out) : occ_q<14, 2>(wpb, lds, out);
+        case 16: return table == 1 ? occ_q<16, 1>(wpb, lds, out) : occ_q<16, 2>(wpb, lds, out);
+        default: return hipErrorInvalidValue;
+        }
+    }
     switch (slots) {
-    case 1: return occ_q<1>(wpb, lds, out);
-    case 2: return occ_q<2>(wpb, lds, out);
-    case 4: return occ_q<4>(wpb, lds, out);
-    case 8: return occ_q<8>(wpb, lds, out);
-    case 14: return occ_q<14>(wpb, lds, out);
-    default: return occ_q<16>(wpb, lds, out);
+    case 1: return occ_q<1, 0>(wpb, lds, out);
+    case 2: return occ_q<2, 0>(wpb, lds, out);
+    case 4: return occ_q<4, 0>(wpb, lds, out);
+    case 8: return occ_q<8, 0>(wpb, lds, out);
+    case 14: return occ_q<14, 0>(wpb, lds, out);
+    default: return occ_q<16, 0>(wpb, lds, out);
     }
 }
 

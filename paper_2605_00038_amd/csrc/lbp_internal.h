@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 namespace lbp {
 
 // Padded row width of the per-shot edge array: check c owns slots c*DEG .. c*DEG+DEG-1.
@@ -37,6 +39,11 @@ struct DevCode {
     const float *mu_f16;      // [n]       prior LLR rounded to fp16 (held as float)
     const int32_t *mu_q;      // [n]       Int3.4 prior
     int32_t mu_q_uniform;     // the Int3.4 prior when every column has the same one, else INT32_MIN
+    // Eq. 1 structure when H is a space-time matrix [I_r (x) H0 | D (x) I_m0] (0 otherwise):
+    // check t*m0 + s touches data columns t*n0 + cols(s) and measurement columns
+    // r*n0 + t*m0 + s and, for t >= 1, r*n0 + (t-1)*m0 + s.
+    int32_t st_r, st_m0, st_n0;
+    const uint32_t *st_tab;   // compact space-time offset table of the Int x.y kernel, or null
 };
 
 // Access to a column's slot positions in either table layout: load(C, v)
@@ -335,11 +342,16 @@ hipError_t osd_max_blocks_per_cu(int variant, int threads, int lds, int *out);
 
 // Int3.4 check-centric kernel (codes with <= 1024 checks): slots per lane
 // (0 = not applicable), block-shared table bytes, per-wave LDS bytes.
+// table: 0 per-check offset table in LDS, 1 compact space-time table in LDS, 2 compact
+// table in global memory (codes with the Eq. 1 structure, 8 / 14 / 16 slots).
 int bp_int8_slots(int m, int n);
-int bp_int8_table_bytes(int slots);
+int bp_int8_table_bytes(int table, int slots, int m0);
 int bp_int8_wave_bytes(int m, int n);
-hipError_t launch_bp_int8(int slots, const BpArgs &a, int blocks, int waves_per_block, hipStream_t s);
-hipError_t bp_int8_max_blocks_per_cu(int slots, int waves_per_block, int lds_bytes, int *out);
+hipError_t launch_bp_int8(int slots, int table, const BpArgs &a, int blocks, int waves_per_block, hipStream_t s);
+hipError_t bp_int8_max_blocks_per_cu(int slots, int table, int waves_per_block, int lds_bytes, int *out);
+// Compact space-time table of a code with the Eq. 1 structure (cols: padded rows,
+// [m][DEG]); false when the code does not qualify.
+bool bp_int8_build_st_table(const uint16_t *cols, int m, int n, int r, int m0, int n0, std::vector<uint32_t> &out);
 
 hipError_t launch_reset(uint32_t *counters, int count, hipStream_t s);
 hipError_t launch_bp(int msg, const BpArgs &a, int blocks, int waves_per_block, hipStream_t s);

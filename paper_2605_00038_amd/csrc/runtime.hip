@@ -111,6 +111,7 @@ struct lbp_decoder_s {
     int64_t max_batch = 0;
     BpParams bp{};
     int wpb = 1, bp_blocks = 1, wave_bytes = 0, int8_slots = 0, table_bytes = 0, group = 0;
+    int int8_table = 0;  // where the Int x.y kernel takes its column offsets from (bp_int8_table_bytes)
     int osd_blocks = 0, osd_lds = 0, osd_variant = 0, osd_threads = 1024, mws = 1, sort_p = 1;
     int64_t fail_cap = 0;
     int64_t llr_bytes = 0;         // staged lambda per failed shot: 2n (int16, Int x.y kernel) or 8n (hi, lo floats)
@@ -175,7 +176,7 @@ lbp_status lbp::serve_launch_bp(lbp_decoder d, const ServeRing *ring_dev, uint32
     a.wave_bytes = d->wave_bytes;
     a.group = d->group;
     blocks = std::max(1, std::min(blocks, d->bp_blocks));  // d_stage holds bp_blocks * wpb waves
-    HIPCHK(d->int8_slots ? launch_bp_int8(d->int8_slots, a, blocks, d->wpb, s)
+    HIPCHK(d->int8_slots ? launch_bp_int8(d->int8_slots, d->int8_table, a, blocks, d->wpb, s)
                          : launch_bp(d->msgk, a, blocks, d->wpb, s));
     return LBP_OK;
 }
@@ -332,6 +333,35 @@ lbp_status lbp_code_create(int32_t m, int32_t n, const int32_t *row_ptr, const i
         muq[v] = (int32_t)(q > 127 ? 127 : (q < -127 ? -127 : q));
         if (p[v] != p[0]) uniform = false;
     }
+    // Eq. 1 structure: the largest r (>= 2) for which every row of H is the row of
+    // a space-time matrix [I_r (x) H0 | D (x) I_m0] with D lower bidiagonal
+    int st_r = 0, st_m0 = 0, st_n0 = 0;
+    for (int r = m; r >= 2 && !st_r; --r) {
+        if (m % r || (n - m) % r) continue;
+        const int m0 = m / r, n0 = (n - m) / r;
+        bool ok = n0 > 0;
+        for (int t = 0; t < r && ok; ++t)
+            for (int s0 = 0; s0 < m0 && ok; ++s0) {
+                const int c = t * m0 + s0, b0 = row_ptr[s0], w0 = row_ptr[s0 + 1] - b0;
+                int nd0 = 0;  // data columns of the round-0 row
+                while (nd0 < w0 && col_idx[b0 + nd0] < n0) ++nd0;
+                const int want = nd0 + (t ? 2 : 1);
+                if (w0 != nd0 + 1 || row_ptr[c + 1] - row_ptr[c] != want) {
+                    ok = false;
+                    break;
+                }
+                const int *cc = col_idx + row_ptr[c];
+                for (int k = 0; k < nd0 && ok; ++k) ok = cc[k] == t * n0 + col_idx[b0 + k];
+                if (!ok) break;
+                if (t) ok = cc[nd0] == r * n0 + (t - 1) * m0 + s0 && cc[nd0 + 1] == r * n0 + t * m0 + s0;
+                else ok = cc[nd0] == r * n0 + s0;
+            }
+        if (ok) {
+            st_r = r;
+            st_m0 = m0;
+            st_n0 = n0;
+        }
+    }
     lbp_code code = new lbp_code_s();
     code->m = m;
     code->n = n;
@@ -340,10 +370,13 @@ lbp_status lbp_code_create(int32_t m, int32_t n, const int32_t *row_ptr, const i
     code->mu.resize(n);
     for (int v = 0; v < n; ++v) code->mu[v] = std::log((1.0 - p[v]) / p[v]);
     hipGetDevice(&code->device);
+    // compact space-time offset table of the Int x.y kernel (codes with the Eq. 1 structure)
+    std::vector<uint32_t> sttab;
+    if (st_r && !bp_int8_build_st_table(cols.data(), m, n, st_r, st_m0, st_n0, sttab)) sttab.clear();
     size_t o_cols = 0, o_deg = align256(o_cols + cols.size() * 2), o_tab = align256(o_deg + (size_t)m),
            o_m32 = align256(o_tab + (size_t)n * 8), o_m16 = align256(o_m32 + (size_t)n * 4),
            o_mq = align256(o_m16 + (size_t)n * 4), o_t4 = align256(o_mq + (size_t)n * 4),
-           total = align256(o_t4 + tab4.size() * 4);
+           o_st = align256(o_t4 + tab4.size() * 4), total = align256(o_st + sttab.size() * 4);
     hipError_t e = hipMalloc(&code->dmem, total);
     if (e != hipSuccess) {
         delete code;
@@ -358,6 +391,7 @@ lbp_status lbp_code_create(int32_t m, int32_t n, const int32_t *row_ptr, const i
     std::memcpy(host.data() + o_m16, mu16.data(), (size_t)n * 4);
     std::memcpy(host.data() + o_mq, muq.data(), (size_t)n * 4);
     if (wide) std::memcpy(host.data() + o_t4, tab4.data(), tab4.size() * 4);
+    if (!sttab.empty()) std::memcpy(host.data() + o_st, sttab.data(), sttab.size() * 4);
     e = hipMemcpy(code->dmem, host.data(), total, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         hipFree(code->dmem);
@@ -377,6 +411,10 @@ lbp_status lbp_code_create(int32_t m, int32_t n, const int32_t *row_ptr, const i
     dc.mu_f16 = (const float *)(b + o_m16);
     dc.mu_q = (const int32_t *)(b + o_mq);
     dc.mu_q_uniform = uniform ? muq[0] : INT32_MIN;
+    dc.st_tab = sttab.empty() ? nullptr : (const uint32_t *)(b + o_st);
+    dc.st_r = st_r;
+    dc.st_m0 = st_m0;
+    dc.st_n0 = st_n0;
     *out = code;
     return LBP_OK;
 }
@@ -490,7 +528,14 @@ lbp_status lbp_decoder_create(lbp_code code, const lbp_params *prm, int64_t max_
     // ---- BP launch shape: the waves-per-block choice with the most resident waves per CU
     d->int8_slots = msgk == LBP_MSG_INT8 ? bp_int8_slots(code->m, code->n) : 0;
     d->wave_bytes = d->int8_slots ? bp_int8_wave_bytes(code->m, code->n) : bp_wave_bytes(msgk, code->m, code->n);
-    d->table_bytes = d->int8_slots ? bp_int8_table_bytes(d->int8_slots) : 0;
+    // LBP_INT8_TABLE=1 / 2 (read here) selects the compact space-time offset table in LDS /
+    // global memory for codes with the Eq. 1 structure (same results; for measurements)
+    if (d->int8_slots && code->dc.st_tab && (d->int8_slots == 8 || d->int8_slots >= 14)) {
+        const char *te = std::getenv("LBP_INT8_TABLE");
+        const int tv = te ? std::atoi(te) : 0;
+        if (tv == 1 || tv == 2) d->int8_table = tv;
+    }
+    d->table_bytes = d->int8_slots ? bp_int8_table_bytes(d->int8_table, d->int8_slots, code->dc.st_m0) : 0;
     if (d->table_bytes + d->wave_bytes > lds_block)
         return cleanup_fail(LBP_EUNSUPPORTED, "lbp_decoder_create: per-shot state exceeds LDS");
     // A workgroup per shot when a shot per wave would leave a CU with fewer than 32
@@ -528,7 +573,7 @@ lbp_status lbp_decoder_create(lbp_code code, const lbp_params *prm, int64_t max_
             int lds = d->table_bytes + d->wave_bytes * wpb;
             if (lds + 64 > lds_block) continue;  // plus the kernels' static LDS
             int bpc = 0;
-            hipError_t oe = d->int8_slots ? bp_int8_max_blocks_per_cu(d->int8_slots, wpb, lds, &bpc)
+            hipError_t oe = d->int8_slots ? bp_int8_max_blocks_per_cu(d->int8_slots, d->int8_table, wpb, lds, &bpc)
                                           : bp_max_blocks_per_cu(msgk, wide, false, wpb, lds, &bpc);
             if (oe != hipSuccess) continue;
             // most resident waves; among equals a multiple of 4 waves per block, whose
@@ -667,7 +712,7 @@ static lbp_status run_pass(lbp_decoder d, const PassBufs &w, int64_t n_work, con
     int blocks = (int)std::min<int64_t>(std::min(d->bp_blocks, w.max_bp_blocks), std::max<int64_t>(1, need_blocks));
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (w.timing && (e0 = take_event(d)) && (e1 = take_event(d))) HIPCHK(hipEventRecord(e0, s));
-    HIPCHK(d->int8_slots ? launch_bp_int8(d->int8_slots, a, blocks, d->wpb, s)
+    HIPCHK(d->int8_slots ? launch_bp_int8(d->int8_slots, d->int8_table, a, blocks, d->wpb, s)
                          : launch_bp(d->msgk, a, blocks, d->wpb, s));
     if (e1) {
         HIPCHK(hipEventRecord(e1, s));
