@@ -229,8 +229,12 @@ __device__ __forceinline__ void check_update(const uint4 cw, uint32_t &bw0, uint
     for (int p = 0; p < 4; ++p) mg[p] = __builtin_elementwise_max(x[p], mg[p]);
 #pragma unroll
     for (int p = 0; p < 4; ++p) mg[p] = __builtin_elementwise_min(mg[p], as_i16(qm2));
+    // |alpha| << 3 | slot as one packed multiply-add (the factor is hidden from the
+    // optimiser, which would otherwise turn it back into a shift and an or)
+    v2u16 eight = {8, 8};
+    asm("" : "+v"(eight));
 #pragma unroll
-    for (int p = 0; p < 4; ++p) key[p] = (as_u16(as_u32(mg[p])) << (v2u16){3, 3}) | kslot[p];  // |alpha| << 3 | slot
+    for (int p = 0; p < 4; ++p) key[p] = as_u16(as_u32(mg[p])) * eight + kslot[p];
     const uint32_t px = as_u32(x[0]) ^ as_u32(x[1]) ^ as_u32(x[2]) ^ as_u32(x[3]);
     v2u16 m1 = __builtin_elementwise_min(key[0], key[1]);
     v2u16 m2 = __builtin_elementwise_max(key[0], key[1]);
@@ -263,6 +267,10 @@ __device__ __forceinline__ void check_update(const uint4 cw, uint32_t &bw0, uint
     for (int p = 0; p < 4; ++p) eq[p] = eq[p] >> (v2i16){15, 15};                 // -1 at the argmin slot
 #pragma unroll
     for (int p = 0; p < 4; ++p) sm[p] = as_i16(as_u32(x[p]) ^ pp) >> (v2i16){15, 15};  // -1 where beta < 0
+    // opaque masks: knowing each half is 0 or -1, the optimiser would rewrite the
+    // bitwise selects below as per-half compares and selects (five times the work)
+#pragma unroll
+    for (int p = 0; p < 4; ++p) asm("" : "+v"(eq[p]), "+v"(sm[p]));
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
         const uint32_t mag = s1p ^ (dxp & as_u32(eq[p]));  // s2 at the argmin, s1 elsewhere
@@ -321,7 +329,9 @@ __device__ __forceinline__ uint4 row_offsets(const uint4 *tab, int s, int lane, 
 
 // The check pass of one iteration over all of the lane's checks.  flipslots (bit s:
 // slot s holds a check of v*) is wave-uniform, so the flip variant is a scalar branch.
-template <int SLOTS, int PAR, bool LLR_FLIP, int TABLE>
+// ANY_FLIP: some slot holds a check of v* this iteration (the lottery's flip acts);
+// the pass without any flip, by far the common one, then has no per-slot branch.
+template <int SLOTS, int PAR, bool LLR_FLIP, int TABLE, bool ANY_FLIP>
 __device__ __forceinline__ void check_pass(const uint4 *tab, const StShape &st, uint32_t (&bq)[SLOTS][2],
                                            uint32_t srow, unsigned char *Lb, uint32_t base, int lane, v2u16 kmul,
                                            v2u16 shv, uint32_t flipslots, uint32_t fo, uint32_t qm2) {
@@ -330,7 +340,7 @@ __device__ __forceinline__ void check_pass(const uint4 *tab, const StShape &st, 
     for (int s = 0; s < SLOTS; ++s) {
         const uint4 cw = row_offsets<TABLE>(tab, s, lane, st);
         const uint32_t sb = (srow >> s) & 1u;
-        if (fs & (1u << s))
+        if (ANY_FLIP && (fs & (1u << s)))
             check_update<PAR, true, LLR_FLIP>(cw, bq[s][0], bq[s][1], sb, Lb, base, kmul, shv, fo, qm2);
         else
             check_update<PAR, false, LLR_FLIP>(cw, bq[s][0], bq[s][1], sb, Lb, base, kmul, shv, fo, qm2);
@@ -488,10 +498,19 @@ __global__ __launch_bounds__(1024) void bp_int8_kernel(BpArgs a) {
             const unsigned short sh = P.scale_mode == 1 ? (unsigned short)15 : (unsigned short)(i + 1 > 15 ? 15 : i + 1);
             const v2u16 shv = {sh, sh};
             // ---- check-node pass: alpha from lambda^(i-1), beta^(i), lambda^(i) += beta^(i)
-            if (par == 0)
-                check_pass<SLOTS, 0, LLR_FLIP, TABLE>(tab, st, bq, srow, Lb, base, lane, kmul, shv, flipslots, fo, qm2);
-            else
-                check_pass<SLOTS, 1, LLR_FLIP, TABLE>(tab, st, bq, srow, Lb, base, lane, kmul, shv, flipslots, fo, qm2);
+            if (flipslots == 0) {
+                if (par == 0)
+                    check_pass<SLOTS, 0, LLR_FLIP, TABLE, false>(tab, st, bq, srow, Lb, base, lane, kmul, shv, 0u, fo, qm2);
+                else
+                    check_pass<SLOTS, 1, LLR_FLIP, TABLE, false>(tab, st, bq, srow, Lb, base, lane, kmul, shv, 0u, fo, qm2);
+            } else {
+                if (par == 0)
+                    check_pass<SLOTS, 0, LLR_FLIP, TABLE, true>(tab, st, bq, srow, Lb, base, lane, kmul, shv, flipslots,
+                                                                fo, qm2);
+                else
+                    check_pass<SLOTS, 1, LLR_FLIP, TABLE, true>(tab, st, bq, srow, Lb, base, lane, kmul, shv, flipslots,
+                                                                fo, qm2);
+            }
             for (int w = lane; w < C.mw; w += 64) SHc[w] = 0u;
             wave_sync();
             // ---- column pass: hard decision, syndrome estimate, reset of the consumed half
