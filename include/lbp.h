@@ -139,7 +139,11 @@ int32_t lbp_code_rows(lbp_code code);
 int32_t lbp_code_cols(lbp_code code);
 
 /* Create a decoder for `code` with parameters *prm, able to decode up to
- * max_batch shots per call.  Allocates the device workspace (on the code's
+ * max_batch shots per call.  *prm fixes Algorithm 1's remaining input, the
+ * iteration limit I, and the choices the paper leaves to the decoder: the
+ * message format (Sec. VII-A), the check-node scale (Algorithm 1, CN update),
+ * the lottery and its rule (Algorithm 3, Sec. III-B) and the OSD fallback
+ * (Algorithm 2, or the OSD-CS sweep).  Allocates the device workspace (on the code's
  * device).  OSD-CS requires a uniform prior (LBP_EUNSUPPORTED otherwise): its
  * candidate cost is the Hamming weight.  The decoder holds a reference to the
  * code: lbp_code_destroy may come before lbp_decoder_destroy (in any order);
@@ -155,7 +159,10 @@ lbp_status lbp_decoder_create(lbp_code code, const lbp_params *prm, int64_t max_
 void lbp_decoder_destroy(lbp_decoder dec);
 
 /* Decode n_shots syndromes, asynchronously on `stream` (a hipStream_t; NULL =
- * the default stream).  All array arguments are DEVICE pointers owned by the
+ * the default stream): per shot, Algorithm 1 (with Algorithm 3 when the lottery
+ * is on) maps the syndrome s to the estimate e_hat; a shot whose run ends
+ * without H e_hat = s goes to Algorithm 2 (OSD) with the lambda of the last
+ * iteration, which replaces e_hat.  All array arguments are DEVICE pointers owned by the
  * caller, which must keep them alive until the stream has passed this call:
  *   syndromes   [n_shots][ceil(m/32)]  in
  *   corrections [n_shots][ceil(n/32)]  out: e_hat (BP hard decision, or OSD result)
@@ -212,10 +219,20 @@ lbp_status lbp_decode_noalloc(lbp_decoder dec, int64_t n_shots, uint64_t first_s
 lbp_status lbp_decode_baseline(lbp_decoder dec, int64_t n_shots, uint64_t first_shot_id, const uint32_t *syndromes,
                                uint32_t *corrections, uint8_t *flags, int32_t *iters, void *stream);
 
-/* Same contract as lbp_decode with HOST pointers; synchronous.  Allocates and
+/* Same contract as lbp_decode (Algorithm 1 with Algorithm 3, then Algorithm 2
+ * on the shots BP leaves unsolved) with HOST pointers; synchronous.  Allocates and
  * frees device staging buffers internally. */
 lbp_status lbp_decode_host(lbp_decoder dec, int64_t n_shots, uint64_t first_shot_id, const uint32_t *syndromes,
                            uint32_t *corrections, uint8_t *flags, int32_t *iters, float *llr_out);
+
+/* The decoder's launch shapes, chosen at creation (any output may be NULL):
+ * BP waves per workgroup and resident workgroups of the persistent grid, BP
+ * group size (waves that decode one shot together; 1 = a wavefront per shot),
+ * and the OSD kernel: variant (> 0: G in registers, 100 * rows per lane + words
+ * per row; 0: G in LDS; -1: G in global memory; -2: G and the per-column arrays
+ * in global memory), threads per workgroup and workgroups. */
+lbp_status lbp_decoder_shape(lbp_decoder dec, int32_t *bp_waves_per_block, int32_t *bp_blocks, int32_t *bp_group,
+                             int32_t *osd_variant, int32_t *osd_threads, int32_t *osd_blocks);
 
 /* Device bytes held by the decoder's workspace, and its max_batch. */
 int64_t lbp_decoder_device_bytes(lbp_decoder dec);

@@ -93,6 +93,7 @@ SIGNATURES = {
     "lbp_decode_keyed": (_I32, [_VP, _I64, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
     "lbp_decode_noalloc": (_I32, [_VP, _I64, _U64, _VP, _VP, _VP, _VP, _VP, _VP]),
     "lbp_decode_baseline": (_I32, [_VP, _I64, _U64, _VP, _VP, _VP, _VP, _VP]),
+    "lbp_decoder_shape": (_I32, [_VP] + [ctypes.POINTER(_I32)] * 6),
     "lbp_decoder_device_bytes": (_I64, [_VP]),
     "lbp_decoder_max_batch": (_I64, [_VP]),
     "lbp_plan_create": (_I32, [_I32, _VP, _I32, ctypes.POINTER(_VP)]),

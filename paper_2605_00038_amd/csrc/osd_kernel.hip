@@ -543,6 +543,8 @@ __global__ __launch_bounds__(1024 / R, 8 / R) void osd_reg_kernel(OsdArgs a) {
     uint16_t *perm = (uint16_t *)q0;                 q0 += ((size_t)n * 2 + 15) & ~(size_t)15;
     uint16_t *tl = (uint16_t *)q0;                   q0 += ((size_t)n * 2 + 15) & ~(size_t)15;
     uint8_t *isb = q0;                               q0 += ((size_t)n + 15) & ~(size_t)15;
+    // candidate rows: aligned to the vector's own size (the row loads and stores assume it)
+    q0 = smem + (((size_t)(q0 - smem) + sizeof(vrow<NW>) - 1) & ~(sizeof(vrow<NW>) - 1));
     vrow<NW> *crow = (vrow<NW> *)q0;                 q0 += (32 * sizeof(vrow<NW>) + 15) & ~(size_t)15;
     uint32_t *csp = (uint32_t *)q0;                  q0 += 32 * 4;
     uint32_t *cw = (uint32_t *)q0;                   q0 += ((size_t)a.nw * 4 + 15) & ~(size_t)15;
@@ -791,7 +793,8 @@ int osd_block_bytes(int m, int n, int lds_limit, int rows_per_lane, int *variant
         *threads = 64 * ((m + 64 * r - 1) / (64 * r));
         size_t vb = 4;  // a vector of nw words occupies the next power of two bytes
         while (vb < (size_t)nw * 4) vb <<= 1;
-        return (int)(al((size_t)P * 8) + common + al(32 * vb) + 32 * 4 + 16 * 8 + 16 * 4);  // key slots: 32 words
+        // + up to vb - 16 bytes to align the candidate rows to their vector size
+        return (int)(al((size_t)P * 8) + common + (vb - 16) + al(32 * vb) + 32 * 4 + 16 * 8 + 16 * 4);  // key slots: 32 words
     }
     *threads = OSD_THREADS;
     // pivot row words, s' ballots, and for G in global memory at large m its occupancy mask

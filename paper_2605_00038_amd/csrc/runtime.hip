@@ -991,6 +991,18 @@ lbp_status lbp_decode_baseline(lbp_decoder d, int64_t n_shots, uint64_t first_sh
     return LBP_OK;
 }
 
+lbp_status lbp_decoder_shape(lbp_decoder d, int32_t *bp_waves_per_block, int32_t *bp_blocks, int32_t *bp_group,
+                             int32_t *osd_variant, int32_t *osd_threads, int32_t *osd_blocks) {
+    if (!d) return fail(LBP_EINVAL, "lbp_decoder_shape: NULL decoder");
+    if (bp_waves_per_block) *bp_waves_per_block = d->wpb;
+    if (bp_blocks) *bp_blocks = d->bp_blocks;
+    if (bp_group) *bp_group = d->group ? d->wpb : 1;
+    if (osd_variant) *osd_variant = d->osd_variant;
+    if (osd_threads) *osd_threads = d->osd_threads;
+    if (osd_blocks) *osd_blocks = d->osd_blocks;
+    return LBP_OK;
+}
+
 int64_t lbp_decoder_device_bytes(lbp_decoder d) { return d ? d->dev_bytes : 0; }
 int64_t lbp_decoder_max_batch(lbp_decoder d) { return d ? d->max_batch : 0; }
 

@@ -169,6 +169,13 @@ class Decoder:
                                          corr.data_ptr(), flags.data_ptr(), iters.data_ptr(), s.cuda_stream))
         return corr, flags, iters
 
+    def shape(self) -> dict:
+        """lbp_decoder_shape: the BP and OSD launch shapes chosen at creation."""
+        v = [ctypes.c_int32() for _ in range(6)]
+        check(load().lbp_decoder_shape(self._h, *[ctypes.byref(x) for x in v]))
+        keys = ("bp_waves_per_block", "bp_blocks", "bp_group", "osd_variant", "osd_threads", "osd_blocks")
+        return {k: x.value for k, x in zip(keys, v)}
+
     @property
     def device_bytes(self) -> int:
         return int(load().lbp_decoder_device_bytes(self._h))

@@ -87,7 +87,12 @@ def test_register_kernel_boundary(m, osd):
     p = 0.07
     e, syn = sample.make_batch(h, p, 60, 1710 + m)
     prm = _params(msg=2, max_iter=8, lottery=False, osd=osd, osd_order=10)
-    _say("osd boundary", m, osd)
+    from paper_2605_00038_amd import Code, Decoder
+    variant = Decoder(Code.from_scipy(h, p), prm, 60).shape()["osd_variant"]
+    _say("osd boundary", m, osd, "variant", variant)
+    # the two sides of the boundary run the two kernels: G in registers (two 32-word
+    # rows per lane), then G in LDS
+    assert variant == (232 if m == 1023 else 0)
     g = gpu_decode(h, p, prm, syn, want_llr=True)
     o = oracle.decode(h, p, oracle_params(prm), syn, want_llr=True, n_threads=8)
     assert ((g["flags"] & 2) != 0).sum() >= 20
