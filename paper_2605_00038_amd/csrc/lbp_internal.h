@@ -332,8 +332,9 @@ int bp_wave_bytes(int msg, int m, int n);
 // variant = 100 * rows per lane + NW words per row; rows_per_lane 1, else 2),
 // 0 keeps G in LDS, -1 in global memory, -2 also keeps the per-column arrays
 // (sort keys, order, non-basis list) in global memory (large n).  Returns LDS
-// bytes per block; *threads is the block size.
-int osd_block_bytes(int m, int n, int lds_limit, int rows_per_lane, int *variant, int *mws, int *sort_p,
+// bytes per block for lambda staged as int16 (i16 = 1) or as fp32 pairs (0);
+// *threads is the block size.
+int osd_block_bytes(int m, int n, int lds_limit, int rows_per_lane, int i16, int *variant, int *mws, int *sort_p,
                     int *threads);
 // Per-block global scratch of the OSD kernel.
 size_t osd_scratch_bytes(int variant, int m, int n, int mws, int sort_p, int cs);

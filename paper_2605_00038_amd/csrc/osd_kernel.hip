@@ -152,6 +152,32 @@ __device__ void sort_columns(const float *lam, int n, int P, int has_lo, int i16
     __syncthreads();
 }
 
+// Step 1 for int16 lambda: the key (lambda + 2^15) << 16 | column is 32 bits, so
+// the sort moves half the bytes of the general one and its keys take P * 4
+// bytes of LDS.
+__device__ void sort_columns_i16(const int16_t *lq, int n, int P, uint32_t *keys, uint16_t *perm) {
+    const int tid = threadIdx.x, nth = blockDim.x;
+    for (int j = tid; j < P; j += nth)
+        keys[j] = j < n ? ((uint32_t)((int32_t)lq[j] + 32768) << 16) | (uint32_t)j : ~0u;
+    __syncthreads();
+    for (int k = 2; k <= P; k <<= 1) {
+        for (int jj = k >> 1; jj > 0; jj >>= 1) {
+            for (int t = tid; t < (P >> 1); t += nth) {
+                const int i = ((t & ~(jj - 1)) << 1) | (t & (jj - 1));
+                const int l = i + jj;
+                const uint32_t x = keys[i], y = keys[l];
+                if ((x > y) == ((i & k) == 0)) {
+                    keys[i] = y;
+                    keys[l] = x;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int j = tid; j < n; j += nth) perm[j] = (uint16_t)(keys[j] & 0xFFFFu);
+    __syncthreads();
+}
+
 // Non-basis columns in sorted order -> tl[0..nt).
 __device__ int list_nonbasis(const uint8_t *isb, const uint16_t *perm, int n, uint16_t *tl, int *scr) {
     const int nth = blockDim.x;
@@ -454,6 +480,37 @@ __global__ __launch_bounds__(1024, 8) void osd_lds_kernel(OsdArgs a) {
 template <int NW>
 using vrow = uint32_t __attribute__((ext_vector_type(NW)));
 
+// Byte offsets of the register kernel's LDS arrays; the host sizes the block's
+// dynamic LDS with the same function.  The sort keys (P u32 for int16 lambda,
+// else P u64) are dead after the sort, and the sorted columns' check lists
+// (n u64) reuse their space.  vb is the byte size of one candidate row vector.
+struct RegLds {
+    uint32_t cols, perm, tl, isb, crow, csp, cw, wkey, scr, Y, best, total;
+};
+
+__host__ __device__ inline RegLds reg_lds_layout(int n, int P, int nw_corr, int vb, int i16) {
+    auto al = [](uint32_t x) { return (x + 15u) & ~15u; };
+    RegLds L{};
+    uint32_t keys = (uint32_t)P * (i16 ? 4u : 8u);
+    if (keys < (uint32_t)n * 8u) keys = (uint32_t)n * 8u;
+    uint32_t o = al(keys);
+    L.cols = o;
+    if (!i16) o += al((uint32_t)n * 4);  // tie-break columns of the pair keys (P u16)
+    L.perm = o;  o += al((uint32_t)n * 2);
+    L.tl = o;    o += al((uint32_t)n * 2);
+    L.isb = o;   o += al((uint32_t)n);
+    o = (o + (uint32_t)vb - 1) & ~((uint32_t)vb - 1);  // the row loads and stores assume this alignment
+    L.crow = o;  o += 32u * (uint32_t)vb;
+    L.csp = o;   o += 32 * 4;
+    L.cw = o;    o += al((uint32_t)nw_corr * 4);
+    L.wkey = o;  o += 32 * 4;
+    L.scr = o;   o += 32 * 4;
+    L.Y = o;     o += 16 * 8;
+    L.best = o;  o += 16;
+    L.total = o;
+    return L;
+}
+
 static_assert(sizeof(vrow<28>) == 128 && sizeof(vrow<32>) == 128 && sizeof(vrow<16>) == 64 && sizeof(vrow<8>) == 32,
               "osd_block_bytes assumes power-of-two vector sizes");
 
@@ -538,20 +595,18 @@ __global__ __launch_bounds__(1024 / R, 8 / R) void osd_reg_kernel(OsdArgs a) {
         row[k] = k * nth + tid;
         valid[k] = row[k] < m;
     }
-    unsigned char *q0 = smem + (((size_t)P * 8 + 15) & ~(size_t)15);
-    uint16_t *scol = (uint16_t *)q0;                 q0 += ((size_t)n * 4 + 15) & ~(size_t)15;
-    uint16_t *perm = (uint16_t *)q0;                 q0 += ((size_t)n * 2 + 15) & ~(size_t)15;
-    uint16_t *tl = (uint16_t *)q0;                   q0 += ((size_t)n * 2 + 15) & ~(size_t)15;
-    uint8_t *isb = q0;                               q0 += ((size_t)n + 15) & ~(size_t)15;
-    // candidate rows: aligned to the vector's own size (the row loads and stores assume it)
-    q0 = smem + (((size_t)(q0 - smem) + sizeof(vrow<NW>) - 1) & ~(sizeof(vrow<NW>) - 1));
-    vrow<NW> *crow = (vrow<NW> *)q0;                 q0 += (32 * sizeof(vrow<NW>) + 15) & ~(size_t)15;
-    uint32_t *csp = (uint32_t *)q0;                  q0 += 32 * 4;
-    uint32_t *cw = (uint32_t *)q0;                   q0 += ((size_t)a.nw * 4 + 15) & ~(size_t)15;
-    uint32_t *wkey = (uint32_t *)q0;                 q0 += 32 * 4;  // per wave and row buffer: candidate key
-    int *scr = (int *)q0;                            q0 += 32 * 4;
-    unsigned long long *Y = (unsigned long long *)q0; q0 += 16 * 8;
-    unsigned long long *best64 = (unsigned long long *)q0;
+    const RegLds L = reg_lds_layout(n, P, a.nw, (int)sizeof(vrow<NW>), a.llr_i16);
+    uint16_t *scol = (uint16_t *)(smem + L.cols);
+    uint16_t *perm = (uint16_t *)(smem + L.perm);
+    uint16_t *tl = (uint16_t *)(smem + L.tl);
+    uint8_t *isb = smem + L.isb;
+    vrow<NW> *crow = (vrow<NW> *)(smem + L.crow);
+    uint32_t *csp = (uint32_t *)(smem + L.csp);
+    uint32_t *cw = (uint32_t *)(smem + L.cw);
+    uint32_t *wkey = (uint32_t *)(smem + L.wkey);  // per wave and row buffer: candidate key
+    int *scr = (int *)(smem + L.scr);
+    unsigned long long *Y = (unsigned long long *)(smem + L.Y);
+    unsigned long long *best64 = (unsigned long long *)(smem + L.best);
     // 64-row ballots of G's columns: group k * nwv + w holds rows k * nth + 64 w + lane (R * nwv <= 16)
     unsigned long long *B = (unsigned long long *)a.gscratch + (size_t)blockIdx.x * 16 * m;
     const int ngr = R * nwv;
@@ -565,7 +620,10 @@ __global__ __launch_bounds__(1024 / R, 8 / R) void osd_reg_kernel(OsdArgs a) {
         const float *lam = a.llr_i16 ? (const float *)((const int16_t *)a.fail_llr + lrow * n) : a.fail_llr + lrow * 2 * n;
 
         // ---- 1. sort (lambda, column) ascending
-        sort_columns(lam, n, P, a.has_lo, a.llr_i16, (unsigned long long *)smem, scol, perm);
+        if (a.llr_i16)
+            sort_columns_i16((const int16_t *)lam, n, P, (uint32_t *)smem, perm);
+        else
+            sort_columns(lam, n, P, a.has_lo, 0, (unsigned long long *)smem, scol, perm);
 
         // check indices of the sorted columns, staged over the dead sort keys
         uint64_t *ptab = (uint64_t *)smem;
@@ -588,8 +646,13 @@ __global__ __launch_bounds__(1024 / R, 8 / R) void osd_reg_kernel(OsdArgs a) {
         const uint32_t *sw = a.synd + shot * a.mw;
 #pragma unroll
         for (int k = 0; k < R; ++k) {
+            // the identity rows depend on the lane only; kept opaque so that they are
+            // rebuilt here per shot instead of being hoisted out of the shot loop
+            // and held (spilled) across it
+            int rk = valid[k] ? row[k] : -1;
+            asm volatile("" : "+v"(rk));
 #pragma unroll
-            for (int w = 0; w < NW; ++w) g[k][w] = (valid[k] && w == (row[k] >> 5)) ? (1u << (row[k] & 31)) : 0u;
+            for (int w = 0; w < NW; ++w) g[k][w] = (rk >= 0 && w == (rk >> 5)) ? (1u << (rk & 31)) : 0u;
             sp[k] = valid[k] ? (sw[row[k] >> 5] >> (row[k] & 31)) & 1u : 0u;
             pcol[k] = 0;
             freem[k] = __ballot(valid[k]);
@@ -775,7 +838,7 @@ __global__ __launch_bounds__(1024 / R, 8 / R) void osd_reg_kernel(OsdArgs a) {
 
 }  // namespace
 
-int osd_block_bytes(int m, int n, int lds_limit, int rows_per_lane, int *variant, int *mws, int *sort_p,
+int osd_block_bytes(int m, int n, int lds_limit, int rows_per_lane, int i16, int *variant, int *mws, int *sort_p,
                     int *threads) {
     int P = 1;
     while (P < n) P <<= 1;
@@ -791,10 +854,9 @@ int osd_block_bytes(int m, int n, int lds_limit, int rows_per_lane, int *variant
         *variant = 100 * r + nw;
         *mws = mw;
         *threads = 64 * ((m + 64 * r - 1) / (64 * r));
-        size_t vb = 4;  // a vector of nw words occupies the next power of two bytes
-        while (vb < (size_t)nw * 4) vb <<= 1;
-        // + up to vb - 16 bytes to align the candidate rows to their vector size
-        return (int)(al((size_t)P * 8) + common + (vb - 16) + al(32 * vb) + 32 * 4 + 16 * 8 + 16 * 4);  // key slots: 32 words
+        int vb = 4;  // a vector of nw words occupies the next power of two bytes
+        while (vb < nw * 4) vb <<= 1;
+        return (int)reg_lds_layout(n, P, (n + 31) / 32, vb, i16).total;
     }
     *threads = OSD_THREADS;
     // pivot row words, s' ballots, and for G in global memory at large m its occupancy mask

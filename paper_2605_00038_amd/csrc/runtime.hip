@@ -113,6 +113,7 @@ struct lbp_decoder_s {
     int wpb = 1, bp_blocks = 1, wave_bytes = 0, int8_slots = 0, table_bytes = 0, group = 0;
     int int8_table = 0;  // where the Int x.y kernel takes its column offsets from (bp_int8_table_bytes)
     int osd_blocks = 0, osd_lds = 0, osd_variant = 0, osd_threads = 1024, mws = 1, sort_p = 1;
+    int osd_lds_pairs = 0;  // OSD LDS per block when lambda is staged as fp32 pairs (general BP kernel)
     int64_t fail_cap = 0;
     int64_t llr_bytes = 0;         // staged lambda per failed shot: 2n (int16, Int x.y kernel) or 8n (hi, lo floats)
     bool fail_cap_pinned = false;  // set by lbp_decoder_set_osd_capacity: never grown
@@ -251,7 +252,7 @@ lbp_status lbp::decoder_launch_osd(lbp_decoder d, const uint32_t *synd, uint32_t
     o.fail_cap = fail_cap;
     o.gscratch = gscratch;
     o.llr_i16 = 0;  // the general kernel stages every format as fp32 pairs
-    HIPCHK(launch_osd(o, d->osd_variant, blocks, d->osd_threads, d->osd_lds, s));
+    HIPCHK(launch_osd(o, d->osd_variant, blocks, d->osd_threads, d->osd_lds_pairs, s));
     return LBP_OK;
 }
 
@@ -597,9 +598,13 @@ lbp_status lbp_decoder_create(lbp_code code, const lbp_params *prm, int64_t max_
     // LBP_OSD_ROWS_PER_LANE=1 (read here) asks for one, for tests.
     const char *rpl_env = std::getenv("LBP_OSD_ROWS_PER_LANE");
     const int rpl = rpl_env && std::atoi(rpl_env) == 1 ? 1 : 2;
-    d->osd_lds = osd_block_bytes(code->m, code->n, lds_block - 1024, rpl, &d->osd_variant, &d->mws, &d->sort_p,
-                                 &d->osd_threads);
-    if (d->osd_lds > lds_block - 1024) return cleanup_fail(LBP_EUNSUPPORTED, "lbp_decoder_create: OSD sort does not fit LDS");
+    d->osd_lds_pairs = osd_block_bytes(code->m, code->n, lds_block - 1024, rpl, 0, &d->osd_variant, &d->mws,
+                                       &d->sort_p, &d->osd_threads);
+    d->osd_lds = d->int8_slots ? osd_block_bytes(code->m, code->n, lds_block - 1024, rpl, 1, &d->osd_variant, &d->mws,
+                                                 &d->sort_p, &d->osd_threads)
+                               : d->osd_lds_pairs;
+    if (d->osd_lds_pairs > lds_block - 1024)
+        return cleanup_fail(LBP_EUNSUPPORTED, "lbp_decoder_create: OSD sort does not fit LDS");
     int obpc = 0;
     if (prm->osd && (osd_max_blocks_per_cu(d->osd_variant, d->osd_threads, d->osd_lds, &obpc) != hipSuccess || obpc < 1))
         return cleanup_fail(LBP_EDEVICE, "lbp_decoder_create: no feasible OSD launch shape");
@@ -986,7 +991,7 @@ lbp_status lbp_decode_baseline(lbp_decoder d, int64_t n_shots, uint64_t first_sh
         o.gscratch = d->d_gscratch;
         o.has_lo = 1;     // the comparison path stages lambda as an fp32 (hi, lo) pair
         o.llr_i16 = 0;
-        HIPCHK(launch_osd(o, d->osd_variant, d->osd_blocks, d->osd_threads, d->osd_lds, s));
+        HIPCHK(launch_osd(o, d->osd_variant, d->osd_blocks, d->osd_threads, d->osd_lds_pairs, s));
     }
     return LBP_OK;
 }
