@@ -140,6 +140,15 @@ struct lbp_decoder_s {
     };
     std::vector<Rec> recs;
     std::vector<hipEvent_t> pool;
+    // pipelined decode of large batches: BP of chunk i + 1 on the caller's stream
+    // while OSD of chunk i runs on `side`; chunks alternate over two failure
+    // workspaces, each sized for a whole chunk (no chunk can overflow its staging)
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_bp[2] = {nullptr, nullptr}, ev_osd[2] = {nullptr, nullptr};
+    int64_t pipe_chunk = 0;  // shots per chunk the workspaces hold (0: none yet)
+    uint32_t *pipe_counters[2] = {nullptr, nullptr};
+    int32_t *pipe_list[2] = {nullptr, nullptr};
+    float *pipe_llr[2] = {nullptr, nullptr};
 };
 
 static hipEvent_t take_event(lbp_decoder d) {
@@ -457,6 +466,15 @@ static void free_decoder(lbp_decoder d) {
     hipFree(d->bl_flipv);
     hipFree(d->bl_active);
     hipFree(d->d_muq);
+    for (int c = 0; c < 2; ++c) {
+        hipFree(d->pipe_counters[c]);
+        hipFree(d->pipe_list[c]);
+        hipFree(d->pipe_llr[c]);
+        if (d->ev_bp[c]) hipEventDestroy(d->ev_bp[c]);
+        if (d->ev_osd[c]) hipEventDestroy(d->ev_osd[c]);
+    }
+    if (d->ev_fork) hipEventDestroy(d->ev_fork);
+    if (d->side) hipStreamDestroy(d->side);
     if (d->code) code_release(d->code);
     d->code = nullptr;
 }
@@ -688,9 +706,11 @@ static PassBufs own_bufs(lbp_decoder d) {
                     d->d_gscratch, d->osd_blocks, d->timing};
 }
 
-static lbp_status run_pass(lbp_decoder d, const PassBufs &w, int64_t n_work, const int32_t *work_list,
-                           uint64_t first_shot_id, const uint64_t *keys, const uint32_t *syn, uint32_t *corr,
-                           uint8_t *flags, int32_t *iters, float *llr, hipStream_t s) {
+// Algorithm 1 (with Algorithm 3) over n_work shots; the failures are listed and
+// their lambda staged in w for bp_pass's OSD.
+static lbp_status bp_pass(lbp_decoder d, const PassBufs &w, int64_t n_work, const int32_t *work_list,
+                          uint64_t first_shot_id, const uint64_t *keys, const uint32_t *syn, uint32_t *corr,
+                          uint8_t *flags, int32_t *iters, float *llr, hipStream_t s) {
     HIPCHK(launch_reset(w.counters, 16, s));
     BpArgs a{};
     a.code = d->dc;
@@ -723,6 +743,12 @@ static lbp_status run_pass(lbp_decoder d, const PassBufs &w, int64_t n_work, con
         HIPCHK(hipEventRecord(e1, s));
         d->recs.push_back({e0, e1, 0});
     }
+    return LBP_OK;
+}
+
+// Algorithm 2 (or OSD-CS) on the failures a bp_pass listed in w.
+static lbp_status osd_pass(lbp_decoder d, const PassBufs &w, const uint32_t *syn, uint32_t *corr, uint8_t *flags,
+                           hipStream_t s) {
     if (d->prm.osd) {
         OsdArgs o = osd_args(d);
         o.synd = syn;
@@ -741,6 +767,93 @@ static lbp_status run_pass(lbp_decoder d, const PassBufs &w, int64_t n_work, con
             d->recs.push_back({f0, f1, 1});
         }
     }
+    return LBP_OK;
+}
+
+static lbp_status run_pass(lbp_decoder d, const PassBufs &w, int64_t n_work, const int32_t *work_list,
+                           uint64_t first_shot_id, const uint64_t *keys, const uint32_t *syn, uint32_t *corr,
+                           uint8_t *flags, int32_t *iters, float *llr, hipStream_t s) {
+    lbp_status st = bp_pass(d, w, n_work, work_list, first_shot_id, keys, syn, corr, flags, iters, llr, s);
+    if (st != LBP_OK) return st;
+    return osd_pass(d, w, syn, corr, flags, s);
+}
+
+// Chunks of a pipelined decode (LBP_PIPELINE_CHUNKS, read at each call: 0 or 1 =
+// one pass); only batches of at least 2^17 shots with OSD are split.
+static int pipeline_chunks(lbp_decoder d, int64_t n_shots) {
+    if (!d->prm.osd || n_shots < ((int64_t)1 << 17)) return 1;
+    const char *e = std::getenv("LBP_PIPELINE_CHUNKS");
+    const int k = e ? std::atoi(e) : 0;
+    return k >= 2 && k <= 64 ? k : 1;
+}
+
+// Workspaces and the side stream of a pipelined decode with chunks of `chunk`
+// shots (grown, never shrunk).
+static lbp_status pipeline_prepare(lbp_decoder d, int64_t chunk) {
+    if (!d->side) {
+        HIPCHK(hipStreamCreateWithFlags(&d->side, hipStreamNonBlocking));
+        HIPCHK(hipEventCreateWithFlags(&d->ev_fork, hipEventDisableTiming));
+        for (int c = 0; c < 2; ++c) {
+            HIPCHK(hipEventCreateWithFlags(&d->ev_bp[c], hipEventDisableTiming));
+            HIPCHK(hipEventCreateWithFlags(&d->ev_osd[c], hipEventDisableTiming));
+        }
+    }
+    if (chunk <= d->pipe_chunk) return LBP_OK;
+    for (int c = 0; c < 2; ++c) {
+        hipFree(d->pipe_counters[c]);
+        hipFree(d->pipe_list[c]);
+        hipFree(d->pipe_llr[c]);
+        d->pipe_counters[c] = nullptr;
+        d->pipe_list[c] = nullptr;
+        d->pipe_llr[c] = nullptr;
+    }
+    d->pipe_chunk = 0;
+    for (int c = 0; c < 2; ++c) {
+        if (hipMalloc((void **)&d->pipe_counters[c], 64) != hipSuccess ||
+            hipMalloc((void **)&d->pipe_list[c], (size_t)chunk * 4) != hipSuccess ||
+            hipMalloc((void **)&d->pipe_llr[c], (size_t)chunk * d->llr_bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(LBP_ENOMEM, "pipelined decode: workspace allocation failed");
+        }
+    }
+    d->pipe_chunk = chunk;
+    return LBP_OK;
+}
+
+// BP of chunk i + 1 overlaps OSD of chunk i: BP runs in order on s, each chunk's
+// OSD on the side stream after that chunk's BP; a chunk reuses the workspace of
+// chunk i - 2 only after that chunk's OSD.  The side stream joins s at the end.
+static lbp_status decode_pipelined(lbp_decoder d, int k, int64_t n_shots, uint64_t first_shot_id,
+                                   const uint64_t *keys, const uint32_t *syndromes, uint32_t *corrections,
+                                   uint8_t *flags, int32_t *iters, float *llr_out, hipStream_t s) {
+    const int64_t chunk = (n_shots + k - 1) / k;
+    lbp_status st = pipeline_prepare(d, chunk);
+    if (st != LBP_OK) return st;
+    const size_t mw = d->code->dc.mw, nw = d->code->dc.nw, n = d->code->n;
+    HIPCHK(hipEventRecord(d->ev_fork, s));
+    HIPCHK(hipStreamWaitEvent(d->side, d->ev_fork, 0));
+    for (int i = 0; i * chunk < n_shots; ++i) {
+        const int c = i & 1;
+        const int64_t off = (int64_t)i * chunk, cnt = std::min(chunk, n_shots - off);
+        PassBufs w = own_bufs(d);
+        w.counters = d->pipe_counters[c];
+        w.fail_list = d->pipe_list[c];
+        w.fail_llr = d->pipe_llr[c];
+        w.fail_cap = chunk;
+        if (i >= 2) HIPCHK(hipStreamWaitEvent(s, d->ev_osd[c], 0));
+        const uint32_t *syn = syndromes + (size_t)off * mw;
+        uint32_t *corr = corrections + (size_t)off * nw;
+        st = bp_pass(d, w, cnt, nullptr, first_shot_id + (keys ? 0 : (uint64_t)off), keys ? keys + 2 * off : nullptr, syn,
+                     corr, flags + off, iters ? iters + off : nullptr, llr_out ? llr_out + (size_t)off * n : nullptr, s);
+        if (st != LBP_OK) return st;
+        HIPCHK(hipEventRecord(d->ev_bp[c], s));
+        HIPCHK(hipStreamWaitEvent(d->side, d->ev_bp[c], 0));
+        st = osd_pass(d, w, syn, corr, flags + off, d->side);
+        if (st != LBP_OK) return st;
+        HIPCHK(hipEventRecord(d->ev_osd[c], d->side));
+    }
+    HIPCHK(hipEventRecord(d->ev_fork, d->side));
+    HIPCHK(hipStreamWaitEvent(s, d->ev_fork, 0));
     return LBP_OK;
 }
 
@@ -804,6 +917,9 @@ static lbp_status decode_impl(const char *who, lbp_decoder d, int64_t n_shots, u
     if (!syndromes || !corrections || !flags) return fail(LBP_EINVAL, std::string(who) + ": NULL buffer");
     DeviceGuard g(d->code->device);
     hipStream_t s = (hipStream_t)stream;
+    const int k = pipeline_chunks(d, n_shots);
+    if (k > 1) return decode_pipelined(d, k, n_shots, first_shot_id, keys, syndromes, corrections, flags, iters,
+                                       llr_out, s);
     lbp_status st = run_pass(d, own_bufs(d), n_shots, nullptr, first_shot_id, keys, syndromes, corrections, flags,
                              iters, llr_out, s);
     if (st != LBP_OK || !d->prm.osd || n_shots <= d->fail_cap) return st;
