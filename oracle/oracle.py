@@ -61,14 +61,23 @@ class OracleParams:
                        self.policy, self.fx_int, self.fx_frac, self.seed & 0xFFFFFFFFFFFFFFFF)
 
 
+# ORACLE_SANITIZE=1 builds and loads an AddressSanitizer + UndefinedBehaviorSanitizer
+# build instead (host code only; the process must preload libasan, see sanitize_check.sh).
+_SANITIZE = os.environ.get("ORACLE_SANITIZE") == "1"
+_SAN_LIB = os.path.join(os.path.dirname(_LIB), "liboracle_san.so")
+
+
 def build(force: bool = False) -> str:
-    """Compile liboracle.so with gcc (plain C, -O2)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-fPIC", "-shared", "-Wall",
-                               "-o", tmp, _SRC, "-lm", "-lpthread"])
-        os.replace(tmp, _LIB)
-    return _LIB
+    """Compile liboracle.so with gcc (plain C, -O2), or the sanitizer build."""
+    lib = _SAN_LIB if _SANITIZE else _LIB
+    if force or not os.path.exists(lib) or os.path.getmtime(lib) < os.path.getmtime(_SRC):
+        tmp = lib + ".tmp"
+        flags = (["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+                  "-fno-sanitize-recover=undefined"] if _SANITIZE else ["-O2"])
+        subprocess.check_call(["gcc"] + flags + ["-std=c11", "-D_GNU_SOURCE", "-fPIC", "-shared", "-Wall",
+                                                 "-o", tmp, _SRC, "-lm", "-lpthread"])
+        os.replace(tmp, lib)
+    return lib
 
 
 _lib = None
