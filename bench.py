@@ -37,6 +37,8 @@ LOTTERY_SEED = 2004
 MSG_CODES = {"fp32": 0, "fp16": 1, "int8": 2}
 # VALU issue peak: 256 CUs x 4 SIMD16 x 16 lanes x 2.4 GHz (32-bit ops, no packing)
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+# LDS peak: 256 CUs x 128 bytes per clock x 2.4 GHz
+LDS_PEAK_TBS = 256 * 128 * 2.4e9 / 1e12
 # Algorithmic 32-bit ALU operations per edge-update of NMS BP:
 # VN: add into lambda, subtract for alpha, saturate/round; CN: |alpha|, two
 # compares for min1/min2, sign xor, select min1/min2, sign apply; hard decision
@@ -155,15 +157,16 @@ def host_buffer_rate(h, syn, shots: int):
                 seconds=dt, syndromes_per_s=shots / dt)
 
 
-def serving(h, syn, n_requests: int, shots_per_request: int = 1):
-    """Serving loop under single-syndrome Poisson requests (latency from the
-    scheduled arrival to the poll-visible result).  Saturation is the highest
-    offered rate the server sustains: achieved >= 97% of offered with a median
-    latency under 2 ms (no backlog).  The rates tried are fractions of the
-    back-to-back (flood) rate; p50/p99 are then reported at 50% and 90% of
-    the sustained saturation rate."""
+def serving(h, syn, n_requests: int, shots_per_request: int = 1, msg: str = "int8", p50_runs: int = 3):
+    """Serving loop under Poisson requests of `shots_per_request` syndromes
+    (latency from the scheduled arrival to the poll-visible result).  The rates
+    tried are fractions of the back-to-back (flood) rate, up to 1.2x flood; the
+    sustained saturation is the highest offered rate with achieved >= 97% of
+    offered and a median latency under 2 ms (no backlog).  p50/p99 are then
+    reported at 50% (p50_runs independent runs) and 90% of that rate."""
     from paper_2605_00038_amd import Code, DecoderParams, Server
-    prm = DecoderParams(max_iter=MAX_ITER, msg=2, lottery=True, lottery_skip=6, osd=2, osd_order=OSD_ORDER)
+    prm = DecoderParams(max_iter=MAX_ITER, msg=MSG_CODES[msg], lottery=True, lottery_skip=6, osd=2,
+                        osd_order=OSD_ORDER)
     srv = Server(max_slots=1)
     slot = srv.add_code(Code.from_scipy(h, P_ERR), prm)
     pool = syn[: min(len(syn), 1 << 18)]
@@ -176,27 +179,48 @@ def serving(h, syn, n_requests: int, shots_per_request: int = 1):
 
     run(0.0, min(n_requests, 20000), LOTTERY_SEED)  # warm-up
     flood = run(0.0, n_requests, LOTTERY_SEED)
-    sweep, sat = [], None
-    for k, frac in enumerate((0.05, 0.1, 0.2, 0.3, 0.4, 0.5, 0.6, 0.7, 0.8, 0.9)):
+    sweep, sat, limit = [], None, None
+    fracs = (0.05, 0.1, 0.2, 0.3, 0.4, 0.5, 0.6, 0.7, 0.8, 0.9, 0.95, 1.0, 1.05, 1.1, 1.2)
+    for k, frac in enumerate(fracs):
         rate = frac * flood["achieved_requests_per_s"]
         r = run(rate, int(max(20000, min(n_requests, rate * 0.5))), LOTTERY_SEED + 1 + k)
+        r["fraction_of_flood"] = frac
         sweep.append(r)
         if r["achieved_requests_per_s"] >= 0.97 * rate and r["p50_us"] < 2000.0:
             sat = rate
         else:
+            limit = "achieved < 97% of offered" if r["achieved_requests_per_s"] < 0.97 * rate else "p50 >= 2 ms"
             break
-    out = dict(shots_per_request=shots_per_request, flood=flood, sweep=sweep, saturation_requests_per_s=sat,
-               saturation_syndromes_per_s=(sat or 0.0) * shots_per_request)
+    out = dict(msg=msg, shots_per_request=shots_per_request, flood=flood, sweep=sweep,
+               saturation_requests_per_s=sat, saturation_syndromes_per_s=(sat or 0.0) * shots_per_request,
+               sweep_stopped_by=limit or "every rate tried was sustained")
     if sat:
-        for frac in (0.5, 0.9):
-            out[f"load{int(frac * 100)}"] = run(frac * sat, int(max(20000, min(n_requests, frac * sat * 1.0))),
-                                                LOTTERY_SEED + 20 + int(frac * 10))
+        runs = [run(0.5 * sat, int(max(20000, min(n_requests, 0.5 * sat))), LOTTERY_SEED + 20 + i)
+                for i in range(p50_runs)]
+        out["load50_runs"] = runs
+        out["load50"] = sorted(runs, key=lambda r: r["p99_us"])[len(runs) // 2]  # the run with the median p99
+        out["load90"] = run(0.9 * sat, int(max(20000, min(n_requests, 0.9 * sat))), LOTTERY_SEED + 29)
     out["slot"] = srv.slot_info(slot)
     srv.close()
     return out
 
 
-def cpu_baseline(h, syn, seconds: float):
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(h, syn, seconds: float, gpu=None):
+    """The oracle on the host cores over a bounded prefix of the benchmark batch;
+    with the GPU's outputs for the same shots, also the number of shots whose
+    correction, flags or iteration count differ (the oracle runs the same Int3.4
+    arithmetic, lottery and OSD-CS(10), so the expected count is 0)."""
     import oracle
     threads = os.cpu_count() or 1
     prm = oracle.OracleParams(max_iter=MAX_ITER, msg=oracle.INT8, lottery=True, lottery_skip=6,
@@ -207,11 +231,17 @@ def cpu_baseline(h, syn, seconds: float):
     rate = cal / (time.perf_counter() - t0)
     n = int(min(len(syn), max(cal, rate * seconds)))
     t0 = time.perf_counter()
-    oracle.decode(h, P_ERR, prm, syn[:n], n_threads=threads)
+    o = oracle.decode(h, P_ERR, prm, syn[:n], n_threads=threads)
     dt = time.perf_counter() - t0
-    return dict(value=n / dt, unit="syndromes/s", cores=threads, kind="oracle",
-                sample=f"first {n} shots of the benchmark batch, Int3.4 oracle with the same lottery "
-                       f"and OSD-CS(10), {threads} threads, {dt:.1f} s")
+    out = dict(value=n / dt, unit="syndromes/s", cores=threads, kind="oracle", cpu_model=cpu_model(),
+               sample=f"first {n} shots of the benchmark batch, Int3.4 oracle with the same lottery "
+                      f"and OSD-CS(10), {threads} threads, {dt:.1f} s")
+    if gpu is not None:
+        bad = ((o["corr"] != gpu["corr"][:n]).any(axis=1) | (o["flags"] != gpu["flags"][:n]) |
+               (o["iters"] != gpu["iters"][:n]))
+        out.update(compared_shots=n, mismatched_shots=int(bad.sum()),
+                   osd_shots_compared=int(((o["flags"] & 2) != 0).sum()))
+    return out
 
 
 def bp_kernel_name(msg: str) -> str:
@@ -223,21 +253,25 @@ def bp_kernel_source(msg: str) -> str:
     return "bp_int8_kernel.hip" if msg == "int8" else "bp_kernel.hip"
 
 
-def traffic_from_profiles(msg: str):
-    """HBM bytes per BP launch from the committed rocprofv3 PMC summary, or None
-    when that summary is missing or was taken on a different kernel source."""
+def profile_figures(msg: str) -> dict:
+    """Per-launch figures of the committed rocprofv3 PMC summary for the Int3.4
+    headline: {"bp_hbm_bytes", "bp_lds_bytes", "osd_hbm_bytes"}, each present
+    only while the summary's sha256 of that kernel's source matches the tree."""
+    out = {}
     path = os.path.join(ROOT, "profiles", f"{bp_kernel_name(msg)}_{WORKLOAD}_pmc.md")
-    src = os.path.join(ROOT, "paper_2605_00038_amd", "csrc", bp_kernel_source(msg))
     if not os.path.exists(path):
-        return None
+        return out
     text = open(path).read()
-    m = re.search(r"source_sha256:\s*([0-9a-f]{64})", text)
-    b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
-    if not m or not b:
-        return None
-    if hashlib.sha256(open(src, "rb").read()).hexdigest() != m.group(1):
-        return None
-    return float(b.group(1))
+    csrc = os.path.join(ROOT, "paper_2605_00038_amd", "csrc")
+    for kern, src in (("bp", bp_kernel_source(msg)), ("osd", "osd_kernel.hip")):
+        m = re.search(rf"{kern}_source_sha256:\s*([0-9a-f]{{64}})", text)
+        if not m or hashlib.sha256(open(os.path.join(csrc, src), "rb").read()).hexdigest() != m.group(1):
+            continue
+        for field in ("hbm", "lds"):
+            b = re.search(rf"{kern}_{field}_bytes_per_launch:\s*([0-9.eE+]+)", text)
+            if b:
+                out[f"{kern}_{field}_bytes"] = float(b.group(1))
+    return out
 
 
 # ---------------------------------------------------------------- experiments
@@ -270,8 +304,9 @@ def checker_for(name: str):
     return h, LogicalChecker(single, hc, r)
 
 
-def decode_point(torch, h, checker, p, err, syn, prm, batch: int = 1 << 18):
-    """Decode every shot (in device batches) and summarize accuracy and iterations."""
+def decode_point(torch, h, checker, p, err, syn, prm, batch: int = 1 << 18, plain_path: bool = False):
+    """Decode every shot (in device batches) and summarize accuracy and iterations;
+    plain_path decodes with lbp_decode_baseline (the global-memory FP32 path)."""
     from paper_2605_00038_amd import Code, Decoder
     shots = syn.shape[0]
     dec = Decoder(Code.from_scipy(h, p), prm, min(batch, shots))
@@ -284,7 +319,10 @@ def decode_point(torch, h, checker, p, err, syn, prm, batch: int = 1 << 18):
     for lo in range(0, shots, batch):
         hi = min(shots, lo + batch)
         s = torch.from_numpy(np.ascontiguousarray(syn[lo:hi]).view(np.int32)).cuda()
-        c, f, it, _ = dec.decode(s, first_shot_id=lo)
+        if plain_path:
+            c, f, it = dec.decode_baseline(s, first_shot_id=lo)
+        else:
+            c, f, it, _ = dec.decode(s, first_shot_id=lo)
         corr[lo:hi] = c.cpu().numpy().view(np.uint32)
         flags[lo:hi] = f.cpu().numpy()
         iters[lo:hi] = it.cpu().numpy()
@@ -521,6 +559,13 @@ def run_experiment(args):
                 for lot in (False, True):
                     grid.append((f"surface{d}_phenpf", p, ("lottery_bp" if lot else "plain_bp") + "/osd0",
                                  prm(lottery=lot, osd=1)))
+    elif args.experiment == "formats":     # equal LER across the headline's formats, where logical errors occur
+        for p in ps or [7e-3, 1e-2]:
+            for o, om in osd_modes.items():
+                for label, code in (("int3.4", MSG_CODES["int8"]), ("fp16", MSG_CODES["fp16"]),
+                                    ("fp32", MSG_CODES["fp32"])):
+                    grid.append((args.exp_bb, p, f"{label}/{o}", prm(msg=code, osd=om)))
+                grid.append((args.exp_bb, p, f"plain_fp32_path/{o}", prm(msg=MSG_CODES["fp32"], osd=om)))
     elif args.experiment == "flip":        # what the lottery negates: next messages or lambda itself
         for name in (sd9, args.exp_bb):
             for p in ps or [1e-3, 3e-3]:
@@ -545,7 +590,7 @@ def run_experiment(args):
         h, checker, err, syn = inputs[key]
         # above 16K columns (surface d >= 25), batches of ~2^28 columns keep OSD staging bounded and progress visible
         nb = 1 << 18 if h.shape[1] <= 16384 else max(4096, (1 << 28) // h.shape[1])
-        r = decode_point(torch, h, checker, p, err, syn, pr, batch=nb)
+        r = decode_point(torch, h, checker, p, err, syn, pr, batch=nb, plain_path=label.startswith("plain_fp32_path"))
         r.update(workload=name, p=p, label=label, max_iter=pr.max_iter, lottery=bool(pr.lottery),
                  lottery_skip=pr.lottery_skip, lottery_rule=pr.lottery_rule, flip=pr.flip, osd=pr.osd,
                  msg=pr.msg)
@@ -585,7 +630,7 @@ def main():
     ap.add_argument("--no-ler", action="store_true")
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
     ap.add_argument("--experiment", choices=["policies", "skip", "iters", "ler", "flip", "quant", "osdheavy", "scale",
-                                             "servemix", "batching"],
+                                             "servemix", "batching", "formats"],
                     help="run one of the paper's ablations instead of the benchmark (prints a JSON table)")
     ap.add_argument("--exp-shots", type=int, default=1 << 20, help="shots per experiment point")
     ap.add_argument("--exp-p", default="", help="comma-separated physical error rates (default: per experiment)")
@@ -654,7 +699,7 @@ def main():
                      osd_ms_per_launch=r["osd_ms"] / max(1, r["osd_launches"]),
                      mean_iters=float(r["iters"].mean()), osd_invoke_rate=float(((r["flags"] & 2) != 0).mean()),
                      edge_updates_per_step=edges, steps=steps,
-                     step_ms_median_of_5=float(np.median(r["step_ms_runs"])))
+                     step_ms_median_of_5=float(np.median(r["step_ms_runs"])), osd_blocks=dec.shape()["osd_blocks"])
         if not args.no_ler:
             sf, lf = failures_packed(checker, err_p, r["corr"], n)
             k = int((sf | lf).sum())
@@ -664,6 +709,7 @@ def main():
         log(fmt, json.dumps({k: v for k, v in entry.items()}))
         if fmt == args.msg:
             head_dec, head = dec, entry
+            head_out = dict(corr=r["corr"], flags=r["flags"], iters=r["iters"])
         else:
             del dec
         torch.cuda.empty_cache()
@@ -692,15 +738,40 @@ def main():
     if args.serve_requests > 0:
         serve = serving(h, syn, args.serve_requests)
         log("serving", json.dumps(serve))
+        # what bounds saturation: the same loop with 64-shot requests (the per-request
+        # host cost is then spread over 64 syndromes), and the FP32 decoder's tail
+        serve["requests_of_64_shots"] = serving(h, syn, max(2000, args.serve_requests // 32), 64, p50_runs=1)
+        log("serving 64-shot", json.dumps(serve["requests_of_64_shots"]))
+        serve["fp32_decoder"] = serving(h, syn, args.serve_requests, 1, msg="fp32", p50_runs=1)
+        log("serving fp32", json.dumps(serve["fp32_decoder"]))
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(h, syn, args.cpu_seconds)
+        cpu = cpu_baseline(h, syn, args.cpu_seconds, head_out)
         log("cpu", json.dumps(cpu))
 
     bp_s = head["bp_ms_per_launch"] / 1e3
     ops = head["edge_updates_per_step"] * ALG_OPS_PER_EDGE
     achieved = ops / bp_s / 1e12
-    traffic = traffic_from_profiles(args.msg)
+    prof = profile_figures(args.msg)
+    traffic = prof.get("bp_hbm_bytes")
+    lds = None
+    if "bp_lds_bytes" in prof:
+        lds_tbs = prof["bp_lds_bytes"] / bp_s / 1e12
+        lds = {"achieved": lds_tbs, "peak": LDS_PEAK_TBS, "unit": "TB/s", "frac": lds_tbs / LDS_PEAK_TBS,
+               "bytes_per_launch": prof["bp_lds_bytes"],
+               "kind": "lane bytes of LDS loads, stores and atomics (rocprofv3 SQ_INSTS_LDS_*_BANDWIDTH) "
+                       "over this run's BP launch time"}
+    # OSD: the dense Gauss-Jordan equivalent of Algorithm 2 per OSD shot, m pivots each
+    # XORing an m-bit row into m rows (ceil(m/32) words), over the OSD launch time
+    osd_s = head["osd_ms_per_launch"] / 1e3
+    n_osd = head["osd_invoke_rate"] * args.shots
+    osd_ops = n_osd * m * m * ((m + 31) // 32)
+    osd_tops = osd_ops / osd_s / 1e12 if osd_s > 0 else 0.0
+    osd_roof = {"bound": "latency", "achieved": osd_tops, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
+                "frac": osd_tops / VALU_PEAK_TOPS, "kind": "dense Gauss-Jordan word-XOR equivalent",
+                "kernel": "osd_reg_kernel", "launch_ms": head["osd_ms_per_launch"], "osd_shots": int(round(n_osd)),
+                "traffic": prof.get("osd_hbm_bytes"),
+                "us_per_shot_per_block": (1e6 * osd_s * head["osd_blocks"] / max(1.0, n_osd))}
     line = {
         "metric": "decoded syndromes/sec and p99 latency on 1 MI355X, BB-144 phenomenological",
         "value": head["syndromes_per_s"],
@@ -720,7 +791,7 @@ def main():
         "p99_latency_us": (serve["load50"]["p99_us"] if serve is not None and "load50" in serve
                            else float(np.percentile(lat, 99)) if lat is not None else None),
         "p99_latency_kind": ("serving loop, single-syndrome Poisson requests at 50% of saturation, "
-                             "arrival to poll-visible result" if serve is not None
+                             "arrival to poll-visible result (median p99 of three runs)" if serve is not None
                              else "single-syndrome decode, host call to stream completion"),
         "serving": serve,
         "latency_us": ({"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
@@ -731,7 +802,8 @@ def main():
                      "frac": achieved / VALU_PEAK_TOPS, "traffic": traffic,
                      "kernel": bp_kernel_name(args.msg), "launch_ms": head["bp_ms_per_launch"],
                      "edge_updates_per_s": head["edge_updates_per_step"] / bp_s,
-                     "ops_per_edge_update": ALG_OPS_PER_EDGE},
+                     "ops_per_edge_update": ALG_OPS_PER_EDGE, "lds": lds},
+        "osd_roofline": osd_roof,
         "cpu_baseline": cpu,
         "gpu_plain_fp32_baseline": base,
         "pcie_inclusive": pcie,

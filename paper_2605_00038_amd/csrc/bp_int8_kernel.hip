@@ -443,11 +443,18 @@ __global__ __launch_bounds__(1024) void bp_int8_kernel(BpArgs a) {
     const unsigned short kscale = P.scale_mode == 1 ? (unsigned short)P.scale_k : (unsigned short)8;
     const v2u16 kmul = {kscale, kscale};
 
+    int64_t ring_next = 0, ring_end = 0;  // serving: items claimed by this wave and not yet decoded
     for (;;) {
         int64_t item = 0;
         if (a.ring) {
-            item = serve_claim_block(*a.ring, &claim_lock, lane);
-            if (item < 0) break;
+            if (ring_next >= ring_end) {
+                uint32_t cnt = 1;
+                const int64_t first = serve_claim_block(*a.ring, &claim_lock, lane, &cnt);
+                if (first < 0) break;
+                ring_next = first;
+                ring_end = first + (int64_t)cnt;
+            }
+            item = ring_next++;
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");  // the host's writes of this ring slot
         } else {
             uint32_t it0 = 0;

@@ -572,12 +572,20 @@ __global__ __launch_bounds__(1024) void bp_kernel(BpArgs a) {
     const int slot = GRP ? (int)blockIdx.x : (int)blockIdx.x * nwv + wv;  // shot slot: its staging row
     float *stage = a.stage + (size_t)slot * 2 * C.n;
 
+    int64_t ring_next = 0, ring_end = 0;  // serving: items claimed by this wave and not yet decoded
     for (;;) {
         int64_t item = 0;
         if constexpr (GRP) {
             if (threadIdx.x == 0) {
                 if (a.ring) {
-                    grp_item = serve_claim(*a.ring);
+                    // thread 0 keeps the block's claimed range in ring_next / ring_end
+                    if (ring_next >= ring_end) {
+                        uint32_t cnt = 1;
+                        const int64_t first = serve_claim(*a.ring, a.ring->claim_max, &cnt);
+                        ring_next = first;
+                        ring_end = first < 0 ? first : first + (int64_t)cnt;
+                    }
+                    grp_item = ring_next < 0 ? -1 : ring_next++;
                 } else {
                     const uint32_t it0 = atomicAdd(&a.counters[0], 1u);
                     grp_item = (int64_t)it0 < a.n_work ? (int64_t)it0 : -1;
@@ -588,8 +596,14 @@ __global__ __launch_bounds__(1024) void bp_kernel(BpArgs a) {
             if (item < 0) break;
             if (a.ring) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");  // the host's writes of this ring slot
         } else if (a.ring) {
-            item = serve_claim_block(*a.ring, &claim_lock, lane);
-            if (item < 0) break;
+            if (ring_next >= ring_end) {
+                uint32_t cnt = 1;
+                const int64_t first = serve_claim_block(*a.ring, &claim_lock, lane, &cnt);
+                if (first < 0) break;
+                ring_next = first;
+                ring_end = first + (int64_t)cnt;
+            }
+            item = ring_next++;
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");  // the host's writes of this ring slot
         } else {
             uint32_t it0 = 0;

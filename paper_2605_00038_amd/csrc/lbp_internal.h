@@ -125,6 +125,8 @@ struct ServeRing {
     int16_t *llr16;                 // device [R][n]: the same buffer as int16 lambda (Int x.y check-centric kernel)
     int64_t mask;                   // R - 1 (R a power of two)
     uint64_t idle_ticks;            // the grid exits after this long without a claim (100 MHz ticks)
+    uint32_t claim_max;             // items a wave may claim at once (>= 1)
+    uint32_t claim_backlog;         // ... one more per this many items waiting beyond the claim
 };
 // flags bit of a ring item whose BP failed and whose OSD has not run yet
 constexpr uint8_t FLAG_OSD_PENDING = 0x80;
@@ -160,7 +162,7 @@ struct BpArgs {
 // waves gone (the host relaunches a full grid when items wait and the old
 // one has drained).  Only the wave holding the token reads host memory; the
 // others watch the device copy of the tail.
-__device__ inline int64_t serve_claim(const ServeRing &r) {
+__device__ inline int64_t serve_claim(const ServeRing &r, uint32_t max_claim, uint32_t *count) {
     const uint64_t t_start = __builtin_amdgcn_s_memrealtime();
     int idle_rounds = 0;
     for (;;) {
@@ -168,10 +170,15 @@ __device__ inline int64_t serve_claim(const ServeRing &r) {
         unsigned long long t = __hip_atomic_load(r.tail, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
         unsigned long long h = __hip_atomic_load(r.head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         while (h < t) {
-            const unsigned long long old = atomicCAS(r.head, h, h + 1);
+            // every claim is one CAS on the shared head, a device-wide round trip: with a
+            // deep backlog a wave takes several items at once (every wave is busy then)
+            unsigned long long want = 1 + (t - h - 1) / r.claim_backlog;
+            if (want > max_claim) want = max_claim;
+            const unsigned long long old = atomicCAS(r.head, h, h + want);
             if (old == h) {
                 __hip_atomic_fetch_max(r.last_claim, (unsigned long long)__builtin_amdgcn_s_memrealtime(),
                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                *count = (uint32_t)want;
                 return (int64_t)h;
             }
             h = old;
@@ -203,14 +210,18 @@ __device__ inline int64_t serve_claim(const ServeRing &r) {
 // Claim for one wave through its workgroup: one wave of the block at a time
 // talks to the ring (an LDS lock), the others wait on the CU.  This keeps the
 // polling and the head CAS to one wave per block instead of every resident
-// wave.  Call from every lane; returns the item (wave-uniform) or -1.
-__device__ inline int64_t serve_claim_block(const ServeRing &r, uint32_t *lds_lock, int lane) {
+// wave.  Call from every lane; returns the first item (wave-uniform) or -1, and
+// in *count how many consecutive items were claimed (the wave decodes them all
+// before it claims again).
+__device__ inline int64_t serve_claim_block(const ServeRing &r, uint32_t *lds_lock, int lane, uint32_t *count) {
     int64_t item = 0;
+    uint32_t cnt = 1;
     if (lane == 0) {
         while (atomicCAS(lds_lock, 0u, 1u) != 0u) __builtin_amdgcn_s_sleep(1);
-        item = serve_claim(r);
+        item = serve_claim(r, r.claim_max, &cnt);
         __hip_atomic_store(lds_lock, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
+    *count = __builtin_amdgcn_readfirstlane(cnt);
     const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(uint64_t)item);
     const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)item >> 32));
     return (int64_t)(((uint64_t)hi << 32) | lo);

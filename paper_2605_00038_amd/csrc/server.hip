@@ -14,9 +14,11 @@
 // One worker thread per server moves requests from the slot queues into the
 // rings (first come first served, at most R items in flight), reads the
 // completion queue, starts OSD launches and completes requests.
+#include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <memory>
@@ -40,6 +42,19 @@ constexpr int64_t kMinRing = 1024;
 constexpr int64_t kQueueFactor = 16;       // admission: queued shots per slot <= kQueueFactor * R
 constexpr int64_t kOsdList = 4096;         // failed shots per OSD launch
 constexpr uint64_t kIdleTicks = 200000;    // the BP grid exits after 2 ms without a claim (100 MHz clock)
+// Batched claims: every claim is one CAS on the ring's head, a device-wide
+// round trip that capped a slot at ~6e5 items/s.  A wave takes up to kClaimMax
+// items at once, one more per two full rounds of the grid's claimers waiting
+// beyond its claim (below that backlog every claim is one item).  LBP_SERVE_CLAIM_MAX / LBP_SERVE_CLAIM_BACKLOG
+// (read at lbp_server_add_code) override the two, for tests.
+constexpr uint32_t kClaimMax = 8;
+
+uint32_t env_u32(const char *name, uint32_t dflt, uint32_t lo, uint32_t hi) {
+    const char *e = std::getenv(name);
+    if (!e) return dflt;
+    const long v = std::atol(e);
+    return v < (long)lo ? lo : (v > (long)hi ? hi : (uint32_t)v);
+}
 // With several code slots the grids share the GPU's few hardware queues: a grid
 // that waits out 2 ms of idleness holds its queue, and every launch of another
 // slot's stream behind it on that queue, so grids of a shared server exit after
@@ -247,6 +262,15 @@ lbp_status setup_slot(Slot &sl, int64_t R) {
     r.llr16 = (int16_t *)sl.d_llr;
     r.mask = R - 1;
     r.idle_ticks = kIdleTicks;
+    // one more item per claim for every two full rounds of the grid's claimers
+    // waiting beyond it: a wave (or a workgroup that decodes one shot) takes
+    // several items only when every claimer has work anyway (the host publishes
+    // in bursts, so one round would split bursts that idle claimers could take)
+    int32_t wpb = 1, blocks = 1, group = 1;
+    (void)lbp_decoder_shape(sl.dec, &wpb, &blocks, &group, nullptr, nullptr, nullptr);
+    const uint32_t claimers = (uint32_t)std::max(1, 2 * sl.shape.bp_blocks * (group > 1 ? 1 : wpb));
+    r.claim_max = env_u32("LBP_SERVE_CLAIM_MAX", kClaimMax, 1, 64);
+    r.claim_backlog = env_u32("LBP_SERVE_CLAIM_BACKLOG", claimers, 1, 1u << 20);
     chk(hipMemcpy(sl.d_ring, &r, sizeof(r), hipMemcpyHostToDevice));
     if (e != hipSuccess) return sfail(LBP_EDEVICE, std::string("lbp_server_add_code: ") + hipGetErrorString(e));
     sl.ref_req.assign((size_t)R, ReqPtr());
