@@ -180,17 +180,34 @@ def serving(h, syn, n_requests: int, shots_per_request: int = 1, msg: str = "int
     run(0.0, min(n_requests, 20000), LOTTERY_SEED)  # warm-up
     flood = run(0.0, n_requests, LOTTERY_SEED)
     sweep, sat, limit = [], None, None
+
+    def sustained(r, rate):
+        return r["achieved_requests_per_s"] >= 0.97 * rate and r["p50_us"] < 2000.0
+
     fracs = (0.05, 0.1, 0.2, 0.3, 0.4, 0.5, 0.6, 0.7, 0.8, 0.9, 0.95, 1.0, 1.05, 1.1, 1.2)
+    lo_frac, hi_frac = 0.0, None
     for k, frac in enumerate(fracs):
         rate = frac * flood["achieved_requests_per_s"]
         r = run(rate, int(max(20000, min(n_requests, rate * 0.5))), LOTTERY_SEED + 1 + k)
         r["fraction_of_flood"] = frac
         sweep.append(r)
-        if r["achieved_requests_per_s"] >= 0.97 * rate and r["p50_us"] < 2000.0:
-            sat = rate
+        if sustained(r, rate):
+            sat, lo_frac = rate, frac
         else:
             limit = "achieved < 97% of offered" if r["achieved_requests_per_s"] < 0.97 * rate else "p50 >= 2 ms"
+            hi_frac = frac
             break
+    # between the last sustained rate and the first that was not: three bisection steps
+    for k in range(3 if hi_frac is not None else 0):
+        frac = 0.5 * (lo_frac + hi_frac)
+        rate = frac * flood["achieved_requests_per_s"]
+        r = run(rate, int(max(20000, min(n_requests, rate * 0.5))), LOTTERY_SEED + 40 + k)
+        r["fraction_of_flood"] = frac
+        sweep.append(r)
+        if sustained(r, rate):
+            sat, lo_frac = rate, frac
+        else:
+            hi_frac = frac
     out = dict(msg=msg, shots_per_request=shots_per_request, flood=flood, sweep=sweep,
                saturation_requests_per_s=sat, saturation_syndromes_per_s=(sat or 0.0) * shots_per_request,
                sweep_stopped_by=limit or "every rate tried was sustained")
@@ -233,9 +250,14 @@ def cpu_baseline(h, syn, seconds: float, gpu=None):
     t0 = time.perf_counter()
     o = oracle.decode(h, P_ERR, prm, syn[:n], n_threads=threads)
     dt = time.perf_counter() - t0
+    n1 = int(min(n, max(1000, rate / threads * seconds / 4)))  # one thread, about a quarter of the time
+    t1 = time.perf_counter()
+    oracle.decode(h, P_ERR, prm, syn[:n1], n_threads=1)
+    dt1 = time.perf_counter() - t1
     out = dict(value=n / dt, unit="syndromes/s", cores=threads, kind="oracle", cpu_model=cpu_model(),
                sample=f"first {n} shots of the benchmark batch, Int3.4 oracle with the same lottery "
-                      f"and OSD-CS(10), {threads} threads, {dt:.1f} s")
+                      f"and OSD-CS(10), {threads} threads, {dt:.1f} s",
+               single_thread_value=n1 / dt1, single_thread_sample=f"first {n1} shots, 1 thread, {dt1:.1f} s")
     if gpu is not None:
         bad = ((o["corr"] != gpu["corr"][:n]).any(axis=1) | (o["flags"] != gpu["flags"][:n]) |
                (o["iters"] != gpu["iters"][:n]))
@@ -355,9 +377,10 @@ SERVE_MIX = [("surface5_phen", 100), ("surface9_phen", 100), ("surface13_phen", 
              ("surface21_phen", 100), ("bb144_phen", 200), ("bb288_phen", 200)]
 
 
-def run_servemix(args):
-    import torch
-    assert torch.cuda.is_available(), "experiments need a GPU"
+def serving_mix(n: int, fracs=(0.1, 0.3, 0.5, 0.7)) -> dict:
+    """Single-syndrome Poisson requests drawn uniformly over the seven codes of
+    SERVE_MIX, n requests per point, at fractions of the mix's back-to-back
+    rate; p50/p99/p99.9 overall and per code."""
     from paper_2605_00038_amd import Code, DecoderParams, Server
     t_start = time.perf_counter()
     srv = Server(device_mem_budget=64 << 30, max_slots=len(SERVE_MIX))  # seven rings, 64 GiB of 288
@@ -383,15 +406,19 @@ def run_servemix(args):
             f"p99 {r['overall']['p99_us']:.0f} p99.9 {r['overall']['p999_us']:.0f} us")
         return r
 
-    n = args.exp_shots
     run(0.0, min(n, 5000), LOTTERY_SEED)  # warm-up
     flood = run(0.0, n, LOTTERY_SEED)
-    points = [run(frac * flood["achieved_requests_per_s"], n, LOTTERY_SEED + 1 + k)
-              for k, frac in enumerate((0.1, 0.3, 0.5, 0.7))]
+    points = [run(frac * flood["achieved_requests_per_s"], n, LOTTERY_SEED + 1 + k) for k, frac in enumerate(fracs)]
     srv.close()
-    out = dict(experiment="servemix", codes=[dict(workload=nm, max_iter=it) for nm, it in SERVE_MIX], p=P_ERR,
-               data="synthetic: i.i.d. Bernoulli(p) flips on every column of H_st, 4096-shot pool per code",
-               flood=flood, points=points, seconds=time.perf_counter() - t_start)
+    return dict(codes=[dict(workload=nm, max_iter=it) for nm, it in SERVE_MIX], p=P_ERR,
+                data="synthetic: i.i.d. Bernoulli(p) flips on every column of H_st, 4096-shot pool per code",
+                flood=flood, points=points, seconds=time.perf_counter() - t_start)
+
+
+def run_servemix(args):
+    import torch
+    assert torch.cuda.is_available(), "experiments need a GPU"
+    out = dict(experiment="servemix", **serving_mix(args.exp_shots))
     text = json.dumps(out)
     if args.exp_out:
         with open(args.exp_out, "w") as f:
@@ -625,6 +652,8 @@ def main():
                     help="skip the PCIe-inclusive lbp_decode_host rate")
     ap.add_argument("--serve-requests", type=int, default=200_000,
                     help="single-syndrome requests per serving-loop run (0 = skip)")
+    ap.add_argument("--mix-requests", type=int, default=20_000,
+                    help="requests per load point of the seven-code serving mix (0 = skip)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-ler", action="store_true")
@@ -744,6 +773,10 @@ def main():
         log("serving 64-shot", json.dumps(serve["requests_of_64_shots"]))
         serve["fp32_decoder"] = serving(h, syn, args.serve_requests, 1, msg="fp32", p50_runs=1)
         log("serving fp32", json.dumps(serve["fp32_decoder"]))
+    mix = None
+    if args.mix_requests > 0:
+        mix = serving_mix(args.mix_requests)
+        log("serving mix", json.dumps(mix))
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(h, syn, args.cpu_seconds, head_out)
@@ -794,6 +827,7 @@ def main():
                              "arrival to poll-visible result (median p99 of three runs)" if serve is not None
                              else "single-syndrome decode, host call to stream completion"),
         "serving": serve,
+        "serving_mix": mix,
         "latency_us": ({"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                         "p99.9": float(np.percentile(lat, 99.9)), "requests": int(len(lat)),
                         "kind": "single-syndrome lbp_decode, host call to stream completion"}

@@ -391,14 +391,18 @@ __device__ __forceinline__ void column_pass(const DevCode &C, uint32_t *L, uint3
     }
 }
 
-template <int SLOTS, bool LLR_FLIP, int TABLE>
+// SERVE: the serving variant (work from a ring, a.ring non-null).  Batch and
+// serving decodes are separate instantiations so that the ring's claim code does
+// not take part in the batch kernel's register allocation, which sits at the
+// 128-VGPR limit.
+template <int SLOTS, bool LLR_FLIP, int TABLE, bool SERVE>
 __global__ __launch_bounds__(1024) void bp_int8_kernel(BpArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ uint32_t claim_lock;  // serving: the wave of this block that polls the ring
+    __shared__ ClaimLds claim;  // serving: the block's ring lock and its waves' claimed items
     const DevCode &C = a.code;
     const BpParams &P = a.prm;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    if (threadIdx.x == 0) claim_lock = 0u;
+    claim.clear(threadIdx.x);
     const int n = C.n, m = C.m;
     // column offsets of the checks (TABLE 0: per check; 1: compact space-time rows in
     // LDS; 2: compact rows read from global memory), ahead of the waves' slices
@@ -443,18 +447,11 @@ __global__ __launch_bounds__(1024) void bp_int8_kernel(BpArgs a) {
     const unsigned short kscale = P.scale_mode == 1 ? (unsigned short)P.scale_k : (unsigned short)8;
     const v2u16 kmul = {kscale, kscale};
 
-    int64_t ring_next = 0, ring_end = 0;  // serving: items claimed by this wave and not yet decoded
     for (;;) {
         int64_t item = 0;
-        if (a.ring) {
-            if (ring_next >= ring_end) {
-                uint32_t cnt = 1;
-                const int64_t first = serve_claim_block(*a.ring, &claim_lock, lane, &cnt);
-                if (first < 0) break;
-                ring_next = first;
-                ring_end = first + (int64_t)cnt;
-            }
-            item = ring_next++;
+        if constexpr (SERVE) {
+            item = serve_claim_block(*a.ring, &claim, wv, lane);
+            if (item < 0) break;
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");  // the host's writes of this ring slot
         } else {
             uint32_t it0 = 0;
@@ -463,13 +460,13 @@ __global__ __launch_bounds__(1024) void bp_int8_kernel(BpArgs a) {
             if (item >= a.n_work) break;
         }
         // a ring item lives in slot item & mask; a batch item names its shot
-        const int64_t shot = a.ring ? (item & a.ring->mask) : a.work_list ? (int64_t)a.work_list[item] : item;
-        const uint64_t *keys = a.ring ? a.ring->keys : a.shot_keys;
+        const int64_t shot = SERVE ? (item & a.ring->mask) : a.work_list ? (int64_t)a.work_list[item] : item;
+        const uint64_t *keys = SERVE ? a.ring->keys : a.shot_keys;
         // wave-uniform: the lottery's Philox rounds then run on the scalar unit
         const uint64_t seed = (uint64_t)uniform64((int64_t)(keys ? keys[2 * shot] : P.seed));
         const uint64_t shot_id =
             (uint64_t)uniform64((int64_t)(keys ? keys[2 * shot + 1] : a.first_shot_id + (uint64_t)shot));
-        const uint32_t *syn_row = (a.ring ? a.ring->syn : a.synd) + shot * C.mw;
+        const uint32_t *syn_row = (SERVE ? a.ring->syn : a.synd) + shot * C.mw;
 
         // SH1 is the estimate "before iteration 0" that the lottery of iteration 0
         // reads when K = 0: the hard decision of the prior, H * 0 = 0
@@ -565,7 +562,7 @@ __global__ __launch_bounds__(1024) void bp_int8_kernel(BpArgs a) {
         const bool osd = !converged && P.osd != OSD_NONE;
         uint32_t *corr_row;
         int16_t *lam_dst = nullptr;
-        if (a.ring) {
+        if constexpr (SERVE) {
             corr_row = a.ring->corr + shot * C.nw;
             if (osd) lam_dst = a.ring->llr16 + shot * n;
         } else {
@@ -590,7 +587,7 @@ __global__ __launch_bounds__(1024) void bp_int8_kernel(BpArgs a) {
                 if (lam_dst) lam_dst[v] = (int16_t)l;
             }
         }
-        if (a.ring) {
+        if constexpr (SERVE) {
             const ServeRing &R = *a.ring;
             if (lane == 0) {
                 R.flags[shot] = converged ? (uint8_t)FLAG_CONVERGED : osd ? (uint8_t)(FLAG_OSD | FLAG_OSD_PENDING) : 0;
@@ -672,14 +669,20 @@ int bp_int8_wave_bytes(int m, int n) {
     return (int)((tot + 15) & ~(size_t)15);
 }
 
-template <int SLOTS, bool LLR_FLIP, int TABLE>
-static hipError_t launch_q(const BpArgs &a, int blocks, int wpb, hipStream_t s) {
+template <int SLOTS, bool LLR_FLIP, int TABLE, bool SERVE>
+static hipError_t launch_v(const BpArgs &a, int blocks, int wpb, hipStream_t s) {
     size_t lds = (size_t)bp_int8_table_bytes_t(TABLE, SLOTS, a.code.st_m0) + (size_t)a.wave_bytes * wpb;
-    hipError_t e = hipFuncSetAttribute((const void *)bp_int8_kernel<SLOTS, LLR_FLIP, TABLE>,
+    hipError_t e = hipFuncSetAttribute((const void *)bp_int8_kernel<SLOTS, LLR_FLIP, TABLE, SERVE>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((bp_int8_kernel<SLOTS, LLR_FLIP, TABLE>), dim3(blocks), dim3(64 * wpb), lds, s, a);
+    hipLaunchKernelGGL((bp_int8_kernel<SLOTS, LLR_FLIP, TABLE, SERVE>), dim3(blocks), dim3(64 * wpb), lds, s, a);
     return hipGetLastError();
+}
+
+template <int SLOTS, bool LLR_FLIP, int TABLE>
+static hipError_t launch_q(const BpArgs &a, int blocks, int wpb, hipStream_t s) {
+    return a.ring ? launch_v<SLOTS, LLR_FLIP, TABLE, true>(a, blocks, wpb, s)
+                  : launch_v<SLOTS, LLR_FLIP, TABLE, false>(a, blocks, wpb, s);
 }
 
 template <int SLOTS, int TABLE>
@@ -692,10 +695,10 @@ template <int SLOTS, int TABLE>
 static hipError_t occ_q(int wpb, int lds, int *out) {
     // both flip variants use the same registers to within the allocation granule;
     // the message-flip variant is the one queried
-    hipError_t e = hipFuncSetAttribute((const void *)bp_int8_kernel<SLOTS, false, TABLE>,
+    hipError_t e = hipFuncSetAttribute((const void *)bp_int8_kernel<SLOTS, false, TABLE, false>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     if (e != hipSuccess) return e;
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(out, bp_int8_kernel<SLOTS, false, TABLE>, 64 * wpb,
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(out, bp_int8_kernel<SLOTS, false, TABLE, false>, 64 * wpb,
                                                          (size_t)lds);
 }
 

@@ -548,7 +548,7 @@ __global__ __launch_bounds__(1024) void bp_kernel(BpArgs a) {
     using F = Fmt<MSG>;
     using T = typename F::T;
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ uint32_t claim_lock;  // serving, a shot per wave: the wave of this block that polls the ring
+    __shared__ ClaimLds claim;  // serving, a shot per wave: the block's ring lock and its waves' claimed items
     __shared__ int64_t grp_item;     // GRP: the block's current work item, -1 when there is none
     __shared__ int32_t grp_fv;       // GRP: the lottery's column of this iteration
     __shared__ uint32_t grp_q;       // GRP: the shot's failure-list position
@@ -560,7 +560,7 @@ __global__ __launch_bounds__(1024) void bp_kernel(BpArgs a) {
     // work split: thread t0 of tn over checks and words, wave w0 of wn over 64-column groups
     const int t0 = GRP ? (int)threadIdx.x : lane, tn = GRP ? (int)blockDim.x : 64;
     const int w0 = GRP ? wv : 0, wn = GRP ? nwv : 1;
-    if (threadIdx.x == 0) claim_lock = 0u;
+    claim.clear(threadIdx.x);
     __syncthreads();
     unsigned char *base = smem + (GRP ? (size_t)0 : (size_t)wv * a.wave_bytes);
     T *E = (T *)base;
@@ -572,7 +572,7 @@ __global__ __launch_bounds__(1024) void bp_kernel(BpArgs a) {
     const int slot = GRP ? (int)blockIdx.x : (int)blockIdx.x * nwv + wv;  // shot slot: its staging row
     float *stage = a.stage + (size_t)slot * 2 * C.n;
 
-    int64_t ring_next = 0, ring_end = 0;  // serving: items claimed by this wave and not yet decoded
+    int64_t ring_next = 0, ring_end = 0;  // serving, a workgroup per shot: thread 0's claimed range
     for (;;) {
         int64_t item = 0;
         if constexpr (GRP) {
@@ -596,14 +596,8 @@ __global__ __launch_bounds__(1024) void bp_kernel(BpArgs a) {
             if (item < 0) break;
             if (a.ring) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");  // the host's writes of this ring slot
         } else if (a.ring) {
-            if (ring_next >= ring_end) {
-                uint32_t cnt = 1;
-                const int64_t first = serve_claim_block(*a.ring, &claim_lock, lane, &cnt);
-                if (first < 0) break;
-                ring_next = first;
-                ring_end = first + (int64_t)cnt;
-            }
-            item = ring_next++;
+            item = serve_claim_block(*a.ring, &claim, wv, lane);
+            if (item < 0) break;
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");  // the host's writes of this ring slot
         } else {
             uint32_t it0 = 0;

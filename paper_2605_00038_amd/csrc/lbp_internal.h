@@ -172,8 +172,9 @@ __device__ inline int64_t serve_claim(const ServeRing &r, uint32_t max_claim, ui
         while (h < t) {
             // every claim is one CAS on the shared head, a device-wide round trip: with a
             // deep backlog a wave takes several items at once (every wave is busy then)
-            unsigned long long want = 1 + (t - h - 1) / r.claim_backlog;
-            if (want > max_claim) want = max_claim;
+            const unsigned long long waiting = t - h;
+            unsigned long long want = 1;  // no division: a handful of scalar compares
+            while (want < max_claim && waiting > want * r.claim_backlog) ++want;
             const unsigned long long old = atomicCAS(r.head, h, h + want);
             if (old == h) {
                 __hip_atomic_fetch_max(r.last_claim, (unsigned long long)__builtin_amdgcn_s_memrealtime(),
@@ -210,18 +211,35 @@ __device__ inline int64_t serve_claim(const ServeRing &r, uint32_t max_claim, ui
 // Claim for one wave through its workgroup: one wave of the block at a time
 // talks to the ring (an LDS lock), the others wait on the CU.  This keeps the
 // polling and the head CAS to one wave per block instead of every resident
-// wave.  Call from every lane; returns the first item (wave-uniform) or -1, and
-// in *count how many consecutive items were claimed (the wave decodes them all
-// before it claims again).
-__device__ inline int64_t serve_claim_block(const ServeRing &r, uint32_t *lds_lock, int lane, uint32_t *count) {
-    int64_t item = 0;
-    uint32_t cnt = 1;
-    if (lane == 0) {
-        while (atomicCAS(lds_lock, 0u, 1u) != 0u) __builtin_amdgcn_s_sleep(1);
-        item = serve_claim(r, r.claim_max, &cnt);
-        __hip_atomic_store(lds_lock, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+// wave.  A claim may take several consecutive items (serve_claim); the wave's
+// unclaimed remainder waits in LDS, so that the next call returns it without
+// touching the ring.  Call from every lane; returns the item (wave-uniform) or
+// -1.  The LDS state must start zeroed (ClaimLds::clear).
+struct ClaimLds {
+    uint32_t lock;
+    int64_t next[16], end[16];  // per wave of the block
+    __device__ void clear(int tid) {
+        if (tid == 0) lock = 0u;
+        if (tid < 16) next[tid] = end[tid] = 0;
     }
-    *count = __builtin_amdgcn_readfirstlane(cnt);
+};
+
+__device__ inline int64_t serve_claim_block(const ServeRing &r, ClaimLds *cs, int wave, int lane) {
+    int64_t item = 0;
+    if (lane == 0) {
+        if (cs->next[wave] < cs->end[wave]) {
+            item = cs->next[wave]++;
+        } else {
+            while (atomicCAS(&cs->lock, 0u, 1u) != 0u) __builtin_amdgcn_s_sleep(1);
+            uint32_t cnt = 1;
+            item = serve_claim(r, r.claim_max, &cnt);
+            __hip_atomic_store(&cs->lock, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (item >= 0) {
+                cs->next[wave] = item + 1;
+                cs->end[wave] = item + (int64_t)cnt;
+            }
+        }
+    }
     const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(uint64_t)item);
     const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)item >> 32));
     return (int64_t)(((uint64_t)hi << 32) | lo);
