@@ -739,6 +739,20 @@ def main():
         if fmt == args.msg:
             head_dec, head = dec, entry
             head_out = dict(corr=r["corr"], flags=r["flags"], iters=r["iters"])
+            if fmt == "int8":
+                # OSD alone (its grid otherwise runs alongside BP): the OSD roofline's launch time
+                prev = os.environ.get("LBP_EARLY_OSD")
+                os.environ["LBP_EARLY_OSD"] = "0"
+                try:
+                    d2, r2 = time_format(torch, h, syn_dev, fmt, 2, 1, args.shots)
+                finally:
+                    if prev is None:
+                        del os.environ["LBP_EARLY_OSD"]
+                    else:
+                        os.environ["LBP_EARLY_OSD"] = prev
+                entry["osd_alone_ms_per_launch"] = r2["osd_ms"] / max(1, r2["osd_launches"])
+                entry["ms_per_step_osd_after_bp"] = 1e3 * r2["seconds"] / 2
+                del d2
         else:
             del dec
         torch.cuda.empty_cache()
@@ -796,13 +810,13 @@ def main():
                        "over this run's BP launch time"}
     # OSD: the dense Gauss-Jordan equivalent of Algorithm 2 per OSD shot, m pivots each
     # XORing an m-bit row into m rows (ceil(m/32) words), over the OSD launch time
-    osd_s = head["osd_ms_per_launch"] / 1e3
+    osd_s = head.get("osd_alone_ms_per_launch", head["osd_ms_per_launch"]) / 1e3
     n_osd = head["osd_invoke_rate"] * args.shots
     osd_ops = n_osd * m * m * ((m + 31) // 32)
     osd_tops = osd_ops / osd_s / 1e12 if osd_s > 0 else 0.0
     osd_roof = {"bound": "latency", "achieved": osd_tops, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
                 "frac": osd_tops / VALU_PEAK_TOPS, "kind": "dense Gauss-Jordan word-XOR equivalent",
-                "kernel": "osd_reg_kernel", "launch_ms": head["osd_ms_per_launch"], "osd_shots": int(round(n_osd)),
+                "kernel": "osd_reg_kernel", "launch_ms": 1e3 * osd_s, "osd_shots": int(round(n_osd)),
                 "traffic": prof.get("osd_hbm_bytes"),
                 "us_per_shot_per_block": (1e6 * osd_s * head["osd_blocks"] / max(1.0, n_osd))}
     line = {

@@ -403,6 +403,7 @@ __global__ __launch_bounds__(1024) void bp_int8_kernel(BpArgs a) {
     const BpParams &P = a.prm;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     claim.clear(threadIdx.x);
+    if (!SERVE && threadIdx.x == 0) atomicAdd(&a.counters[3], 1u);  // resident BP blocks, for OSD alongside
     const int n = C.n, m = C.m;
     // column offsets of the checks (TABLE 0: per check; 1: compact space-time rows in
     // LDS; 2: compact rows read from global memory), ahead of the waves' slices
@@ -560,6 +561,7 @@ __global__ __launch_bounds__(1024) void bp_int8_kernel(BpArgs a) {
         // lambda outputs, and for a failed shot its lambda for OSD as int16
         const int fin_hi = ((it - 1) & 1) == 0;  // half holding lambda of the last iteration
         const bool osd = !converged && P.osd != OSD_NONE;
+        uint32_t fail_q = 0;  // the failed shot's list position
         uint32_t *corr_row;
         int16_t *lam_dst = nullptr;
         if constexpr (SERVE) {
@@ -570,9 +572,8 @@ __global__ __launch_bounds__(1024) void bp_int8_kernel(BpArgs a) {
             if (osd) {
                 uint32_t q = 0;
                 if (lane == 0) q = atomicAdd(&a.counters[1], 1u);
-                q = __builtin_amdgcn_readfirstlane(q);
-                if (lane == 0) a.fail_list[q] = (int32_t)shot;
-                if ((int64_t)q < a.fail_cap) lam_dst = a.fail_q + (size_t)q * n;
+                fail_q = __builtin_amdgcn_readfirstlane(q);
+                if ((int64_t)fail_q < a.fail_cap) lam_dst = a.fail_q + (size_t)fail_q * n;
             }
         }
         float *llr_row = a.llr_out ? a.llr_out + shot * n : nullptr;
@@ -602,7 +603,21 @@ __global__ __launch_bounds__(1024) void bp_int8_kernel(BpArgs a) {
             a.flags[shot] = fl;
             if (a.iters) a.iters[shot] = it;
         }
+        if (osd) {
+            // publish the list entry after the staged lambda, the correction and the
+            // flags: an OSD block running alongside takes the position only then
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            if (lane == 0)
+                __hip_atomic_store(&a.fail_list[fail_q], (int32_t)shot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
         wave_sync();
+    }
+    if constexpr (!SERVE) {
+        __syncthreads();  // every wave of the block is done: count the block finished
+        if (threadIdx.x == 0) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            atomicAdd(&a.counters[4], 1u);
+        }
     }
 }
 

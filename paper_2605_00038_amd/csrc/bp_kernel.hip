@@ -697,6 +697,11 @@ __global__ void reset_kernel(uint32_t *c, int count) {
     if (i < count) c[i] = 0u;
 }
 
+__global__ void fill_i32_kernel(int32_t *b, int32_t v, int64_t count) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) b[i] = v;
+}
+
 __global__ void gather_list_kernel(const uint32_t *counters, const int32_t *fail_list, int64_t from, int32_t *out,
                                    int64_t count) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -717,6 +722,12 @@ int bp_wave_bytes(int msg, int m, int n) {
 
 hipError_t launch_reset(uint32_t *counters, int count, hipStream_t s) {
     hipLaunchKernelGGL(reset_kernel, dim3((count + 255) / 256), dim3(256), 0, s, counters, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int32_t *buf, int32_t value, int64_t count, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_i32_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, buf, value, count);
     return hipGetLastError();
 }
 

@@ -292,6 +292,15 @@ struct OsdArgs {
     int32_t cols_global;        // G-in-global variant: the per-column arrays live in the block's scratch too
     int64_t scratch_words;      // per-block stride of gscratch in 32-bit words
     int64_t cs_offset_words;    // OSD-CS column ballots in the block's scratch (kernels for m > 1024)
+    // How blocks take failures: 0 strided over [0, counters[1]) (the list is complete);
+    // 1 (alongside BP) and 2 (after BP) claim list positions from *claim in order, a
+    // position once BP has published its entry (fail_list[q] >= 0, written after the
+    // staged lambda).  Mode 1 waits for entries only while every one of BP's bp_grid
+    // blocks is resident (counters[3] counts the started blocks, counters[4] the
+    // finished ones), so it never holds resources BP needs; otherwise it exits.
+    int32_t claim_mode;
+    int32_t bp_grid;
+    uint32_t *claim;            // counters + 2
 };
 
 // One group of a multi-group launch (lbp_plan): a code with its format and
@@ -384,6 +393,8 @@ hipError_t bp_int8_max_blocks_per_cu(int slots, int table, int waves_per_block, 
 bool bp_int8_build_st_table(const uint16_t *cols, int m, int n, int r, int m0, int n0, std::vector<uint32_t> &out);
 
 hipError_t launch_reset(uint32_t *counters, int count, hipStream_t s);
+// buf[0, count) = value
+hipError_t launch_fill_i32(int32_t *buf, int32_t value, int64_t count, hipStream_t s);
 hipError_t launch_bp(int msg, const BpArgs &a, int blocks, int waves_per_block, hipStream_t s);
 hipError_t bp_max_blocks_per_cu(int msg, bool wide, bool group, int waves_per_block, int lds_bytes, int *out);
 hipError_t launch_osd(const OsdArgs &a, int variant, int blocks, int threads, int lds_bytes, hipStream_t s);

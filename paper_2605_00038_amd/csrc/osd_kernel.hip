@@ -201,6 +201,42 @@ __device__ __forceinline__ void pair_of(int pi, int w, int &aa, int &bb) {
     bb = aa + 1 + rem;
 }
 
+// Next failure-list position for the calling block, or -1 (thread 0 calls it;
+// the modes are those of OsdArgs::claim_mode 1 and 2).
+__device__ int64_t osd_claim(const OsdArgs &a) {
+    const uint32_t cap = a.fail_cap < (int64_t)0xFFFFFFFFu ? (uint32_t)a.fail_cap : 0xFFFFFFFFu;
+    int idle = 0;
+    for (;;) {
+        uint32_t produced = __hip_atomic_load(&a.counters[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (produced > cap) produced = cap;
+        const uint32_t c = __hip_atomic_load(a.claim, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (c < produced) {
+            if (atomicCAS(a.claim, c, c + 1) == c) {
+                // the wave that took this position publishes it right after its stores
+                int32_t *fl = const_cast<int32_t *>(a.fail_list);
+                while (__hip_atomic_load(fl + c, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < 0)
+                    __builtin_amdgcn_s_sleep(1);
+                return (int64_t)c;
+            }
+            continue;
+        }
+        if (a.claim_mode != 1) return -1;
+        const uint32_t done = __hip_atomic_load(&a.counters[4], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        if (done >= (uint32_t)a.bp_grid) {  // BP has finished: the count is final
+            produced = __hip_atomic_load(&a.counters[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (produced > cap) produced = cap;
+            if (c >= produced) return -1;
+            continue;
+        }
+        // wait for more failures only while every BP block is resident (BP then
+        // finishes whatever this block holds); otherwise leave them to the launch after BP
+        if (__hip_atomic_load(&a.counters[3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < (uint32_t)a.bp_grid)
+            return -1;
+        if (idle < 5) ++idle;
+        for (int z = 0; z < (1 << idle); ++z) __builtin_amdgcn_s_sleep(2);
+    }
+}
+
 __global__ __launch_bounds__(1024, 8) void osd_lds_kernel(OsdArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int m = a.m, n = a.n, tid = threadIdx.x, lane = tid & 63;
@@ -258,7 +294,22 @@ __global__ __launch_bounds__(1024, 8) void osd_lds_kernel(OsdArgs a) {
     uint32_t nfail = a.counters[1];
     if ((int64_t)nfail > a.fail_cap) nfail = (uint32_t)a.fail_cap;
 
-    for (uint32_t q = blockIdx.x; q < nfail; q += gridDim.x) {
+    __shared__ int32_t claimed;
+    uint32_t qs = blockIdx.x;  // claim_mode 0: strided over the complete list
+    for (;;) {
+        uint32_t q;
+        if (a.claim_mode == 0) {
+            if (qs >= nfail) break;
+            q = qs;
+            qs += gridDim.x;
+        } else {
+            if (tid == 0) claimed = (int32_t)osd_claim(a);
+            __syncthreads();
+            const int32_t qq = claimed;
+            __syncthreads();  // rewritten next round only after every thread read it
+            if (qq < 0) break;
+            q = (uint32_t)qq;
+        }
         const int64_t shot = a.fail_list[q];
         // hi[n] then lo[n], or int16 [n]
         const size_t lrow = (size_t)(a.llr_by_shot ? shot : (int64_t)q);
@@ -614,7 +665,22 @@ __global__ __launch_bounds__(1024 / R, 8 / R) void osd_reg_kernel(OsdArgs a) {
     uint32_t nfail = a.counters[1];
     if ((int64_t)nfail > a.fail_cap) nfail = (uint32_t)a.fail_cap;
 
-    for (uint32_t q = blockIdx.x; q < nfail; q += gridDim.x) {
+    __shared__ int32_t claimed;
+    uint32_t qs = blockIdx.x;  // claim_mode 0: strided over the complete list
+    for (;;) {
+        uint32_t q;
+        if (a.claim_mode == 0) {
+            if (qs >= nfail) break;
+            q = qs;
+            qs += gridDim.x;
+        } else {
+            if (tid == 0) claimed = (int32_t)osd_claim(a);
+            __syncthreads();
+            const int32_t qq = claimed;
+            __syncthreads();  // rewritten next round only after every thread read it
+            if (qq < 0) break;
+            q = (uint32_t)qq;
+        }
         const int64_t shot = a.fail_list[q];
         const size_t lrow = (size_t)(a.llr_by_shot ? shot : (int64_t)q);
         const float *lam = a.llr_i16 ? (const float *)((const int16_t *)a.fail_llr + lrow * n) : a.fail_llr + lrow * 2 * n;

@@ -57,3 +57,42 @@ def test_pipelined_decode_equals_one_pass(msg):
     got_k = _decode(dec, torch, s, 3, kt)
     for a, b in zip(ref_k, got_k):
         np.testing.assert_array_equal(a, b)
+
+
+@pytest.mark.parametrize("cap", [None, 300], ids=["staging", "overflow"])
+def test_osd_alongside_bp_equals_osd_after_bp(cap):
+    """An OSD grid takes failures while BP runs (the Int3.4 kernel; the default,
+    LBP_EARLY_OSD=0 turns it off) and the launch after BP takes the rest; every
+    output equals the decoder that runs OSD after BP only, also when more shots
+    fail than the staging holds (the overflow passes run the same way)."""
+    import torch
+    from paper_2605_00038_amd import Code, Decoder, DecoderParams
+    h, _, syn = batch("bb144_phen", 0.006, SHOTS, 1502)
+    prm = DecoderParams(max_iter=200, msg=2, lottery=True, lottery_skip=6, osd=2, osd_order=10, seed=2502)
+    s = torch.from_numpy(np.ascontiguousarray(syn).view(np.int32)).cuda()
+    outs = []
+    for early in (0, 1):
+        old = os.environ.get("LBP_EARLY_OSD")
+        os.environ["LBP_EARLY_OSD"] = str(early)
+        try:
+            dec = Decoder(Code.from_scipy(h, 0.006), prm, SHOTS)
+        finally:
+            if old is None:
+                del os.environ["LBP_EARLY_OSD"]
+            else:
+                os.environ["LBP_EARLY_OSD"] = old
+        if cap is not None:
+            dec.set_osd_capacity(cap)
+        runs = []
+        for rep in range(2):
+            corr, flags, iters, _ = dec.decode(s, first_shot_id=5)
+            torch.cuda.synchronize()
+            runs.append((corr.cpu().numpy(), flags.cpu().numpy(), iters.cpu().numpy()))
+        outs.append(runs)
+        del dec
+    n_osd = int(((outs[0][0][1] & 2) != 0).sum())
+    print(f"cap={cap}: {n_osd} OSD shots", file=sys.stderr, flush=True)
+    assert n_osd > 1000
+    for r in range(2):
+        for a, b in zip(outs[0][0], outs[1][r]):
+            np.testing.assert_array_equal(a, b)
