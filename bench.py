@@ -728,7 +728,8 @@ def main():
                      osd_ms_per_launch=r["osd_ms"] / max(1, r["osd_launches"]),
                      mean_iters=float(r["iters"].mean()), osd_invoke_rate=float(((r["flags"] & 2) != 0).mean()),
                      edge_updates_per_step=edges, steps=steps,
-                     step_ms_median_of_5=float(np.median(r["step_ms_runs"])), osd_blocks=dec.shape()["osd_blocks"])
+                     step_ms_median_of_5=float(np.median(r["step_ms_runs"])), osd_blocks=dec.shape()["osd_blocks"],
+                     bp_waves_per_block=dec.shape()["bp_waves_per_block"], bp_blocks=dec.shape()["bp_blocks"])
         if not args.no_ler:
             sf, lf = failures_packed(checker, err_p, r["corr"], n)
             k = int((sf | lf).sum())
