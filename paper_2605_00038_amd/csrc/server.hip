@@ -26,7 +26,6 @@
 #include <random>
 #include <string>
 #include <thread>
-#include <unordered_map>
 #include <vector>
 
 #include "../../include/lbp.h"
@@ -88,6 +87,32 @@ struct Request {
 };
 using ReqPtr = std::shared_ptr<Request>;
 
+// Requests by ticket.  Tickets are handed out in submission order (under the
+// inbox lock) and enter the table in that order, so the live tickets form a
+// window [base, base + q.size()) over a deque: insert, find and erase are O(1)
+// and the table never rehashes (a hash map's rehash of ~10^5 requests stalled
+// the worker, which holds the server lock while it publishes and completes
+// shots, for milliseconds).  Erased or never-entered tickets are null entries;
+// the window's front advances past them.
+struct TicketTable {
+    uint64_t base = 0;
+    std::deque<ReqPtr> q;
+    void put(uint64_t t, ReqPtr r) {
+        if (q.empty()) base = t;
+        if (t < base) return;  // tickets enter in order: not reached
+        while (base + q.size() <= t) q.emplace_back();
+        q[(size_t)(t - base)] = std::move(r);
+    }
+    ReqPtr find(uint64_t t) const { return t >= base && t - base < q.size() ? q[(size_t)(t - base)] : nullptr; }
+    void erase(uint64_t t) {
+        if (t >= base && t - base < q.size()) q[(size_t)(t - base)].reset();
+        while (!q.empty() && !q.front()) {
+            q.pop_front();
+            ++base;
+        }
+    }
+};
+
 enum : uint8_t { S_FREE = 0, S_BP = 1, S_OSD_WAIT = 2, S_OSD_RUN = 3, S_DONE = 4 };
 
 // What submit needs of a slot without taking the server lock.
@@ -145,7 +170,7 @@ struct lbp_server_s {
     // mu: slots, tickets and request progress (worker, poll, wait, cancel)
     std::mutex mu;
     std::vector<std::unique_ptr<Slot>> slots;
-    std::unordered_map<uint64_t, ReqPtr> tickets;
+    TicketTable tickets;
     std::condition_variable cv_done;
     std::string dead_msg;
     // in_mu: the inbox of submitted requests and the worker's sleep (lock order: mu, then in_mu)
@@ -435,10 +460,10 @@ void fail_all(lbp_server srv) {
         in.swap(srv->inbox);
         srv->inbox_n.store(0);
     }
-    for (auto &r : in) srv->tickets[r->ticket] = r;
-    for (auto &kv : srv->tickets) {
-        Request &r = *kv.second;
-        if (r.done) continue;
+    for (auto &r : in) srv->tickets.put(r->ticket, r);
+    for (auto &p : srv->tickets.q) {
+        if (!p || p->done) continue;
+        Request &r = *p;
         r.status = (lbp_status)srv->dead.load();
         r.err = srv->dead_msg;
         r.done = true;
@@ -461,7 +486,7 @@ bool drain_inbox(lbp_server srv) {
         srv->inbox_n.store(0, std::memory_order_relaxed);
     }
     for (auto &r : in) {
-        srv->tickets[r->ticket] = r;
+        srv->tickets.put(r->ticket, r);
         srv->slots[r->slot]->queue.push_back(r);
     }
     return true;
@@ -647,13 +672,14 @@ static lbp_status submit_impl(lbp_server srv, int32_t code_slot, int64_t n_shots
         inf.queued.fetch_sub(n_shots);
         return sfail(LBP_ENOMEM, "lbp_server_submit: host allocation failed");
     }
-    r->ticket = srv->next_ticket.fetch_add(1);
     r->t_submit = Clock::now();
-    *ticket = r->ticket;
-    if (out_req) *out_req = r;
     bool wake;
     {
+        // tickets are numbered in inbox order, the order the ticket table takes them in
         std::lock_guard<std::mutex> il(srv->in_mu);
+        r->ticket = srv->next_ticket.fetch_add(1);
+        *ticket = r->ticket;
+        if (out_req) *out_req = r;
         srv->inbox.push_back(std::move(r));
         srv->inbox_n.fetch_add(1, std::memory_order_release);
         wake = srv->idle;
@@ -665,8 +691,7 @@ static lbp_status submit_impl(lbp_server srv, int32_t code_slot, int64_t n_shots
 // The request of a ticket, from the ticket table or the inbox (mu held).
 static ReqPtr find_ticket(lbp_server srv, uint64_t ticket, bool *in_inbox) {
     *in_inbox = false;
-    auto it = srv->tickets.find(ticket);
-    if (it != srv->tickets.end()) return it->second;
+    if (ReqPtr r = srv->tickets.find(ticket)) return r;
     std::lock_guard<std::mutex> il(srv->in_mu);
     for (auto &r : srv->inbox)
         if (r->ticket == ticket) {
