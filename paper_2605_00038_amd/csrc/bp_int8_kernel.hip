@@ -336,10 +336,15 @@ __device__ __forceinline__ void check_pass(const uint4 *tab, const StShape &st, 
                                            uint32_t srow, unsigned char *Lb, uint32_t base, int lane, v2u16 kmul,
                                            v2u16 shv, uint32_t flipslots, uint32_t fo, uint32_t qm2) {
     const uint32_t fs = __builtin_amdgcn_readfirstlane(flipslots);
+    // opaque: otherwise the per-slot bits are hoisted out of the iteration loop and
+    // held (and spilled) as SLOTS registers across it (with the global-memory table
+    // the allocation without this is the better one)
+    uint32_t sr = srow;
+    if constexpr (TABLE != 2) asm volatile("" : "+v"(sr));
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
         const uint4 cw = row_offsets<TABLE>(tab, s, lane, st);
-        const uint32_t sb = (srow >> s) & 1u;
+        const uint32_t sb = (sr >> s) & 1u;
         if (ANY_FLIP && (fs & (1u << s)))
             check_update<PAR, true, LLR_FLIP>(cw, bq[s][0], bq[s][1], sb, Lb, base, kmul, shv, fo, qm2);
         else
