@@ -230,7 +230,15 @@ __device__ inline int64_t serve_claim_block(const ServeRing &r, ClaimLds *cs, in
         if (cs->next[wave] < cs->end[wave]) {
             item = cs->next[wave]++;
         } else {
-            while (atomicCAS(&cs->lock, 0u, 1u) != 0u) __builtin_amdgcn_s_sleep(1);
+            // the lock is held while its wave waits for the ring: test before the CAS and
+            // back off, so that waiting waves leave the CU's LDS and issue slots to the
+            // waves decoding
+            int back = 0;
+            while (__hip_atomic_load(&cs->lock, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) != 0u ||
+                   atomicCAS(&cs->lock, 0u, 1u) != 0u) {
+                for (int z = 0; z < (1 << back); ++z) __builtin_amdgcn_s_sleep(2);
+                if (back < 5) ++back;
+            }
             uint32_t cnt = 1;
             item = serve_claim(r, r.claim_max, &cnt);
             __hip_atomic_store(&cs->lock, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
