@@ -379,6 +379,35 @@ __device__ __forceinline__ void column_pass(const DevCode &C, uint32_t *L, uint3
                                             uint32_t mu_b) {
     uint16_t *Lh = (uint16_t *)L;
     const int nfull = n >> 6;
+    if (nfull < 64) {
+        // first the hard decisions (bit vs: column 64 vs + lane has e = 1), then the
+        // column-table loads of those columns, one per lane at a time: a wave waits
+        // for about one table load per iteration instead of one per group with an e = 1
+        uint64_t emask = 0;
+#pragma unroll 2
+        for (int vs = 0; vs < nfull; ++vs) {
+            const int v = vs * 64 + lane;
+            const uint32_t w = L[v];
+            const uint32_t h = PAR == 0 ? (w >> 16) : (w & 0xFFFFu);
+            emask |= (uint64_t)(h <= (uint32_t)BIAS) << vs;
+            Lh[2 * v + PAR] = (uint16_t)(MU_UNIFORM ? mu_b : (uint32_t)(C.mu_q[v] + BIAS));
+        }
+        const int v = nfull * 64 + lane;
+        if (v < n) {
+            const uint32_t w = L[v];
+            const uint32_t h = PAR == 0 ? (w >> 16) : (w & 0xFFFFu);
+            emask |= (uint64_t)(h <= (uint32_t)BIAS) << nfull;
+            Lh[2 * v + PAR] = (uint16_t)(MU_UNIFORM ? mu_b : (uint32_t)(C.mu_q[v] + BIAS));
+        }
+        while (__ballot(emask != 0ull)) {
+            if (emask) {
+                const int vs = __ffsll((unsigned long long)emask) - 1;
+                emask &= emask - 1ull;
+                xor_checks(C, vs * 64 + lane, SHc);
+            }
+        }
+        return;
+    }
 #pragma unroll 2
     for (int vs = 0; vs < nfull; ++vs) {
         const int v = vs * 64 + lane;
