@@ -592,34 +592,54 @@ __device__ __forceinline__ uint64_t uniform_tab(const uint64_t *vn_tab, int col)
     return ((uint64_t)hi << 32) | lo;
 }
 
-// popcount over the block's rows of (s' + reduced column(s)) using per-wave ballots
-__device__ __forceinline__ uint32_t ballot_cost(const unsigned long long *B, const unsigned long long *Y, int m,
-                                                int nwv, uint64_t ta, uint64_t tb) {
-    uint32_t cost = 0;
-    for (int w = 0; w < nwv; ++w) {
-        unsigned long long x = Y[w];
+// The candidate sweep's 64-row ballots of G's columns are stored column-major,
+// 16 group slots per column: the ballots of check c are B[16 c .. 16 c + ngr), so
+// one thread reads a check's groups as ceil(ngr / 2) 16-byte loads.  Y holds the
+// groups' ballots of s'.
+
+// popcount over the block's rows of (s' + reduced columns named by ta and tb):
+// every load of a candidate is issued before the first XOR that needs it.
+__device__ __forceinline__ uint32_t ballot_cost(const uint4 *B4, const uint4 *Y4, int ngr, uint64_t ta,
+                                                uint64_t tb) {
+    const int nq = (ngr + 1) >> 1;
+    uint4 acc[8];
 #pragma unroll
-        for (int j = 0; j < CDEG; ++j) {
-            uint32_t p = (uint32_t)(ta >> (16 * j)) & 0xFFFFu;
-            if (p != NOPOS) x ^= B[(size_t)w * m + p / DEG];
-            uint32_t q = (uint32_t)(tb >> (16 * j)) & 0xFFFFu;
-            if (q != NOPOS) x ^= B[(size_t)w * m + q / DEG];
+    for (int q = 0; q < 8; ++q) acc[q] = q < nq ? Y4[q] : make_uint4(0u, 0u, 0u, 0u);
+#pragma unroll
+    for (int j = 0; j < 2 * CDEG; ++j) {
+        const uint32_t p = (uint32_t)((j < CDEG ? ta : tb) >> (16 * (j % CDEG))) & 0xFFFFu;
+        if (p != NOPOS) {
+            const uint4 *col = B4 + (size_t)(p / DEG) * 8;
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                if (q < nq) {
+                    const uint4 v = col[q];
+                    acc[q].x ^= v.x;
+                    acc[q].y ^= v.y;
+                    acc[q].z ^= v.z;
+                    acc[q].w ^= v.w;
+                }
         }
-        cost += __popcll(x);
     }
+    uint32_t cost = 0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+        if (q < nq) {
+            cost += __popc(acc[q].x) + __popc(acc[q].y);
+            if (2 * q + 1 < ngr) cost += __popc(acc[q].z) + __popc(acc[q].w);  // the slot after the last group is not written
+        }
     return cost;
 }
 
-// Wave `w`'s 64-row mask of the XOR of the reduced columns named by ta and tb.
-__device__ __forceinline__ uint64_t ballot_cost_mask(const unsigned long long *B, int m, int w, uint64_t ta,
-                                                     uint64_t tb) {
+// Group `w`'s 64-row mask of the XOR of the reduced columns named by ta and tb.
+__device__ __forceinline__ uint64_t ballot_cost_mask(const unsigned long long *B, int w, uint64_t ta, uint64_t tb) {
     unsigned long long x = 0;
 #pragma unroll
     for (int j = 0; j < CDEG; ++j) {
         uint32_t p = (uint32_t)(ta >> (16 * j)) & 0xFFFFu;
-        if (p != NOPOS) x ^= B[(size_t)w * m + p / DEG];
+        if (p != NOPOS) x ^= B[(size_t)(p / DEG) * 16 + w];
         uint32_t q = (uint32_t)(tb >> (16 * j)) & 0xFFFFu;
-        if (q != NOPOS) x ^= B[(size_t)w * m + q / DEG];
+        if (q != NOPOS) x ^= B[(size_t)(q / DEG) * 16 + w];
     }
     return x;
 }
@@ -658,7 +678,8 @@ __global__ __launch_bounds__(1024 / R, 8 / R) void osd_reg_kernel(OsdArgs a) {
     int *scr = (int *)(smem + L.scr);
     unsigned long long *Y = (unsigned long long *)(smem + L.Y);
     unsigned long long *best64 = (unsigned long long *)(smem + L.best);
-    // 64-row ballots of G's columns: group k * nwv + w holds rows k * nth + 64 w + lane (R * nwv <= 16)
+    // 64-row ballots of G's columns, column-major: B[16 c + g] for group g = k * nwv + w,
+    // rows k * nth + 64 w + lane (R * nwv <= 16)
     unsigned long long *B = (unsigned long long *)a.gscratch + (size_t)blockIdx.x * 16 * m;
     const int ngr = R * nwv;
 
@@ -833,11 +854,22 @@ __global__ __launch_bounds__(1024 / R, 8 / R) void osd_reg_kernel(OsdArgs a) {
         for (int k = 0; k < R; ++k) e[k] = sp[k];
         if (a.mode == OSD_CS) {
             const int nt = list_nonbasis(isb, perm, n, tl, scr);
-            for (int c = 0; c < m; ++c) {
+            // lane i keeps the ballot of column c0 + i; one store per 64 columns and slot
+            for (int c0 = 0; c0 < m; c0 += 64) {
+                const int cend = m - c0 < 64 ? m - c0 : 64;
+                uint64_t mine[R];
 #pragma unroll
-                for (int k = 0; k < R; ++k) {
-                    const uint64_t b = __ballot(valid[k] && row_bit<NW>(g[k], c));
-                    if (lane == 0) B[(size_t)(k * nwv + wid) * m + c] = b;
+                for (int k = 0; k < R; ++k) mine[k] = 0ull;
+                for (int i = 0; i < cend; ++i) {
+#pragma unroll
+                    for (int k = 0; k < R; ++k) {
+                        const uint64_t b = __ballot(valid[k] && row_bit<NW>(g[k], c0 + i));
+                        if (lane == i) mine[k] = b;
+                    }
+                }
+                if (lane < cend) {
+#pragma unroll
+                    for (int k = 0; k < R; ++k) B[(size_t)(c0 + lane) * 16 + k * nwv + wid] = mine[k];
                 }
             }
 #pragma unroll
@@ -851,7 +883,7 @@ __global__ __launch_bounds__(1024 / R, 8 / R) void osd_reg_kernel(OsdArgs a) {
             for (int w = 0; w < ngr; ++w) cost0 += __popcll(Y[w]);
             unsigned long long best = (unsigned long long)cost0 << 32;
             for (int ai = tid; ai < nt; ai += nth) {
-                unsigned long long cost = 1 + ballot_cost(B, Y, m, ngr, a.vn_tab[tl[ai]], ~0ull);
+                unsigned long long cost = 1 + ballot_cost((const uint4 *)B, (const uint4 *)Y, ngr, a.vn_tab[tl[ai]], ~0ull);
                 unsigned long long key = (cost << 32) | (unsigned long long)(1 + ai);
                 best = key < best ? key : best;
             }
@@ -860,7 +892,8 @@ __global__ __launch_bounds__(1024 / R, 8 / R) void osd_reg_kernel(OsdArgs a) {
             for (int pi = tid; pi < npairs; pi += nth) {
                 int aa, bb;
                 pair_of(pi, w, aa, bb);
-                unsigned long long cost = 2 + ballot_cost(B, Y, m, ngr, a.vn_tab[tl[aa]], a.vn_tab[tl[bb]]);
+                unsigned long long cost =
+                    2 + ballot_cost((const uint4 *)B, (const uint4 *)Y, ngr, a.vn_tab[tl[aa]], a.vn_tab[tl[bb]]);
                 unsigned long long key = (cost << 32) | (unsigned long long)(1 + nt + pi);
                 best = key < best ? key : best;
             }
@@ -880,7 +913,7 @@ __global__ __launch_bounds__(1024 / R, 8 / R) void osd_reg_kernel(OsdArgs a) {
             const uint64_t tab0 = t0 >= 0 ? a.vn_tab[t0] : ~0ull, tab1 = t1 >= 0 ? a.vn_tab[t1] : ~0ull;
 #pragma unroll
             for (int k = 0; k < R; ++k) {
-                const uint64_t xb = ballot_cost_mask(B, m, k * nwv + wid, tab0, tab1);
+                const uint64_t xb = ballot_cost_mask(B, k * nwv + wid, tab0, tab1);
                 e[k] ^= (uint32_t)(xb >> lane) & 1u;
             }
         }
