@@ -144,6 +144,46 @@ def test_server_cancel_admission_and_tickets():
     srv.close()
 
 
+def test_server_many_outstanding_tickets_out_of_order():
+    """Tens of thousands of requests in flight before the first wait, collected
+    in a shuffled order (a few cancelled, some polled first): the ticket table
+    keeps every one until it is collected, and each result is the lone decode's."""
+    from paper_2605_00038_amd import Server
+    from paper_2605_00038_amd._lib import LbpError, LBP_EINVAL
+    name, p, kw = CODES[1]
+    n = 24000
+    h, e, syn = batch(name, p, n, 920)
+    srv = Server(max_slots=1)
+    slot = srv.add_code(_code(h, p), _params(**kw))
+    tickets = [srv.submit(slot, syn[k:k + 1], 5, k) for k in range(n)]
+    ref = gpu_decode(h, p, _params(**kw, seed=5), syn)
+    cancelled = set(range(7, n, 997))
+    for k in cancelled:
+        srv.cancel(tickets[k])
+    order = np.random.default_rng(921).permutation(n)
+    polled = 0
+    for k in order[: n // 4]:
+        if k in cancelled:
+            continue
+        r = srv.poll(tickets[k], slot, 1)
+        if r is not None:
+            polled += 1
+            assert np.array_equal(r[0][0], ref["corr"][k]) and r[1][0] == ref["flags"][k]
+        else:
+            r = srv.wait(tickets[k], slot, 1, timeout_us=60_000_000)
+            assert np.array_equal(r[0][0], ref["corr"][k]) and r[1][0] == ref["flags"][k]
+    for k in order[n // 4:][::-1]:
+        if k in cancelled:
+            with pytest.raises(LbpError) as ei:
+                srv.poll(tickets[k], slot, 1)
+            assert ei.value.status == LBP_EINVAL
+            continue
+        r = srv.wait(tickets[k], slot, 1, timeout_us=60_000_000)
+        assert np.array_equal(r[0][0], ref["corr"][k]) and r[1][0] == ref["flags"][k] and r[2][0] == ref["iters"][k]
+    _say("outstanding tickets", n, "polled ready", polled)
+    srv.close()
+
+
 def test_server_memory_budget_limits_ring_size():
     from paper_2605_00038_amd import Server
     from paper_2605_00038_amd._lib import LbpError, LBP_ENOMEM
