@@ -854,20 +854,30 @@ __global__ __launch_bounds__(1024 / R, 8 / R) void osd_reg_kernel(OsdArgs a) {
         for (int k = 0; k < R; ++k) e[k] = sp[k];
         if (a.mode == OSD_CS) {
             const int nt = list_nonbasis(isb, perm, n, tl, scr);
-            // lane i keeps the ballot of column c0 + i; one store per 64 columns and slot
+            // lane i keeps the ballot of column c0 + i; one store per 64 columns and slot.
+            // A word of G is moved out of the row once per 32 columns (one indexed move
+            // instead of one per column), and rows of invalid lanes are zero, so they
+            // need no test.
             for (int c0 = 0; c0 < m; c0 += 64) {
-                const int cend = m - c0 < 64 ? m - c0 : 64;
                 uint64_t mine[R];
 #pragma unroll
                 for (int k = 0; k < R; ++k) mine[k] = 0ull;
-                for (int i = 0; i < cend; ++i) {
+                for (int h = 0; h < 2 && c0 + 32 * h < m; ++h) {
+                    const int w = (c0 >> 5) + h;
+                    uint32_t gw[R];
 #pragma unroll
-                    for (int k = 0; k < R; ++k) {
-                        const uint64_t b = __ballot(valid[k] && row_bit<NW>(g[k], c0 + i));
-                        if (lane == i) mine[k] = b;
+                    for (int k = 0; k < R; ++k) gw[k] = g[k][w];
+                    const int bend = m - 32 * w < 32 ? m - 32 * w : 32;
+                    for (int bit = 0; bit < bend; ++bit) {
+                        const bool here = lane == 32 * h + bit;
+#pragma unroll
+                        for (int k = 0; k < R; ++k) {
+                            const uint64_t bl = __ballot((gw[k] >> bit) & 1u);
+                            if (here) mine[k] = bl;
+                        }
                     }
                 }
-                if (lane < cend) {
+                if (c0 + lane < m) {
 #pragma unroll
                     for (int k = 0; k < R; ++k) B[(size_t)(c0 + lane) * 16 + k * nwv + wid] = mine[k];
                 }
