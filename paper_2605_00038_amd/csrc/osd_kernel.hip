@@ -592,6 +592,36 @@ __device__ __forceinline__ uint64_t uniform_tab(const uint64_t *vn_tab, int col)
     return ((uint64_t)hi << 32) | lo;
 }
 
+// 32 x 32 bit transpose within each half of the wave: afterwards bit i of lane
+// 32 h + j is bit j of lane 32 h + i's input.  Five block-swap stages (Hacker's
+// Delight, transpose32), the partner lane of stage s being lane ^ s (ds_swizzle in
+// bit-mask mode, within 32 lanes).
+template <int S>
+__device__ __forceinline__ uint32_t transpose_stage(uint32_t x, int lane) {
+    constexpr uint32_t M = S == 16 ? 0x0000FFFFu : S == 8 ? 0x00FF00FFu : S == 4 ? 0x0F0F0F0Fu
+                         : S == 2 ? 0x33333333u : 0x55555555u;  // bits whose index has bit S clear
+    const uint32_t p = (uint32_t)__builtin_amdgcn_ds_swizzle((int)x, (S << 10) | 0x1F);
+    return (lane & S) ? ((x & ~M) | ((p >> S) & M)) : ((x & M) | ((p << S) & ~M));
+}
+
+__device__ __forceinline__ uint32_t transpose32(uint32_t x, int lane) {
+    x = transpose_stage<16>(x, lane);
+    x = transpose_stage<8>(x, lane);
+    x = transpose_stage<4>(x, lane);
+    x = transpose_stage<2>(x, lane);
+    return transpose_stage<1>(x, lane);
+}
+
+// Lane i's 64-row ballot of column 32 w + i (words w and w + 1 of the wave's
+// rows xa and xb): each half transposes both words, then the halves trade the
+// parts the other one needs.
+__device__ __forceinline__ uint64_t column_ballots(uint32_t xa, uint32_t xb, int lane) {
+    const uint32_t ta = transpose32(xa, lane), tb = transpose32(xb, lane);
+    const bool lo = lane < 32;
+    const uint32_t y = (uint32_t)__shfl_xor((int)(lo ? tb : ta), 32, 64);
+    return lo ? (((uint64_t)y << 32) | ta) : (((uint64_t)tb << 32) | y);
+}
+
 // The candidate sweep's 64-row ballots of G's columns are stored column-major,
 // 16 group slots per column: the ballots of check c are B[16 c .. 16 c + ngr), so
 // one thread reads a check's groups as ceil(ngr / 2) 16-byte loads.  Y holds the
@@ -854,32 +884,16 @@ __global__ __launch_bounds__(1024 / R, 8 / R) void osd_reg_kernel(OsdArgs a) {
         for (int k = 0; k < R; ++k) e[k] = sp[k];
         if (a.mode == OSD_CS) {
             const int nt = list_nonbasis(isb, perm, n, tl, scr);
-            // lane i keeps the ballot of column c0 + i; one store per 64 columns and slot.
-            // A word of G is moved out of the row once per 32 columns (one indexed move
-            // instead of one per column), and rows of invalid lanes are zero, so they
-            // need no test.
+            // lane i takes the ballot of column c0 + i from a bit transpose of words
+            // c0 / 32 and c0 / 32 + 1 of the rows (rows of invalid lanes are zero); one
+            // store per 64 columns and slot
+            static_assert(NW % 2 == 0, "rows are read as word pairs");
             for (int c0 = 0; c0 < m; c0 += 64) {
-                uint64_t mine[R];
+                const int w = c0 >> 5;
 #pragma unroll
-                for (int k = 0; k < R; ++k) mine[k] = 0ull;
-                for (int h = 0; h < 2 && c0 + 32 * h < m; ++h) {
-                    const int w = (c0 >> 5) + h;
-                    uint32_t gw[R];
-#pragma unroll
-                    for (int k = 0; k < R; ++k) gw[k] = g[k][w];
-                    const int bend = m - 32 * w < 32 ? m - 32 * w : 32;
-                    for (int bit = 0; bit < bend; ++bit) {
-                        const bool here = lane == 32 * h + bit;
-#pragma unroll
-                        for (int k = 0; k < R; ++k) {
-                            const uint64_t bl = __ballot((gw[k] >> bit) & 1u);
-                            if (here) mine[k] = bl;
-                        }
-                    }
-                }
-                if (c0 + lane < m) {
-#pragma unroll
-                    for (int k = 0; k < R; ++k) B[(size_t)(c0 + lane) * 16 + k * nwv + wid] = mine[k];
+                for (int k = 0; k < R; ++k) {
+                    const uint64_t bl = column_ballots(g[k][w], g[k][w + 1], lane);
+                    if (c0 + lane < m) B[(size_t)(c0 + lane) * 16 + k * nwv + wid] = bl;
                 }
             }
 #pragma unroll
