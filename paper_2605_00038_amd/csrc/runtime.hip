@@ -634,9 +634,20 @@ lbp_status lbp_decoder_create(lbp_code code, const lbp_params *prm, int64_t max_
     d->osd_blocks = ncu * std::max(1, obpc);
     {
         // An OSD grid alongside the Int x.y kernel's BP grid fills BP's tail (BB144 r=12,
-        // 10^6 shots: 35.9 -> 33.8 ms per decode); LBP_EARLY_OSD=0 (read here) turns it off
+        // 10^6 shots: 31.8 -> 29.8 ms per decode), where BP's blocks leave no room for an
+        // OSD block in a CU's LDS: the side grid's blocks then start as BP's blocks leave.
+        // Where one fits beside them (small codes), the side grid's blocks would be
+        // resident from the start, polling the counters that BP claims its shots with (a
+        // 72-check code at p = 0.06: 70 ms -> 3.6 s per 2^20 shots), so OSD runs after BP
+        // there.  LBP_EARLY_OSD=0 (read here) turns it off everywhere.
+        int lds_cu = 0;
+        if (hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess)
+            lds_cu = lds_block;
+        const int64_t bp_lds_cu = (int64_t)(d->bp_blocks / std::max(1, ncu)) *
+                                  ((int64_t)d->table_bytes + (int64_t)d->wave_bytes * d->wpb + 64);
+        const bool osd_waits_for_bp = (int64_t)lds_cu - bp_lds_cu < (int64_t)d->osd_lds;
         const char *eo = std::getenv("LBP_EARLY_OSD");
-        d->early_osd = d->int8_slots && prm->osd && !(eo && std::atoi(eo) == 0);
+        d->early_osd = d->int8_slots && prm->osd && osd_waits_for_bp && !(eo && std::atoi(eo) == 0);
     }
     hipError_t e;
 #define ALLOC(ptr, bytes)                                                                                     \
