@@ -119,7 +119,7 @@ __device__ int lottery_pick_q(const DevCode &C, int rule, uint64_t seed, uint64_
             uint32_t u = w < C.mw ? (SHp[w] ^ S[w]) : 0u;
             int cnt = __popc(u);
             int incl = wave_incl_scan(cnt, lane);
-            int tot = __shfl(incl, 63, 64);
+            int tot = __builtin_amdgcn_readlane(incl, 63);
             if ((int)k < tot) {
                 int excl = incl - cnt;
                 bool here = (int)k >= excl && (int)k < incl;
@@ -129,7 +129,7 @@ __device__ int lottery_pick_q(const DevCode &C, int rule, uint64_t seed, uint64_
                     for (int q = (int)k - excl; q > 0; --q) t &= t - 1;
                     pos = w * 32 + __ffs(t) - 1;
                 }
-                cstar = __shfl(pos, __ffsll((unsigned long long)__ballot(here)) - 1, 64);
+                cstar = __builtin_amdgcn_readlane(pos, __ffsll((unsigned long long)__ballot(here)) - 1);
                 break;
             }
             k -= (uint32_t)tot;
@@ -161,7 +161,8 @@ __device__ int lottery_pick_q(const DevCode &C, int rule, uint64_t seed, uint64_
     int bc = -1, bq = 0, bv = -1;
 #pragma unroll
     for (int kk = 0; kk < DEG; ++kk) {
-        int ck = __shfl(cnt, kk, 64), vk = __shfl(v, kk, 64), qk = __shfl(q, kk, 64);
+        int ck = __builtin_amdgcn_readlane(cnt, kk), vk = __builtin_amdgcn_readlane(v, kk),
+            qk = __builtin_amdgcn_readlane(q, kk);
         if (ck < 0) continue;
         if (bv < 0 || lottery_key_less(vn_rule, ck, qk, vk, bc, bq, bv)) {
             bc = ck;

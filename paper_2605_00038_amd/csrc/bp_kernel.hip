@@ -276,7 +276,7 @@ __device__ int lottery_select(const DevCode &C, const BpParams &P, uint64_t seed
             uint32_t u = w < C.mw ? (SHp[w] ^ S[w]) : 0u;
             int cnt = __popc(u);
             int incl = wave_incl_scan(cnt, lane);
-            int tot = __shfl(incl, 63, 64);
+            int tot = __builtin_amdgcn_readlane(incl, 63);
             if ((int)k < tot) {
                 int excl = incl - cnt;
                 bool here = (int)k >= excl && (int)k < incl;
@@ -287,7 +287,7 @@ __device__ int lottery_select(const DevCode &C, const BpParams &P, uint64_t seed
                     pos = w * 32 + __ffs(t) - 1;
                 }
                 uint64_t b = __ballot(here);
-                cstar = __shfl(pos, __ffsll((unsigned long long)b) - 1, 64);
+                cstar = __builtin_amdgcn_readlane(pos, __ffsll((unsigned long long)b) - 1);
                 break;
             }
             k -= (uint32_t)tot;
@@ -324,8 +324,9 @@ __device__ int lottery_select(const DevCode &C, const BpParams &P, uint64_t seed
     uint64_t bq = 0;
 #pragma unroll
     for (int k = 0; k < DEG; ++k) {
-        int ck = __shfl(cnt, k, 64), vk = __shfl(v, k, 64);
-        uint64_t qk = __shfl(q, k, 64);
+        int ck = __builtin_amdgcn_readlane(cnt, k), vk = __builtin_amdgcn_readlane(v, k);
+        uint64_t qk = ((uint64_t)__builtin_amdgcn_readlane((uint32_t)(q >> 32), k) << 32) |
+                      __builtin_amdgcn_readlane((uint32_t)q, k);
         if (ck < 0) continue;
         if (bv < 0 || lottery_key_less(vn_rule, ck, qk, vk, bc, bq, bv)) {
             bc = ck;
