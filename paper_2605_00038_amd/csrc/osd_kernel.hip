@@ -570,18 +570,31 @@ __device__ __forceinline__ uint32_t row_bit(const vrow<NW> &g, int c) {
     return (g[c >> 5] >> (c & 31)) & 1u;  // c is wave-uniform
 }
 
-// Bit of each of the lane's R rows of the reduced column whose CDEG check indices
-// are packed as u16 in chk (wave-uniform).  An absent slot names check m, a bit
-// that is zero in every row of G (its support is [0, m), and m < 32 NW).
+// A column's checks for the elimination, wave-uniform: its D <= CDEG check indices
+// (< 2^13) in the low 16-bit fields, the fields past D naming check m (a bit that is
+// zero in every row of G: its support is [0, m), and m < 32 NW), D in bits 61-63.
+static_assert(CDEG == 4, "the packed check list holds four checks");
+
+template <int NW, int R>
+__device__ __forceinline__ void reduced_bits_add(const vrow<NW> (&g)[R], uint64_t chk, int j, uint32_t (&x)[R]) {
+    const int c = (int)((chk >> (16 * j)) & 0x1FFFu);
+#pragma unroll
+    for (int k = 0; k < R; ++k) x[k] ^= row_bit<NW>(g[k], c);
+}
+
+// Bit of each of the lane's R rows of the reduced column G h_j, from the packed
+// check list of column j (one indexed register read per check and row; checks 3
+// and 4 only where the column has them).
 template <int NW, int R>
 __device__ __forceinline__ void reduced_bits(const vrow<NW> (&g)[R], uint64_t chk, uint32_t (&x)[R]) {
+    const uint32_t d = __builtin_amdgcn_readfirstlane((uint32_t)(chk >> 32) >> 29);
 #pragma unroll
     for (int k = 0; k < R; ++k) x[k] = 0;
-#pragma unroll
-    for (int j = 0; j < CDEG; ++j) {
-        const int c = (int)((chk >> (16 * j)) & 0xFFFFu);
-#pragma unroll
-        for (int k = 0; k < R; ++k) x[k] ^= row_bit<NW>(g[k], c);
+    reduced_bits_add<NW, R>(g, chk, 0, x);
+    reduced_bits_add<NW, R>(g, chk, 1, x);
+    if (d > 2u) {
+        reduced_bits_add<NW, R>(g, chk, 2, x);
+        if (d > 3u) reduced_bits_add<NW, R>(g, chk, 3, x);
     }
 }
 
@@ -684,6 +697,8 @@ __device__ __forceinline__ uint64_t ballot_cost_mask(const unsigned long long *B
 template <int NW, int R>
 __global__ __launch_bounds__(1024 / R, 8 / R) void osd_reg_kernel(OsdArgs a) {
     static_assert(R == 1 || R == 2, "one or two rows per lane");
+    // a published candidate row carries its s' bit in the vector's padding word, if it has one
+    constexpr bool SP_IN_ROW = sizeof(vrow<NW>) > 4 * NW;
     extern __shared__ __align__(16) unsigned char smem[];
     const int m = a.m, n = a.n, tid = threadIdx.x, lane = tid & 63;
     const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -704,7 +719,7 @@ __global__ __launch_bounds__(1024 / R, 8 / R) void osd_reg_kernel(OsdArgs a) {
     vrow<NW> *crow = (vrow<NW> *)(smem + L.crow);
     uint32_t *csp = (uint32_t *)(smem + L.csp);
     uint32_t *cw = (uint32_t *)(smem + L.cw);
-    uint32_t *wkey = (uint32_t *)(smem + L.wkey);  // per wave and row buffer: candidate key
+    uint32_t *wkey = (uint32_t *)(smem + L.wkey);  // two alternating slots of the step's pivot key
     int *scr = (int *)(smem + L.scr);
     unsigned long long *Y = (unsigned long long *)(smem + L.Y);
     unsigned long long *best64 = (unsigned long long *)(smem + L.best);
@@ -742,17 +757,23 @@ __global__ __launch_bounds__(1024 / R, 8 / R) void osd_reg_kernel(OsdArgs a) {
         else
             sort_columns(lam, n, P, a.has_lo, 0, (unsigned long long *)smem, scol, perm);
 
-        // check indices of the sorted columns, staged over the dead sort keys
+        // check lists of the sorted columns (packed as reduced_bits reads them),
+        // staged over the dead sort keys
         uint64_t *ptab = (uint64_t *)smem;
         for (int j = tid; j < n; j += nth) {
             const uint64_t t = a.vn_tab[perm[j]];
             uint64_t c = 0;
+            uint32_t d = 0;
 #pragma unroll
             for (int k = 0; k < CDEG; ++k) {
                 const uint32_t p = (uint32_t)(t >> (16 * k)) & 0xFFFFu;
-                c |= (uint64_t)(p == NOPOS ? (uint32_t)m : p / DEG) << (16 * k);
+                if (p != NOPOS) {
+                    c |= (uint64_t)(p / DEG) << (16 * d);
+                    ++d;
+                }
             }
-            ptab[j] = c;
+            for (uint32_t k = d; k < (uint32_t)CDEG; ++k) c |= (uint64_t)m << (16 * k);
+            ptab[j] = c | ((uint64_t)d << 61);
         }
 
         // ---- 2. G = I, s' = s
@@ -775,14 +796,17 @@ __global__ __launch_bounds__(1024 / R, 8 / R) void osd_reg_kernel(OsdArgs a) {
             freem[k] = __ballot(valid[k]);
         }
         for (int j = tid; j < n; j += nth) isb[j] = 0;
-        if (tid < 32) wkey[tid] = 0u;  // slots of waves that do not exist stay 0
+        if (tid < 2) wkey[tid] = 0u;
         __syncthreads();
 
         // ---- 3. Gauss-Jordan in sorted column order, one block barrier per column:
         // each wave publishes its first candidate row before the barrier, so the
-        // winner's row is already in LDS when the pivot is known.  Each wave also
-        // writes its key 0xFFFF - row (0: no candidate) to its slot, every step;
-        // after the barrier every wave takes the maximum over the slots.
+        // winner's row is already in LDS when the pivot is known.  A wave with a
+        // candidate takes the atomic maximum of its key (j + 1) << 16 | (0xFFFF -
+        // row) into slot j & 1, which every wave reads after the barrier; a key of
+        // an earlier step (smaller) left there means no candidate.  Step j + 2
+        // writes the slot again only after every wave passed barrier j + 1, so
+        // after its read of step j's key (n < 2^16: slot positions are u16).
         int rank = 0;
         int buf = 0;  // row buffers and key slots alternate over 2
         uint64_t tab = n > 0 ? ptab[0] : 0ull;
@@ -804,30 +828,30 @@ __global__ __launch_bounds__(1024 / R, 8 / R) void osd_reg_kernel(OsdArgs a) {
                 if (cm) {
                     const int first = __ffsll((unsigned long long)cm) - 1;
                     if (lane == first) {
-                        crow[buf * 16 + k * nwv + wid] = g[k];
-                        csp[buf * 16 + k * nwv + wid] = sp[k];
+                        vrow<NW> *cr = &crow[buf * 16 + k * nwv + wid];
+                        *cr = g[k];
+                        if constexpr (SP_IN_ROW)
+                            ((uint32_t *)cr)[NW] = sp[k];
+                        else
+                            csp[buf * 16 + k * nwv + wid] = sp[k];
                     }
                     key = 0xFFFFu - (uint32_t)(k * nth + wid * 64 + first);
                 }
             }
-            if (lane == 0) wkey[buf * 16 + wid] = key;
-            __syncthreads();
-            uint32_t kmax = 0;
-            {
-                const uint4 *kv = (const uint4 *)(wkey + buf * 16);
-#pragma unroll
-                for (int q4 = 0; q4 < 4; ++q4) {
-                    const uint4 v = kv[q4];
-                    const uint32_t a01 = v.x > v.y ? v.x : v.y, a23 = v.z > v.w ? v.z : v.w;
-                    const uint32_t a = a01 > a23 ? a01 : a23;
-                    kmax = a > kmax ? a : kmax;
-                }
+            const uint32_t tag = (uint32_t)(j + 1) << 16;
+            if (key) {
+                // a uniform operand: one lane of the wave performs the atomic
+                const uint32_t tk = __builtin_amdgcn_readfirstlane(tag | key);
+                __hip_atomic_fetch_max(&wkey[j & 1], tk, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             }
-            const uint32_t rv = __builtin_amdgcn_readfirstlane(kmax);
+            __syncthreads();
+            // this step's key less the tag is its 0xFFFF - row in [1, 0xFFFF]; an
+            // earlier step's key is below the tag
+            const int rv = (int)(__builtin_amdgcn_readfirstlane(wkey[j & 1]) - tag);
             const int pb = buf;
             buf ^= 1;
-            if (rv == 0) continue;  // no row of this column is free
-            const int pv = (int)(0xFFFFu - rv);
+            if (rv <= 0) continue;  // no row of this column is free
+            const int pv = 0xFFFF - rv;
             const int pk = (R == 2 && pv >= nth) ? 1 : 0;
             const int pt = pv - pk * nth;  // the pivot row's thread, in wave pw
             const int pw = pt >> 6;
@@ -852,8 +876,13 @@ __global__ __launch_bounds__(1024 / R, 8 / R) void osd_reg_kernel(OsdArgs a) {
             }
             // reduced columns are sparse early on: waves with no row to update skip the row read
             if (um[0] | um[R - 1]) {
-                const vrow<NW> pr = crow[pb * 16 + pk * nwv + pw];
-                const uint32_t ps = csp[pb * 16 + pk * nwv + pw];
+                const vrow<NW> *cr = &crow[pb * 16 + pk * nwv + pw];
+                const vrow<NW> pr = *cr;
+                uint32_t ps;
+                if constexpr (SP_IN_ROW)
+                    ps = ((const uint32_t *)cr)[NW];
+                else
+                    ps = csp[pb * 16 + pk * nwv + pw];
 #pragma unroll
                 for (int k = 0; k < R; ++k)
                     if ((um[k] >> lane) & 1ull) {
