@@ -813,7 +813,7 @@ __global__ __launch_bounds__(1024 / R, 8 / R) void osd_reg_kernel(OsdArgs a) {
         for (int j = 0; j < n && rank < m; ++j) {
             const uint64_t tu = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(tab >> 32)) << 32) |
                                 __builtin_amdgcn_readfirstlane((uint32_t)tab);
-            if (j + 1 < n) tab = ptab[j + 1];  // prefetch the next column's checks
+            tab = ptab[j + 1];  // the next column's checks (past the list at j = n - 1: unused, inside the block's LDS)
             uint32_t x[R];
             reduced_bits<NW, R>(g, tu, x);
             uint64_t xm[R];
@@ -876,16 +876,20 @@ __global__ __launch_bounds__(1024 / R, 8 / R) void osd_reg_kernel(OsdArgs a) {
             }
             // reduced columns are sparse early on: waves with no row to update skip the row read
             if (um[0] | um[R - 1]) {
-                const vrow<NW> *cr = &crow[pb * 16 + pk * nwv + pw];
-                const vrow<NW> pr = *cr;
+                // one load of the whole padded row (its s' bit in the padding word, if any)
+                using vpad = vrow<sizeof(vrow<NW>) / 4>;
+                const vpad full = *(const vpad *)&crow[pb * 16 + pk * nwv + pw];
+                vrow<NW> pr;
+#pragma unroll
+                for (int w = 0; w < NW; ++w) pr[w] = full[w];
                 uint32_t ps;
                 if constexpr (SP_IN_ROW)
-                    ps = ((const uint32_t *)cr)[NW];
+                    ps = full[NW];
                 else
                     ps = csp[pb * 16 + pk * nwv + pw];
 #pragma unroll
                 for (int k = 0; k < R; ++k)
-                    if ((um[k] >> lane) & 1ull) {
+                    if (__builtin_amdgcn_inverse_ballot_w64(um[k])) {  // lane's row k has a 1
                         g[k] ^= pr;
                         sp[k] ^= ps;
                     }
