@@ -811,62 +811,62 @@ __global__ __launch_bounds__(1024 / R, 8 / R) void osd_reg_kernel(OsdArgs a) {
         int buf = 0;  // row buffers and key slots alternate over 2
         uint64_t tab = n > 0 ? ptab[0] : 0ull;
         for (int j = 0; j < n && rank < m; ++j) {
-            const uint64_t tu = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(tab >> 32)) << 32) |
-                                __builtin_amdgcn_readfirstlane((uint32_t)tab);
+            const uint64_t tu = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(tab >> 32)) << 32) |
+                                (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)tab);
             tab = ptab[j + 1];  // the next column's checks (past the list at j = n - 1: unused, inside the block's LDS)
             uint32_t x[R];
             reduced_bits<NW, R>(g, tu, x);
             uint64_t xm[R];
 #pragma unroll
             for (int k = 0; k < R; ++k) xm[k] = __ballot(x[k]);
-            // every slot k publishes its lowest free row with a 1 (row buffer k * nwv + wave);
-            // the wave's candidate is the lowest of them (its rows tid precede its rows nth + tid)
-            uint32_t key = 0;
+            // every slot k publishes its lowest free row with a 1 in row buffer k * 8 + wave
+            // (R = 1: the wave), and the publishing lane takes the atomic maximum of the key
+            // tag | (1024 - row) << 4 | buffer: the block's lowest candidate row wins
+            const uint32_t tag = (uint32_t)(j + 1) << 16;
 #pragma unroll
             for (int k = R - 1; k >= 0; --k) {
                 const uint64_t cm = xm[k] & freem[k];
                 if (cm) {
                     const int first = __ffsll((unsigned long long)cm) - 1;
                     if (lane == first) {
-                        vrow<NW> *cr = &crow[buf * 16 + k * nwv + wid];
+                        const int slot = k * 8 + wid;
+                        vrow<NW> *cr = &crow[buf * 16 + slot];
                         *cr = g[k];
                         if constexpr (SP_IN_ROW)
                             ((uint32_t *)cr)[NW] = sp[k];
                         else
-                            csp[buf * 16 + k * nwv + wid] = sp[k];
+                            csp[buf * 16 + slot] = sp[k];
+                        // marked uniform (one lane is active here): the atomic then needs no
+                        // cross-lane combining
+                        const uint32_t kk = __builtin_amdgcn_readfirstlane(
+                            tag | (uint32_t)(1024 - (k * nth + wid * 64 + first)) << 4 | (uint32_t)slot);
+                        __hip_atomic_fetch_max(&wkey[j & 1], kk, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                     }
-                    key = 0xFFFFu - (uint32_t)(k * nth + wid * 64 + first);
                 }
             }
-            const uint32_t tag = (uint32_t)(j + 1) << 16;
-            if (key) {
-                // a uniform operand: one lane of the wave performs the atomic
-                const uint32_t tk = __builtin_amdgcn_readfirstlane(tag | key);
-                __hip_atomic_fetch_max(&wkey[j & 1], tk, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            }
             __syncthreads();
-            // this step's key less the tag is its 0xFFFF - row in [1, 0xFFFF]; an
-            // earlier step's key is below the tag
+            // this step's winning key less the tag is (1024 - row) << 4 | buffer, positive;
+            // an earlier step's key is below the tag
             const int rv = (int)(__builtin_amdgcn_readfirstlane(wkey[j & 1]) - tag);
             const int pb = buf;
             buf ^= 1;
             if (rv <= 0) continue;  // no row of this column is free
-            const int pv = 0xFFFF - rv;
-            const int pk = (R == 2 && pv >= nth) ? 1 : 0;
-            const int pt = pv - pk * nth;  // the pivot row's thread, in wave pw
-            const int pw = pt >> 6;
+            const int slot = rv & 15;
+            const int pk = R == 2 ? slot >> 3 : 0;
+            const int pw = R == 2 ? slot & 7 : slot;  // the pivot row's wave
             uint64_t um[R];  // rows to update: every row with a 1 but the pivot row
 #pragma unroll
             for (int k = 0; k < R; ++k) um[k] = xm[k];
             if (wid == pw) {
-                const uint64_t bit = 1ull << (pt & 63);
+                const int pl = (1024 - (rv >> 4)) & 63;  // the pivot row's lane
+                const uint64_t bit = 1ull << pl;
 #pragma unroll
                 for (int k = 0; k < R; ++k)
                     if (k == pk) {
                         freem[k] &= ~bit;
                         um[k] &= ~bit;
                     }
-                if (lane == (pt & 63)) {
+                if (lane == pl) {
                     if (pk == 0)
                         pcol[0] = perm[j];
                     else
@@ -878,7 +878,7 @@ __global__ __launch_bounds__(1024 / R, 8 / R) void osd_reg_kernel(OsdArgs a) {
             if (um[0] | um[R - 1]) {
                 // one load of the whole padded row (its s' bit in the padding word, if any)
                 using vpad = vrow<sizeof(vrow<NW>) / 4>;
-                const vpad full = *(const vpad *)&crow[pb * 16 + pk * nwv + pw];
+                const vpad full = *(const vpad *)&crow[pb * 16 + slot];
                 vrow<NW> pr;
 #pragma unroll
                 for (int w = 0; w < NW; ++w) pr[w] = full[w];
@@ -886,7 +886,7 @@ __global__ __launch_bounds__(1024 / R, 8 / R) void osd_reg_kernel(OsdArgs a) {
                 if constexpr (SP_IN_ROW)
                     ps = full[NW];
                 else
-                    ps = csp[pb * 16 + pk * nwv + pw];
+                    ps = csp[pb * 16 + slot];
 #pragma unroll
                 for (int k = 0; k < R; ++k)
                     if (__builtin_amdgcn_inverse_ballot_w64(um[k])) {  // lane's row k has a 1
