@@ -827,6 +827,9 @@ __global__ __launch_bounds__(1024 / R, 8 / R) void osd_reg_kernel(OsdArgs a) {
             for (int k = R - 1; k >= 0; --k) {
                 const uint64_t cm = xm[k] & freem[k];
                 if (cm) {
+                    // waves on the step's critical path (a candidate to publish, rows to
+                    // update) issue ahead of the others until the next barrier
+                    __builtin_amdgcn_s_setprio(2);
                     const int first = __ffsll((unsigned long long)cm) - 1;
                     if (lane == first) {
                         const int slot = k * 8 + wid;
@@ -845,6 +848,7 @@ __global__ __launch_bounds__(1024 / R, 8 / R) void osd_reg_kernel(OsdArgs a) {
                 }
             }
             __syncthreads();
+            __builtin_amdgcn_s_setprio(0);
             // this step's winning key less the tag is (1024 - row) << 4 | buffer, positive;
             // an earlier step's key is below the tag
             const int rv = (int)(__builtin_amdgcn_readfirstlane(wkey[j & 1]) - tag);
@@ -876,6 +880,7 @@ __global__ __launch_bounds__(1024 / R, 8 / R) void osd_reg_kernel(OsdArgs a) {
             }
             // reduced columns are sparse early on: waves with no row to update skip the row read
             if (um[0] | um[R - 1]) {
+                __builtin_amdgcn_s_setprio(2);
                 // one load of the whole padded row (its s' bit in the padding word, if any)
                 using vpad = vrow<sizeof(vrow<NW>) / 4>;
                 const vpad full = *(const vpad *)&crow[pb * 16 + slot];
@@ -896,6 +901,7 @@ __global__ __launch_bounds__(1024 / R, 8 / R) void osd_reg_kernel(OsdArgs a) {
             }
             ++rank;
         }
+        __builtin_amdgcn_s_setprio(0);
         bool piv[R];
 #pragma unroll
         for (int k = 0; k < R; ++k) piv[k] = valid[k] && !((freem[k] >> lane) & 1ull);
