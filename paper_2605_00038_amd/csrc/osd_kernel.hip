@@ -870,11 +870,11 @@ __global__ __launch_bounds__(1024 / R, 8 / R) void osd_reg_kernel(OsdArgs a) {
                         freem[k] &= ~bit;
                         um[k] &= ~bit;
                     }
-                if (lane == pl) {
+                if (lane == pl) {  // the sorted position; its column is looked up after the elimination
                     if (pk == 0)
-                        pcol[0] = perm[j];
+                        pcol[0] = j;
                     else
-                        pcol[R - 1] = perm[j];
+                        pcol[R - 1] = j;
                     isb[j] = 1;
                 }
             }
@@ -904,7 +904,10 @@ __global__ __launch_bounds__(1024 / R, 8 / R) void osd_reg_kernel(OsdArgs a) {
         __builtin_amdgcn_s_setprio(0);
         bool piv[R];
 #pragma unroll
-        for (int k = 0; k < R; ++k) piv[k] = valid[k] && !((freem[k] >> lane) & 1ull);
+        for (int k = 0; k < R; ++k) {
+            piv[k] = valid[k] && !((freem[k] >> lane) & 1ull);
+            if (piv[k]) pcol[k] = perm[pcol[k]];
+        }
 
         // ---- consistency: a row with no pivot reduced to 0 = s'_r
         bool bad = false;
