@@ -157,18 +157,24 @@ __device__ void sort_columns(const float *lam, int n, int P, int has_lo, int i16
 // bytes of LDS.
 __device__ void sort_columns_i16(const int16_t *lq, int n, int P, uint32_t *keys, uint16_t *perm) {
     const int tid = threadIdx.x, nth = blockDim.x;
-    for (int j = tid; j < P; j += nth)
-        keys[j] = j < n ? ((uint32_t)((int32_t)lq[j] + 32768) << 16) | (uint32_t)j : ~0u;
+    for (int j = tid; j < n; j += nth) keys[j] = ((uint32_t)((int32_t)lq[j] + 32768) << 16) | (uint32_t)j;
     __syncthreads();
+    // Bitonic network with every block sorted ascending: each merge of blocks of size k
+    // first compares element i with its mirror i ^ (k - 1), then halves as usual.  The
+    // slots n .. P - 1 stand for +infinity (keys are unique and below ~0u), which never
+    // moves in this form, so every pair whose upper slot is >= n is skipped and those
+    // slots are never stored.
     for (int k = 2; k <= P; k <<= 1) {
         for (int jj = k >> 1; jj > 0; jj >>= 1) {
             for (int t = tid; t < (P >> 1); t += nth) {
                 const int i = ((t & ~(jj - 1)) << 1) | (t & (jj - 1));
-                const int l = i + jj;
-                const uint32_t x = keys[i], y = keys[l];
-                if ((x > y) == ((i & k) == 0)) {
-                    keys[i] = y;
-                    keys[l] = x;
+                const int l = jj == (k >> 1) ? i ^ (k - 1) : i + jj;
+                if (l < n) {
+                    const uint32_t x = keys[i], y = keys[l];
+                    if (x > y) {
+                        keys[i] = y;
+                        keys[l] = x;
+                    }
                 }
             }
             __syncthreads();
