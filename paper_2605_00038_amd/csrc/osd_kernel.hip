@@ -166,7 +166,9 @@ __device__ void sort_columns_i16(const int16_t *lq, int n, int P, uint32_t *keys
     // slots are never stored.
     for (int k = 2; k <= P; k <<= 1) {
         for (int jj = k >> 1; jj > 0; jj >>= 1) {
-            for (int t = tid; t < (P >> 1); t += nth) {
+            // pair t has i >= 2 (t - jj + 1): none from t = n / 2 + jj on reaches below n
+            const int tb = (n >> 1) + jj < (P >> 1) ? (n >> 1) + jj : (P >> 1);
+            for (int t = tid; t < tb; t += nth) {
                 const int i = ((t & ~(jj - 1)) << 1) | (t & (jj - 1));
                 const int l = jj == (k >> 1) ? i ^ (k - 1) : i + jj;
                 if (l < n) {
