@@ -116,32 +116,30 @@ __device__ void sort_columns(const float *lam, int n, int P, int has_lo, int i16
                              uint16_t *cols, uint16_t *perm) {
     const int tid = threadIdx.x, nth = blockDim.x;
     const int16_t *lq = (const int16_t *)lam;
-    for (int j = tid; j < P; j += nth) {
-        if (j < n) {
-            const uint32_t hk = i16 ? (uint32_t)((int32_t)lq[j] + 32768) : orderable(lam[j]);
-            const unsigned long long h = (unsigned long long)hk << 32;
-            keys[j] = h | (has_lo ? orderable(lam[n + j]) : (unsigned)j);
-            if (has_lo) cols[j] = (uint16_t)j;
-        } else {
-            keys[j] = ~0ull;
-            if (has_lo) cols[j] = 0xFFFFu;
-        }
+    for (int j = tid; j < n; j += nth) {
+        const uint32_t hk = i16 ? (uint32_t)((int32_t)lq[j] + 32768) : orderable(lam[j]);
+        const unsigned long long h = (unsigned long long)hk << 32;
+        keys[j] = h | (has_lo ? orderable(lam[n + j]) : (unsigned)j);
+        if (has_lo) cols[j] = (uint16_t)j;
     }
     __syncthreads();
+    // the ascending bitonic network of sort_columns_i16 below: the slots n .. P - 1
+    // stand for an element above every (key, column) pair and are never touched
     for (int k = 2; k <= P; k <<= 1) {
         for (int jj = k >> 1; jj > 0; jj >>= 1) {
-            for (int t = tid; t < (P >> 1); t += nth) {
-                int i = ((t & ~(jj - 1)) << 1) | (t & (jj - 1));
-                int l = i + jj;
-                bool asc = (i & k) == 0;
-                unsigned long long x = keys[i], y = keys[l];
+            const int tb = (n >> 1) + jj < (P >> 1) ? (n >> 1) + jj : (P >> 1);
+            for (int t = tid; t < tb; t += nth) {
+                const int i = ((t & ~(jj - 1)) << 1) | (t & (jj - 1));
+                const int l = jj == (k >> 1) ? i ^ (k - 1) : i + jj;
+                if (l >= n) continue;
+                const unsigned long long x = keys[i], y = keys[l];
                 if (has_lo) {
                     const uint16_t cx = cols[i], cy = cols[l];
-                    if ((x > y || (x == y && cx > cy)) == asc) {
+                    if (x > y || (x == y && cx > cy)) {
                         keys[i] = y; keys[l] = x;
                         cols[i] = cy; cols[l] = cx;
                     }
-                } else if ((x > y) == asc) {
+                } else if (x > y) {
                     keys[i] = y; keys[l] = x;
                 }
             }
