@@ -593,7 +593,8 @@ __device__ __forceinline__ void reduced_bits_add(const vrow<NW> (&g)[R], uint64_
 // and 4 only where the column has them).
 template <int NW, int R>
 __device__ __forceinline__ void reduced_bits(const vrow<NW> (&g)[R], uint64_t chk, uint32_t (&x)[R]) {
-    const uint32_t d = __builtin_amdgcn_readfirstlane((uint32_t)(chk >> 32) >> 29);
+    uint32_t d = (uint32_t)(chk >> 32) >> 29;
+    asm volatile("" : "+s"(d));  // a 32-bit scalar: the tests below stay scalar compares
 #pragma unroll
     for (int k = 0; k < R; ++k) x[k] = 0;
     reduced_bits_add<NW, R>(g, chk, 0, x);
