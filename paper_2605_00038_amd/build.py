@@ -18,6 +18,11 @@ def hipcc() -> str:
     return os.path.join(rocm, "bin", "hipcc")
 
 
+# The OSD kernels take LDS atomics from one lane that a data-dependent test picked;
+# the compiler's atomic optimizer would wrap each in a lane election it cannot drop.
+EXTRA_FLAGS = {"osd_kernel.hip": ["-mllvm", "-amdgpu-atomic-optimizer-strategy=None"]}
+
+
 def build(verbose: bool = False) -> str:
     """Always recompiles (objects in parallel), then links liblbp.so atomically."""
     objs = []
@@ -28,7 +33,7 @@ def build(verbose: bool = False) -> str:
                "-mcode-object-version=5",
                # keep the compiler from forming packed-fp32 VALU instructions
                "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-               "-c", os.path.join(CSRC, src), "-o", obj]
+               "-c", os.path.join(CSRC, src), "-o", obj] + EXTRA_FLAGS.get(src, [])
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append(subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT))

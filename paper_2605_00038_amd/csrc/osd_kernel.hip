@@ -846,10 +846,7 @@ __global__ __launch_bounds__(1024 / R, 8 / R) void osd_reg_kernel(OsdArgs a) {
                             ((uint32_t *)cr)[NW] = sp[k];
                         else
                             csp[buf * 16 + slot] = sp[k];
-                        // marked uniform (one lane is active here): the atomic then needs no
-                        // cross-lane combining
-                        const uint32_t kk = __builtin_amdgcn_readfirstlane(
-                            tag | (uint32_t)(1024 - (k * nth + wid * 64 + first)) << 4 | (uint32_t)slot);
+                        const uint32_t kk = tag | (uint32_t)(1024 - row[k]) << 4 | (uint32_t)slot;
                         __hip_atomic_fetch_max(&wkey[j & 1], kk, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                     }
                 }
