@@ -616,12 +616,20 @@ __device__ __forceinline__ uint64_t uniform_tab(const uint64_t *vn_tab, int col)
 // 32 h + j is bit j of lane 32 h + i's input.  Five block-swap stages (Hacker's
 // Delight, transpose32), the partner lane of stage s being lane ^ s (ds_swizzle in
 // bit-mask mode, within 32 lanes).
+// Branch-free: the lower lane of a pair keeps x's bits in M and takes the
+// partner's M bits shifted up (rotl(p, S) & ~M); the upper lane keeps ~M and takes
+// rotr(p, S) & M (the bits a rotation wraps around fall outside the taken mask).
 template <int S>
 __device__ __forceinline__ uint32_t transpose_stage(uint32_t x, int lane) {
     constexpr uint32_t M = S == 16 ? 0x0000FFFFu : S == 8 ? 0x00FF00FFu : S == 4 ? 0x0F0F0F0Fu
                          : S == 2 ? 0x33333333u : 0x55555555u;  // bits whose index has bit S clear
+    constexpr int LS = S == 16 ? 4 : S == 8 ? 3 : S == 4 ? 2 : S == 2 ? 1 : 0;
     const uint32_t p = (uint32_t)__builtin_amdgcn_ds_swizzle((int)x, (S << 10) | 0x1F);
-    return (lane & S) ? ((x & ~M) | ((p >> S) & M)) : ((x & M) | ((p << S) & ~M));
+    const uint32_t up = 0u - ((uint32_t)(lane >> LS) & 1u);  // ~0 in the upper lane of the pair
+    const uint32_t keep = M ^ up;
+    const uint32_t rot = (32u - S) ^ (up & ((uint32_t)S ^ (32u - S)));  // upper: S, lower: 32 - S
+    const uint32_t q = __builtin_amdgcn_alignbit(p, p, rot);           // rotate right by rot
+    return (x & keep) | (q & ~keep);
 }
 
 __device__ __forceinline__ uint32_t transpose32(uint32_t x, int lane) {
@@ -936,9 +944,13 @@ __global__ __launch_bounds__(1024 / R, 8 / R) void osd_reg_kernel(OsdArgs a) {
             static_assert(NW % 2 == 0, "rows are read as word pairs");
             for (int c0 = 0; c0 < m; c0 += 64) {
                 const int w = c0 >> 5;
+                // the transpose's per-lane masks are rebuilt here rather than hoisted and
+                // held across the shot loop, where they crowd the elimination's registers
+                int ln = lane;
+                asm volatile("" : "+v"(ln));
 #pragma unroll
                 for (int k = 0; k < R; ++k) {
-                    const uint64_t bl = column_ballots(g[k][w], g[k][w + 1], lane);
+                    const uint64_t bl = column_ballots(g[k][w], g[k][w + 1], ln);
                     if (c0 + lane < m) B[(size_t)(c0 + lane) * 16 + k * nwv + wid] = bl;
                 }
             }
