@@ -964,20 +964,40 @@ __global__ __launch_bounds__(1024 / R, 8 / R) void osd_reg_kernel(OsdArgs a) {
             uint32_t cost0 = 0;
             for (int w = 0; w < ngr; ++w) cost0 += __popcll(Y[w]);
             unsigned long long best = (unsigned long long)cost0 << 32;
-            for (int ai = tid; ai < nt; ai += nth) {
-                unsigned long long cost = 1 + ballot_cost((const uint4 *)B, (const uint4 *)Y, ngr, a.vn_tab[tl[ai]], ~0ull);
-                unsigned long long key = (cost << 32) | (unsigned long long)(1 + ai);
-                best = key < best ? key : best;
-            }
+            // candidates 0 .. nt - 1 flip one non-basis column, nt + pi the pair pi of the
+            // first w; the enumeration index 1 + ci breaks cost ties.  One index space keeps
+            // every thread at ceil((nt + npairs) / nth) candidates, and a thread issues the
+            // column-table loads of QS candidates before it scores the first.
             const int w = a.order < nt ? a.order : nt;
             const int npairs = w * (w - 1) / 2;
-            for (int pi = tid; pi < npairs; pi += nth) {
-                int aa, bb;
-                pair_of(pi, w, aa, bb);
-                unsigned long long cost =
-                    2 + ballot_cost((const uint4 *)B, (const uint4 *)Y, ngr, a.vn_tab[tl[aa]], a.vn_tab[tl[bb]]);
-                unsigned long long key = (cost << 32) | (unsigned long long)(1 + nt + pi);
-                best = key < best ? key : best;
+            const int ncand = nt + npairs;
+            constexpr int QS = 4;
+            for (int cb = tid; cb < ncand; cb += QS * nth) {
+                uint64_t ta[QS], tb[QS];
+#pragma unroll
+                for (int q = 0; q < QS; ++q) {
+                    const int ci = cb + q * nth;
+                    ta[q] = ~0ull;
+                    tb[q] = ~0ull;
+                    if (ci < nt) {
+                        ta[q] = a.vn_tab[tl[ci]];
+                    } else if (ci < ncand) {
+                        int aa, bb;
+                        pair_of(ci - nt, w, aa, bb);
+                        ta[q] = a.vn_tab[tl[aa]];
+                        tb[q] = a.vn_tab[tl[bb]];
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < QS; ++q) {
+                    const int ci = cb + q * nth;
+                    if (ci < ncand) {
+                        const unsigned long long cost =
+                            (ci < nt ? 1u : 2u) + ballot_cost((const uint4 *)B, (const uint4 *)Y, ngr, ta[q], tb[q]);
+                        const unsigned long long key = (cost << 32) | (unsigned long long)(1 + ci);
+                        best = key < best ? key : best;
+                    }
+                }
             }
             best = wave_min_u64(best);
             if (lane == 0) atomicMin(best64, best);
