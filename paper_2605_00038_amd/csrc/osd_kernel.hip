@@ -861,12 +861,14 @@ __global__ __launch_bounds__(1024 / R, 8 / R) void osd_reg_kernel(OsdArgs a) {
             }
             __syncthreads();
             __builtin_amdgcn_s_setprio(0);
-            // this step's winning key less the tag is (1024 - row) << 4 | buffer, positive;
-            // an earlier step's key is below the tag
-            const int rv = (int)(__builtin_amdgcn_readfirstlane(wkey[j & 1]) - tag);
+            // this step's winning key less the tag is (1024 - row) << 4 | buffer, in
+            // [1, 0xFFFF]; an earlier step's key (tag t' < t, or the initial 0) leaves
+            // 2^32 - (t - t') 2^16 + low >= 2^16 modulo 2^32
+            const uint32_t kd = (uint32_t)__builtin_amdgcn_readfirstlane(wkey[j & 1]) - tag;
             const int pb = buf;
             buf ^= 1;
-            if (rv <= 0) continue;  // no row of this column is free
+            if (kd - 1u >= 0xFFFFu) continue;  // no row of this column is free
+            const int rv = (int)kd;
             const int slot = rv & 15;
             const int pk = R == 2 ? slot >> 3 : 0;
             const int pw = R == 2 ? slot & 7 : slot;  // the pivot row's wave
