@@ -184,6 +184,71 @@ __device__ void sort_columns_i16(const int16_t *lq, int n, int P, uint32_t *keys
     __syncthreads();
 }
 
+// Step 1 for int16 lambda, as a stable LSD radix sort on lambda + 2^15 (four 4-bit
+// digits).  The columns enter in index order, so the result is the ascending
+// (lambda, column) order of the keys above.  Elements go in tiles of 64; a lane's
+// rank among the equal digits of its tile comes from four ballots, the (digit,
+// tile) counts are scanned digit-major, and each element lands at its count's
+// offset plus its rank.  keys holds 2n words (source and destination), hist
+// 16 ceil(n / 64) u16 counts, scr the block scan's 17 ints.
+__device__ void sort_columns_radix16(const int16_t *lq, int n, uint32_t *keys, uint16_t *hist, int *scr,
+                                     uint16_t *perm) {
+    const int tid = threadIdx.x, nth = blockDim.x, lane = tid & 63;
+    const int wid = __builtin_amdgcn_readfirstlane(tid >> 6), nwv = nth >> 6;
+    const int ntl = (n + 63) >> 6, ne = 16 * ntl;
+    const uint64_t below = (1ull << lane) - 1ull;  // lanes before this one
+    uint32_t *src = keys, *dst = keys + n;
+    for (int j = tid; j < n; j += nth) src[j] = ((uint32_t)((int32_t)lq[j] + 32768) << 16) | (uint32_t)j;
+    __syncthreads();
+    for (int pass = 0; pass < 4; ++pass) {
+        const int sh = 16 + 4 * pass;
+        // counts of digit l in tile T, written by lane l
+        for (int T = wid; T < ntl; T += nwv) {
+            const int i = 64 * T + lane;
+            const bool valid = i < n;
+            const uint32_t d = valid ? (src[i] >> sh) & 15u : 0u;
+            const uint64_t vm = __ballot(valid);
+            const uint64_t b0 = __ballot(d & 1u), b1 = __ballot(d & 2u), b2 = __ballot(d & 4u), b3 = __ballot(d & 8u);
+            if (lane < 16) {
+                const uint64_t mk = vm & ((lane & 1) ? b0 : ~b0) & ((lane & 2) ? b1 : ~b1) &
+                                    ((lane & 4) ? b2 : ~b2) & ((lane & 8) ? b3 : ~b3);
+                hist[lane * ntl + T] = (uint16_t)__popcll(mk);
+            }
+        }
+        __syncthreads();
+        // exclusive scan of the counts in (digit, tile) order
+        const int per = (ne + nth - 1) / nth, e0 = tid * per;
+        const int e1 = e0 + per < ne ? e0 + per : ne;
+        int sum = 0;
+        for (int e = e0; e < e1; ++e) sum += hist[e];
+        int total;
+        int off = block_excl_scan(sum, scr, &total);
+        for (int e = e0; e < e1; ++e) {
+            const int c = hist[e];
+            hist[e] = (uint16_t)off;
+            off += c;
+        }
+        __syncthreads();
+        for (int T = wid; T < ntl; T += nwv) {
+            const int i = 64 * T + lane;
+            const bool valid = i < n;
+            const uint32_t v = valid ? src[i] : 0u;
+            const uint32_t d = (v >> sh) & 15u;
+            const uint64_t vm = __ballot(valid);
+            const uint64_t b0 = __ballot(d & 1u), b1 = __ballot(d & 2u), b2 = __ballot(d & 4u), b3 = __ballot(d & 8u);
+            const uint64_t mk = vm & ((d & 1u) ? b0 : ~b0) & ((d & 2u) ? b1 : ~b1) & ((d & 4u) ? b2 : ~b2) &
+                                ((d & 8u) ? b3 : ~b3);
+            if (valid) dst[hist[d * ntl + T] + __popcll(mk & below)] = v;
+        }
+        __syncthreads();
+        uint32_t *t = src;
+        src = dst;
+        dst = t;
+    }
+    for (int j = tid; j < n; j += nth) perm[j] = (uint16_t)(src[j] & 0xFFFFu);  // four passes: src is keys
+    __syncthreads();
+}
+
 // Non-basis columns in sorted order -> tl[0..nt).
 __device__ int list_nonbasis(const uint8_t *isb, const uint16_t *perm, int n, uint16_t *tl, int *scr) {
     const int nth = blockDim.x;
@@ -767,10 +832,15 @@ __global__ __launch_bounds__(1024 / R, 8 / R) void osd_reg_kernel(OsdArgs a) {
         const float *lam = a.llr_i16 ? (const float *)((const int16_t *)a.fail_llr + lrow * n) : a.fail_llr + lrow * 2 * n;
 
         // ---- 1. sort (lambda, column) ascending
-        if (a.llr_i16)
-            sort_columns_i16((const int16_t *)lam, n, P, (uint32_t *)smem, perm);
-        else
+        if (a.llr_i16) {
+            // the radix sort's counts use the candidate-row buffers, idle until the elimination
+            if (32 * ((n + 63) >> 6) <= 32 * (int)sizeof(vrow<NW>))
+                sort_columns_radix16((const int16_t *)lam, n, (uint32_t *)smem, (uint16_t *)crow, scr, perm);
+            else
+                sort_columns_i16((const int16_t *)lam, n, P, (uint32_t *)smem, perm);
+        } else {
             sort_columns(lam, n, P, a.has_lo, 0, (unsigned long long *)smem, scol, perm);
+        }
 
         // check lists of the sorted columns (packed as reduced_bits reads them),
         // staged over the dead sort keys
