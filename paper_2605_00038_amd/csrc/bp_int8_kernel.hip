@@ -313,7 +313,10 @@ __device__ __forceinline__ uint4 row_offsets(const uint4 *tab, int s, int lane, 
     if constexpr (TABLE == 0) {
         return tab[s * 64 + lane];
     } else {
-        const uint32_t c = (uint32_t)(lane + 64 * s);
+        uint32_t c = (uint32_t)(lane + 64 * s);
+        // opaque: the offsets depend on the lane and slot only, and hoisted out of the
+        // iteration loop all slots' offsets are held (spilled) across it
+        if constexpr (TABLE != 0) asm volatile("" : "+v"(c));
         const uint32_t t = __umulhi(c, st.magic);
         const uint32_t s0 = c - t * st.m0;
         const uint32_t row = t == 0 ? s0 : (t < st.r ? st.m0 + s0 : 2 * st.m0);
